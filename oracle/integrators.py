@@ -1,0 +1,111 @@
+"""Explicit Runge-Kutta integrators for the RT-CC initial-value problem (oracle).
+
+Oracle (test infrastructure). Follows the paper's "Propagation of the RT-CC
+equations" subsection and "Comparison of numerical integrators":
+
+* generic explicit RK (Eqs. rk_y, rk_k; Table tab:butcher): stage
+  k_i = f(t_n + c_i h, y_n + h sum_j a_ij k_j), step y_{n+1} = y_n + h sum_i b_i k_i;
+* classical RK4 (Eq. rk4truncation; the printed formula leaves out the factor h,
+  which is restored here: y_{n+1} = y_n + (h/6)(k1 + 2k2 + 2k3 + k4));
+* Cash-Karp embedded pair (Eqs. ck-k, ck-y). Three printed coefficients
+  contradict the row-sum condition sum_j a_ij = c_i and are replaced by the
+  values of Cash and Karp's own tableau: c4 = 3/5, c5 = 1, a42 = -9/10 and
+  a63 = +575/13824. The weight set beginning 37/378 is the fifth-order one
+  (the text labels it fourth order); the step advances with it;
+* step-size control (Eqs. ck-h, ck-h-final): accept when Delta <= eps, with
+  h_new = 0.84 h (eps/Delta)^(1/5); otherwise reject and retry with
+  h_new = 0.84 h (eps/Delta)^(1/4). The error Delta is the largest complex
+  modulus of y5 - y4 over the state. The factor is clamped to [0.1, 5]
+  (not stated in the paper).
+"""
+from __future__ import annotations
+
+from fractions import Fraction as Fr
+
+import numpy as np
+
+RK4_C = [0.0, 0.5, 0.5, 1.0]
+RK4_A = [[], [0.5], [0.0, 0.5], [0.0, 0.0, 1.0]]
+RK4_B = [1 / 6, 1 / 3, 1 / 3, 1 / 6]
+
+CK_C = [Fr(0), Fr(1, 5), Fr(3, 10), Fr(3, 5), Fr(1), Fr(7, 8)]
+CK_A = [
+    [],
+    [Fr(1, 5)],
+    [Fr(3, 40), Fr(9, 40)],
+    [Fr(3, 10), Fr(-9, 10), Fr(6, 5)],
+    [Fr(-11, 54), Fr(5, 2), Fr(-70, 27), Fr(35, 27)],
+    [Fr(1631, 55296), Fr(175, 512), Fr(575, 13824), Fr(44275, 110592), Fr(253, 4096)],
+]
+CK_B5 = [Fr(37, 378), Fr(0), Fr(250, 621), Fr(125, 594), Fr(0), Fr(512, 1771)]
+CK_B4 = [Fr(2825, 27648), Fr(0), Fr(18575, 48384), Fr(13525, 55296), Fr(277, 14336), Fr(1, 4)]
+
+SAFETY = 0.84
+FACTOR_MIN, FACTOR_MAX = 0.1, 5.0
+
+
+def rk_stages(f, t, y, h, c, A):
+    """All stage derivatives k_i of an explicit tableau (Eq. rk_k)."""
+    ks = []
+    for i in range(len(c)):
+        yi = y.copy()
+        for j, a in enumerate(A[i]):
+            if a != 0:
+                yi = yi + h * float(a) * ks[j]
+        ks.append(f(t + float(c[i]) * h, yi))
+    return ks
+
+
+def rk_combine(y, h, b, ks):
+    """y + h sum_i b_i k_i (Eq. rk_y)."""
+    out = y.copy()
+    for bi, k in zip(b, ks):
+        if bi != 0:
+            out = out + h * float(bi) * k
+    return out
+
+
+def rk4_step(f, t, y, h):
+    """One classical RK4 step."""
+    ks = rk_stages(f, t, y, h, RK4_C, RK4_A)
+    return rk_combine(y, h, RK4_B, ks)
+
+
+def cashkarp_trial(f, t, y, h):
+    """One Cash-Karp trial: (fifth-order solution, fourth-order solution, Delta)."""
+    ks = rk_stages(f, t, y, h, CK_C, CK_A)
+    y5 = rk_combine(y, h, CK_B5, ks)
+    y4 = rk_combine(y, h, CK_B4, ks)
+    delta = float(np.max(np.abs(y5 - y4))) if y5.size else 0.0
+    return y5, y4, delta
+
+
+def ck_factor(eps, delta):
+    """Step-size factor of Eq. ck-h-final (with the clamp)."""
+    if delta == 0.0:
+        return FACTOR_MAX
+    p = 0.2 if delta <= eps else 0.25
+    fac = SAFETY * (eps / delta) ** p
+    return min(max(fac, FACTOR_MIN), FACTOR_MAX)
+
+
+def cashkarp_step(f, t, y, h, eps, t_end=None, max_tries=50):
+    """Adaptive step: retry with shrinking h until accepted.
+
+    Returns (y_new, t_new, h_used, h_next, n_rejected).
+    """
+    rejected = 0
+    for _ in range(max_tries):
+        hh = h if t_end is None else min(h, t_end - t)
+        y5, _, delta = cashkarp_trial(f, t, y, hh)
+        fac = ck_factor(eps, delta)
+        if delta <= eps:
+            return y5, t + hh, hh, hh * fac, rejected
+        rejected += 1
+        h = hh * fac
+    raise RuntimeError("Cash-Karp step not accepted")
+
+
+def butcher_row_sums(c, A):
+    """sum_j a_ij - c_i for each row (zero for a consistent tableau)."""
+    return [sum(A[i], Fr(0)) - c[i] for i in range(len(c))]
