@@ -1,0 +1,139 @@
+/*
+ * rtcc.h -- C ABI of the MI355X (gfx950) real-time CCSD propagation library.
+ *
+ * The library evaluates the time derivatives of the coupled-cluster amplitudes
+ * (T1, T2) and Lambda amplitudes (L1, L2) of real-time CCSD under a dipole
+ * field and integrates them with explicit Runge-Kutta methods, after
+ * Wang, Peyton and Crawford, "Accelerating real-time coupled cluster methods
+ * with single-precision arithmetic and adaptive numerical integration"
+ * (arXiv 2205.05175):
+ *   - equations of motion: Theory section, Eq. derivT (dt/dt = -i <mu|Hbar|0>)
+ *     and Eq. derivL (dlambda/dt = +i <0|(1+Lambda)[Hbar, tau_mu]|0>), with
+ *     Hbar = e^{-T} H e^{T} (Eq. simtranH);
+ *   - field coupling: V(t) = -mu.E(t) (linear-absorption subsection), entering
+ *     only through the Fock matrix f(t) = f - sum_a E_a(t) mu_a;
+ *   - Gaussian pulse: Eq. field; Dirac-delta kick: E(t) = kappa delta(t) n;
+ *   - integrators: Eqs. rk_y/rk_k (Table tab:butcher), RK4 (Eq. rk4truncation),
+ *     Cash-Karp (Eqs. ck-k, ck-y) with the controller of Eqs. ck-h/ck-h-final;
+ *   - dipole: Eq. dipole, mu_a = Tr(rho mu_a) with the unrelaxed density.
+ *
+ * Closed-shell variables. With o doubly occupied and v virtual spatial orbitals
+ * (occupied first), the state y is complex128 (interleaved Re, Im), row-major:
+ *     y = [ T1 (o*v) | T2 (o*o*v*v) | L1 (o*v) | L2 (o*o*v*v) ]
+ * where T1[i,a] = t_{i alpha}^{a alpha}, T2[i,j,a,b] = t_{i alpha, j beta}^{a alpha, b beta}
+ * (so T2[i,j,a,b] == T2[j,i,b,a]) and Lambda uses the same map.
+ *
+ * Ownership and streams. rtcc_init copies the integrals; the context owns its
+ * device copies and workspaces until rtcc_destroy. State and output buffers
+ * (y, dydt, mu_dev) are caller-owned DEVICE memory; the library keeps no pointer
+ * to them after a call returns. Work is enqueued on the stream given to
+ * rtcc_init and is asynchronous, except for calls that return host values
+ * (rtcc_dipole, rtcc_step_cashkarp, rtcc_ground_state, rtcc_check_state), which
+ * synchronise that stream. A context is used by one host thread at a time.
+ *
+ * Errors. Every call returns RTCC_OK (0) or a negative code; the message is
+ * available from rtcc_last_error(ctx) (or rtcc_last_error(NULL) for a failed
+ * rtcc_init). No call aborts or throws across the ABI.
+ */
+#ifndef RTCC_H
+#define RTCC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rtcc_ctx rtcc_ctx;
+
+/* Contraction precision. The RK state, the stage updates, the dipole and the
+ * ground-state iterations are always FP64. */
+enum { RTCC_FP64 = 0, RTCC_FP32 = 1 };
+
+enum {
+  RTCC_OK = 0,
+  RTCC_EINVAL = -1,     /* bad argument (sizes, null pointers, non-finite scalars) */
+  RTCC_ENOMEM = -2,     /* device allocation or scratch exhausted */
+  RTCC_EHIP = -3,       /* HIP runtime error */
+  RTCC_ENONFINITE = -4, /* non-finite values in the state */
+  RTCC_ENOTCONV = -5    /* ground-state iterations did not converge */
+};
+
+/* External field. kind 0: none. kind 1: Gaussian pulse of Eq. field,
+ * E(t) = -E0 exp(-(t-t0)^2/(2 sigma^2)) cos(omega (t-t0)) n. kind 2: Dirac-delta
+ * kick of strength E0 along n at t = 0 -- apply it with rtcc_kick; the stepping
+ * functions treat kind 2 as field-free. n need not be normalised (it is used as given). */
+typedef struct {
+  int kind;
+  double E0, omega, sigma, t0;
+  double n[3];
+} rtcc_field;
+
+/* Create a context.
+ *   o, v     : occupied / virtual spatial orbitals (o >= 1, v >= 1), n = o + v.
+ *   eri      : HOST, n^4 doubles, chemists' order (pq|rs), row-major, real, 8-fold symmetric.
+ *   fock     : HOST, n*n doubles, real symmetric Fock matrix (occupied orbitals first).
+ *   dipole   : HOST, 3*n*n doubles, real symmetric dipole integrals (x, y, z).
+ *   precision: RTCC_FP64 or RTCC_FP32 (contractions of rtcc_rhs and the steppers).
+ *   hip_stream: hipStream_t to run on (NULL = default stream).
+ * All host arrays are copied; the caller may free them on return. */
+int rtcc_init(rtcc_ctx** ctx, int o, int v, const double* eri, const double* fock, const double* dipole,
+              int precision, void* hip_stream);
+
+/* Switch the contraction precision of an existing context (allocates FP32 copies on first use). */
+int rtcc_set_precision(rtcc_ctx* ctx, int precision);
+
+/* dydt = ( -i R_T(y; f - E.mu), +i R_L(y; f - E.mu) ): the right-hand side of
+ * Eqs. derivT/derivL at the field value E[3] (HOST). y, dydt: DEVICE, state layout above;
+ * they must not overlap. t is the time label (unused by the operator itself). */
+int rtcc_rhs(rtcc_ctx* ctx, const void* y, double t, const double E[3], void* dydt);
+
+/* One classical RK4 step of size h from time t; y (DEVICE) is updated in place. */
+int rtcc_step_rk4(rtcc_ctx* ctx, void* y, double t, double h, const rtcc_field* field);
+
+/* nsteps RK4 steps of size h from t0. If mu_dev (DEVICE, (nsteps+1)*6 doubles) is not NULL,
+ * the complex dipole (Re x, Im x, Re y, Im y, Re z, Im z) at t0 and after every step is
+ * written to it. Asynchronous. */
+int rtcc_propagate_rk4(rtcc_ctx* ctx, void* y, double t0, double h, int nsteps, const rtcc_field* field,
+                       double* mu_dev);
+
+/* One Cash-Karp trial of size *h from *t with absolute tolerance eps on the largest complex
+ * modulus of y5 - y4. If accepted (*accepted = 1) y advances by the fifth-order solution and
+ * *t += h; otherwise y is unchanged. In both cases *h becomes the controller's next trial size
+ * and *delta the error estimate. Synchronises. */
+int rtcc_step_cashkarp(rtcc_ctx* ctx, void* y, double* t, double* h, double eps, const rtcc_field* field,
+                       int* accepted, double* delta);
+
+/* Complex dipole expectation value (Eq. dipole), reference part included, into mu[6] (HOST):
+ * (Re mu_x, Im mu_x, Re mu_y, Im mu_y, Re mu_z, Im mu_z). Computed in FP64. Synchronises. */
+int rtcc_dipole(rtcc_ctx* ctx, const void* y, double mu[6]);
+
+/* Same as rtcc_dipole but written to DEVICE memory mu_dev[6]; asynchronous. */
+int rtcc_dipole_dev(rtcc_ctx* ctx, const void* y, double* mu_dev);
+
+/* Ground state at zero field (the initial condition y0 of the propagation): Jacobi iterations
+ * with orbital-energy denominators and DIIS, first T from the T part of y (zeros are fine),
+ * then Lambda from lambda = t, each to max|R| <= tol. FP64. *e_corr (HOST, may be NULL)
+ * receives the CCSD correlation energy. Returns RTCC_ENOTCONV after maxiter iterations. */
+int rtcc_ground_state(rtcc_ctx* ctx, void* y, double tol, int maxiter, double* e_corr);
+
+/* Dirac-delta kick E(t) = kappa delta(t) n applied to y in place: the flow of the dipole
+ * operator n.mu alone over unit "time", integrated with 100 RK4 sub-steps. FP64. */
+int rtcc_kick(rtcc_ctx* ctx, void* y, double kappa, const double n[3]);
+
+/* *nonfinite (HOST) = number of non-finite complex entries of y. Synchronises. */
+int rtcc_check_state(rtcc_ctx* ctx, const void* y, int64_t* nonfinite);
+
+/* Diagnostics: out[0] = o, out[1] = v, out[2] = state length (complex entries),
+ * out[3] = real flops issued to the MFMA GEMMs by the last rtcc_rhs call,
+ * out[4] = device bytes held by the context, out[5] = current precision. */
+int rtcc_info(rtcc_ctx* ctx, int64_t out[6]);
+
+void rtcc_destroy(rtcc_ctx* ctx);
+const char* rtcc_last_error(const rtcc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTCC_H */

@@ -27,9 +27,13 @@ a,b,e,f. ``P(pq) X = X - X(p<->q)``.
 """
 from __future__ import annotations
 
+from functools import partial
+
 import numpy as np
 
 from . import spinorb
+
+_einsum = partial(np.einsum, optimize=True)  # BLAS-backed pairwise contraction
 
 
 def _blocks(g, no):
@@ -53,7 +57,7 @@ def _Pab(x):
 
 def taus(t1, t2):
     """tau-tilde and tau of the factorised equations."""
-    tt = np.einsum("ia,jb->ijab", t1, t1)
+    tt = _einsum("ia,jb->ijab", t1, t1)
     tt = tt - tt.swapaxes(2, 3)
     return t2 + 0.5 * tt, t2 + tt
 
@@ -68,22 +72,22 @@ def intermediates(f, g, t1, t2):
     o, v = slice(0, no), slice(no, f.shape[0])
     fov, foo, fvv = f[o, v], f[o, o], f[v, v]
     tau_t, tau = taus(t1, t2)
-    Fae = fvv - 0.5 * np.einsum("me,ma->ae", fov, t1)
-    Fmi = foo + 0.5 * np.einsum("ie,me->mi", t1, fov)
+    Fae = fvv - 0.5 * _einsum("me,ma->ae", fov, t1)
+    Fmi = foo + 0.5 * _einsum("ie,me->mi", t1, fov)
     Fme = fov.astype(np.complex128)
     W = {}
     if g is not None:
         b = _blocks(g, no)
-        Fae = Fae + np.einsum("mf,mafe->ae", t1, b["ovvv"]) - 0.5 * np.einsum("mnaf,mnef->ae", tau_t, b["oovv"])
-        Fmi = Fmi + np.einsum("ne,mnie->mi", t1, b["ooov"]) + 0.5 * np.einsum("inef,mnef->mi", tau_t, b["oovv"])
-        Fme = Fme + np.einsum("nf,mnef->me", t1, b["oovv"])
-        x = np.einsum("je,mnie->mnij", t1, b["ooov"])
-        W["mnij"] = b["oooo"] + x - x.swapaxes(2, 3) + 0.25 * np.einsum("ijef,mnef->mnij", tau, b["oovv"])
-        x = np.einsum("mb,amef->abef", t1, b["vovv"])
-        W["abef"] = b["vvvv"] - (x - x.swapaxes(0, 1)) + 0.25 * np.einsum("mnab,mnef->abef", tau, b["oovv"])
-        W["mbej"] = (b["ovvo"] + np.einsum("jf,mbef->mbej", t1, b["ovvv"])
-                     - np.einsum("nb,mnej->mbej", t1, b["oovo"])
-                     - np.einsum("jnfb,mnef->mbej", 0.5 * t2 + np.einsum("jf,nb->jnfb", t1, t1), b["oovv"]))
+        Fae = Fae + _einsum("mf,mafe->ae", t1, b["ovvv"]) - 0.5 * _einsum("mnaf,mnef->ae", tau_t, b["oovv"])
+        Fmi = Fmi + _einsum("ne,mnie->mi", t1, b["ooov"]) + 0.5 * _einsum("inef,mnef->mi", tau_t, b["oovv"])
+        Fme = Fme + _einsum("nf,mnef->me", t1, b["oovv"])
+        x = _einsum("je,mnie->mnij", t1, b["ooov"])
+        W["mnij"] = b["oooo"] + x - x.swapaxes(2, 3) + 0.25 * _einsum("ijef,mnef->mnij", tau, b["oovv"])
+        x = _einsum("mb,amef->abef", t1, b["vovv"])
+        W["abef"] = b["vvvv"] - (x - x.swapaxes(0, 1)) + 0.25 * _einsum("mnab,mnef->abef", tau, b["oovv"])
+        W["mbej"] = (b["ovvo"] + _einsum("jf,mbef->mbej", t1, b["ovvv"])
+                     - _einsum("nb,mnej->mbej", t1, b["oovo"])
+                     - _einsum("jnfb,mnef->mbej", 0.5 * t2 + _einsum("jf,nb->jnfb", t1, t1), b["oovv"]))
     return Fae, Fmi, Fme, W
 
 
@@ -95,23 +99,23 @@ def t_residual(f, g, t1, t2):
     tau_t, tau = taus(t1, t2)
     Fae, Fmi, Fme, W = intermediates(f, g, t1, t2)
 
-    r1 = (fov + np.einsum("ie,ae->ia", t1, Fae) - np.einsum("ma,mi->ia", t1, Fmi)
-          + np.einsum("imae,me->ia", t2, Fme))
-    X = Fae - 0.5 * np.einsum("mb,me->be", t1, Fme)
-    Y = Fmi + 0.5 * np.einsum("je,me->mj", t1, Fme)
-    r2 = _Pab(np.einsum("ijae,be->ijab", t2, X)) - _Pij(np.einsum("imab,mj->ijab", t2, Y))
+    r1 = (fov + _einsum("ie,ae->ia", t1, Fae) - _einsum("ma,mi->ia", t1, Fmi)
+          + _einsum("imae,me->ia", t2, Fme))
+    X = Fae - 0.5 * _einsum("mb,me->be", t1, Fme)
+    Y = Fmi + 0.5 * _einsum("je,me->mj", t1, Fme)
+    r2 = _Pab(_einsum("ijae,be->ijab", t2, X)) - _Pij(_einsum("imab,mj->ijab", t2, Y))
     if g is not None:
         b = _blocks(g, no)
-        r1 = r1 - np.einsum("nf,naif->ia", t1, b["ovov"]) \
-            - 0.5 * np.einsum("imef,maef->ia", t2, b["ovvv"]) \
-            - 0.5 * np.einsum("mnae,nmei->ia", t2, b["oovo"])
+        r1 = r1 - _einsum("nf,naif->ia", t1, b["ovov"]) \
+            - 0.5 * _einsum("imef,maef->ia", t2, b["ovvv"]) \
+            - 0.5 * _einsum("mnae,nmei->ia", t2, b["oovo"])
         r2 = r2 + b["oovv"]
-        r2 = r2 + 0.5 * np.einsum("mnab,mnij->ijab", tau, W["mnij"])
-        r2 = r2 + 0.5 * np.einsum("ijef,abef->ijab", tau, W["abef"])
-        x = np.einsum("imae,mbej->ijab", t2, W["mbej"]) - np.einsum("ie,ma,mbej->ijab", t1, t1, b["ovvo"])
+        r2 = r2 + 0.5 * _einsum("mnab,mnij->ijab", tau, W["mnij"])
+        r2 = r2 + 0.5 * _einsum("ijef,abef->ijab", tau, W["abef"])
+        x = _einsum("imae,mbej->ijab", t2, W["mbej"]) - _einsum("ie,ma,mbej->ijab", t1, t1, b["ovvo"])
         r2 = r2 + _Pab(_Pij(x))
-        r2 = r2 + _Pij(np.einsum("ie,abej->ijab", t1, b["vvvo"]))
-        r2 = r2 - _Pab(np.einsum("ma,mbij->ijab", t1, b["ovoo"]))
+        r2 = r2 + _Pij(_einsum("ie,abej->ijab", t1, b["vvvo"]))
+        r2 = r2 - _Pab(_einsum("ma,mbij->ijab", t1, b["ovoo"]))
     return r1, r2
 
 
@@ -119,10 +123,10 @@ def energy(f, g, t1, t2):
     """Correlation part of <0|Hbar|0>: sum f_ia t_ia + 1/4 <ij||ab> t_ijab + 1/2 <ij||ab> t_ia t_jb."""
     no = t1.shape[0]
     o, v = slice(0, no), slice(no, f.shape[0])
-    e = np.einsum("ia,ia->", f[o, v], t1)
+    e = _einsum("ia,ia->", f[o, v], t1)
     if g is not None:
         govv = g[o, o, v, v]
-        e = e + 0.25 * np.einsum("ijab,ijab->", govv, t2) + 0.5 * np.einsum("ijab,ia,jb->", govv, t1, t1)
+        e = e + 0.25 * _einsum("ijab,ijab->", govv, t2) + 0.5 * _einsum("ijab,ia,jb->", govv, t1, t1)
     return e
 
 
@@ -132,30 +136,30 @@ def hbar(f, g, t1, t2):
     _, tau = taus(t1, t2)
     Fae, Fmi, Fme, W = intermediates(f, g, t1, t2)
     H = {"ov": Fme,
-         "oo": Fmi + 0.5 * np.einsum("ie,me->mi", t1, Fme),
-         "vv": Fae - 0.5 * np.einsum("ma,me->ae", t1, Fme)}
+         "oo": Fmi + 0.5 * _einsum("ie,me->mi", t1, Fme),
+         "vv": Fae - 0.5 * _einsum("ma,me->ae", t1, Fme)}
     if g is None:
         # the Fock parts of Hbar_mbij and Hbar_abei survive without two-electron integrals
-        H["ovoo"] = -np.einsum("me,ijbe->mbij", Fme, t2)
-        H["vvvo"] = -np.einsum("me,miab->abei", Fme, t2)
+        H["ovoo"] = -_einsum("me,ijbe->mbij", Fme, t2)
+        H["vvvo"] = -_einsum("me,miab->abei", Fme, t2)
         return H
     b = _blocks(g, no)
-    H["oooo"] = W["mnij"] + 0.25 * np.einsum("ijef,mnef->mnij", tau, b["oovv"])
-    H["vvvv"] = W["abef"] + 0.25 * np.einsum("mnab,mnef->abef", tau, b["oovv"])
-    H["ovvo"] = W["mbej"] - 0.5 * np.einsum("jnfb,mnef->mbej", t2, b["oovv"])
-    H["ooov"] = b["ooov"] + np.einsum("if,mnfe->mnie", t1, b["oovv"])
-    H["vovv"] = b["vovv"] - np.einsum("na,nmef->amef", t1, b["oovv"])
-    x = b["ovvo"] - np.einsum("njbf,mnef->mbej", t2, b["oovv"])
-    H["ovoo"] = (b["ovoo"] - np.einsum("me,ijbe->mbij", Fme, t2)
-                 - np.einsum("nb,mnij->mbij", t1, H["oooo"])
-                 + 0.5 * np.einsum("mbef,ijef->mbij", b["ovvv"], tau)
-                 + _Pab(np.einsum("mnie,jnbe->mbij", b["ooov"], t2))
-                 + _Pab(np.einsum("ie,mbej->mbij", t1, x)))
-    x = b["ovvo"] - np.einsum("nibf,mnef->mbei", t2, b["oovv"])
-    y = np.einsum("mbef,miaf->abei", b["ovvv"], t2) + np.einsum("ma,mbei->abei", t1, x)
-    H["vvvo"] = (b["vvvo"] - np.einsum("me,miab->abei", Fme, t2)
-                 + np.einsum("if,abef->abei", t1, H["vvvv"])
-                 + 0.5 * np.einsum("mnei,mnab->abei", b["oovo"], tau)
+    H["oooo"] = W["mnij"] + 0.25 * _einsum("ijef,mnef->mnij", tau, b["oovv"])
+    H["vvvv"] = W["abef"] + 0.25 * _einsum("mnab,mnef->abef", tau, b["oovv"])
+    H["ovvo"] = W["mbej"] - 0.5 * _einsum("jnfb,mnef->mbej", t2, b["oovv"])
+    H["ooov"] = b["ooov"] + _einsum("if,mnfe->mnie", t1, b["oovv"])
+    H["vovv"] = b["vovv"] - _einsum("na,nmef->amef", t1, b["oovv"])
+    x = b["ovvo"] - _einsum("njbf,mnef->mbej", t2, b["oovv"])
+    H["ovoo"] = (b["ovoo"] - _einsum("me,ijbe->mbij", Fme, t2)
+                 - _einsum("nb,mnij->mbij", t1, H["oooo"])
+                 + 0.5 * _einsum("mbef,ijef->mbij", b["ovvv"], tau)
+                 + _Pab(_einsum("mnie,jnbe->mbij", b["ooov"], t2))
+                 + _Pab(_einsum("ie,mbej->mbij", t1, x)))
+    x = b["ovvo"] - _einsum("nibf,mnef->mbei", t2, b["oovv"])
+    y = _einsum("mbef,miaf->abei", b["ovvv"], t2) + _einsum("ma,mbei->abei", t1, x)
+    H["vvvo"] = (b["vvvo"] - _einsum("me,miab->abei", Fme, t2)
+                 + _einsum("if,abef->abei", t1, H["vvvv"])
+                 + 0.5 * _einsum("mnei,mnab->abei", b["oovo"], tau)
                  - (y - y.swapaxes(0, 1)))
     return H
 
@@ -164,27 +168,27 @@ def l_residual(f, g, t1, t2, l1, l2):
     """R_L = <0|(1+Lambda)[Hbar, tau_mu]|0> (Eq. derivL's left side), singles and doubles."""
     H = hbar(f, g, t1, t2)
     no = t1.shape[0]
-    r1 = (H["ov"] + np.einsum("ie,ea->ia", l1, H["vv"]) - np.einsum("ma,im->ia", l1, H["oo"])
-          + 0.5 * np.einsum("imef,efam->ia", l2, H["vvvo"])
-          - 0.5 * np.einsum("mnae,iemn->ia", l2, H["ovoo"]))
-    r2 = (_Pab(np.einsum("ijae,eb->ijab", l2, H["vv"])) - _Pij(np.einsum("imab,jm->ijab", l2, H["oo"]))
-          + _Pij(_Pab(np.einsum("ia,jb->ijab", l1, H["ov"]))))
+    r1 = (H["ov"] + _einsum("ie,ea->ia", l1, H["vv"]) - _einsum("ma,im->ia", l1, H["oo"])
+          + 0.5 * _einsum("imef,efam->ia", l2, H["vvvo"])
+          - 0.5 * _einsum("mnae,iemn->ia", l2, H["ovoo"]))
+    r2 = (_Pab(_einsum("ijae,eb->ijab", l2, H["vv"])) - _Pij(_einsum("imab,jm->ijab", l2, H["oo"]))
+          + _Pij(_Pab(_einsum("ia,jb->ijab", l1, H["ov"]))))
     if g is not None:
         o, v = slice(0, no), slice(no, f.shape[0])
         govv = g[o, o, v, v]
-        Gvv = -0.5 * np.einsum("mnef,mnaf->ae", t2, l2)
-        Goo = 0.5 * np.einsum("mnef,inef->mi", t2, l2)
-        r1 = r1 + (np.einsum("me,ieam->ia", l1, H["ovvo"])
-                   - np.einsum("ef,eifa->ia", Gvv, H["vovv"])
-                   - np.einsum("mn,mina->ia", Goo, H["ooov"]))
+        Gvv = -0.5 * _einsum("mnef,mnaf->ae", t2, l2)
+        Goo = 0.5 * _einsum("mnef,inef->mi", t2, l2)
+        r1 = r1 + (_einsum("me,ieam->ia", l1, H["ovvo"])
+                   - _einsum("ef,eifa->ia", Gvv, H["vovv"])
+                   - _einsum("mn,mina->ia", Goo, H["ooov"]))
         r2 = r2 + (govv
-                   + 0.5 * np.einsum("mnab,ijmn->ijab", l2, H["oooo"])
-                   + 0.5 * np.einsum("ijef,efab->ijab", l2, H["vvvv"])
-                   + _Pij(np.einsum("ie,ejab->ijab", l1, H["vovv"]))
-                   - _Pab(np.einsum("ma,ijmb->ijab", l1, H["ooov"]))
-                   + _Pij(_Pab(np.einsum("imae,jebm->ijab", l2, H["ovvo"])))
-                   + _Pab(np.einsum("ijae,be->ijab", govv, Gvv))
-                   - _Pij(np.einsum("imab,mj->ijab", govv, Goo)))
+                   + 0.5 * _einsum("mnab,ijmn->ijab", l2, H["oooo"])
+                   + 0.5 * _einsum("ijef,efab->ijab", l2, H["vvvv"])
+                   + _Pij(_einsum("ie,ejab->ijab", l1, H["vovv"]))
+                   - _Pab(_einsum("ma,ijmb->ijab", l1, H["ooov"]))
+                   + _Pij(_Pab(_einsum("imae,jebm->ijab", l2, H["ovvo"])))
+                   + _Pab(_einsum("ijae,be->ijab", govv, Gvv))
+                   - _Pij(_einsum("imab,mj->ijab", govv, Goo)))
     return r1, r2
 
 
@@ -201,7 +205,7 @@ class SpinOrbitalSystem:
     def fock(self, E):
         """f(t) = f - sum_a E_a mu_a (field-dressed Fock matrix)."""
         E = np.asarray(E, float)
-        return self.f0 - np.einsum("a,apq->pq", E, self.mu)
+        return self.f0 - _einsum("a,apq->pq", E, self.mu)
 
 
 def _so_amps(t1, t2, l1, l2):
@@ -236,7 +240,7 @@ def one_body_rhs(sys: SpinOrbitalSystem, t1, t2, l1, l2, n):
     """RHS of the operator sum_a n_a mu_a alone (no two-electron part): (-i R_T[mu,0], +i R_L[mu,0])."""
     o, v = sys.o, sys.v
     T1, T2, L1, L2 = _so_amps(t1, t2, l1, l2)
-    m = np.einsum("a,apq->pq", np.asarray(n, float), sys.mu)
+    m = _einsum("a,apq->pq", np.asarray(n, float), sys.mu)
     rt1, rt2 = spinorb.so_to_cs(*t_residual(m, None, T1, T2), o, v)
     rl1, rl2 = spinorb.so_to_cs(*l_residual(m, None, T1, T2, L1, L2), o, v)
     return -1j * rt1, -1j * rt2, 1j * rl1, 1j * rl2

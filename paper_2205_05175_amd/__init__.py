@@ -1,0 +1,210 @@
+"""MI355X real-time CCSD propagation: thin Python binding of the HIP library ``librtcc.so``.
+
+Argument marshalling only: every step of the right-hand side, the integrators,
+the kick, the dipole and the ground state runs in the library's HIP kernels
+(see ``include/rtcc.h``). PyTorch provides device memory and the stream. There
+is no CPU fallback: if the library is missing, importing ``RTCC`` fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtcc.so")
+
+FP64, FP32 = 0, 1
+_PREC = {"fp64": FP64, "fp32": FP32}
+FIELD_NONE, FIELD_GAUSSIAN, FIELD_KICK = 0, 1, 2
+
+
+class Field(ctypes.Structure):
+    """rtcc_field: kind, E0, omega, sigma, t0, n[3]."""
+    _fields_ = [("kind", ctypes.c_int), ("E0", ctypes.c_double), ("omega", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("t0", ctypes.c_double), ("n", ctypes.c_double * 3)]
+
+    @classmethod
+    def gaussian(cls, E0, omega, sigma, t0, n):
+        return cls(FIELD_GAUSSIAN, E0, omega, sigma, t0, (ctypes.c_double * 3)(*n))
+
+    @classmethod
+    def none(cls):
+        return cls(FIELD_NONE, 0.0, 0.0, 1.0, 0.0, (ctypes.c_double * 3)(0.0, 0.0, 0.0))
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librtcc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_2205_05175_amd.build` "
+                          "(or __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    vp, d, i, i64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.rtcc_init.argtypes = [ctypes.POINTER(vp), i, i, dp, dp, dp, i, vp]
+    L.rtcc_set_precision.argtypes = [vp, i]
+    L.rtcc_rhs.argtypes = [vp, vp, d, dp, vp]
+    L.rtcc_step_rk4.argtypes = [vp, vp, d, d, ctypes.POINTER(Field)]
+    L.rtcc_propagate_rk4.argtypes = [vp, vp, d, d, i, ctypes.POINTER(Field), vp]
+    L.rtcc_step_cashkarp.argtypes = [vp, vp, dp, dp, d, ctypes.POINTER(Field), ctypes.POINTER(i), dp]
+    L.rtcc_dipole.argtypes = [vp, vp, dp]
+    L.rtcc_dipole_dev.argtypes = [vp, vp, vp]
+    L.rtcc_ground_state.argtypes = [vp, vp, d, i, dp]
+    L.rtcc_kick.argtypes = [vp, vp, d, dp]
+    L.rtcc_check_state.argtypes = [vp, vp, ctypes.POINTER(i64)]
+    L.rtcc_info.argtypes = [vp, ctypes.POINTER(i64)]
+    L.rtcc_destroy.argtypes = [vp]
+    L.rtcc_destroy.restype = None
+    L.rtcc_last_error.argtypes = [vp]
+    L.rtcc_last_error.restype = ctypes.c_char_p
+    for name in ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
+                 "rtcc_step_cashkarp", "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick",
+                 "rtcc_check_state", "rtcc_info"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+EXPORTED = ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
+            "rtcc_step_cashkarp", "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick",
+            "rtcc_check_state", "rtcc_info", "rtcc_destroy", "rtcc_last_error")
+
+
+class RTCCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rtcc error {code}: {msg}")
+        self.code = code
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class RTCC:
+    """One closed-shell system on one GPU (a context of the C ABI).
+
+    ``eri`` (n^4, chemists' order), ``fock`` (n x n) and ``mu`` (3 x n x n) are host float64
+    arrays; states are complex128 CUDA tensors of length ``state_size(o, v)`` laid out as
+    [T1 | T2 | L1 | L2].
+    """
+
+    def __init__(self, eri, fock, mu, o, v, precision="fp64", stream=None):
+        import torch
+        self.L = load_library()
+        self.o, self.v = int(o), int(v)
+        self.n = self.o + self.v
+        self.nstate = 2 * (self.o * self.v + (self.o * self.v) ** 2)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        fock = np.ascontiguousarray(fock, dtype=np.float64)
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        n = self.n
+        if eri.shape != (n, n, n, n) or fock.shape != (n, n) or mu.shape != (3, n, n):
+            raise ValueError("integral shapes do not match o + v")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.ctx = ctypes.c_void_p()
+        rc = self.L.rtcc_init(ctypes.byref(self.ctx), self.o, self.v, _dptr(eri), _dptr(fock), _dptr(mu),
+                              _PREC[precision], ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise RTCCError(rc, self.L.rtcc_last_error(None).decode())
+
+    # -- helpers ---------------------------------------------------------------------------
+    def _check(self, rc):
+        if rc != 0:
+            raise RTCCError(rc, self.L.rtcc_last_error(self.ctx).decode())
+
+    def _state(self, y, name="y"):
+        import torch
+        if not (isinstance(y, torch.Tensor) and y.is_cuda and y.dtype == torch.complex128
+                and y.is_contiguous() and y.numel() == self.nstate):
+            raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of {self.nstate} entries")
+        return ctypes.c_void_p(y.data_ptr())
+
+    def new_state(self):
+        import torch
+        return torch.zeros(self.nstate, dtype=torch.complex128, device="cuda")
+
+    # -- ABI -------------------------------------------------------------------------------
+    def set_precision(self, precision):
+        self._check(self.L.rtcc_set_precision(self.ctx, _PREC[precision]))
+
+    def rhs(self, y, E, out=None, t=0.0):
+        if out is None:
+            out = self.new_state()
+        Ea = (ctypes.c_double * 3)(*[float(x) for x in E])
+        self._check(self.L.rtcc_rhs(self.ctx, self._state(y), float(t), Ea, self._state(out, "out")))
+        return out
+
+    def step_rk4(self, y, t, h, field=None):
+        f = field if field is not None else Field.none()
+        self._check(self.L.rtcc_step_rk4(self.ctx, self._state(y), float(t), float(h), ctypes.byref(f)))
+
+    def propagate_rk4(self, y, t0, h, nsteps, field=None, mu_out=None):
+        """nsteps RK4 steps; if mu_out (float64 CUDA tensor (nsteps+1, 6)) is given, the dipole is recorded."""
+        import torch
+        f = field if field is not None else Field.none()
+        ptr = None
+        if mu_out is not None:
+            if not (mu_out.is_cuda and mu_out.dtype == torch.float64 and mu_out.is_contiguous()
+                    and mu_out.numel() >= 6 * (nsteps + 1)):
+                raise ValueError("mu_out must be a contiguous float64 CUDA tensor with (nsteps+1)*6 entries")
+            ptr = ctypes.c_void_p(mu_out.data_ptr())
+        self._check(self.L.rtcc_propagate_rk4(self.ctx, self._state(y), float(t0), float(h), int(nsteps),
+                                              ctypes.byref(f), ptr))
+
+    def step_cashkarp(self, y, t, h, eps, field=None):
+        f = field if field is not None else Field.none()
+        tt, hh = ctypes.c_double(t), ctypes.c_double(h)
+        acc, delta = ctypes.c_int(0), ctypes.c_double(0.0)
+        self._check(self.L.rtcc_step_cashkarp(self.ctx, self._state(y), ctypes.byref(tt), ctypes.byref(hh),
+                                              float(eps), ctypes.byref(f), ctypes.byref(acc), ctypes.byref(delta)))
+        return tt.value, hh.value, bool(acc.value), delta.value
+
+    def dipole(self, y):
+        out = np.zeros(6)
+        self._check(self.L.rtcc_dipole(self.ctx, self._state(y), _dptr(out)))
+        return out[0::2] + 1j * out[1::2]
+
+    def dipole_dev(self, y, out6):
+        self._check(self.L.rtcc_dipole_dev(self.ctx, self._state(y), ctypes.c_void_p(out6.data_ptr())))
+
+    def ground_state(self, y, tol=1e-12, maxiter=200):
+        e = ctypes.c_double(0.0)
+        self._check(self.L.rtcc_ground_state(self.ctx, self._state(y), float(tol), int(maxiter), ctypes.byref(e)))
+        return e.value
+
+    def kick(self, y, kappa, n):
+        na = (ctypes.c_double * 3)(*[float(x) for x in n])
+        self._check(self.L.rtcc_kick(self.ctx, self._state(y), float(kappa), na))
+
+    def check_state(self, y):
+        k = ctypes.c_int64(0)
+        self._check(self.L.rtcc_check_state(self.ctx, self._state(y), ctypes.byref(k)))
+        return k.value
+
+    def info(self):
+        out = (ctypes.c_int64 * 6)()
+        self._check(self.L.rtcc_info(self.ctx, out))
+        return {"o": out[0], "v": out[1], "nstate": out[2], "last_rhs_flops": out[3],
+                "device_bytes": out[4], "precision": out[5]}
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.L.rtcc_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def state_size(o, v):
+    return 2 * (o * v + (o * v) ** 2)

@@ -1,0 +1,545 @@
+// C ABI: context lifetime, right-hand side, RK4 / Cash-Karp stepping, delta kick, dipole and
+// ground state. See include/rtcc.h for the contract of every entry point.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/rtcc.h"
+#include "rhs.h"
+
+using namespace rtcc;
+
+namespace {
+
+// Classical RK4 (paper: Eq. rk4truncation; c = 0, 1/2, 1/2, 1).
+const double kRk4C[4] = {0.0, 0.5, 0.5, 1.0};
+const double kRk4A[4][3] = {{0, 0, 0}, {0.5, 0, 0}, {0, 0.5, 0}, {0, 0, 1.0}};
+const double kRk4B[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+
+// Cash-Karp pair (Eqs. ck-k, ck-y). The printed c4, c5, a42 and a63 violate sum_j a_ij = c_i;
+// Cash and Karp's values are used: c4 = 3/5, c5 = 1, a42 = -9/10, a63 = +575/13824.
+const double kCkC[6] = {0.0, 1.0 / 5, 3.0 / 10, 3.0 / 5, 1.0, 7.0 / 8};
+const double kCkA[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0},
+    {3.0 / 10, -9.0 / 10, 6.0 / 5, 0, 0},
+    {-11.0 / 54, 5.0 / 2, -70.0 / 27, 35.0 / 27, 0},
+    {1631.0 / 55296, 175.0 / 512, 575.0 / 13824, 44275.0 / 110592, 253.0 / 4096}};
+// fifth-order weights (the step advances with these) and the embedded fourth-order ones
+const double kCkB5[6] = {37.0 / 378, 0.0, 250.0 / 621, 125.0 / 594, 0.0, 512.0 / 1771};
+const double kCkB4[6] = {2825.0 / 27648, 0.0, 18575.0 / 48384, 13525.0 / 55296, 277.0 / 14336, 1.0 / 4};
+const double kSafety = 0.84, kFacMin = 0.1, kFacMax = 5.0;
+
+thread_local std::string g_init_error;
+
+}  // namespace
+
+struct rtcc_ctx {
+  int o = 0, v = 0, n = 0, precision = RTCC_FP64;
+  int64_t n1 = 0, n2 = 0, nstate = 0;  // complex entries
+  hipStream_t stream = nullptr;
+  std::string err;
+  Engine E;
+  Arena arena;        // integrals and workspaces
+  Arena arena32;      // FP32 integrals and workspace (allocated on demand)
+  bool have32 = false;
+  double* f0 = nullptr;
+  double* mu = nullptr;
+  double* fdiag = nullptr;
+  double mu_ref[3] = {0, 0, 0};
+  double* mu_ref_dev = nullptr;
+  Ints<double> I64;
+  Work<double> W64;
+  Ints<float> I32;
+  Work<float> W32;
+  std::vector<void*> k;  // RK stage derivatives (FP64 state-sized)
+  void* ytmp = nullptr;
+  void* y4 = nullptr;
+  void* y5 = nullptr;
+  double* red = nullptr;      // reduction partials
+  double* redout = nullptr;   // reduction results (device)
+  double* host_pinned = nullptr;
+  std::vector<void*> diis_x, diis_e;
+  void* diis_err = nullptr;
+  size_t bytes = 0;
+  int64_t last_flops = 0;
+};
+
+namespace {
+
+__global__ void add_mu_ref(double* mu6, const double* ref) {
+  if (threadIdx.x < 3) mu6[2 * threadIdx.x] += ref[threadIdx.x];
+}
+
+template <typename F>
+int guarded(rtcc_ctx* c, F&& f) {
+  try {
+    f();
+    return RTCC_OK;
+  } catch (const Error& e) {
+    if (c) c->err = e.what();
+    else g_init_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    else g_init_error = e.what();
+    return RTCC_EHIP;
+  }
+}
+
+void field_at(const rtcc_field* f, double t, double E[3]) {
+  E[0] = E[1] = E[2] = 0.0;
+  if (!f || f->kind != 1) return;
+  double env = std::exp(-0.5 * (t - f->t0) * (t - f->t0) / (f->sigma * f->sigma));
+  double a = -f->E0 * env * std::cos(f->omega * (t - f->t0));
+  for (int i = 0; i < 3; ++i) E[i] = a * f->n[i];
+}
+
+template <typename T>
+Planes4<T> planes(Work<T>& w, bool inputs) {
+  Planes4<T> P;
+  if (inputs) {
+    Ten<T>* ts[4] = {&w.t1, &w.t2, &w.l1, &w.l2};
+    for (int i = 0; i < 4; ++i) {
+      P.re[i] = ts[i]->re;
+      P.im[i] = ts[i]->im;
+    }
+  } else {
+    Ten<T>* ts[4] = {&w.R1, &w.R2, &w.S1, &w.S2};
+    for (int i = 0; i < 4; ++i) {
+      P.re[i] = ts[i]->re;
+      P.im[i] = ts[i]->im;
+    }
+  }
+  return P;
+}
+
+void ensure32(rtcc_ctx* c, const double* eri_dev) {
+  if (c->have32) return;
+  RTCC_CHECK(eri_dev != nullptr, kEInval, "FP32 integrals requested after initialisation without them");
+  build_ints<float>(c->E, c->arena32, c->o, c->v, eri_dev, c->I32);
+  build_work<float>(c->arena32, c->o, c->v, c->W32);
+  c->have32 = true;
+}
+
+// out = scale * F(y) with F the RHS at field E (s0 = 1) or of the operator -E.mu alone (s0 = 0, twobody = false)
+template <typename T>
+void eval_rhs(rtcc_ctx* c, Ints<T>& I, Work<T>& w, const void* y, const double E[3], double s0, bool twobody,
+              void* out, double scale) {
+  field_fock<T>(c->stream, c->n, c->f0, c->mu, E, s0, w.f.re);
+  unpack_state<T>(c->stream, y, c->o, c->v, planes(w, true));
+  int64_t f0 = c->E.gemm_flops;
+  residuals<T>(c->E, I, w, twobody, true);
+  c->last_flops = c->E.gemm_flops - f0;
+  pack_rhs<T>(c->stream, c->o, c->v, planes(w, false), out, scale);
+}
+
+void rhs_any(rtcc_ctx* c, const void* y, const double E[3], void* out, double scale) {
+  if (c->precision == RTCC_FP32) eval_rhs<float>(c, c->I32, c->W32, y, E, 1.0, true, out, scale);
+  else eval_rhs<double>(c, c->I64, c->W64, y, E, 1.0, true, out, scale);
+}
+
+void dipole_dev(rtcc_ctx* c, const void* y, double* out6) {
+  Work<double>& w = c->W64;
+  unpack_state<double>(c->stream, y, c->o, c->v, planes(w, true));
+  density<double>(c->E, w);
+  int64_t nn = (int64_t)c->n * c->n;
+  for (int a = 0; a < 3; ++a)
+    dot_planar_real<double>(c->stream, nn, w.rho.re, w.rho.im, c->mu + a * nn, c->red, out6 + 2 * a);
+  hipLaunchKernelGGL(add_mu_ref, dim3(1), dim3(64), 0, c->stream, out6, c->mu_ref_dev);
+  RTCC_HIP(hipGetLastError());
+}
+
+void rk4_step(rtcc_ctx* c, void* y, double t, double h, const rtcc_field* field) {
+  for (int s = 0; s < 4; ++s) {
+    const void* ys = y;
+    if (s > 0) {
+      const void* ks[3] = {c->k[0], c->k[1], c->k[2]};
+      double cs[3] = {h * kRk4A[s][0], h * kRk4A[s][1], h * kRk4A[s][2]};
+      state_combo(c->stream, c->nstate, y, s, ks, cs, c->ytmp);
+      ys = c->ytmp;
+    }
+    double E[3];
+    field_at(field, t + kRk4C[s] * h, E);
+    rhs_any(c, ys, E, c->k[s], 1.0);
+  }
+  const void* ks[4] = {c->k[0], c->k[1], c->k[2], c->k[3]};
+  double cs[4] = {h * kRk4B[0], h * kRk4B[1], h * kRk4B[2], h * kRk4B[3]};
+  state_combo(c->stream, c->nstate, y, 4, ks, cs, y);
+}
+
+void sync_read(rtcc_ctx* c, const double* dev, double* host, int n) {
+  RTCC_HIP(hipMemcpyAsync(c->host_pinned, dev, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  RTCC_HIP(hipStreamSynchronize(c->stream));
+  std::memcpy(host, c->host_pinned, n * sizeof(double));
+}
+
+bool solve_small(std::vector<double>& A, std::vector<double>& b, int n) {
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(A[r * n + col]) > std::fabs(A[piv * n + col])) piv = r;
+    if (std::fabs(A[piv * n + col]) < 1e-300) return false;
+    if (piv != col) {
+      for (int j = 0; j < n; ++j) std::swap(A[col * n + j], A[piv * n + j]);
+      std::swap(b[col], b[piv]);
+    }
+    for (int r = col + 1; r < n; ++r) {
+      double f = A[r * n + col] / A[col * n + col];
+      for (int j = col; j < n; ++j) A[r * n + j] -= f * A[col * n + j];
+      b[r] -= f * b[col];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double s = b[r];
+    for (int j = r + 1; j < n; ++j) s -= A[r * n + j] * b[j];
+    b[r] = s / A[r * n + r];
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* fock, const double* dipole,
+              int precision, void* hip_stream) {
+  if (!out) {
+    g_init_error = "rtcc_init: ctx pointer is NULL";
+    return RTCC_EINVAL;
+  }
+  *out = nullptr;
+  if (o < 1 || v < 1 || !eri || !fock || !dipole || (precision != RTCC_FP64 && precision != RTCC_FP32)) {
+    g_init_error = "rtcc_init: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  auto c = std::make_unique<rtcc_ctx>();
+  int st = guarded(nullptr, [&] {
+    c->o = o;
+    c->v = v;
+    c->n = o + v;
+    c->precision = precision;
+    c->n1 = (int64_t)o * v;
+    c->n2 = c->n1 * c->n1;
+    c->nstate = 2 * (c->n1 + c->n2);
+    c->stream = (hipStream_t)hip_stream;
+    c->E.stream = c->stream;
+    const int64_t n = c->n, nn = n * n, n4 = nn * nn;
+    for (int64_t i = 0; i < nn; ++i)
+      RTCC_CHECK(std::isfinite(fock[i]) && std::isfinite(dipole[i]) && std::isfinite(dipole[nn + i]) &&
+                     std::isfinite(dipole[2 * nn + i]),
+                 kEInval, "rtcc_init: non-finite Fock or dipole integrals");
+    c->f0 = c->arena.alloc<double>(nn);
+    c->mu = c->arena.alloc<double>(3 * nn);
+    c->fdiag = c->arena.alloc<double>(n);
+    c->mu_ref_dev = c->arena.alloc<double>(3);
+    std::vector<double> diag(n);
+    for (int i = 0; i < n; ++i) diag[i] = fock[i * n + i];
+    for (int a = 0; a < 3; ++a) {
+      c->mu_ref[a] = 0;
+      for (int i = 0; i < o; ++i) c->mu_ref[a] += 2.0 * dipole[a * nn + i * n + i];
+    }
+    RTCC_HIP(hipMemcpy(c->f0, fock, nn * sizeof(double), hipMemcpyHostToDevice));
+    RTCC_HIP(hipMemcpy(c->mu, dipole, 3 * nn * sizeof(double), hipMemcpyHostToDevice));
+    RTCC_HIP(hipMemcpy(c->fdiag, diag.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    RTCC_HIP(hipMemcpy(c->mu_ref_dev, c->mu_ref, 3 * sizeof(double), hipMemcpyHostToDevice));
+    double* eri_dev = nullptr;
+    RTCC_HIP(hipMalloc(&eri_dev, n4 * sizeof(double)));
+    std::unique_ptr<double, void (*)(double*)> guard(eri_dev, [](double* p) { (void)hipFree(p); });
+    RTCC_HIP(hipMemcpy(eri_dev, eri, n4 * sizeof(double), hipMemcpyHostToDevice));
+    // scratch: largest permuted operand or temporary output, twice, plus split-K partials
+    int64_t big = std::max<int64_t>({(int64_t)o * v * v * v, 2 * c->n2, (int64_t)o * o * o * o, c->n2 * 2});
+    c->E.scratch.cap = (size_t)(8 * big + (1 << 22)) * sizeof(double) * 2;
+    c->E.scratch.base = c->arena.alloc<char>(c->E.scratch.cap);
+    build_ints<double>(c->E, c->arena, o, v, eri_dev, c->I64);
+    build_work<double>(c->arena, o, v, c->W64);
+    if (precision == RTCC_FP32) ensure32(c.get(), eri_dev);
+    c->k.resize(6);
+    for (auto& p : c->k) p = c->arena.alloc<double>(2 * c->nstate);
+    c->ytmp = c->arena.alloc<double>(2 * c->nstate);
+    c->y4 = c->arena.alloc<double>(2 * c->nstate);
+    c->y5 = c->arena.alloc<double>(2 * c->nstate);
+    c->red = c->arena.alloc<double>(2 * 1024);
+    c->redout = c->arena.alloc<double>(64);
+    RTCC_HIP(hipHostMalloc((void**)&c->host_pinned, 64 * sizeof(double), hipHostMallocDefault));
+    RTCC_HIP(hipStreamSynchronize(c->stream));
+  });
+  if (st != RTCC_OK) return st;
+  *out = c.release();
+  return RTCC_OK;
+}
+
+int rtcc_set_precision(rtcc_ctx* c, int precision) {
+  if (!c) return RTCC_EINVAL;
+  if (precision != RTCC_FP64 && precision != RTCC_FP32) {
+    c->err = "rtcc_set_precision: unknown precision";
+    return RTCC_EINVAL;
+  }
+  if (precision == RTCC_FP32 && !c->have32) {
+    c->err = "rtcc_set_precision: context was created without FP32 integrals; create it with RTCC_FP32";
+    return RTCC_EINVAL;
+  }
+  c->precision = precision;
+  return RTCC_OK;
+}
+
+int rtcc_rhs(rtcc_ctx* c, const void* y, double t, const double E[3], void* dydt) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !dydt || !E || y == dydt || !std::isfinite(t) || !std::isfinite(E[0]) || !std::isfinite(E[1]) ||
+      !std::isfinite(E[2])) {
+    c->err = "rtcc_rhs: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] { rhs_any(c, y, E, dydt, 1.0); });
+}
+
+int rtcc_step_rk4(rtcc_ctx* c, void* y, double t, double h, const rtcc_field* field) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !std::isfinite(t) || !std::isfinite(h)) {
+    c->err = "rtcc_step_rk4: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] { rk4_step(c, y, t, h, field); });
+}
+
+int rtcc_propagate_rk4(rtcc_ctx* c, void* y, double t0, double h, int nsteps, const rtcc_field* field,
+                       double* mu_dev) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || nsteps < 0 || !std::isfinite(t0) || !std::isfinite(h)) {
+    c->err = "rtcc_propagate_rk4: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] {
+    if (mu_dev) dipole_dev(c, y, mu_dev);
+    for (int s = 0; s < nsteps; ++s) {
+      rk4_step(c, y, t0 + s * h, h, field);
+      if (mu_dev) dipole_dev(c, y, mu_dev + 6 * (int64_t)(s + 1));
+    }
+  });
+}
+
+int rtcc_step_cashkarp(rtcc_ctx* c, void* y, double* t, double* h, double eps, const rtcc_field* field,
+                       int* accepted, double* delta) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !t || !h || !accepted || !(eps > 0) || !std::isfinite(*t) || !std::isfinite(*h) || !(*h > 0)) {
+    c->err = "rtcc_step_cashkarp: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] {
+    const double hh = *h;
+    for (int s = 0; s < 6; ++s) {
+      const void* ys = y;
+      if (s > 0) {
+        const void* ks[5] = {c->k[0], c->k[1], c->k[2], c->k[3], c->k[4]};
+        double cs[5];
+        for (int j = 0; j < 5; ++j) cs[j] = hh * kCkA[s][j];
+        state_combo(c->stream, c->nstate, y, s, ks, cs, c->ytmp);
+        ys = c->ytmp;
+      }
+      double E[3];
+      field_at(field, *t + kCkC[s] * hh, E);
+      rhs_any(c, ys, E, c->k[s], 1.0);
+    }
+    const void* ks[6] = {c->k[0], c->k[1], c->k[2], c->k[3], c->k[4], c->k[5]};
+    double c5[6], c4[6];
+    for (int j = 0; j < 6; ++j) {
+      c5[j] = hh * kCkB5[j];
+      c4[j] = hh * kCkB4[j];
+    }
+    state_combo(c->stream, c->nstate, y, 6, ks, c5, c->y5);
+    state_combo(c->stream, c->nstate, y, 6, ks, c4, c->y4);
+    max_abs_diff(c->stream, c->nstate, c->y5, c->y4, c->red, c->redout);
+    double d[2];
+    sync_read(c, c->redout, d, 2);
+    const double dl = d[0];
+    if (delta) *delta = dl;
+    RTCC_CHECK(std::isfinite(dl), kENonFinite, "rtcc_step_cashkarp: non-finite error estimate");
+    double fac;
+    if (dl == 0.0) fac = kFacMax;
+    else fac = kSafety * std::pow(eps / dl, dl <= eps ? 0.2 : 0.25);
+    fac = std::min(std::max(fac, kFacMin), kFacMax);
+    if (dl <= eps) {
+      RTCC_HIP(hipMemcpyAsync(y, c->y5, c->nstate * 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      *t += hh;
+      *accepted = 1;
+    } else {
+      *accepted = 0;
+    }
+    *h = hh * fac;
+  });
+}
+
+int rtcc_dipole_dev(rtcc_ctx* c, const void* y, double* mu_dev) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !mu_dev) {
+    c->err = "rtcc_dipole_dev: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] { dipole_dev(c, y, mu_dev); });
+}
+
+int rtcc_dipole(rtcc_ctx* c, const void* y, double mu[6]) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !mu) {
+    c->err = "rtcc_dipole: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] {
+    dipole_dev(c, y, c->redout + 8);
+    sync_read(c, c->redout + 8, mu, 6);
+  });
+}
+
+int rtcc_kick(rtcc_ctx* c, void* y, double kappa, const double n[3]) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !n || !std::isfinite(kappa) || !std::isfinite(n[0]) || !std::isfinite(n[1]) || !std::isfinite(n[2])) {
+    c->err = "rtcc_kick: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] {
+    // dy/ds = -kappa * F_m(y), F_m the right-hand side of m = n.mu alone: f <- n.mu (s0 = 0, E = -n)
+    const int nsub = 100;
+    const double hs = 1.0 / nsub;
+    const double E[3] = {-n[0], -n[1], -n[2]};
+    for (int it = 0; it < nsub; ++it) {
+      for (int s = 0; s < 4; ++s) {
+        const void* ys = y;
+        if (s > 0) {
+          const void* ks[3] = {c->k[0], c->k[1], c->k[2]};
+          double cs[3] = {hs * kRk4A[s][0], hs * kRk4A[s][1], hs * kRk4A[s][2]};
+          state_combo(c->stream, c->nstate, y, s, ks, cs, c->ytmp);
+          ys = c->ytmp;
+        }
+        eval_rhs<double>(c, c->I64, c->W64, ys, E, 0.0, false, c->k[s], -kappa);
+      }
+      const void* ks[4] = {c->k[0], c->k[1], c->k[2], c->k[3]};
+      double cs[4] = {hs * kRk4B[0], hs * kRk4B[1], hs * kRk4B[2], hs * kRk4B[3]};
+      state_combo(c->stream, c->nstate, y, 4, ks, cs, y);
+    }
+  });
+}
+
+int rtcc_check_state(rtcc_ctx* c, const void* y, int64_t* nonfinite) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !nonfinite) {
+    c->err = "rtcc_check_state: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] {
+    count_nonfinite(c->stream, c->nstate, y, c->red, c->redout);
+    double d[2];
+    sync_read(c, c->redout, d, 2);
+    *nonfinite = (int64_t)d[0];
+  });
+}
+
+int rtcc_ground_state(rtcc_ctx* c, void* y, double tol, int maxiter, double* e_corr) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !(tol > 0) || maxiter < 1) {
+    c->err = "rtcc_ground_state: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] {
+    Work<double>& w = c->W64;
+    const double E0[3] = {0, 0, 0};
+    field_fock<double>(c->stream, c->n, c->f0, c->mu, E0, 1.0, w.f.re);
+    const int64_t nsub = c->n1 + c->n2;
+    const int kmax = 8;
+    if (c->diis_x.empty()) {
+      for (int i = 0; i < kmax; ++i) {
+        c->diis_x.push_back(c->arena.alloc<double>(2 * nsub));
+        c->diis_e.push_back(c->arena.alloc<double>(2 * nsub));
+      }
+      c->diis_err = c->arena.alloc<double>(2 * nsub);
+    }
+    double2* ybase = (double2*)y;
+    for (int phase = 0; phase < 2; ++phase) {
+      double2* x = ybase + phase * nsub;  // T part, then Lambda part
+      if (phase == 1)
+        RTCC_HIP(hipMemcpyAsync(x, ybase, nsub * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+      int count = 0, head = 0;
+      bool conv = false;
+      for (int it = 0; it < maxiter; ++it) {
+        unpack_state<double>(c->stream, y, c->o, c->v, planes(w, true));
+        residuals<double>(c->E, c->I64, w, true, phase == 1);
+        const Ten<double>& r1 = phase ? w.S1 : w.R1;
+        const Ten<double>& r2 = phase ? w.S2 : w.R2;
+        maxabs_planar<double>(c->stream, c->n1, r1.re, r1.im, c->red, c->redout);
+        maxabs_planar<double>(c->stream, c->n2, r2.re, r2.im, c->red + 1024, c->redout + 2);
+        double m[4];
+        sync_read(c, c->redout, m, 4);
+        RTCC_CHECK(std::isfinite(m[0]) && std::isfinite(m[2]), kENonFinite, "ground state: non-finite residual");
+        if (std::max(m[0], m[2]) <= tol) {
+          conv = true;
+          break;
+        }
+        double2* e = (double2*)c->diis_err;
+        jacobi_update<double>(c->stream, c->o, c->v, c->fdiag, r1.re, r2.re, x, x + c->n1, e, e + c->n1);
+        // DIIS on the updated vectors with the Jacobi steps as error vectors
+        RTCC_HIP(hipMemcpyAsync(c->diis_x[head], x, nsub * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+        RTCC_HIP(hipMemcpyAsync(c->diis_e[head], e, nsub * sizeof(double2), hipMemcpyDeviceToDevice, c->stream));
+        head = (head + 1) % kmax;
+        count = std::min(count + 1, kmax);
+        if (count >= 2) {
+          std::vector<double> B((count + 1) * (count + 1), 0.0), rhsv(count + 1, 0.0);
+          for (int i = 0; i < count; ++i)
+            for (int j = i; j < count; ++j) {
+              vdot(c->stream, nsub, c->diis_e[i], c->diis_e[j], c->red, c->redout + 16);
+              double d[2];
+              sync_read(c, c->redout + 16, d, 2);
+              B[i * (count + 1) + j] = B[j * (count + 1) + i] = d[0];
+            }
+          for (int i = 0; i < count; ++i) {
+            B[i * (count + 1) + count] = B[count * (count + 1) + i] = -1.0;
+          }
+          rhsv[count] = -1.0;
+          if (solve_small(B, rhsv, count + 1)) {
+            std::vector<const void*> ks(c->diis_x.begin(), c->diis_x.begin() + count);
+            state_combo(c->stream, nsub, nullptr, count, ks.data(), rhsv.data(), x);
+          }
+        }
+      }
+      RTCC_CHECK(conv, kENotConv, phase == 0 ? "ground state: T equations did not converge"
+                                             : "ground state: Lambda equations did not converge");
+    }
+    if (e_corr) {
+      // E = 2 sum f_ia t_ia + sum_ijab L_ijab tau_ijab
+      unpack_state<double>(c->stream, y, c->o, c->v, planes(w, true));
+      Ten<double> s = make_ten<double>(c->redout + 32, c->redout + 33, {});
+      padd<double>(c->E, 1, "ijab->ijab", w.t2, w.tau, 0);
+      ein<double>(c->E, 1, "ia,jb->ijab", w.t1, w.t1, w.tau, 1);
+      ein<double>(c->E, 2, "ia,ia->", w.fov, w.t1, s, 0);
+      ein<double>(c->E, 1, "ijab,ijab->", c->I64.Loovv, w.tau, s, 1);
+      double d[2];
+      sync_read(c, c->redout + 32, d, 2);
+      *e_corr = d[0];
+    }
+  });
+}
+
+int rtcc_info(rtcc_ctx* c, int64_t out[6]) {
+  if (!c || !out) return RTCC_EINVAL;
+  out[0] = c->o;
+  out[1] = c->v;
+  out[2] = c->nstate;
+  out[3] = c->last_flops;
+  size_t free_b = 0, total_b = 0;
+  (void)hipMemGetInfo(&free_b, &total_b);
+  out[4] = (int64_t)(total_b - free_b);
+  out[5] = c->precision;
+  return RTCC_OK;
+}
+
+void rtcc_destroy(rtcc_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+  delete c;
+}
+
+const char* rtcc_last_error(const rtcc_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+}  // extern "C"

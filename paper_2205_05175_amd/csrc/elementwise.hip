@@ -1,0 +1,374 @@
+// Memory-bound kernels: strided permute-axpby, state (un)packing, RK stage updates, field,
+// and fixed-order wavefront reductions.
+#include "elementwise.h"
+
+namespace rtcc {
+
+struct PermGeom {
+  int nd;
+  int64_t d[kMaxDim];
+  int64_t is[kMaxDim];
+  int64_t os[kMaxDim];
+};
+
+template <typename T>
+__global__ void permute_kernel(PermGeom g, int64_t total, const T* __restrict__ inre, const T* __restrict__ inim,
+                               T* outre, T* outim, T alpha, T beta) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = idx, io = 0, oo = 0;
+#pragma unroll
+    for (int k = kMaxDim - 1; k >= 0; --k) {
+      if (k >= g.nd) continue;
+      int64_t c = rem % g.d[k];
+      rem /= g.d[k];
+      io += c * g.is[k];
+      oo += c * g.os[k];
+    }
+    T vr = inre ? alpha * inre[io] : T(0);
+    if (beta != T(0)) vr += beta * outre[oo];
+    outre[oo] = vr;
+    if (outim) {
+      T vi = inim ? alpha * inim[io] : T(0);
+      if (beta != T(0)) vi += beta * outim[oo];
+      outim[oo] = vi;
+    }
+  }
+}
+
+template <typename T>
+void permute_axpby(hipStream_t st, int nd, const int64_t* dims, const T* inre, const T* inim, const int64_t* instr,
+                   T* outre, T* outim, const int64_t* outstr, double alpha, double beta) {
+  RTCC_CHECK(nd >= 0 && nd <= kMaxDim, kEInval, "permute: too many dimensions");
+  // order loops so the fastest-running index is the output's unit-stride one
+  int ord[kMaxDim];
+  for (int i = 0; i < nd; ++i) ord[i] = i;
+  for (int i = 0; i < nd; ++i)
+    for (int j = i + 1; j < nd; ++j)
+      if (outstr[ord[j]] > outstr[ord[i]]) std::swap(ord[i], ord[j]);
+  PermGeom g;
+  g.nd = nd;
+  int64_t total = 1;
+  for (int i = 0; i < nd; ++i) {
+    g.d[i] = dims[ord[i]];
+    g.is[i] = instr[ord[i]];
+    g.os[i] = outstr[ord[i]];
+    total *= g.d[i];
+  }
+  if (total == 0) return;
+  if (alpha == 0.0) {
+    inre = nullptr;
+    inim = nullptr;
+  }
+  int64_t blocks = std::min<int64_t>(cdiv(total, 256), 65536);
+  hipLaunchKernelGGL(permute_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, g, total, inre, inim, outre, outim,
+                     (T)alpha, (T)beta);
+  RTCC_HIP(hipGetLastError());
+}
+template void permute_axpby<double>(hipStream_t, int, const int64_t*, const double*, const double*, const int64_t*,
+                                    double*, double*, const int64_t*, double, double);
+template void permute_axpby<float>(hipStream_t, int, const int64_t*, const float*, const float*, const int64_t*,
+                                   float*, float*, const int64_t*, double, double);
+
+// ---- state vector <-> planar amplitudes ------------------------------------------------
+// y layout (complex128 interleaved): [T1 o*v | T2 o*o*v*v | L1 o*v | L2 o*o*v*v]
+template <typename T>
+__global__ void unpack_kernel(const double2* __restrict__ y, int64_t n1, int64_t n2, Planes4<T> P) {
+  int64_t ntot = 2 * (n1 + n2);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += (int64_t)gridDim.x * blockDim.x) {
+    double2 z = y[i];
+    int seg;
+    int64_t j;
+    if (i < n1) { seg = 0; j = i; }
+    else if (i < n1 + n2) { seg = 1; j = i - n1; }
+    else if (i < 2 * n1 + n2) { seg = 2; j = i - n1 - n2; }
+    else { seg = 3; j = i - 2 * n1 - n2; }
+    P.re[seg][j] = (T)z.x;
+    P.im[seg][j] = (T)z.y;
+  }
+}
+
+template <typename T>
+void unpack_state(hipStream_t st, const void* y, int o, int v, Planes4<T> P) {
+  int64_t n1 = (int64_t)o * v, n2 = n1 * n1;
+  int64_t blocks = std::min<int64_t>(cdiv(2 * (n1 + n2), 256), 65536);
+  hipLaunchKernelGGL(unpack_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, (const double2*)y, n1, n2, P);
+  RTCC_HIP(hipGetLastError());
+}
+
+// out = scale * (-i R_T, +i R_L)
+template <typename T>
+__global__ void pack_kernel(int64_t n1, int64_t n2, Planes4<T> P, double2* out, double scale) {
+  int64_t ntot = 2 * (n1 + n2);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += (int64_t)gridDim.x * blockDim.x) {
+    int seg;
+    int64_t j;
+    if (i < n1) { seg = 0; j = i; }
+    else if (i < n1 + n2) { seg = 1; j = i - n1; }
+    else if (i < 2 * n1 + n2) { seg = 2; j = i - n1 - n2; }
+    else { seg = 3; j = i - 2 * n1 - n2; }
+    double sgn = seg < 2 ? -1.0 : 1.0;
+    double re = (double)P.re[seg][j], im = (double)P.im[seg][j];
+    // (sgn i)(re + i im) = -sgn im + i sgn re
+    out[i] = make_double2(-sgn * im * scale, sgn * re * scale);
+  }
+}
+
+template <typename T>
+void pack_rhs(hipStream_t st, int o, int v, Planes4<T> P, void* out, double scale) {
+  int64_t n1 = (int64_t)o * v, n2 = n1 * n1;
+  int64_t blocks = std::min<int64_t>(cdiv(2 * (n1 + n2), 256), 65536);
+  hipLaunchKernelGGL(pack_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, n1, n2, P, (double2*)out, scale);
+  RTCC_HIP(hipGetLastError());
+}
+
+template void unpack_state<double>(hipStream_t, const void*, int, int, Planes4<double>);
+template void unpack_state<float>(hipStream_t, const void*, int, int, Planes4<float>);
+template void pack_rhs<double>(hipStream_t, int, int, Planes4<double>, void*, double);
+template void pack_rhs<float>(hipStream_t, int, int, Planes4<float>, void*, double);
+
+// ---- field-dressed Fock matrix f(t) = f0 - sum_a E_a mu_a -------------------------------------
+template <typename T>
+__global__ void fock_kernel(int64_t nn, const double* f0, const double* mu, double ex, double ey, double ez, double s0,
+                            T* f) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  f[i] = (T)(s0 * f0[i] - ex * mu[i] - ey * mu[nn + i] - ez * mu[2 * nn + i]);
+}
+
+template <typename T>
+void field_fock(hipStream_t st, int n, const double* f0, const double* mu, const double E[3], double s0, T* f) {
+  int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(fock_kernel<T>, dim3((unsigned)cdiv(nn, 256)), dim3(256), 0, st, nn, f0, mu, E[0], E[1], E[2],
+                     s0, f);
+  RTCC_HIP(hipGetLastError());
+}
+template void field_fock<double>(hipStream_t, int, const double*, const double*, const double*, double, double*);
+template void field_fock<float>(hipStream_t, int, const double*, const double*, const double*, double, float*);
+
+// ---- RK combinations on the FP64 state ----------------------------------------------------------
+struct Combo {
+  const double2* k[8];
+  double c[8];
+  int nk;
+};
+
+__global__ void combo_kernel(int64_t n, const double2* __restrict__ y, Combo cb, double2* out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double2 a = y ? y[i] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j >= cb.nk) break;
+      double2 kk = cb.k[j][i];
+      a.x += cb.c[j] * kk.x;
+      a.y += cb.c[j] * kk.y;
+    }
+    out[i] = a;
+  }
+}
+
+void state_combo(hipStream_t st, int64_t n, const void* y, int nk, const void* const* ks, const double* cs, void* out) {
+  RTCC_CHECK(nk <= 8, kEInval, "state_combo: too many terms");
+  Combo cb;
+  cb.nk = 0;
+  for (int j = 0; j < nk; ++j) {
+    if (cs[j] == 0.0) continue;
+    cb.k[cb.nk] = (const double2*)ks[j];
+    cb.c[cb.nk] = cs[j];
+    cb.nk++;
+  }
+  int64_t blocks = std::min<int64_t>(cdiv(n, 256), 8192);
+  hipLaunchKernelGGL(combo_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n, (const double2*)y, cb, (double2*)out);
+  RTCC_HIP(hipGetLastError());
+}
+
+// ---- fixed-order reductions -------------------------------------------------------------------
+// Stage 1: each block reduces a contiguous chunk (wavefront shuffles, then LDS across waves);
+// stage 2: one block reduces the per-block partials in index order.
+constexpr int kRedBlocks = 512;
+
+__device__ inline double wave_sum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+__device__ inline double wave_max(double x) {
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+  return x;
+}
+
+// mode 0: sum of Re(a*conj?)...  we use explicit modes:
+//   MODE_DOT_RC  : sum_i (ar_i + i ai_i) * b_i        (complex a planar, real b)  -> 2 doubles
+//   MODE_MAXDIFF : max_i |y5_i - y4_i| (interleaved complex)                        -> 1 double
+//   MODE_VDOT    : sum_i conj(a_i) b_i (interleaved complex)                          -> 2 doubles
+//   MODE_NONFIN  : count of non-finite entries (interleaved complex)                 -> 1 double
+template <typename T, int MODE>
+__global__ void reduce_stage1(int64_t n, const void* a, const void* b, const void* c, double* partial) {
+  __shared__ double sh0[4], sh1[4];
+  int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  int64_t beg = (int64_t)blockIdx.x * chunk, end = min(n, beg + chunk);
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    if (MODE == 0) {
+      const T* ar = (const T*)a;
+      const T* ai = (const T*)c;
+      double bv = ((const double*)b)[i];
+      s0 += (double)ar[i] * bv;
+      s1 += (double)ai[i] * bv;
+    } else if (MODE == 1) {
+      double2 p = ((const double2*)a)[i], q = ((const double2*)b)[i];
+      double dx = p.x - q.x, dy = p.y - q.y;
+      s0 = fmax(s0, sqrt(dx * dx + dy * dy));
+    } else if (MODE == 2) {
+      double2 p = ((const double2*)a)[i], q = ((const double2*)b)[i];
+      s0 += p.x * q.x + p.y * q.y;
+      s1 += p.x * q.y - p.y * q.x;
+    } else {
+      double2 p = ((const double2*)a)[i];
+      if (!isfinite(p.x) || !isfinite(p.y)) s0 += 1.0;
+    }
+  }
+  if (MODE == 1) s0 = wave_max(s0);
+  else {
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+  }
+  int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh0[w] = s0;
+    sh1[w] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r0 = sh0[0], r1 = sh1[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+      if (MODE == 1) r0 = fmax(r0, sh0[k]);
+      else {
+        r0 += sh0[k];
+        r1 += sh1[k];
+      }
+    }
+    partial[2 * blockIdx.x] = r0;
+    partial[2 * blockIdx.x + 1] = r1;
+  }
+}
+
+template <int MODE>
+__global__ void reduce_stage2(int nb, const double* partial, double* out) {
+  if (threadIdx.x != 0) return;
+  double r0 = partial[0], r1 = partial[1];
+  for (int k = 1; k < nb; ++k) {
+    if (MODE == 1) r0 = fmax(r0, partial[2 * k]);
+    else {
+      r0 += partial[2 * k];
+      r1 += partial[2 * k + 1];
+    }
+  }
+  out[0] = r0;
+  out[1] = r1;
+}
+
+template <typename T, int MODE>
+static void reduce(hipStream_t st, int64_t n, const void* a, const void* b, const void* c, double* partial,
+                   double* out) {
+  int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, cdiv(n, 256)));
+  hipLaunchKernelGGL((reduce_stage1<T, MODE>), dim3(nb), dim3(256), 0, st, n, a, b, c, partial);
+  RTCC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(reduce_stage2<MODE>, dim3(1), dim3(64), 0, st, nb, partial, out);
+  RTCC_HIP(hipGetLastError());
+}
+
+template <typename T>
+void dot_planar_real(hipStream_t st, int64_t n, const T* are, const T* aim, const double* b, double* partial,
+                     double* out2) {
+  reduce<T, 0>(st, n, are, b, aim, partial, out2);
+}
+template void dot_planar_real<double>(hipStream_t, int64_t, const double*, const double*, const double*, double*,
+                                      double*);
+template void dot_planar_real<float>(hipStream_t, int64_t, const float*, const float*, const double*, double*,
+                                     double*);
+
+void max_abs_diff(hipStream_t st, int64_t n, const void* a, const void* b, double* partial, double* out2) {
+  reduce<double, 1>(st, n, a, b, nullptr, partial, out2);
+}
+void vdot(hipStream_t st, int64_t n, const void* a, const void* b, double* partial, double* out2) {
+  reduce<double, 2>(st, n, a, b, nullptr, partial, out2);
+}
+void count_nonfinite(hipStream_t st, int64_t n, const void* a, double* partial, double* out2) {
+  reduce<double, 3>(st, n, a, nullptr, nullptr, partial, out2);
+}
+
+// ---- ground-state Jacobi update on the interleaved state: x += R / D ---------------------------
+// R given as planar residuals (r1 = o*v, r2 = o*o*v*v), D from the diagonal of the spatial Fock matrix
+template <typename T>
+__global__ void jacobi_kernel(int o, int v, const double* fdiag, const T* r1, const T* r2, double2* x1, double2* x2,
+                              double2* e1, double2* e2) {
+  int64_t n1 = (int64_t)o * v, n2 = n1 * n1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n1 + n2; i += (int64_t)gridDim.x * blockDim.x) {
+    double d, rr, ri;
+    if (i < n1) {
+      int a = (int)(i % v), ii = (int)(i / v);
+      d = fdiag[ii] - fdiag[o + a];
+      rr = r1[i];
+      ri = r1[i + n1];
+      double2 q = make_double2(rr / d, ri / d);
+      e1[i] = q;
+      x1[i] = make_double2(x1[i].x + q.x, x1[i].y + q.y);
+    } else {
+      int64_t j = i - n1;
+      int b = (int)(j % v), a = (int)((j / v) % v), jj = (int)((j / v / v) % o), ii = (int)(j / v / v / o);
+      d = fdiag[ii] + fdiag[jj] - fdiag[o + a] - fdiag[o + b];
+      rr = r2[j];
+      ri = r2[j + n2];
+      double2 q = make_double2(rr / d, ri / d);
+      e2[j] = q;
+      x2[j] = make_double2(x2[j].x + q.x, x2[j].y + q.y);
+    }
+  }
+}
+
+template <typename T>
+void jacobi_update(hipStream_t st, int o, int v, const double* fdiag, const T* r1, const T* r2, void* x1, void* x2,
+                   void* e1, void* e2) {
+  int64_t n = (int64_t)o * v + (int64_t)o * o * v * v;
+  int64_t blocks = std::min<int64_t>(cdiv(n, 256), 8192);
+  hipLaunchKernelGGL(jacobi_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, o, v, fdiag, r1, r2, (double2*)x1,
+                     (double2*)x2, (double2*)e1, (double2*)e2);
+  RTCC_HIP(hipGetLastError());
+}
+template void jacobi_update<double>(hipStream_t, int, int, const double*, const double*, const double*, void*, void*,
+                                    void*, void*);
+
+// max |R| over planar residual arrays (convergence test)
+template <typename T>
+__global__ void maxabs_planar_kernel(int64_t n, const T* re, const T* im, double* partial) {
+  __shared__ double sh[4];
+  int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  int64_t beg = (int64_t)blockIdx.x * chunk, end = min(n, beg + chunk);
+  double m = 0.0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    double a = re[i], b = im[i];
+    double x = sqrt(a * a + b * b);
+    m = (x != x) ? INFINITY : fmax(m, x);
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) r = fmax(r, sh[k]);
+    partial[2 * blockIdx.x] = r;
+    partial[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
+template <typename T>
+void maxabs_planar(hipStream_t st, int64_t n, const T* re, const T* im, double* partial, double* out2) {
+  int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, cdiv(n, 256)));
+  hipLaunchKernelGGL(maxabs_planar_kernel<T>, dim3(nb), dim3(256), 0, st, n, re, im, partial);
+  RTCC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(reduce_stage2<1>, dim3(1), dim3(64), 0, st, nb, partial, out2);
+  RTCC_HIP(hipGetLastError());
+}
+template void maxabs_planar<double>(hipStream_t, int64_t, const double*, const double*, double*, double*);
+
+}  // namespace rtcc

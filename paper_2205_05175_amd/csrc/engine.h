@@ -1,0 +1,99 @@
+// Tensor views and the two-operand contraction engine.
+//
+// Every coupled-cluster term is evaluated as  C[c] = alpha * sum_k A[a] B[b] + beta * C[c]
+// with index strings in einsum notation ("ijef,abef->ijab"). Contracted letters appear in A
+// and B only; free letters of C come from exactly one operand. An operand whose memory
+// layout already groups its letters as one matrix (row- or column-major) is passed to the
+// MFMA GEMM as a strided view; otherwise it is permuted into scratch first. Complex
+// tensors are planar: separate real and imaginary planes.
+#pragma once
+#include <vector>
+#include "common.h"
+
+namespace rtcc {
+
+constexpr int kMaxDim = 6;
+
+template <typename T>
+struct Ten {
+  T* re = nullptr;
+  T* im = nullptr;  // nullptr: real tensor
+  int nd = 0;
+  int64_t d[kMaxDim] = {0};
+  int64_t s[kMaxDim] = {0};  // element strides
+  bool cplx() const { return im != nullptr; }
+  int64_t size() const {
+    int64_t n = 1;
+    for (int i = 0; i < nd; ++i) n *= d[i];
+    return n;
+  }
+};
+
+// Row-major view of a (possibly complex) contiguous buffer.
+template <typename T>
+Ten<T> make_ten(T* re, T* im, std::initializer_list<int64_t> dims) {
+  Ten<T> t;
+  t.re = re;
+  t.im = im;
+  t.nd = (int)dims.size();
+  int i = 0;
+  for (auto x : dims) t.d[i++] = x;
+  int64_t st = 1;
+  for (int k = t.nd - 1; k >= 0; --k) {
+    t.s[k] = st;
+    st *= t.d[k];
+  }
+  return t;
+}
+
+// Bump allocator for per-call temporaries (device memory owned by the context).
+struct Scratch {
+  char* base = nullptr;
+  size_t cap = 0, used = 0, peak = 0;
+  template <typename T>
+  T* get(int64_t n) {
+    size_t bytes = ((size_t)n * sizeof(T) + 255) & ~(size_t)255;
+    RTCC_CHECK(used + bytes <= cap, kENoMem, "contraction scratch exhausted");
+    T* p = reinterpret_cast<T*>(base + used);
+    used += bytes;
+    if (used > peak) peak = used;
+    return p;
+  }
+  void reset(size_t mark = 0) { used = mark; }
+};
+
+struct Engine {
+  hipStream_t stream = nullptr;
+  Scratch scratch;
+  int64_t gemm_flops = 0;  // algorithmic real flops issued (accounting)
+};
+
+// C = alpha * contraction(A, B) + beta * C   (beta 0 or 1)
+template <typename T>
+void ein(Engine& E, double alpha, const char* spec, const Ten<T>& A, const Ten<T>& B, const Ten<T>& C,
+         double beta);
+
+// C = alpha * permute(A) + beta * C   ("ijab->jiba"; the identity spec is an axpby)
+template <typename T>
+void padd(Engine& E, double alpha, const char* spec, const Ten<T>& A, const Ten<T>& C, double beta);
+
+// Raw GEMM entry (used by the engine and directly for the shared ladder):
+// C(m,n) = alpha * sum_k A(m,k) B(k,n) + beta * C(m,n)
+// A(m,k) = transA ? A[k*lda + m] : A[m*lda + k];  B(k,n) = transB ? B[n*ldb + k] : B[k*ldb + n]
+template <typename T>
+struct GemmOp {
+  const T* re;
+  const T* im;
+  int64_t ld;
+  int trans;
+};
+template <typename T>
+void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A, GemmOp<T> B, T* Cre, T* Cim,
+          int64_t ldc, double beta);
+
+// General strided permute-axpby on planar complex or real data (nd <= 6).
+template <typename T>
+void permute_axpby(hipStream_t st, int nd, const int64_t* dims, const T* inre, const T* inim,
+                   const int64_t* instr, T* outre, T* outim, const int64_t* outstr, double alpha, double beta);
+
+}  // namespace rtcc

@@ -1,0 +1,454 @@
+// Closed-shell (spin-adapted) RT-CCSD right-hand side.
+//
+// Residuals of the paper's equations of motion (Theory: Eq. derivT for the cluster
+// amplitudes, Eq. derivL for Lambda, Hbar of Eq. simtranH) in closed-shell variables
+// t_i^a = t_{ia,aa}, t_ij^ab = t_{i alpha j beta}^{a alpha b beta} (Lambda mapped the same
+// way), for a general (field-dressed, non-canonical) Fock matrix and a non-stationary state.
+// The factorisation keeps every contraction at o^3 v^3 or below except the particle-particle
+// ladder sum_ef <ab|ef> X_ij^ef, which is one real-by-complex GEMM over the stacked operand
+// X = [tau; lambda2] shared by the T2 and Lambda2 equations. Hbar_abef and Hbar_abei are
+// never formed: their t1 and tau dressings are contracted with tau or lambda first.
+#include "rhs.h"
+
+namespace rtcc {
+
+namespace {
+
+template <typename T>
+Ten<T> view(const Ten<T>& base, int64_t off, std::initializer_list<int64_t> dims, std::initializer_list<int64_t> strides) {
+  Ten<T> t;
+  t.re = base.re + off;
+  t.im = base.im ? base.im + off : nullptr;
+  t.nd = (int)dims.size();
+  int i = 0;
+  for (auto d : dims) t.d[i++] = d;
+  i = 0;
+  for (auto s : strides) t.s[i++] = s;
+  return t;
+}
+
+// block[p,q,r,s] = <pq|rs> = (pr|qs) from the chemists'-order n^4 array
+template <typename T>
+void extract(Engine& E, const double* eri, int n, int p0, int q0, int r0, int s0, const Ten<double>& out) {
+  int64_t nn = n;
+  const double* base = eri + (int64_t)p0 * nn * nn * nn + (int64_t)r0 * nn * nn + (int64_t)q0 * nn + s0;
+  int64_t is[4] = {nn * nn * nn, nn, nn * nn, 1};
+  permute_axpby<double>(E.stream, 4, out.d, base, nullptr, is, out.re, nullptr, out.s, 1.0, 0.0);
+}
+
+__global__ void convert_kernel(int64_t n, const double* in, float* out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
+}  // namespace
+
+template <typename T>
+void build_ints(Engine& E, Arena& A, int o, int v, const double* eri, Ints<T>& I);
+
+template <>
+void build_ints<double>(Engine& E, Arena& A, int o, int v, const double* eri, Ints<double>& I) {
+  const int n = o + v;
+  I.oooo = A.real<double>({o, o, o, o});
+  I.ooov = A.real<double>({o, o, o, v});
+  I.oovv = A.real<double>({o, o, v, v});
+  I.ovov = A.real<double>({o, v, o, v});
+  I.ovvo = A.real<double>({o, v, v, o});
+  I.ovvv = A.real<double>({o, v, v, v});
+  I.vvvv = A.real<double>({v, v, v, v});
+  extract<double>(E, eri, n, 0, 0, 0, 0, I.oooo);
+  extract<double>(E, eri, n, 0, 0, 0, o, I.ooov);
+  extract<double>(E, eri, n, 0, 0, o, o, I.oovv);
+  extract<double>(E, eri, n, 0, o, 0, o, I.ovov);
+  extract<double>(E, eri, n, 0, o, o, 0, I.ovvo);
+  extract<double>(E, eri, n, 0, o, o, o, I.ovvv);
+  extract<double>(E, eri, n, o, o, o, o, I.vvvv);
+  I.Loovv = A.real<double>({o, o, v, v});
+  I.Looov = A.real<double>({o, o, o, v});
+  I.Lovvv = A.real<double>({o, v, v, v});
+  I.Lovvo = A.real<double>({o, v, v, o});
+  padd<double>(E, 2.0, "mnef->mnef", I.oovv, I.Loovv, 0.0);
+  padd<double>(E, -1.0, "mnfe->mnef", I.oovv, I.Loovv, 1.0);
+  padd<double>(E, 2.0, "mnie->mnie", I.ooov, I.Looov, 0.0);
+  padd<double>(E, -1.0, "nmie->mnie", I.ooov, I.Looov, 1.0);
+  padd<double>(E, 2.0, "maef->maef", I.ovvv, I.Lovvv, 0.0);
+  padd<double>(E, -1.0, "mafe->maef", I.ovvv, I.Lovvv, 1.0);
+  padd<double>(E, 2.0, "nafi->nafi", I.ovvo, I.Lovvo, 0.0);
+  padd<double>(E, -1.0, "naif->nafi", I.ovov, I.Lovvo, 1.0);
+}
+
+template <>
+void build_ints<float>(Engine& E, Arena& A, int o, int v, const double* eri, Ints<float>& I) {
+  Arena tmp;
+  Ints<double> D;
+  build_ints<double>(E, tmp, o, v, eri, D);
+  auto cvt = [&](const Ten<double>& src) {
+    Ten<float> t = make_ten<float>(A.alloc<float>(src.size()), nullptr, {});
+    t.nd = src.nd;
+    for (int i = 0; i < src.nd; ++i) {
+      t.d[i] = src.d[i];
+      t.s[i] = src.s[i];
+    }
+    int64_t nel = src.size();
+    hipLaunchKernelGGL(convert_kernel, dim3((unsigned)std::min<int64_t>(cdiv(nel, 256), 65536)), dim3(256), 0,
+                       E.stream, nel, src.re, t.re);
+    RTCC_HIP(hipGetLastError());
+    return t;
+  };
+  I.oooo = cvt(D.oooo);
+  I.ooov = cvt(D.ooov);
+  I.oovv = cvt(D.oovv);
+  I.ovov = cvt(D.ovov);
+  I.ovvo = cvt(D.ovvo);
+  I.ovvv = cvt(D.ovvv);
+  I.vvvv = cvt(D.vvvv);
+  I.Loovv = cvt(D.Loovv);
+  I.Looov = cvt(D.Looov);
+  I.Lovvv = cvt(D.Lovvv);
+  I.Lovvo = cvt(D.Lovvo);
+  RTCC_HIP(hipStreamSynchronize(E.stream));  // tmp is freed on return
+}
+
+template <typename T>
+void build_work(Arena& A, int o, int v, Work<T>& w) {
+  const int64_t n = o + v, ov = (int64_t)o * v, oovv = ov * ov;
+  w.o = o;
+  w.v = v;
+  w.n = (int)n;
+  w.f = A.real<T>({n, n});
+  w.fov = view(w.f, o, {o, v}, {n, 1});
+  w.foo = view(w.f, 0, {o, o}, {n, 1});
+  w.fvv = view(w.f, o * n + o, {v, v}, {n, 1});
+  w.t1 = A.cplx<T>({o, v});
+  w.l1 = A.cplx<T>({o, v});
+  w.t2 = A.cplx<T>({o, o, v, v});
+  w.X = A.cplx<T>({2, o, o, v, v});
+  w.tau = view(w.X, 0, {o, o, v, v}, {o * v * v, v * v, v, 1});
+  w.l2 = view(w.X, oovv, {o, o, v, v}, {o * v * v, v * v, v, 1});
+  w.taut = A.cplx<T>({o, o, v, v});
+  w.t2s = A.cplx<T>({o, o, v, v});
+  w.l2s = A.cplx<T>({o, o, v, v});
+  w.Fae = A.cplx<T>({v, v});
+  w.Fmi = A.cplx<T>({o, o});
+  w.Fme = A.cplx<T>({o, v});
+  w.Hvv = A.cplx<T>({v, v});
+  w.Hoo = A.cplx<T>({o, o});
+  w.Gvv = A.cplx<T>({v, v});
+  w.Goo = A.cplx<T>({o, o});
+  w.Q = A.cplx<T>({o, o});
+  w.Gx = A.cplx<T>({v, v});
+  w.W = A.cplx<T>({o, o, o, o});
+  w.M = A.cplx<T>({o, o, o, o});
+  w.Mp = A.cplx<T>({o, o, o, o});
+  w.Hooov = A.cplx<T>({o, o, o, v});
+  w.Hvovv = A.cplx<T>({v, o, v, v});
+  w.Z1 = A.cplx<T>({o, o, v, o});
+  w.Y = A.cplx<T>({o, o, v, o});
+  w.U = A.cplx<T>({o, o, v, o});
+  w.U2 = A.cplx<T>({o, o, o, v});
+  w.Y3 = A.cplx<T>({o, o, o, v});
+  w.Y6 = A.cplx<T>({o, o, v, o});
+  w.B4 = A.cplx<T>({o, o, v, o});
+  w.B5 = A.cplx<T>({o, o, o, v});
+  w.B7 = A.cplx<T>({o, o, v, o});
+  w.D = A.cplx<T>({o, o, v, o});
+  w.Nn = A.cplx<T>({o, o, o, v});
+  w.Lad = A.cplx<T>({2, o, o, v, v});
+  w.LadT = view(w.Lad, 0, {o, o, v, v}, {o * v * v, v * v, v, 1});
+  w.LadL = view(w.Lad, oovv, {o, o, v, v}, {o * v * v, v * v, v, 1});
+  // ring intermediates, element X_mbej stored at (m,e,j,b)
+  w.Pd = A.cplx<T>({o, v, o, v});
+  w.Px = A.cplx<T>({o, v, o, v});
+  w.Bd = A.cplx<T>({o, v, o, v});
+  w.Bx = A.cplx<T>({o, v, o, v});
+  w.WW = A.cplx<T>({2, o, v, o, v});
+  w.Wd = view(w.WW, 0, {o, v, o, v}, {v * ov, ov, v, 1});
+  w.Wx = view(w.WW, oovv, {o, v, o, v}, {v * ov, ov, v, 1});
+  // Hbar_mbej (s=0 direct, s=1 exchange) stored at (j,b,s,m,e)
+  w.HH = A.cplx<T>({o, v, 2, o, v});
+  w.HH5 = w.HH;
+  w.HHd = view(w.HH, 0, {o, v, o, v}, {v, 1, 2 * ov * v, 2 * ov});
+  w.HHx = view(w.HH, ov, {o, v, o, v}, {v, 1, 2 * ov * v, 2 * ov});
+  // stacked left operands of the ring GEMMs: (i,a,s,m,e) for T and (i,a,m,e,s) for Lambda
+  w.T2R = A.cplx<T>({o, v, 2, o, v});
+  w.T2R0 = view(w.T2R, 0, {o, o, v, v}, {2 * ov * v, v, 2 * ov, 1});
+  w.T2R1 = view(w.T2R, ov, {o, o, v, v}, {2 * ov * v, v, 2 * ov, 1});
+  w.L2R = A.cplx<T>({o, v, o, v, 2});
+  w.L2R0 = view(w.L2R, 0, {o, o, v, v}, {2 * ov * v, 2 * v, 2 * ov, 2});
+  w.L2R1 = view(w.L2R, 1, {o, o, v, v}, {2 * ov * v, 2 * v, 2 * ov, 2});
+  w.Zt = A.cplx<T>({o, v, o, v});
+  w.ZLt = A.cplx<T>({o, v, o, v});
+  w.B2 = A.cplx<T>({o, v, o, v});
+  w.B3 = A.cplx<T>({o, v, o, v});
+  w.Wr = A.cplx<T>({o, o, v, v});
+  w.Z = A.cplx<T>({o, o, v, v});
+  w.S1t = A.cplx<T>({o, v, o, o});
+  w.ZL = A.cplx<T>({o, o, v, v});
+  w.R1 = A.cplx<T>({o, v});
+  w.R2 = A.cplx<T>({o, o, v, v});
+  w.S1 = A.cplx<T>({o, v});
+  w.S2 = A.cplx<T>({o, o, v, v});
+  w.rho = A.cplx<T>({n, n});
+  w.Dvv = A.cplx<T>({v, v});
+  w.Doo = A.cplx<T>({o, o});
+  w.P1 = A.cplx<T>({o, o});
+}
+
+template <typename T>
+void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
+  auto C = [&](double a, const char* s, const Ten<T>& x, const Ten<T>& y, const Ten<T>& z, double b) {
+    ein<T>(E, a, s, x, y, z, b);
+  };
+  auto P = [&](double a, const char* s, const Ten<T>& x, const Ten<T>& z, double b) { padd<T>(E, a, s, x, z, b); };
+  const int o = w.o, v = w.v;
+  const Ten<T>&t1 = w.t1, &t2 = w.t2, &l1 = w.l1, &l2 = w.l2, &tau = w.tau;
+
+  // ---- amplitude combinations
+  P(1, "ijab->ijab", t2, tau, 0);
+  C(1, "ia,jb->ijab", t1, t1, tau, 1);
+  P(1, "ijab->ijab", t2, w.taut, 0);
+  C(0.5, "ia,jb->ijab", t1, t1, w.taut, 1);
+  P(2, "ijab->ijab", t2, w.t2s, 0);
+  P(-1, "ijab->ijba", t2, w.t2s, 1);
+  if (lambda) {
+    P(2, "ijab->ijab", l2, w.l2s, 0);
+    P(-1, "ijab->ijba", l2, w.l2s, 1);
+  }
+
+  // ---- one-body intermediates
+  P(1, "ae->ae", w.fvv, w.Fae, 0);
+  C(-0.5, "me,ma->ae", w.fov, t1, w.Fae, 1);
+  P(1, "mi->mi", w.foo, w.Fmi, 0);
+  C(0.5, "ie,me->mi", t1, w.fov, w.Fmi, 1);
+  P(1, "me->me", w.fov, w.Fme, 0);
+  if (tb) {
+    C(1, "mf,mafe->ae", t1, I.Lovvv, w.Fae, 1);
+    C(-1, "mnaf,mnef->ae", w.taut, I.Loovv, w.Fae, 1);
+    C(1, "ne,mnie->mi", t1, I.Looov, w.Fmi, 1);
+    C(1, "inef,mnef->mi", w.taut, I.Loovv, w.Fmi, 1);
+    C(1, "nf,mnef->me", t1, I.Loovv, w.Fme, 1);
+  }
+  P(1, "ae->ae", w.Fae, w.Hvv, 0);
+  C(-0.5, "ma,me->ae", t1, w.Fme, w.Hvv, 1);
+  P(1, "mi->mi", w.Fmi, w.Hoo, 0);
+  C(0.5, "ie,me->mi", t1, w.Fme, w.Hoo, 1);
+
+  // ---- T1 residual
+  P(1, "ia->ia", w.fov, w.R1, 0);
+  C(1, "ie,ae->ia", t1, w.Fae, w.R1, 1);
+  C(-1, "ma,mi->ia", t1, w.Fmi, w.R1, 1);
+  C(1, "imae,me->ia", w.t2s, w.Fme, w.R1, 1);
+  if (tb) {
+    C(1, "nf,nafi->ia", t1, I.Lovvo, w.R1, 1);
+    C(1, "imef,mafe->ia", t2, I.Lovvv, w.R1, 1);
+    C(-1, "mnae,mnie->ia", t2, I.Looov, w.R1, 1);
+  }
+
+  // ---- two-electron intermediates
+  if (tb) {
+    P(1, "mnij->mnij", I.oooo, w.W, 0);
+    C(1, "je,mnie->mnij", t1, I.ooov, w.W, 1);
+    C(1, "ie,nmje->mnij", t1, I.ooov, w.W, 1);
+    C(1, "ijef,mnef->mnij", tau, I.oovv, w.W, 1);
+    P(1, "mnie->mnie", I.ooov, w.Hooov, 0);
+    C(1, "if,mnfe->mnie", t1, I.oovv, w.Hooov, 1);
+    if (lambda) {
+      P(1, "mafe->amef", I.ovvv, w.Hvovv, 0);
+      C(-1, "na,nmef->amef", t1, I.oovv, w.Hvovv, 1);
+    }
+    // particle-particle ladder: one GEMM over the stacked [tau; lambda2] rows
+    {
+      const int64_t rows = (lambda ? 2 : 1) * (int64_t)o * o, vv = (int64_t)v * v;
+      GemmOp<T> a{w.X.re, w.X.im, vv, 0};
+      GemmOp<T> b{I.vvvv.re, nullptr, vv, 0};  // <ef|ab> = <ab|ef>
+      gemm<T>(E, rows, vv, vv, 1.0, a, b, w.Lad.re, w.Lad.im, vv, 0.0);
+    }
+    C(1, "ijef,mafe->ijam", tau, I.ovvv, w.Z1, 0);
+    // ring intermediates (element X_mbej at (m,e,j,b))
+    C(1, "njfb,mnef->mejb", t2, I.Loovv, w.Pd, 0);
+    C(-1, "jnfb,mnef->mejb", t2, I.oovv, w.Pd, 1);
+    C(1, "jnfb,mnfe->mejb", t2, I.oovv, w.Px, 0);
+    P(1, "mbej->mejb", I.ovvo, w.Bd, 0);
+    C(1, "jf,mbef->mejb", t1, I.ovvv, w.Bd, 1);
+    C(-1, "nb,nmje->mejb", t1, w.Hooov, w.Bd, 1);
+    P(-1, "mbje->mejb", I.ovov, w.Bx, 0);
+    C(-1, "jf,mbfe->mejb", t1, I.ovvv, w.Bx, 1);
+    C(1, "nb,mnje->mejb", t1, w.Hooov, w.Bx, 1);
+    P(1, "mejb->mejb", w.Bd, w.Wd, 0);
+    P(0.5, "mejb->mejb", w.Pd, w.Wd, 1);
+    P(1, "mejb->mejb", w.Bx, w.Wx, 0);
+    P(0.5, "mejb->mejb", w.Px, w.Wx, 1);
+    if (lambda) {
+      P(1, "mejb->mejb", w.Bd, w.HHd, 0);
+      P(1, "mejb->mejb", w.Pd, w.HHd, 1);
+      P(1, "mejb->mejb", w.Bx, w.HHx, 0);
+      P(1, "mejb->mejb", w.Px, w.HHx, 1);
+    }
+  }
+
+  // ---- T2 residual: R2 = <ij|ab> + tau.W + ladder + (1 + P(ia,jb)) Z
+  C(1, "ijae,be->ijab", t2, w.Hvv, w.Z, 0);
+  C(-1, "imab,mj->ijab", t2, w.Hoo, w.Z, 1);
+  if (tb) {
+    P(1, "imae->imae", w.t2s, w.T2R0, 0);
+    P(1, "imae->imae", t2, w.T2R1, 0);
+    C(1, "iasme,smejb->iajb", w.T2R, w.WW, w.Zt, 0);
+    C(1, "mjae,meib->iajb", t2, w.Wx, w.Zt, 1);
+    C(-1, "mb,ijam->ijab", t1, w.Z1, w.Z, 1);
+    // t1 t1 ring pieces: S[m,b,i,j] = sum_e t_ie <mb|ej> + t_je <mb|ie>
+    {
+      const Ten<T>& S = w.S1t;
+      C(1, "ie,mbej->mbij", t1, I.ovvo, S, 0);
+      C(1, "je,mbie->mbij", t1, I.ovov, S, 1);
+      C(-1, "ma,mbij->ijab", t1, S, w.Z, 1);
+    }
+    C(1, "ie,jeba->ijab", t1, I.ovvv, w.Z, 1);
+    C(-1, "ma,ijmb->ijab", t1, I.ooov, w.Z, 1);
+    P(1, "iajb->ijab", w.Zt, w.Z, 1);
+    P(1, "ijab->ijab", I.oovv, w.R2, 0);
+    C(1, "mnab,mnij->ijab", tau, w.W, w.R2, 1);
+    P(1, "ijab->ijab", w.LadT, w.R2, 1);
+    P(1, "ijab->ijab", w.Z, w.R2, 1);
+  } else {
+    P(1, "ijab->ijab", w.Z, w.R2, 0);
+  }
+  P(1, "ijab->jiba", w.Z, w.R2, 1);
+  if (!lambda) return;
+
+  // ---- Lambda2 residual
+  C(1, "ijae,eb->ijab", l2, w.Hvv, w.ZL, 0);
+  C(-1, "imab,jm->ijab", l2, w.Hoo, w.ZL, 1);
+  C(1, "ia,jb->ijab", l1, w.Fme, w.ZL, 1);
+  if (tb) {
+    C(-1, "mnef,mnaf->ae", w.t2s, l2, w.Gvv, 0);
+    C(1, "mnef,inef->mi", w.t2s, l2, w.Goo, 0);
+    C(1, "ijef,mf->ijem", l2, t1, w.Y, 0);
+    C(1, "ijef,mnef->ijmn", l2, tau, w.M, 0);
+    C(1, "ie,ejab->ijab", l1, w.Hvovv, w.ZL, 1);
+    C(-1, "ma,ijmb->ijab", l1, w.Hooov, w.ZL, 1);
+    P(1, "imae->imae", w.l2s, w.L2R0, 0);
+    P(1, "imae->imae", l2, w.L2R1, 0);
+    C(1, "iames,mesjb->iajb", w.L2R, w.HH5, w.ZLt, 0);
+    C(1, "mjae,ibme->iajb", l2, w.HHx, w.ZLt, 1);
+    P(1, "iajb->ijab", w.ZLt, w.ZL, 1);
+    C(1, "ijae,be->ijab", I.oovv, w.Gvv, w.ZL, 1);
+    C(-1, "imab,mj->ijab", I.oovv, w.Goo, w.ZL, 1);
+    C(-1, "ijem,meba->ijab", w.Y, I.ovvv, w.ZL, 1);
+    P(1, "ijab->ijab", I.oovv, w.S2, 0);
+    C(1, "mnab,ijmn->ijab", l2, w.W, w.S2, 1);
+    P(1, "ijab->ijab", w.LadL, w.S2, 1);
+    C(1, "ijmn,mnab->ijab", w.M, I.oovv, w.S2, 1);
+    P(1, "ijab->ijab", w.ZL, w.S2, 1);
+  } else {
+    P(1, "ijab->ijab", w.ZL, w.S2, 0);
+  }
+  P(1, "ijab->jiba", w.ZL, w.S2, 1);
+
+  // ---- Lambda1 residual: S1 = Fme + l1.Hvv - l1.Hoo + ... + A1 - A2
+  P(1, "ia->ia", w.Fme, w.S1, 0);
+  C(1, "ie,ea->ia", l1, w.Hvv, w.S1, 1);
+  C(-1, "ma,im->ia", l1, w.Hoo, w.S1, 1);
+  // Fock parts of A1 and A2 (present without two-electron integrals too)
+  C(1, "imef,nmef->in", w.l2s, t2, w.Q, 0);
+  C(-1, "in,na->ia", w.Q, w.Fme, w.S1, 1);
+  C(1, "mnae,mnfe->af", w.l2s, t2, w.Gx, 0);
+  C(-1, "if,af->ia", w.Fme, w.Gx, w.S1, 1);
+  if (!tb) return;
+  C(2, "me,iame->ia", l1, w.HHd, w.S1, 1);
+  C(1, "me,iame->ia", l1, w.HHx, w.S1, 1);
+  C(-2, "ef,eifa->ia", w.Gvv, w.Hvovv, w.S1, 1);
+  C(1, "ef,eiaf->ia", w.Gvv, w.Hvovv, w.S1, 1);
+  C(-2, "mn,mina->ia", w.Goo, w.Hooov, w.S1, 1);
+  C(1, "mn,imna->ia", w.Goo, w.Hooov, w.S1, 1);
+  // A1 = sum_mef l2s_im^ef Hbar_efam
+  C(1, "imef,mafe->ia", w.l2s, I.ovvv, w.S1, 1);
+  C(2, "mg,imag->ia", t1, w.LadL, w.S1, 1);
+  C(-1, "mg,imga->ia", t1, w.LadL, w.S1, 1);
+  C(1, "imef,kf->imek", w.l2s, t1, w.U, 0);
+  C(1, "imef,ke->imkf", w.l2s, t1, w.U2, 0);
+  C(1, "mg,kega->meka", t1, I.ovvv, w.B2, 0);
+  C(-1, "imek,meka->ia", w.U, w.B2, w.S1, 1);
+  C(1, "mg,kfag->mfka", t1, I.ovvv, w.B3, 0);
+  C(-1, "imkf,mfka->ia", w.U2, w.B3, w.S1, 1);
+  C(1, "imef,klef->imkl", w.l2s, tau, w.Mp, 0);
+  C(1, "mg,klag->klma", t1, I.oovv, w.Nn, 0);
+  C(1, "imkl,klma->ia", w.Mp, w.Nn, w.S1, 1);
+  C(1, "imnk,knma->ia", w.Mp, I.ooov, w.S1, 1);
+  C(1, "imef,nmeg->infg", w.l2s, t2, w.Wr, 0);
+  C(-1, "infg,nfag->ia", w.Wr, I.ovvv, w.S1, 1);
+  C(1, "imef,nmgf->ineg", w.l2s, t2, w.Wr, 0);
+  C(1, "ineg,nega->ia", w.Wr, I.Lovvv, w.S1, 1);
+  C(1, "imef,nmfg->ineg", w.l2s, t2, w.Wr, 0);
+  C(-1, "ineg,nega->ia", w.Wr, I.ovvv, w.S1, 1);
+  C(-1, "imnf,nfam->ia", w.U2, I.ovvo, w.S1, 1);
+  C(1, "imnf,kmfg->inkg", w.U2, t2, w.Y3, 0);
+  C(1, "inkg,nkag->ia", w.Y3, I.oovv, w.S1, 1);
+  C(1, "imnf,kmgf->inkg", w.U2, t2, w.Y3, 0);
+  C(-1, "inkg,nkag->ia", w.Y3, I.Loovv, w.S1, 1);
+  C(-1, "imen,nema->ia", w.U, I.ovov, w.S1, 1);
+  C(1, "imen,kmeg->inkg", w.U, t2, w.Y3, 0);
+  C(1, "inkg,nkga->ia", w.Y3, I.oovv, w.S1, 1);
+  // -A2 = -sum_mne l2s_mn^ae Hbar_iemn
+  C(-1, "mnae,mnie->ia", w.l2s, I.ooov, w.S1, 1);
+  C(1, "mnae,ke->mnak", w.l2s, t1, w.Y6, 0);
+  C(1, "mnak,ikmn->ia", w.Y6, w.W, w.S1, 1);
+  C(-1, "mnae,nmei->ia", w.l2s, w.Z1, w.S1, 1);
+  C(1, "mnae,nkef->mkaf", w.l2s, t2, w.Wr, 0);
+  C(-1, "mkaf,ikmf->ia", w.Wr, I.Looov, w.S1, 1);
+  C(1, "mnae,nkfe->mkaf", w.l2s, t2, w.Wr, 0);
+  C(1, "mkaf,ikmf->ia", w.Wr, I.ooov, w.S1, 1);
+  C(1, "mnae,mkfe->nkaf", w.l2s, t2, w.Wr, 0);
+  C(1, "nkaf,kinf->ia", w.Wr, I.ooov, w.S1, 1);
+  C(1, "mf,iefn->mien", t1, I.ovvo, w.B4, 0);
+  C(-1, "mnae,mien->ia", w.l2s, w.B4, w.S1, 1);
+  C(1, "mf,ikfg->mikg", t1, I.oovv, w.B5, 0);
+  C(-1, "kneg,mikg->mnei", t2, w.B5, w.D, 0);
+  C(1, "mf,ikfg->mikg", t1, I.Loovv, w.B5, 0);
+  C(1, "knge,mikg->mnei", t2, w.B5, w.D, 1);
+  C(1, "nf,ikgf->nikg", t1, I.oovv, w.B5, 0);
+  C(-1, "mkge,nikg->mnei", t2, w.B5, w.D, 1);
+  C(-1, "mnae,mnei->ia", w.l2s, w.D, w.S1, 1);
+  C(1, "nf,iemf->niem", t1, I.ovov, w.B7, 0);
+  C(-1, "mnae,niem->ia", w.l2s, w.B7, w.S1, 1);
+}
+
+template <typename T>
+void density(Engine& E, Work<T>& w) {
+  auto C = [&](double a, const char* s, const Ten<T>& x, const Ten<T>& y, const Ten<T>& z, double b) {
+    ein<T>(E, a, s, x, y, z, b);
+  };
+  auto P = [&](double a, const char* s, const Ten<T>& x, const Ten<T>& z, double b) { padd<T>(E, a, s, x, z, b); };
+  const int64_t o = w.o, v = w.v, n = w.n;
+  const Ten<T>&t1 = w.t1, &t2 = w.t2, &l1 = w.l1, &l2 = w.l2;
+  Ten<T> roo = view(w.rho, 0, {o, o}, {n, 1});
+  Ten<T> rov = view(w.rho, o, {o, v}, {n, 1});
+  Ten<T> rvo = view(w.rho, o * n, {v, o}, {n, 1});
+  Ten<T> rvv = view(w.rho, o * n + o, {v, v}, {n, 1});
+  P(2, "ijab->ijab", l2, w.l2s, 0);
+  P(-1, "ijab->ijba", l2, w.l2s, 1);
+  P(2, "ijab->ijab", t2, w.t2s, 0);
+  P(-1, "ijab->ijba", t2, w.t2s, 1);
+  C(1, "ijab,ijae->be", w.l2s, t2, w.Dvv, 0);
+  C(1, "ijab,imab->jm", w.l2s, t2, w.Doo, 0);
+  C(1, "ma,ia->mi", t1, l1, w.P1, 0);
+  P(0, "ai->ai", rvo, rvo, 0);
+  P(-2, "mi->mi", w.P1, roo, 0);
+  P(-2, "jm->mj", w.Doo, roo, 1);
+  P(2, "me->me", t1, rov, 0);
+  P(2, "me->me", l1, rov, 1);
+  C(-2, "mi,ie->me", w.P1, t1, rov, 1);
+  C(2, "ia,imae->me", l1, w.t2s, rov, 1);
+  C(-2, "mb,be->me", t1, w.Dvv, rov, 1);
+  C(-2, "jm,je->me", w.Doo, t1, rov, 1);
+  C(2, "ia,ie->ae", l1, t1, rvv, 0);
+  P(2, "be->be", w.Dvv, rvv, 1);
+}
+
+template void build_work<double>(Arena&, int, int, Work<double>&);
+template void build_work<float>(Arena&, int, int, Work<float>&);
+template void residuals<double>(Engine&, const Ints<double>&, Work<double>&, bool, bool);
+template void residuals<float>(Engine&, const Ints<float>&, Work<float>&, bool, bool);
+template void density<double>(Engine&, Work<double>&);
+template void density<float>(Engine&, Work<float>&);
+
+}  // namespace rtcc

@@ -1,0 +1,225 @@
+"""HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Every case uses seeded synthetic inputs from ``synth``: the water-cluster-shaped
+Hamiltonian plus a random symmetric Fock perturbation (non-canonical, f_ov != 0),
+and random NON-stationary complex amplitudes. Sizes span several 64-wide GEMM
+tiles with ragged tails: (6, 25) has ov = 150 and v^2 = 625.
+
+Tolerances: FP64 contractions 1e-11 (relative to the largest entry); FP32
+contractions 3e-5 relative (single-precision rounding accumulated over sums of
+up to v^2 terms, with FP64 state and output).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ccsd, field, ground, integrators
+from synth import make_system, pack_state, random_state, random_symmetric, unpack_state
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(1, 1), (1, 4), (2, 3), (4, 16), (5, 19), (6, 25)]
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu(require_gpu):
+    yield
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    return torch
+
+
+def _system(o, v, seed, perturb=0.05):
+    eri, fock, mu = make_system(o, v, seed)
+    if perturb:
+        fock = fock + random_symmetric(o + v, perturb, np.random.default_rng(1000 + seed))
+    return eri, fock, mu
+
+
+def _ctx(eri, fock, mu, o, v, precision="fp64"):
+    from paper_2205_05175_amd import RTCC
+    return RTCC(eri, fock, mu, o, v, precision)
+
+
+def _dev(x):
+    torch = _torch()
+    return torch.tensor(np.asarray(x, dtype=np.complex128), device="cuda")
+
+
+@pytest.mark.parametrize("o,v", SIZES)
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 3e-5)])
+def test_rhs_matches_oracle(o, v, precision, tol):
+    print(f"rhs parity o={o} v={v} {precision}", flush=True)
+    eri, fock, mu = _system(o, v, 1)
+    S = ccsd.SpinOrbitalSystem(eri, fock, mu, o, v)
+    st = random_state(o, v, 3, 0.05, 0.02)
+    E = np.array([0.003, -0.002, 0.01])
+    ref = pack_state(*ccsd.rhs(S, *st, E))
+    R = _ctx(eri, fock, mu, o, v, precision)
+    out = R.rhs(_dev(pack_state(*st)), E).cpu().numpy()
+    scale = max(1.0, np.abs(ref).max())
+    err = np.abs(out - ref).max() / scale
+    assert err < tol, f"max error {err:.3e}"
+    # the closed-shell pair symmetry of the doubles derivatives
+    d = unpack_state(out, o, v)
+    assert np.abs(d[1] - d[1].transpose(1, 0, 3, 2)).max() < 10 * tol * scale
+    R.close()
+
+
+def test_rhs_bitwise_repeatable():
+    o, v = 5, 19
+    eri, fock, mu = _system(o, v, 2)
+    R = _ctx(eri, fock, mu, o, v)
+    y = _dev(pack_state(*random_state(o, v, 4)))
+    a = R.rhs(y, [0.0, 0.0, 0.01]).cpu().numpy()
+    b = R.rhs(y, [0.0, 0.0, 0.01]).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("o,v", [(1, 4), (4, 16), (6, 25)])
+def test_dipole_matches_oracle(o, v):
+    eri, fock, mu = _system(o, v, 5)
+    S = ccsd.SpinOrbitalSystem(eri, fock, mu, o, v)
+    st = random_state(o, v, 6, 0.05, 0.02)
+    R = _ctx(eri, fock, mu, o, v)
+    got = R.dipole(_dev(pack_state(*st)))
+    ref = ccsd.dipole(S, *st)
+    assert np.abs(got - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("o,v", [(2, 3), (4, 16)])
+def test_kick_matches_oracle(o, v):
+    eri, fock, mu = _system(o, v, 7)
+    S = ccsd.SpinOrbitalSystem(eri, fock, mu, o, v)
+    st = random_state(o, v, 8, 0.05, 0.02)
+    n = np.array([0.3, -0.5, 0.8])
+    ref = pack_state(*field.kick(S, st, 2e-2, n))
+    R = _ctx(eri, fock, mu, o, v)
+    y = _dev(pack_state(*st))
+    R.kick(y, 2e-2, n)
+    assert np.abs(y.cpu().numpy() - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_rk4_step_matches_oracle(precision, tol):
+    o, v = 4, 16
+    eri, fock, mu = _system(o, v, 9)
+    S = ccsd.SpinOrbitalSystem(eri, fock, mu, o, v)
+    st = random_state(o, v, 10, 0.05, 0.02)
+    pulse = dict(E0=0.01, omega=0.5, sigma=5.0, t0=15.0)
+    n = [0.0, 0.0, 1.0]
+    Ef = lambda t: field.gaussian(t, pulse["E0"], pulse["omega"], pulse["sigma"], pulse["t0"], n)
+    f = lambda t, yy: pack_state(*ccsd.rhs(S, *unpack_state(yy, o, v), Ef(t)))
+    y0 = pack_state(*st)
+    ref = integrators.rk4_step(f, 14.0, y0, 0.05)
+    from paper_2205_05175_amd import Field
+    R = _ctx(eri, fock, mu, o, v, precision)
+    y = _dev(y0)
+    R.step_rk4(y, 14.0, 0.05, Field.gaussian(pulse["E0"], pulse["omega"], pulse["sigma"], pulse["t0"], n))
+    assert np.abs(y.cpu().numpy() - ref).max() < tol
+
+
+def test_cashkarp_trial_matches_oracle():
+    o, v = 4, 16
+    eri, fock, mu = _system(o, v, 11)
+    S = ccsd.SpinOrbitalSystem(eri, fock, mu, o, v)
+    st = random_state(o, v, 12, 0.05, 0.02)
+    pulse = dict(E0=0.05, omega=0.5, sigma=2.0, t0=3.0)
+    n = [0.0, 1.0, 0.0]
+    Ef = lambda t: field.gaussian(t, pulse["E0"], pulse["omega"], pulse["sigma"], pulse["t0"], n)
+    f = lambda t, yy: pack_state(*ccsd.rhs(S, *unpack_state(yy, o, v), Ef(t)))
+    y0 = pack_state(*st)
+    y5, y4, delta = integrators.cashkarp_trial(f, 2.5, y0, 0.04)
+    from paper_2205_05175_amd import Field
+    R = _ctx(eri, fock, mu, o, v)
+    fld = Field.gaussian(pulse["E0"], pulse["omega"], pulse["sigma"], pulse["t0"], n)
+    # rejected trial: state unchanged, h shrinks by the controller's factor
+    y = _dev(y0)
+    t, h, acc, d = R.step_cashkarp(y, 2.5, 0.04, delta * 0.5, fld)
+    assert not acc and t == 2.5
+    # Delta is a difference of nearly equal solutions: compare it relatively
+    assert abs(d - delta) < 1e-8 * delta
+    assert abs(h - 0.04 * integrators.ck_factor(delta * 0.5, d)) < 1e-15
+    assert np.array_equal(y.cpu().numpy(), y0)
+    # accepted trial: advances with the fifth-order solution
+    t, h, acc, d = R.step_cashkarp(y, 2.5, 0.04, delta * 2.0, fld)
+    assert acc and abs(t - 2.54) < 1e-15
+    assert np.abs(y.cpu().numpy() - y5).max() < 1e-12
+    assert abs(h - 0.04 * integrators.ck_factor(delta * 2.0, d)) < 1e-15
+
+
+@pytest.mark.parametrize("o,v", [(1, 4), (4, 16)])
+def test_ground_state_matches_oracle(o, v):
+    eri, fock, mu = make_system(o, v, 0)
+    S = ccsd.SpinOrbitalSystem(eri, fock, mu, o, v)
+    t1, t2, l1, l2, e = ground.solve(S, fock)
+    R = _ctx(eri, fock, mu, o, v)
+    y = R.new_state()
+    eg = R.ground_state(y, 1e-12, 200)
+    got = unpack_state(y.cpu().numpy(), o, v)
+    for a, b in zip(got, (t1, t2, l1, l2)):
+        assert np.abs(a - b).max() < 1e-10
+    assert abs(eg - e.real) < 1e-11
+    # stationarity of the GPU right-hand side at its own ground state
+    d = R.rhs(y, [0.0, 0.0, 0.0]).cpu().numpy()
+    assert np.abs(d).max() < 1e-11
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} missing (run tests/golden/make_trajectories.py)")
+    g = json.load(open(path))
+    mu = np.array(g["mu"])
+    return g, mu[..., 0] + 1j * mu[..., 1]
+
+
+def test_delta_kick_trajectory_fp64():
+    """(4,16): ground state, kick 1e-3 along z, RK4 dt=0.05 x 200; every dipole within 1e-10 au."""
+    torch = _torch()
+    g, ref = _golden("delta_kick_o4v16")
+    c = g["case"]
+    o, v = c["o"], c["v"]
+    eri, fock, mu = make_system(o, v, c["seed"])
+    R = _ctx(eri, fock, mu, o, v)
+    y = R.new_state()
+    e = R.ground_state(y, 1e-12, 200)
+    assert abs(e - g["e_corr"]) < 1e-11
+    R.kick(y, c["kick"], c["n"])
+    mu_out = torch.zeros((c["steps"] + 1, 6), dtype=torch.float64, device="cuda")
+    R.propagate_rk4(y, 0.0, c["dt"], c["steps"], None, mu_out)
+    m = mu_out.cpu().numpy()
+    got = m[:, 0::2] + 1j * m[:, 1::2]
+    err = np.abs(got - ref).max()
+    print(f"delta-kick trajectory max |dmu| = {err:.3e}")
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-6)])
+def test_gaussian_pulse_trajectory(precision, tol):
+    """(5,19): Gaussian pulse, RK4 dt=0.02 x 1000: FP64 within 1e-10 au, FP32 within 1e-6 au."""
+    torch = _torch()
+    g, ref = _golden("gaussian_o5v19")
+    c = g["case"]
+    o, v = c["o"], c["v"]
+    eri, fock, mu = make_system(o, v, c["seed"])
+    R = _ctx(eri, fock, mu, o, v, precision)
+    y = R.new_state()
+    R.ground_state(y, 1e-12, 200)
+    from paper_2205_05175_amd import Field
+    p = c["pulse"]
+    fld = Field.gaussian(p["E0"], p["omega"], p["sigma"], p["t0"], c["n"])
+    mu_out = torch.zeros((c["steps"] + 1, 6), dtype=torch.float64, device="cuda")
+    R.propagate_rk4(y, 0.0, c["dt"], c["steps"], fld, mu_out)
+    m = mu_out.cpu().numpy()
+    got = m[:, 0::2] + 1j * m[:, 1::2]
+    err = np.abs(got - ref).max()
+    print(f"gaussian trajectory {precision}: max |dmu| = {err:.3e}")
+    assert err < tol
