@@ -124,6 +124,14 @@ int rtcc_kick(rtcc_ctx* ctx, void* y, double kappa, const double n[3]);
 /* *nonfinite (HOST) = number of non-finite complex entries of y. Synchronises. */
 int rtcc_check_state(rtcc_ctx* ctx, const void* y, int64_t* nonfinite);
 
+/* Live timing of the dominant kernel, the particle-particle ladder GEMM. rtcc_profile(ctx, 1)
+ * resets the statistics and brackets every subsequent ladder launch with HIP events recorded on
+ * the context stream; rtcc_profile(ctx, 0) stops. rtcc_profile_read synchronises and returns the
+ * number of timed launches, their summed duration in ms and the algorithmic real flops of one
+ * launch (4 * rows * v^2 * v^2 for rows = 2 o^2 complex rows times the real <ab|ef> matrix). */
+int rtcc_profile(rtcc_ctx* ctx, int enable);
+int rtcc_profile_read(rtcc_ctx* ctx, int64_t* launches, double* total_ms, double* flops_per_launch);
+
 /* Diagnostics: out[0] = o, out[1] = v, out[2] = state length (complex entries),
  * out[3] = real flops issued to the MFMA GEMMs by the last rtcc_rhs call,
  * out[4] = device bytes held by the context, out[5] = current precision. */

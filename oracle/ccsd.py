@@ -196,9 +196,10 @@ class SpinOrbitalSystem:
     """Spin-orbital Fock, antisymmetrised integrals and dipole integrals of a closed-shell system."""
 
     def __init__(self, eri, fock, mu, o, v):
+        """``eri=None`` builds a system without two-electron integrals (enough for the dipole)."""
         self.o, self.v = o, v
         self.f0 = spinorb.so_one_body(np.asarray(fock, float), o, v)
-        self.g = spinorb.so_antisym_eri(np.asarray(eri, float), o, v)
+        self.g = None if eri is None else spinorb.so_antisym_eri(np.asarray(eri, float), o, v)
         self.mu = np.stack([spinorb.so_one_body(np.asarray(m, float), o, v) for m in mu])
         self.mu_ref = np.array([np.trace(m[:2 * o, :2 * o]) for m in self.mu])
 

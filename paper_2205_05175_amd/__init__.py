@@ -60,13 +60,15 @@ def load_library(path: str = LIB_PATH):
     L.rtcc_kick.argtypes = [vp, vp, d, dp]
     L.rtcc_check_state.argtypes = [vp, vp, ctypes.POINTER(i64)]
     L.rtcc_info.argtypes = [vp, ctypes.POINTER(i64)]
+    L.rtcc_profile.argtypes = [vp, i]
+    L.rtcc_profile_read.argtypes = [vp, ctypes.POINTER(i64), dp, dp]
     L.rtcc_destroy.argtypes = [vp]
     L.rtcc_destroy.restype = None
     L.rtcc_last_error.argtypes = [vp]
     L.rtcc_last_error.restype = ctypes.c_char_p
     for name in ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
                  "rtcc_step_cashkarp", "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick",
-                 "rtcc_check_state", "rtcc_info"):
+                 "rtcc_check_state", "rtcc_info", "rtcc_profile", "rtcc_profile_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -74,7 +76,8 @@ def load_library(path: str = LIB_PATH):
 
 EXPORTED = ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
             "rtcc_step_cashkarp", "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick",
-            "rtcc_check_state", "rtcc_info", "rtcc_destroy", "rtcc_last_error")
+            "rtcc_check_state", "rtcc_info", "rtcc_profile", "rtcc_profile_read", "rtcc_destroy",
+            "rtcc_last_error")
 
 
 class RTCCError(RuntimeError):
@@ -187,6 +190,14 @@ class RTCC:
         k = ctypes.c_int64(0)
         self._check(self.L.rtcc_check_state(self.ctx, self._state(y), ctypes.byref(k)))
         return k.value
+
+    def profile(self, enable=True):
+        self._check(self.L.rtcc_profile(self.ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        n, ms, fl = ctypes.c_int64(0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+        self._check(self.L.rtcc_profile_read(self.ctx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
+        return n.value, ms.value, fl.value
 
     def info(self):
         out = (ctypes.c_int64 * 6)()

@@ -66,6 +66,12 @@ struct rtcc_ctx {
   void* diis_err = nullptr;
   size_t bytes = 0;
   int64_t last_flops = 0;
+  // live timing of the particle-particle ladder GEMM (HIP events on the context stream)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  int64_t prof_launches = 0;
+  double prof_ms = 0.0, prof_flops = 0.0;
 };
 
 namespace {
@@ -135,6 +141,25 @@ void eval_rhs(rtcc_ctx* c, Ints<T>& I, Work<T>& w, const void* y, const double E
   residuals<T>(c->E, I, w, twobody, true);
   c->last_flops = c->E.gemm_flops - f0;
   pack_rhs<T>(c->stream, c->o, c->v, planes(w, false), out, scale);
+}
+
+void prof_flush(rtcc_ctx* c) {
+  if (c->ev_used == 0) return;
+  RTCC_HIP(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < c->ev_used; i += 2) {
+    float ms = 0.f;
+    RTCC_HIP(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+    c->prof_ms += ms;
+  }
+  c->ev_used = 0;
+}
+
+void prof_mark(void* user, int phase) {
+  rtcc_ctx* c = (rtcc_ctx*)user;
+  if (!c->prof) return;
+  if (phase == 0 && c->ev_used + 2 > (int)c->ev.size()) prof_flush(c);
+  RTCC_HIP(hipEventRecord(c->ev[c->ev_used++], c->stream));
+  if (phase == 1) c->prof_launches++;
 }
 
 void rhs_any(rtcc_ctx* c, const void* y, const double E[3], void* out, double scale) {
@@ -520,6 +545,34 @@ int rtcc_ground_state(rtcc_ctx* c, void* y, double tol, int maxiter, double* e_c
   });
 }
 
+int rtcc_profile(rtcc_ctx* c, int enable) {
+  if (!c) return RTCC_EINVAL;
+  return guarded(c, [&] {
+    if (c->ev.empty()) {
+      c->ev.resize(1024);
+      for (auto& e : c->ev) RTCC_HIP(hipEventCreate(&e));
+    }
+    if (enable) {
+      prof_flush(c);
+      c->prof_launches = 0;
+      c->prof_ms = 0.0;
+    }
+    c->prof = enable != 0;
+    c->E.mark = enable ? prof_mark : nullptr;
+    c->E.mark_user = c;
+  });
+}
+
+int rtcc_profile_read(rtcc_ctx* c, int64_t* launches, double* total_ms, double* flops_per_launch) {
+  if (!c || !launches || !total_ms || !flops_per_launch) return RTCC_EINVAL;
+  return guarded(c, [&] {
+    prof_flush(c);
+    *launches = c->prof_launches;
+    *total_ms = c->prof_ms;
+    *flops_per_launch = c->E.ladder_flops;
+  });
+}
+
 int rtcc_info(rtcc_ctx* c, int64_t out[6]) {
   if (!c || !out) return RTCC_EINVAL;
   out[0] = c->o;
@@ -536,6 +589,7 @@ int rtcc_info(rtcc_ctx* c, int64_t out[6]) {
 void rtcc_destroy(rtcc_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  for (auto e : c->ev) (void)hipEventDestroy(e);
   if (c->host_pinned) (void)hipHostFree(c->host_pinned);
   delete c;
 }

@@ -66,6 +66,10 @@ struct Engine {
   hipStream_t stream = nullptr;
   Scratch scratch;
   int64_t gemm_flops = 0;  // algorithmic real flops issued (accounting)
+  // optional hook called before (phase 0) and after (phase 1) the ladder GEMM launch
+  void (*mark)(void*, int) = nullptr;
+  void* mark_user = nullptr;
+  double ladder_flops = 0.0;  // algorithmic real flops of the last ladder GEMM
 };
 
 // C = alpha * contraction(A, B) + beta * C   (beta 0 or 1)

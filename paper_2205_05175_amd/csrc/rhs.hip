@@ -261,7 +261,10 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
       const int64_t rows = (lambda ? 2 : 1) * (int64_t)o * o, vv = (int64_t)v * v;
       GemmOp<T> a{w.X.re, w.X.im, vv, 0};
       GemmOp<T> b{I.vvvv.re, nullptr, vv, 0};  // <ef|ab> = <ab|ef>
+      if (E.mark) E.mark(E.mark_user, 0);
       gemm<T>(E, rows, vv, vv, 1.0, a, b, w.Lad.re, w.Lad.im, vv, 0.0);
+      if (E.mark) E.mark(E.mark_user, 1);
+      E.ladder_flops = 4.0 * (double)rows * (double)vv * (double)vv;  // real x complex: 2 MACs per entry
     }
     C(1, "ijef,mafe->ijam", tau, I.ovvv, w.Z1, 0);
     // ring intermediates (element X_mbej at (m,e,j,b))

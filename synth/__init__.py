@@ -10,13 +10,23 @@ Water-cluster-shaped Hamiltonian (closed shell, ``o`` doubly occupied and
 
 1. occupied orbital energies ~ U[-1.5, -0.5] (sorted ascending),
 2. virtual orbital energies ~ U[0.2, 3.0] (sorted ascending),
-3. ``B`` ~ N(0, 0.05^2) of shape ``(3n, n, n)``, made symmetric in its last
-   two indices by mirroring the upper triangle,
+3. ``B`` ~ N(0, s^2) of shape ``(3n, n, n)``, made symmetric in its last
+   two indices by mirroring the upper triangle, with s = 0.05 for n <= 24 and
+   s = 0.05 * 24 / n beyond (see below),
 4. dipole integrals ``mu`` ~ N(0, 0.3^2) of shape ``(3, n, n)``, mirrored the
    same way.
 
 Then ``(pq|rs) = sum_Q B[Q,p,q] B[Q,r,s]`` (chemists' order, 8-fold symmetric)
 and ``f = diag(eps_occ, eps_vir)`` with the occupied orbitals first.
+
+Size scaling of ``s``: with a fixed s = 0.05 every exchange-type integral
+(ia|ia) = sum_Q B[Q,i,a]^2 grows like 3n s^2 and the random off-diagonal ones like
+sqrt(3n) s^2, so the correlation grows much faster than the system: at
+(o, v) = (10, 38) the MP2 energy is -62 Eh and at (20, 76) -1739 Eh, and the CCSD
+equations have no convergent solution. Scaling s by 24/n for n > 24 keeps the
+coherent per-orbital sums (Fock-like dressings of size o^2 v (ia|jb)^2 / D)
+independent of n, so the correlation energy grows linearly with the size, as
+for a water cluster. Systems with n <= 24 are drawn exactly as before.
 """
 from __future__ import annotations
 
@@ -29,13 +39,18 @@ def _mirror_upper(x: np.ndarray) -> np.ndarray:
     return np.where(iu, x, np.swapaxes(x, -1, -2))
 
 
+def b_sigma(n: int) -> float:
+    """Standard deviation of the factors B for a system of n orbitals."""
+    return 0.05 * min(1.0, 24.0 / n)
+
+
 def make_system(o: int, v: int, seed: int = 0, dtype=np.float64):
     """Return ``(eri, fock, mu)``: eri ``(n,n,n,n)`` chemists' order, fock ``(n,n)``, mu ``(3,n,n)``."""
     n = o + v
     rng = np.random.default_rng(seed)
     eps_o = np.sort(rng.uniform(-1.5, -0.5, size=o))
     eps_v = np.sort(rng.uniform(0.2, 3.0, size=v))
-    B = _mirror_upper(rng.normal(0.0, 0.05, size=(3 * n, n, n)))
+    B = _mirror_upper(rng.normal(0.0, b_sigma(n), size=(3 * n, n, n)))
     mu = _mirror_upper(rng.normal(0.0, 0.3, size=(3, n, n)))
     Bm = B.reshape(3 * n, n * n)
     eri = (Bm.T @ Bm).reshape(n, n, n, n).astype(dtype)
