@@ -93,7 +93,10 @@ int rtcc_step_rk4(rtcc_ctx* ctx, void* y, double t, double h, const rtcc_field* 
 
 /* nsteps RK4 steps of size h from t0. If mu_dev (DEVICE, (nsteps+1)*6 doubles) is not NULL,
  * the complex dipole (Re x, Im x, Re y, Im y, Re z, Im z) at t0 and after every step is
- * written to it. Asynchronous. */
+ * written to it. Asynchronous. One step (its four right-hand sides, stage updates and dipole,
+ * with the field evaluated on the device) is captured once as a HIP graph and replayed for every
+ * step; the graph is rebuilt when y, h, the field or the precision change. Setting the environment
+ * variable RTCC_NO_GRAPH=1 before rtcc_init selects plain launches. */
 int rtcc_propagate_rk4(rtcc_ctx* ctx, void* y, double t0, double h, int nsteps, const rtcc_field* field,
                        double* mu_dev);
 
@@ -126,7 +129,9 @@ int rtcc_check_state(rtcc_ctx* ctx, const void* y, int64_t* nonfinite);
 
 /* Live timing of the dominant kernel, the particle-particle ladder GEMM. rtcc_profile(ctx, 1)
  * resets the statistics and brackets every subsequent ladder launch with HIP events recorded on
- * the context stream; rtcc_profile(ctx, 0) stops. rtcc_profile_read synchronises and returns the
+ * the context stream; rtcc_profile(ctx, 0) stops. While profiling is on, rtcc_propagate_rk4 issues
+ * its kernels one by one instead of replaying the captured step graph (events recorded inside a
+ * captured graph cannot be timed). rtcc_profile_read synchronises and returns the
  * number of timed launches, their summed duration in ms and the algorithmic real flops of one
  * launch (4 * rows * v^2 * v^2 for rows = 2 o^2 complex rows times the real <ab|ef> matrix). */
 int rtcc_profile(rtcc_ctx* ctx, int enable);

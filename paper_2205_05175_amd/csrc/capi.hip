@@ -1,6 +1,7 @@
 // C ABI: context lifetime, right-hand side, RK4 / Cash-Karp stepping, delta kick, dipole and
 // ground state. See include/rtcc.h for the contract of every entry point.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -72,6 +73,25 @@ struct rtcc_ctx {
   int ev_used = 0;
   int64_t prof_launches = 0;
   double prof_ms = 0.0, prof_flops = 0.0;
+  // streams: all work runs on `stream` (owned), ordered with the caller's `ustream` by events
+  hipStream_t ustream = nullptr;
+  hipEvent_t e_in = nullptr, e_out = nullptr;
+  double* tdev = nullptr;     // start time of the current step (device)
+  double* mu_slot = nullptr;  // dipole written by a captured step
+  // captured RK4 step
+  bool use_graph = true, capturing = false;
+  hipGraphExec_t gexec = nullptr;
+  struct Key {
+    const void* y;
+    double h;
+    int prec, dip, prof, kind;
+    double E0, omega, sigma, t0, n[3];
+    bool operator==(const Key& o) const {
+      return y == o.y && h == o.h && prec == o.prec && dip == o.dip && prof == o.prof && kind == o.kind &&
+             E0 == o.E0 && omega == o.omega && sigma == o.sigma && t0 == o.t0 && n[0] == o.n[0] &&
+             n[1] == o.n[1] && n[2] == o.n[2];
+    }
+  } gkey{};
 };
 
 namespace {
@@ -83,7 +103,15 @@ __global__ void add_mu_ref(double* mu6, const double* ref) {
 template <typename F>
 int guarded(rtcc_ctx* c, F&& f) {
   try {
+    if (c && c->e_in) {
+      RTCC_HIP(hipEventRecord(c->e_in, c->ustream));
+      RTCC_HIP(hipStreamWaitEvent(c->stream, c->e_in, 0));
+    }
     f();
+    if (c && c->e_out) {
+      RTCC_HIP(hipEventRecord(c->e_out, c->stream));
+      RTCC_HIP(hipStreamWaitEvent(c->ustream, c->e_out, 0));
+    }
     return RTCC_OK;
   } catch (const Error& e) {
     if (c) c->err = e.what();
@@ -94,14 +122,6 @@ int guarded(rtcc_ctx* c, F&& f) {
     else g_init_error = e.what();
     return RTCC_EHIP;
   }
-}
-
-void field_at(const rtcc_field* f, double t, double E[3]) {
-  E[0] = E[1] = E[2] = 0.0;
-  if (!f || f->kind != 1) return;
-  double env = std::exp(-0.5 * (t - f->t0) * (t - f->t0) / (f->sigma * f->sigma));
-  double a = -f->E0 * env * std::cos(f->omega * (t - f->t0));
-  for (int i = 0; i < 3; ++i) E[i] = a * f->n[i];
 }
 
 template <typename T>
@@ -162,6 +182,33 @@ void prof_mark(void* user, int phase) {
   if (phase == 1) c->prof_launches++;
 }
 
+FieldDev to_dev(const rtcc_field* f) {
+  FieldDev d{};
+  if (f) {
+    d.kind = f->kind;
+    d.E0 = f->E0;
+    d.omega = f->omega;
+    d.sigma = f->sigma;
+    d.t0 = f->t0;
+    for (int i = 0; i < 3; ++i) d.n[i] = f->n[i];
+  }
+  return d;
+}
+
+// out = F(y) at t = *tdev + toff, field evaluated on the device
+template <typename T>
+void eval_rhs_t(rtcc_ctx* c, Ints<T>& I, Work<T>& w, const void* y, const FieldDev& fd, double toff, void* out) {
+  field_fock_t<T>(c->stream, c->n, c->f0, c->mu, fd, c->tdev, toff, w.f.re);
+  unpack_state<T>(c->stream, y, c->o, c->v, planes(w, true));
+  residuals<T>(c->E, I, w, true, true);
+  pack_rhs<T>(c->stream, c->o, c->v, planes(w, false), out, 1.0);
+}
+
+void rhs_t(rtcc_ctx* c, const void* y, const FieldDev& fd, double toff, void* out) {
+  if (c->precision == RTCC_FP32) eval_rhs_t<float>(c, c->I32, c->W32, y, fd, toff, out);
+  else eval_rhs_t<double>(c, c->I64, c->W64, y, fd, toff, out);
+}
+
 void rhs_any(rtcc_ctx* c, const void* y, const double E[3], void* out, double scale) {
   if (c->precision == RTCC_FP32) eval_rhs<float>(c, c->I32, c->W32, y, E, 1.0, true, out, scale);
   else eval_rhs<double>(c, c->I64, c->W64, y, E, 1.0, true, out, scale);
@@ -178,7 +225,8 @@ void dipole_dev(rtcc_ctx* c, const void* y, double* out6) {
   RTCC_HIP(hipGetLastError());
 }
 
-void rk4_step(rtcc_ctx* c, void* y, double t, double h, const rtcc_field* field) {
+// One RK4 step from t = *tdev; advances *tdev by h; optionally the dipole of the new state.
+void rk4_step(rtcc_ctx* c, void* y, double h, const FieldDev& fd, double* dip) {
   for (int s = 0; s < 4; ++s) {
     const void* ys = y;
     if (s > 0) {
@@ -187,13 +235,52 @@ void rk4_step(rtcc_ctx* c, void* y, double t, double h, const rtcc_field* field)
       state_combo(c->stream, c->nstate, y, s, ks, cs, c->ytmp);
       ys = c->ytmp;
     }
-    double E[3];
-    field_at(field, t + kRk4C[s] * h, E);
-    rhs_any(c, ys, E, c->k[s], 1.0);
+    rhs_t(c, ys, fd, kRk4C[s] * h, c->k[s]);
   }
   const void* ks[4] = {c->k[0], c->k[1], c->k[2], c->k[3]};
   double cs[4] = {h * kRk4B[0], h * kRk4B[1], h * kRk4B[2], h * kRk4B[3]};
   state_combo(c->stream, c->nstate, y, 4, ks, cs, y);
+  if (dip) dipole_dev(c, y, dip);
+  scalar_update(c->stream, c->tdev, h, true);
+}
+
+// Capture one RK4 step (with its dipole) as a graph; replayed while the key is unchanged.
+void capture_step(rtcc_ctx* c, void* y, double h, const rtcc_field* field, bool dip) {
+  rtcc_ctx::Key key{};
+  key.y = y;
+  key.h = h;
+  key.prec = c->precision;
+  key.dip = dip;
+  key.prof = c->prof;
+  FieldDev fd = to_dev(field);
+  key.kind = fd.kind;
+  key.E0 = fd.E0;
+  key.omega = fd.omega;
+  key.sigma = fd.sigma;
+  key.t0 = fd.t0;
+  for (int i = 0; i < 3; ++i) key.n[i] = fd.n[i];
+  if (c->gexec && key == c->gkey) return;
+  if (c->gexec) {
+    RTCC_HIP(hipGraphExecDestroy(c->gexec));
+    c->gexec = nullptr;
+  }
+  RTCC_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+  c->capturing = true;
+  hipGraph_t g = nullptr;
+  try {
+    rk4_step(c, y, h, fd, dip ? c->mu_slot : nullptr);
+  } catch (...) {
+    c->capturing = false;
+    (void)hipStreamEndCapture(c->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  c->capturing = false;
+  RTCC_HIP(hipStreamEndCapture(c->stream, &g));
+  hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  RTCC_HIP(e);
+  c->gkey = key;
 }
 
 void sync_read(rtcc_ctx* c, const double* dev, double* host, int n) {
@@ -250,8 +337,15 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     c->n1 = (int64_t)o * v;
     c->n2 = c->n1 * c->n1;
     c->nstate = 2 * (c->n1 + c->n2);
-    c->stream = (hipStream_t)hip_stream;
+    c->ustream = (hipStream_t)hip_stream;
+    RTCC_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    RTCC_HIP(hipEventCreateWithFlags(&c->e_in, hipEventDisableTiming));
+    RTCC_HIP(hipEventCreateWithFlags(&c->e_out, hipEventDisableTiming));
     c->E.stream = c->stream;
+    const char* ng = std::getenv("RTCC_NO_GRAPH");
+    c->use_graph = !(ng && ng[0] == '1');
+    const char* tr = std::getenv("RTCC_TRACE");
+    c->E.trace = tr && tr[0] == '1';
     const int64_t n = c->n, nn = n * n, n4 = nn * nn;
     for (int64_t i = 0; i < nn; ++i)
       RTCC_CHECK(std::isfinite(fock[i]) && std::isfinite(dipole[i]) && std::isfinite(dipole[nn + i]) &&
@@ -287,12 +381,19 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     c->ytmp = c->arena.alloc<double>(2 * c->nstate);
     c->y4 = c->arena.alloc<double>(2 * c->nstate);
     c->y5 = c->arena.alloc<double>(2 * c->nstate);
+    c->tdev = c->arena.alloc<double>(1);
+    c->mu_slot = c->arena.alloc<double>(6);
     c->red = c->arena.alloc<double>(2 * 1024);
     c->redout = c->arena.alloc<double>(64);
     RTCC_HIP(hipHostMalloc((void**)&c->host_pinned, 64 * sizeof(double), hipHostMallocDefault));
     RTCC_HIP(hipStreamSynchronize(c->stream));
   });
-  if (st != RTCC_OK) return st;
+  if (st != RTCC_OK) {
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->e_in) (void)hipEventDestroy(c->e_in);
+    if (c->e_out) (void)hipEventDestroy(c->e_out);
+    return st;
+  }
   *out = c.release();
   return RTCC_OK;
 }
@@ -327,7 +428,10 @@ int rtcc_step_rk4(rtcc_ctx* c, void* y, double t, double h, const rtcc_field* fi
     c->err = "rtcc_step_rk4: invalid arguments";
     return RTCC_EINVAL;
   }
-  return guarded(c, [&] { rk4_step(c, y, t, h, field); });
+  return guarded(c, [&] {
+    scalar_update(c->stream, c->tdev, t, false);
+    rk4_step(c, y, h, to_dev(field), nullptr);
+  });
 }
 
 int rtcc_propagate_rk4(rtcc_ctx* c, void* y, double t0, double h, int nsteps, const rtcc_field* field,
@@ -338,10 +442,21 @@ int rtcc_propagate_rk4(rtcc_ctx* c, void* y, double t0, double h, int nsteps, co
     return RTCC_EINVAL;
   }
   return guarded(c, [&] {
+    scalar_update(c->stream, c->tdev, t0, false);
     if (mu_dev) dipole_dev(c, y, mu_dev);
+    const FieldDev fd = to_dev(field);
+    // HIP cannot time events recorded inside a captured graph: profiling runs the eager launches
+    const bool graph = c->use_graph && !c->prof;
     for (int s = 0; s < nsteps; ++s) {
-      rk4_step(c, y, t0 + s * h, h, field);
-      if (mu_dev) dipole_dev(c, y, mu_dev + 6 * (int64_t)(s + 1));
+      if (graph) {
+        capture_step(c, y, h, field, mu_dev != nullptr);
+        RTCC_HIP(hipGraphLaunch(c->gexec, c->stream));
+        if (mu_dev)
+          RTCC_HIP(hipMemcpyAsync(mu_dev + 6 * (int64_t)(s + 1), c->mu_slot, 6 * sizeof(double),
+                                  hipMemcpyDeviceToDevice, c->stream));
+      } else {
+        rk4_step(c, y, h, fd, mu_dev ? mu_dev + 6 * (int64_t)(s + 1) : nullptr);
+      }
     }
   });
 }
@@ -355,6 +470,8 @@ int rtcc_step_cashkarp(rtcc_ctx* c, void* y, double* t, double* h, double eps, c
   }
   return guarded(c, [&] {
     const double hh = *h;
+    const FieldDev fd = to_dev(field);
+    scalar_update(c->stream, c->tdev, *t, false);
     for (int s = 0; s < 6; ++s) {
       const void* ys = y;
       if (s > 0) {
@@ -364,9 +481,7 @@ int rtcc_step_cashkarp(rtcc_ctx* c, void* y, double* t, double* h, double eps, c
         state_combo(c->stream, c->nstate, y, s, ks, cs, c->ytmp);
         ys = c->ytmp;
       }
-      double E[3];
-      field_at(field, *t + kCkC[s] * hh, E);
-      rhs_any(c, ys, E, c->k[s], 1.0);
+      rhs_t(c, ys, fd, kCkC[s] * hh, c->k[s]);
     }
     const void* ks[6] = {c->k[0], c->k[1], c->k[2], c->k[3], c->k[4], c->k[5]};
     double c5[6], c4[6];
@@ -590,8 +705,13 @@ void rtcc_destroy(rtcc_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (auto e : c->ev) (void)hipEventDestroy(e);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->e_in) (void)hipEventDestroy(c->e_in);
+  if (c->e_out) (void)hipEventDestroy(c->e_out);
   if (c->host_pinned) (void)hipHostFree(c->host_pinned);
-  delete c;
+  hipStream_t st = c->stream;
+  delete c;  // frees device memory first
+  if (st) (void)hipStreamDestroy(st);
 }
 
 const char* rtcc_last_error(const rtcc_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }

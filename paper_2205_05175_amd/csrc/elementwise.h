@@ -15,6 +15,14 @@ template <typename T>
 void pack_rhs(hipStream_t st, int o, int v, Planes4<T> P, void* out, double scale);
 template <typename T>
 void field_fock(hipStream_t st, int n, const double* f0, const double* mu, const double E[3], double s0, T* f);
+struct FieldDev {
+  int kind;
+  double E0, omega, sigma, t0, n[3];
+};
+template <typename T>
+void field_fock_t(hipStream_t st, int n, const double* f0, const double* mu, const FieldDev& fd, const double* tdev,
+                  double toff, T* f);
+void scalar_update(hipStream_t st, double* p, double v, bool add);
 void state_combo(hipStream_t st, int64_t n, const void* y, int nk, const void* const* ks, const double* cs, void* out);
 template <typename T>
 void dot_planar_real(hipStream_t st, int64_t n, const T* are, const T* aim, const double* b, double* partial,

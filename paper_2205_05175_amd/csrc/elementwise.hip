@@ -146,6 +146,40 @@ void field_fock(hipStream_t st, int n, const double* f0, const double* mu, const
 template void field_fock<double>(hipStream_t, int, const double*, const double*, const double*, double, double*);
 template void field_fock<float>(hipStream_t, int, const double*, const double*, const double*, double, float*);
 
+// Field evaluated on the device at t = *tdev + toff (Eq. field; kinds other than the Gaussian
+// pulse give zero), so a captured step can be replayed at successive times.
+template <typename T>
+__global__ void fock_time_kernel(int64_t nn, const double* f0, const double* mu, FieldDev fd, const double* tdev,
+                                 double toff, T* f) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  double a = 0.0;
+  if (fd.kind == 1) {
+    double x = tdev[0] + toff - fd.t0;
+    a = -fd.E0 * exp(-0.5 * x * x / (fd.sigma * fd.sigma)) * cos(fd.omega * x);
+  }
+  f[i] = (T)(f0[i] - a * (fd.n[0] * mu[i] + fd.n[1] * mu[nn + i] + fd.n[2] * mu[2 * nn + i]));
+}
+
+template <typename T>
+void field_fock_t(hipStream_t st, int n, const double* f0, const double* mu, const FieldDev& fd, const double* tdev,
+                  double toff, T* f) {
+  int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(fock_time_kernel<T>, dim3((unsigned)cdiv(nn, 256)), dim3(256), 0, st, nn, f0, mu, fd, tdev,
+                     toff, f);
+  RTCC_HIP(hipGetLastError());
+}
+template void field_fock_t<double>(hipStream_t, int, const double*, const double*, const FieldDev&, const double*,
+                                   double, double*);
+template void field_fock_t<float>(hipStream_t, int, const double*, const double*, const FieldDev&, const double*,
+                                  double, float*);
+
+__global__ void scalar_kernel(double* p, double v, int add) { p[0] = add ? p[0] + v : v; }
+void scalar_update(hipStream_t st, double* p, double v, bool add) {
+  hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(1), 0, st, p, v, add ? 1 : 0);
+  RTCC_HIP(hipGetLastError());
+}
+
 // ---- RK combinations on the FP64 state ----------------------------------------------------------
 struct Combo {
   const double2* k[8];

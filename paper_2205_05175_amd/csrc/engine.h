@@ -70,6 +70,7 @@ struct Engine {
   void (*mark)(void*, int) = nullptr;
   void* mark_user = nullptr;
   double ladder_flops = 0.0;  // algorithmic real flops of the last ladder GEMM
+  bool trace = false;         // print every contraction's layout decisions to stderr
 };
 
 // C = alpha * contraction(A, B) + beta * C   (beta 0 or 1)

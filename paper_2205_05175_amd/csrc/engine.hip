@@ -1,5 +1,6 @@
 // Two-operand contraction engine: einsum specs mapped onto the MFMA GEMM.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <string>
 
@@ -173,6 +174,13 @@ void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A, const Te
   for (char c : bn) N *= dim_of(C, sp.c, c);
   for (char c : bk) K *= dim_of(A, sp.a, c);
 
+  if (E.trace) {
+    GemmOp<T> xa, xb, xc;
+    bool pa = !view2d(A, sp.a, bm, bk, &xa), pb = !view2d(B, sp.b, bk, bn, &xb), pc = !view2d(C, sp.c, bm, bn, &xc);
+    fprintf(stderr, "[rtcc] ein %-22s M=%lld N=%lld K=%lld permute:%s%s%s (A %lld, B %lld, C %lld elems)\n", specstr,
+            (long long)M, (long long)N, (long long)K, pa ? " A" : "", pb ? " B" : "", pc ? " C" : "",
+            (long long)A.size(), (long long)B.size(), (long long)C.size());
+  }
   size_t mark = E.scratch.used;
   GemmOp<T> oa, ob, oc;
   Ten<T> Ap = A, Bp = B;

@@ -8,6 +8,8 @@
 // (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32). Skinny products with long K are split
 // over K into per-split partial planes and reduced by a second kernel in a fixed order, so
 // results are bitwise repeatable.
+#include <cstdint>
+
 #include "engine.h"
 
 namespace rtcc {
@@ -55,12 +57,71 @@ struct GemmParams {
 constexpr int kBK = 16;
 constexpr int kThreads = 256;
 
-template <typename T, int BM, int BN, int AC, int BC>
+// Register-staged load of one operand tile of ROWS x COLS elements whose COLS index is contiguous
+// in memory (row stride ld). VEC consecutive elements are fetched per load when the whole vector
+// is in range and the operand is VEC-aligned; out-of-range elements read as zero.
+template <typename T, int ROWS, int COLS, int VEC, int NPL>
+struct TileRegs {
+  static constexpr int NV = ROWS * COLS / VEC / kThreads;
+  static_assert(NV >= 1 && NV * VEC * kThreads == ROWS * COLS, "tile not divisible among threads");
+  T r[NPL][NV][VEC];
+
+  __device__ inline void load(const T* const* base, int64_t ld, int row0, int col0, int rowLim, int colLim,
+                              int tid) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int idx = v * kThreads + tid;
+      const int row = idx / (COLS / VEC), colv = (idx % (COLS / VEC)) * VEC;
+      const int gr = row0 + row, gc = col0 + colv;
+      const int64_t off = (int64_t)gr * ld + gc;
+      if (VEC > 1 && gr < rowLim && gc + VEC <= colLim) {
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) {
+          if constexpr (VEC == 4) {
+            typedef T v4t __attribute__((ext_vector_type(4)));
+            v4t x = *reinterpret_cast<const v4t*>(base[pl] + off);
+            r[pl][v][0] = x[0]; r[pl][v][1] = x[1]; r[pl][v][2] = x[2]; r[pl][v][3] = x[3];
+          } else if constexpr (VEC == 2) {
+            typedef T v2t __attribute__((ext_vector_type(2)));
+            v2t x = *reinterpret_cast<const v2t*>(base[pl] + off);
+            r[pl][v][0] = x[0]; r[pl][v][1] = x[1];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const bool ok = gr < rowLim && gc + e < colLim;
+#pragma unroll
+          for (int pl = 0; pl < NPL; ++pl) r[pl][v][e] = ok ? base[pl][off + e] : T(0);
+        }
+      }
+    }
+  }
+  // store into an LDS tile S[k][x]; KMAJOR: the memory rows are k (contiguous x), else rows are x
+  template <bool ROWS_ARE_K, int LD>
+  __device__ inline void store(T* S, int plane_stride, int tid) const {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int idx = v * kThreads + tid;
+      const int row = idx / (COLS / VEC), colv = (idx % (COLS / VEC)) * VEC;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) {
+          if (ROWS_ARE_K) S[pl * plane_stride + row * LD + colv + e] = r[pl][v][e];
+          else S[pl * plane_stride + (colv + e) * LD + row] = r[pl][v][e];
+        }
+    }
+  }
+};
+
+// TA: A stored as [k][m] (else [m][k]); TB: B stored as [n][k] (else [k][n]).
+template <typename T, int BM, int BN, int AC, int BC, int TA, int TB, int VEC>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
   constexpr int NA = AC ? 2 : 1, NB = BC ? 2 : 1;
-  constexpr int PADA = 1, PADB = 1;
-  __shared__ T As[NA][kBK][BM + PADA];
-  __shared__ T Bs[NB][kBK][BN + PADB];
+  constexpr int LDA = BM + 1, LDB = BN + 1;  // padded LDS rows
+  __shared__ T As[NA * kBK * LDA];
+  __shared__ T Bs[NB * kBK * LDB];
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
   using V4 = typename Mfma<T>::v4;
 
@@ -78,74 +139,41 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
       accr[i][j] = V4{0, 0, 0, 0};
       acci[i][j] = V4{0, 0, 0, 0};
     }
-
   const T* Ap[2] = {p.Are, p.Aim};
   const T* Bp[2] = {p.Bre, p.Bim};
 
+  // A tile: TA ? (rows k, cols m) : (rows m, cols k);  B tile: TB ? (rows n, cols k) : (rows k, cols n)
+  TileRegs<T, TA ? kBK : BM, TA ? BM : kBK, VEC, NA> ra;
+  TileRegs<T, TB ? BN : kBK, TB ? kBK : BN, VEC, NB> rb;
+  auto fetch = [&](int k0) {
+    if (TA) ra.load(Ap, p.lda, k0, m0, kend, p.M, tid);
+    else ra.load(Ap, p.lda, m0, k0, p.M, kend, tid);
+    if (TB) rb.load(Bp, p.ldb, n0, k0, p.N, kend, tid);
+    else rb.load(Bp, p.ldb, k0, n0, kend, p.N, tid);
+  };
+  if (kbeg < kend) fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += kBK) {
-    // ---- stage A(m0:m0+BM, k0:k0+BK) into As[pl][k][m]
-    if (!p.ta) {
-#pragma unroll
-      for (int it = 0; it < BM * kBK / kThreads; ++it) {
-        int idx = it * kThreads + tid;
-        int k = idx % kBK, m = idx / kBK;
-        int gm = m0 + m, gk = k0 + k;
-        bool ok = gm < p.M && gk < kend;
-        int64_t off = (int64_t)gm * p.lda + gk;
-#pragma unroll
-        for (int pl = 0; pl < NA; ++pl) As[pl][k][m] = ok ? Ap[pl][off] : T(0);
-      }
-    } else {
-#pragma unroll
-      for (int it = 0; it < BM * kBK / kThreads; ++it) {
-        int idx = it * kThreads + tid;
-        int m = idx % BM, k = idx / BM;
-        int gm = m0 + m, gk = k0 + k;
-        bool ok = gm < p.M && gk < kend;
-        int64_t off = (int64_t)gk * p.lda + gm;
-#pragma unroll
-        for (int pl = 0; pl < NA; ++pl) As[pl][k][m] = ok ? Ap[pl][off] : T(0);
-      }
-    }
-    // ---- stage B(k0:k0+BK, n0:n0+BN) into Bs[pl][k][n]
-    if (!p.tb) {
-#pragma unroll
-      for (int it = 0; it < BN * kBK / kThreads; ++it) {
-        int idx = it * kThreads + tid;
-        int n = idx % BN, k = idx / BN;
-        int gn = n0 + n, gk = k0 + k;
-        bool ok = gn < p.N && gk < kend;
-        int64_t off = (int64_t)gk * p.ldb + gn;
-#pragma unroll
-        for (int pl = 0; pl < NB; ++pl) Bs[pl][k][n] = ok ? Bp[pl][off] : T(0);
-      }
-    } else {
-#pragma unroll
-      for (int it = 0; it < BN * kBK / kThreads; ++it) {
-        int idx = it * kThreads + tid;
-        int k = idx % kBK, n = idx / kBK;
-        int gn = n0 + n, gk = k0 + k;
-        bool ok = gn < p.N && gk < kend;
-        int64_t off = (int64_t)gn * p.ldb + gk;
-#pragma unroll
-        for (int pl = 0; pl < NB; ++pl) Bs[pl][k][n] = ok ? Bp[pl][off] : T(0);
-      }
-    }
+    ra.template store<TA != 0, LDA>(As, kBK * LDA, tid);
+    rb.template store<TB == 0, LDB>(Bs, kBK * LDB, tid);
     __syncthreads();
-
+    if (k0 + kBK < kend) fetch(k0 + kBK);  // next tile in flight while this one is multiplied
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 4) {
       const int kr = kk + (lane >> 4), col = lane & 15;
       T ar[FM], ai[FM], br[FN], bi[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        ar[i] = As[0][kr][wm * WM + i * 16 + col];
-        if (AC) ai[i] = As[NA - 1][kr][wm * WM + i * 16 + col];
+        ar[i] = As[kr * LDA + wm * WM + i * 16 + col];
+        if (AC) ai[i] = As[kBK * LDA + kr * LDA + wm * WM + i * 16 + col];
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        br[j] = Bs[0][kr][wn * WN + j * 16 + col];
-        if (BC) bi[j] = Bs[NB - 1][kr][wn * WN + j * 16 + col];
+        br[j] = Bs[kr * LDB + wn * WN + j * 16 + col];
+        if (BC) bi[j] = Bs[kBK * LDB + kr * LDB + wn * WN + j * 16 + col];
+      }
+      if (AC && BC) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i) ai[i] = -ai[i];
       }
 #pragma unroll
       for (int i = 0; i < FM; ++i)
@@ -153,9 +181,9 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
         for (int j = 0; j < FN; ++j) {
           if (AC && BC) {
             accr[i][j] = Mfma<T>::mma(ar[i], br[j], accr[i][j]);
-            accr[i][j] = Mfma<T>::mma(-ai[i], bi[j], accr[i][j]);
+            accr[i][j] = Mfma<T>::mma(ai[i], bi[j], accr[i][j]);  // ai holds -Im(A)
             acci[i][j] = Mfma<T>::mma(ar[i], bi[j], acci[i][j]);
-            acci[i][j] = Mfma<T>::mma(ai[i], br[j], acci[i][j]);
+            acci[i][j] = Mfma<T>::mma(-ai[i], br[j], acci[i][j]);
           } else if (AC) {
             accr[i][j] = Mfma<T>::mma(ar[i], br[j], accr[i][j]);
             acci[i][j] = Mfma<T>::mma(ai[i], br[j], acci[i][j]);
@@ -200,34 +228,83 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
       }
 }
 
-// Sum the split-K partial planes in a fixed order and apply alpha/beta.
+// Sum the split-K partial planes and apply alpha/beta. A block handles 16 outputs with 16
+// lanes each; lane l sums the splits l, l+16, ... and the 16 lane sums are added in lane order,
+// so the result does not depend on scheduling.
 template <typename T>
-__global__ void splitk_reduce(const T* Pre, const T* Pim, int splits, int64_t stride, int M, int N, T* Cre,
-                              T* Cim, int64_t ldc, T alpha, T beta) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)M * N) return;
-  int row = (int)(idx / N), col = (int)(idx % N);
+__global__ __launch_bounds__(256) void splitk_reduce(const T* Pre, const T* Pim, int splits, int64_t stride, int M,
+                                                     int N, T* Cre, T* Cim, int64_t ldc, T alpha, T beta) {
+  __shared__ T shr[16][17], shi[16][17];
+  const int ol = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int64_t idx = (int64_t)blockIdx.x * 16 + ol;
+  const bool ok = idx < (int64_t)M * N;
   T sr = 0, si = 0;
-  for (int s = 0; s < splits; ++s) {
-    sr += Pre[s * stride + idx];
-    if (Pim) si += Pim[s * stride + idx];
+  if (ok)
+    for (int s = sl; s < splits; s += 16) {
+      sr += Pre[s * stride + idx];
+      if (Pim) si += Pim[s * stride + idx];
+    }
+  shr[sl][ol] = sr;
+  shi[sl][ol] = si;
+  __syncthreads();
+  if (sl == 0 && ok) {
+    T ar = 0, ai = 0;
+    for (int k = 0; k < 16; ++k) {
+      ar += shr[k][ol];
+      ai += shi[k][ol];
+    }
+    int row = (int)(idx / N), col = (int)(idx % N);
+    int64_t off = (int64_t)row * ldc + col;
+    T outr = alpha * ar, outi = alpha * ai;
+    if (beta != T(0)) {
+      outr += beta * Cre[off];
+      if (Cim) outi += beta * Cim[off];
+    }
+    Cre[off] = outr;
+    if (Cim && Pim) Cim[off] = outi;
   }
-  int64_t off = (int64_t)row * ldc + col;
-  T outr = alpha * sr, outi = alpha * si;
-  if (beta != T(0)) {
-    outr += beta * Cre[off];
-    if (Cim) outi += beta * Cim[off];
-  }
-  Cre[off] = outr;
-  if (Cim && Pim) Cim[off] = outi;
+}
+
+template <typename T, int BM, int BN, int AC, int BC, int TA, int TB, int VEC>
+static void launch_one(hipStream_t st, const GemmParams<T>& p, int splits) {
+  dim3 grid((unsigned)cdiv(p.N, BN), (unsigned)cdiv(p.M, BM), (unsigned)splits);
+  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, AC, BC, TA, TB, VEC>), grid, dim3(kThreads), 0, st, p);
+  RTCC_HIP(hipGetLastError());
 }
 
 template <typename T, int BM, int BN, int AC, int BC>
-static void launch_gemm(hipStream_t st, const GemmParams<T>& p, int splits) {
-  dim3 grid((unsigned)cdiv(p.N, BN), (unsigned)cdiv(p.M, BM), (unsigned)splits);
-  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, AC, BC>), grid, dim3(kThreads), 0, st, p);
-  RTCC_HIP(hipGetLastError());
+static void launch_gemm(hipStream_t st, const GemmParams<T>& p, int splits, bool vec) {
+  constexpr int V = 16 / sizeof(T);
+  const int sel = (p.ta ? 2 : 0) + (p.tb ? 1 : 0);
+  if (vec) {
+    switch (sel) {
+      case 0: launch_one<T, BM, BN, AC, BC, 0, 0, V>(st, p, splits); break;
+      case 1: launch_one<T, BM, BN, AC, BC, 0, 1, V>(st, p, splits); break;
+      case 2: launch_one<T, BM, BN, AC, BC, 1, 0, V>(st, p, splits); break;
+      default: launch_one<T, BM, BN, AC, BC, 1, 1, V>(st, p, splits); break;
+    }
+  } else {
+    switch (sel) {
+      case 0: launch_one<T, BM, BN, AC, BC, 0, 0, 1>(st, p, splits); break;
+      case 1: launch_one<T, BM, BN, AC, BC, 0, 1, 1>(st, p, splits); break;
+      case 2: launch_one<T, BM, BN, AC, BC, 1, 0, 1>(st, p, splits); break;
+      default: launch_one<T, BM, BN, AC, BC, 1, 1, 1>(st, p, splits); break;
+    }
+  }
 }
+
+template <typename T, int BM, int BN>
+static void launch_typed(hipStream_t st, const GemmParams<T>& p, int splits, bool vec) {
+  const int sel = (p.Aim ? 2 : 0) + (p.Bim ? 1 : 0);
+  switch (sel) {
+    case 0: launch_gemm<T, BM, BN, 0, 0>(st, p, splits, vec); break;
+    case 1: launch_gemm<T, BM, BN, 0, 1>(st, p, splits, vec); break;
+    case 2: launch_gemm<T, BM, BN, 1, 0>(st, p, splits, vec); break;
+    default: launch_gemm<T, BM, BN, 1, 1>(st, p, splits, vec); break;
+  }
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 template <typename T>
 void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A, GemmOp<T> B, T* Cre, T* Cim,
@@ -261,12 +338,20 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
   p.K = (int)K;
   p.alpha = (T)alpha;
   p.beta = (T)beta;
-  constexpr int BM = 64, BN = 64;
+  // 16-byte vector loads need every plane pointer and leading dimension VEC-aligned
+  constexpr int V = 16 / sizeof(T);
+  const bool vec = aligned16(A.re) && (!AC || aligned16(A.im)) && aligned16(B.re) && (!BC || aligned16(B.im)) &&
+                   A.ld % V == 0 && B.ld % V == 0;
+  // large products: big tiles; small ones: 64 x 64 tiles split over K toward ~512 workgroups
+  constexpr int LBM = 128, LBN = sizeof(T) == 8 ? 64 : 128;
+  const bool large = cdiv(M, LBM) * cdiv(N, LBN) >= 192;
+  const int BM = large ? LBM : 64, BN = large ? LBN : 64;
   const int64_t tiles = cdiv(M, BM) * cdiv(N, BN);
+  // fewer than ~2 workgroups per CU: split K (chunks of >= 256) toward ~1024 workgroups
   int splits = 1;
-  if (tiles < 512 && K >= 8 * kBK) {
+  if (!large && tiles < 512 && K >= 512) {
     int64_t want = std::max<int64_t>(1, 1024 / tiles);
-    splits = (int)std::min<int64_t>(want, cdiv(K, 4 * kBK));
+    splits = (int)std::min<int64_t>({want, cdiv(K, 256), 1024});
   }
   int64_t kchunk = cdiv(cdiv(K, splits), kBK) * kBK;
   splits = (int)cdiv(K, kchunk);
@@ -287,21 +372,20 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
     p.Cim = Cim;
     p.ldc = ldc;
   }
-  const int sel = (AC ? 2 : 0) + (BC ? 1 : 0);
-  switch (sel) {
-    case 0: launch_gemm<T, BM, BN, 0, 0>(E.stream, p, splits); break;
-    case 1: launch_gemm<T, BM, BN, 0, 1>(E.stream, p, splits); break;
-    case 2: launch_gemm<T, BM, BN, 1, 0>(E.stream, p, splits); break;
-    default: launch_gemm<T, BM, BN, 1, 1>(E.stream, p, splits); break;
-  }
+  if (large) launch_typed<T, LBM, LBN>(E.stream, p, splits, vec);
+  else launch_typed<T, 64, 64>(E.stream, p, splits, vec);
   if (splits > 1) {
     int64_t n = M * N;
-    hipLaunchKernelGGL(splitk_reduce<T>, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, E.stream, Pre, Pim, splits,
+    hipLaunchKernelGGL(splitk_reduce<T>, dim3((unsigned)cdiv(n, 16)), dim3(256), 0, E.stream, Pre, Pim, splits,
                        M * N, (int)M, (int)N, Cre, Cim, ldc, (T)alpha, (T)beta);
     RTCC_HIP(hipGetLastError());
   }
   E.scratch.reset(mark);
   E.gemm_flops += 2 * M * N * K * ((AC && BC) ? 4 : (AC || BC) ? 2 : 1);
+  if (E.trace)
+    fprintf(stderr, "[rtcc] gemm M=%lld N=%lld K=%lld %s%s ta=%d tb=%d tile=%dx%d splits=%d vec=%d\n",
+            (long long)M, (long long)N, (long long)K, AC ? "c" : "r", BC ? "c" : "r", A.trans, B.trans, BM, BN,
+            splits, (int)vec);
 }
 
 template void gemm<double>(Engine&, int64_t, int64_t, int64_t, double, GemmOp<double>, GemmOp<double>, double*,
