@@ -47,8 +47,15 @@ extern "C" {
 typedef struct rtcc_ctx rtcc_ctx;
 
 /* Contraction precision. The RK state, the stage updates, the dipole and the
- * ground-state iterations are always FP64. */
-enum { RTCC_FP64 = 0, RTCC_FP32 = 1 };
+ * ground-state iterations are always FP64.
+ *   RTCC_FP64   : FP64 operands, v_mfma_f64_16x16x4f64.
+ *   RTCC_FP32   : complex FP32 operands, v_mfma_f32_16x16x4f32, FP32 accumulation.
+ *   RTCC_BF16X3 : FP32 operands; every complex product of more than 5e8 flops splits each
+ *                 element into two BF16 halves (hi = bf16(x), lo = bf16(x - hi)) and forms
+ *                 hi*hi + hi*lo + lo*hi with v_mfma_f32_16x16x32_bf16, FP32 accumulation;
+ *                 smaller products as RTCC_FP32 (the threshold can be overridden by the
+ *                 environment variable RTCC_BF16_MIN_FLOPS, read by rtcc_init). */
+enum { RTCC_FP64 = 0, RTCC_FP32 = 1, RTCC_BF16X3 = 2 };
 
 enum {
   RTCC_OK = 0,
@@ -74,7 +81,8 @@ typedef struct {
  *   eri      : HOST, n^4 doubles, chemists' order (pq|rs), row-major, real, 8-fold symmetric.
  *   fock     : HOST, n*n doubles, real symmetric Fock matrix (occupied orbitals first).
  *   dipole   : HOST, 3*n*n doubles, real symmetric dipole integrals (x, y, z).
- *   precision: RTCC_FP64 or RTCC_FP32 (contractions of rtcc_rhs and the steppers).
+ *   precision: RTCC_FP64, RTCC_FP32 or RTCC_BF16X3 (contractions of rtcc_rhs and the steppers);
+ *              a context created with RTCC_FP32 or RTCC_BF16X3 can switch among all three.
  *   hip_stream: hipStream_t to run on (NULL = default stream).
  * All host arrays are copied; the caller may free them on return. */
 int rtcc_init(rtcc_ctx** ctx, int o, int v, const double* eri, const double* fock, const double* dipole,

@@ -15,8 +15,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtcc.so")
 
-FP64, FP32 = 0, 1
-_PREC = {"fp64": FP64, "fp32": FP32}
+FP64, FP32, BF16X3 = 0, 1, 2
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 FIELD_NONE, FIELD_GAUSSIAN, FIELD_KICK = 0, 1, 2
 
 

@@ -205,13 +205,23 @@ void eval_rhs_t(rtcc_ctx* c, Ints<T>& I, Work<T>& w, const void* y, const FieldD
 }
 
 void rhs_t(rtcc_ctx* c, const void* y, const FieldDev& fd, double toff, void* out) {
-  if (c->precision == RTCC_FP32) eval_rhs_t<float>(c, c->I32, c->W32, y, fd, toff, out);
-  else eval_rhs_t<double>(c, c->I64, c->W64, y, fd, toff, out);
+  if (c->precision == RTCC_FP64) {
+    eval_rhs_t<double>(c, c->I64, c->W64, y, fd, toff, out);
+  } else {
+    c->E.bf16x3 = c->precision == RTCC_BF16X3;
+    eval_rhs_t<float>(c, c->I32, c->W32, y, fd, toff, out);
+    c->E.bf16x3 = false;
+  }
 }
 
 void rhs_any(rtcc_ctx* c, const void* y, const double E[3], void* out, double scale) {
-  if (c->precision == RTCC_FP32) eval_rhs<float>(c, c->I32, c->W32, y, E, 1.0, true, out, scale);
-  else eval_rhs<double>(c, c->I64, c->W64, y, E, 1.0, true, out, scale);
+  if (c->precision == RTCC_FP64) {
+    eval_rhs<double>(c, c->I64, c->W64, y, E, 1.0, true, out, scale);
+  } else {
+    c->E.bf16x3 = c->precision == RTCC_BF16X3;
+    eval_rhs<float>(c, c->I32, c->W32, y, E, 1.0, true, out, scale);
+    c->E.bf16x3 = false;
+  }
 }
 
 void dipole_dev(rtcc_ctx* c, const void* y, double* out6) {
@@ -324,7 +334,8 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     return RTCC_EINVAL;
   }
   *out = nullptr;
-  if (o < 1 || v < 1 || !eri || !fock || !dipole || (precision != RTCC_FP64 && precision != RTCC_FP32)) {
+  if (o < 1 || v < 1 || !eri || !fock || !dipole ||
+      (precision != RTCC_FP64 && precision != RTCC_FP32 && precision != RTCC_BF16X3)) {
     g_init_error = "rtcc_init: invalid arguments";
     return RTCC_EINVAL;
   }
@@ -342,6 +353,8 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     RTCC_HIP(hipEventCreateWithFlags(&c->e_in, hipEventDisableTiming));
     RTCC_HIP(hipEventCreateWithFlags(&c->e_out, hipEventDisableTiming));
     c->E.stream = c->stream;
+    const char* bm = std::getenv("RTCC_BF16_MIN_FLOPS");
+    if (bm && bm[0]) c->E.bf16_min_flops = std::atof(bm);
     const char* ng = std::getenv("RTCC_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');
     const char* tr = std::getenv("RTCC_TRACE");
@@ -375,7 +388,7 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     c->E.scratch.base = c->arena.alloc<char>(c->E.scratch.cap);
     build_ints<double>(c->E, c->arena, o, v, eri_dev, c->I64);
     build_work<double>(c->arena, o, v, c->W64);
-    if (precision == RTCC_FP32) ensure32(c.get(), eri_dev);
+    if (precision != RTCC_FP64) ensure32(c.get(), eri_dev);
     c->k.resize(6);
     for (auto& p : c->k) p = c->arena.alloc<double>(2 * c->nstate);
     c->ytmp = c->arena.alloc<double>(2 * c->nstate);
@@ -400,12 +413,13 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
 
 int rtcc_set_precision(rtcc_ctx* c, int precision) {
   if (!c) return RTCC_EINVAL;
-  if (precision != RTCC_FP64 && precision != RTCC_FP32) {
+  if (precision != RTCC_FP64 && precision != RTCC_FP32 && precision != RTCC_BF16X3) {
     c->err = "rtcc_set_precision: unknown precision";
     return RTCC_EINVAL;
   }
-  if (precision == RTCC_FP32 && !c->have32) {
-    c->err = "rtcc_set_precision: context was created without FP32 integrals; create it with RTCC_FP32";
+  if (precision != RTCC_FP64 && !c->have32) {
+    c->err = "rtcc_set_precision: context was created without FP32 integrals; create it with RTCC_FP32 or "
+             "RTCC_BF16X3";
     return RTCC_EINVAL;
   }
   c->precision = precision;

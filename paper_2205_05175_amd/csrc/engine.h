@@ -71,7 +71,10 @@ struct Engine {
   void* mark_user = nullptr;
   double ladder_flops = 0.0;  // algorithmic real flops of the last ladder GEMM
   bool trace = false;         // print every contraction's layout decisions to stderr
+  bool bf16x3 = false;        // FP32 GEMMs above bf16_min_flops use the split-BF16 three-term kernel
+  double bf16_min_flops = 5e8;
 };
+
 
 // C = alpha * contraction(A, B) + beta * C   (beta 0 or 1)
 template <typename T>
@@ -95,6 +98,9 @@ struct GemmOp {
 template <typename T>
 void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A, GemmOp<T> B, T* Cre, T* Cim,
           int64_t ldc, double beta);
+
+bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<float> A, GemmOp<float> B,
+                 float* Cre, float* Cim, int64_t ldc, double beta);
 
 // General strided permute-axpby on planar complex or real data (nd <= 6).
 template <typename T>

@@ -324,6 +324,11 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
     permute_axpby<T>(E.stream, 2, d, Cim, (T*)nullptr, s, Cim, (T*)nullptr, s, 0.0, beta);
     Cim = nullptr;
   }
+  if constexpr (sizeof(T) == 4) {
+    if (E.bf16x3 && 2.0 * (double)M * (double)N * (double)K >= E.bf16_min_flops &&
+        gemm_bf16x3(E, M, N, K, alpha, A, B, Cre, Cim, ldc, beta))
+      return;
+  }
   GemmParams<T> p;
   p.Are = A.re;
   p.Aim = A.im;

@@ -223,3 +223,64 @@ def test_gaussian_pulse_trajectory(precision, tol):
     err = np.abs(got - ref).max()
     print(f"gaussian trajectory {precision}: max |dmu| = {err:.3e}")
     assert err < tol
+    if precision == "fp32":
+        assert err < 1e-7  # the premise of the split-BF16 bound below
+
+
+def _ctx_env(eri, fock, mu, o, v, precision, **env):
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(x) for k, x in env.items()})
+    try:
+        return _ctx(eri, fock, mu, o, v, precision)
+    finally:
+        for k, x in old.items():
+            if x is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = x
+
+
+@pytest.mark.parametrize("o,v", [(2, 3), (5, 19), (6, 25)])
+def test_rhs_bf16x3_matches_oracle(o, v):
+    """Split-BF16 three-term products (forced onto every eligible GEMM): ~2^-16 relative per product."""
+    eri, fock, mu = _system(o, v, 1)
+    S = ccsd.SpinOrbitalSystem(eri, fock, mu, o, v)
+    st = random_state(o, v, 3, 0.05, 0.02)
+    E = np.array([0.003, -0.002, 0.01])
+    ref = pack_state(*ccsd.rhs(S, *st, E))
+    R = _ctx_env(eri, fock, mu, o, v, "bf16x3", RTCC_BF16_MIN_FLOPS=0)
+    out = R.rhs(_dev(pack_state(*st)), E).cpu().numpy()
+    err = np.abs(out - ref).max() / max(1.0, np.abs(ref).max())
+    print(f"bf16x3 rhs o={o} v={v}: max rel error {err:.3e}")
+    assert err < 3e-4
+    # and it is a different arithmetic from FP32 (the split kernel really ran)
+    R32 = _ctx(eri, fock, mu, o, v, "fp32")
+    out32 = R32.rhs(_dev(pack_state(*st)), E).cpu().numpy()
+    assert np.abs(out - out32).max() > 0
+
+
+def test_gaussian_pulse_trajectory_bf16x3():
+    """(5,19) Gaussian pulse, 1000 RK4 steps with the split forced onto EVERY complex product.
+
+    Bound: the three-term split represents each product to 2^-18 relative (vs 2^-24 for FP32),
+    i.e. 64x the FP32 per-product rounding. The FP32 trajectory of the same case stays below
+    1e-7 au, so 64x that, rounded up, gives 5e-6 au. (At production settings only products above
+    5e8 flop use the split, none at this size; the o=20, v=76 benchmark gates the split path on
+    <= 1e-6 au against FP64.)"""
+    torch = _torch()
+    g, ref = _golden("gaussian_o5v19")
+    c = g["case"]
+    o, v = c["o"], c["v"]
+    eri, fock, mu = make_system(o, v, c["seed"])
+    R = _ctx_env(eri, fock, mu, o, v, "bf16x3", RTCC_BF16_MIN_FLOPS=0)
+    y = R.new_state()
+    R.ground_state(y, 1e-12, 200)
+    from paper_2205_05175_amd import Field
+    p = c["pulse"]
+    fld = Field.gaussian(p["E0"], p["omega"], p["sigma"], p["t0"], c["n"])
+    mu_out = torch.zeros((c["steps"] + 1, 6), dtype=torch.float64, device="cuda")
+    R.propagate_rk4(y, 0.0, c["dt"], c["steps"], fld, mu_out)
+    m = mu_out.cpu().numpy()
+    err = np.abs((m[:, 0::2] + 1j * m[:, 1::2]) - ref).max()
+    print(f"gaussian trajectory bf16x3: max |dmu| = {err:.3e}")
+    assert err < 5e-6
