@@ -171,29 +171,34 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
         br[j] = Bs[kr * LDB + wn * WN + j * 16 + col];
         if (BC) bi[j] = Bs[kBK * LDB + kr * LDB + wn * WN + j * 16 + col];
       }
+      T nai[FM];
       if (AC && BC) {
 #pragma unroll
-        for (int i = 0; i < FM; ++i) ai[i] = -ai[i];
+        for (int i = 0; i < FM; ++i) nai[i] = -ai[i];
       }
+      // term-major issue: consecutive MFMAs update different accumulators
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          if (AC && BC) {
-            accr[i][j] = Mfma<T>::mma(ar[i], br[j], accr[i][j]);
-            accr[i][j] = Mfma<T>::mma(ai[i], bi[j], accr[i][j]);  // ai holds -Im(A)
-            acci[i][j] = Mfma<T>::mma(ar[i], bi[j], acci[i][j]);
-            acci[i][j] = Mfma<T>::mma(-ai[i], br[j], acci[i][j]);
-          } else if (AC) {
-            accr[i][j] = Mfma<T>::mma(ar[i], br[j], accr[i][j]);
-            acci[i][j] = Mfma<T>::mma(ai[i], br[j], acci[i][j]);
-          } else if (BC) {
-            accr[i][j] = Mfma<T>::mma(ar[i], br[j], accr[i][j]);
-            acci[i][j] = Mfma<T>::mma(ar[i], bi[j], acci[i][j]);
-          } else {
-            accr[i][j] = Mfma<T>::mma(ar[i], br[j], accr[i][j]);
-          }
-        }
+        for (int j = 0; j < FN; ++j) accr[i][j] = Mfma<T>::mma(ar[i], br[j], accr[i][j]);
+      if (BC) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acci[i][j] = Mfma<T>::mma(ar[i], bi[j], acci[i][j]);
+      }
+      if (AC) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acci[i][j] = Mfma<T>::mma(ai[i], br[j], acci[i][j]);
+      }
+      if (AC && BC) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) accr[i][j] = Mfma<T>::mma(nai[i], bi[j], accr[i][j]);
+      }
     }
     __syncthreads();
   }
@@ -347,9 +352,10 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
   constexpr int V = 16 / sizeof(T);
   const bool vec = aligned16(A.re) && (!AC || aligned16(A.im)) && aligned16(B.re) && (!BC || aligned16(B.im)) &&
                    A.ld % V == 0 && B.ld % V == 0;
-  // large products: big tiles; small ones: 64 x 64 tiles split over K toward ~512 workgroups
-  constexpr int LBM = 128, LBN = sizeof(T) == 8 ? 64 : 128;
-  const bool large = cdiv(M, LBM) * cdiv(N, LBN) >= 192;
+  // FP32: 128 x 128 tiles when the grid still holds >= 2 tiles per CU; FP64 (longer MFMA,
+  // more registers per tile): always 64 x 64 for occupancy. Small grids split over K.
+  constexpr int LBM = 128, LBN = 128;
+  const bool large = sizeof(T) == 4 && cdiv(M, LBM) * cdiv(N, LBN) >= 512;
   const int BM = large ? LBM : 64, BN = large ? LBN : 64;
   const int64_t tiles = cdiv(M, BM) * cdiv(N, BN);
   // fewer than ~2 workgroups per CU: split K (chunks of >= 256) toward ~1024 workgroups

@@ -80,22 +80,33 @@ struct Regs {
   // S[pl][h][x][k]; ROWS_ARE_K: memory rows are k (else memory rows are x)
   template <bool ROWS_ARE_K, int XDIM>
   __device__ inline void store(__bf16* S, int tid) const {
+    typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int idx = v * kThr + tid;
       const int row = idx / (COLS / 4), col = (idx % (COLS / 4)) * 4;
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int pl = 0; pl < NPL; ++pl) {
+        bf4 hi, lo;
 #pragma unroll
-        for (int pl = 0; pl < NPL; ++pl) {
+        for (int e = 0; e < 4; ++e) {
           const float x = r[pl][v][e];
-          const __bf16 hi = (__bf16)x;
-          const __bf16 lo = (__bf16)(x - (float)hi);
-          const int xi = ROWS_ARE_K ? col + e : row, ki = ROWS_ARE_K ? row : col + e;
-          __bf16* base = S + (size_t)pl * 2 * XDIM * kLDK;
-          base[xi * kLDK + ki] = hi;
-          base[XDIM * kLDK + xi * kLDK + ki] = lo;
+          hi[e] = (__bf16)x;
+          lo[e] = (__bf16)(x - (float)hi[e]);
         }
+        __bf16* base = S + (size_t)pl * 2 * XDIM * kLDK;
+        if (!ROWS_ARE_K) {
+          // four consecutive k of one row: one 8-byte store per half
+          *reinterpret_cast<bf4*>(&base[row * kLDK + col]) = hi;
+          *reinterpret_cast<bf4*>(&base[XDIM * kLDK + row * kLDK + col]) = lo;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            base[(col + e) * kLDK + row] = hi[e];
+            base[XDIM * kLDK + (col + e) * kLDK + row] = lo[e];
+          }
+        }
+      }
     }
   }
 };
@@ -135,8 +146,9 @@ __global__ __launch_bounds__(kThr) void gemm_bf16x3_kernel(Params p, int vec) {
     rb.template store<TB == 0, BN>(Bs, tid);
     __syncthreads();
     if (k0 + kBK < p.K) fetch(k0 + kBK);
-    // B fragments of this wave (hi, lo for each plane)
-    bf8 bfr[FN][NB][2];
+    // all fragments of this wave (hi, lo for each plane), then term-major MFMA issue so that
+    // consecutive MFMAs update different accumulators
+    bf8 bfr[FN][NB][2], afr[FM][NA][2];
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
@@ -146,36 +158,42 @@ __global__ __launch_bounds__(kThr) void gemm_bf16x3_kernel(Params p, int vec) {
           bfr[j][pl][h] = *reinterpret_cast<const bf8*>(
               &Bs[((pl * 2 + h) * BN + wn * WN + j * 16 + c16) * kLDK + 8 * g]);
 #pragma unroll
-    for (int i = 0; i < FM; ++i) {
-      bf8 afr[NA][2];
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int pl = 0; pl < NA; ++pl)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
-          afr[pl][h] = *reinterpret_cast<const bf8*>(
+          afr[i][pl][h] = *reinterpret_cast<const bf8*>(
               &As[((pl * 2 + h) * BM + wm * WM + i * 16 + c16) * kLDK + 8 * g]);
+    // (ha, hb): the three split products hi*hi, hi*lo, lo*hi
 #pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        // Re(C) += Re(A) Re(B) [- Im(A) Im(B)];  Im(C) += Re(A) Im(B) + Im(A) Re(B)
-        accr[i][j] = mma(afr[0][0], bfr[j][0][0], accr[i][j]);
-        accr[i][j] = mma(afr[0][0], bfr[j][0][1], accr[i][j]);
-        accr[i][j] = mma(afr[0][1], bfr[j][0][0], accr[i][j]);
-        if (AC && BC) {
-          const bf8 nh = neg(afr[NA - 1][0]), nl = neg(afr[NA - 1][1]);
-          accr[i][j] = mma(nh, bfr[j][NB - 1][0], accr[i][j]);
-          accr[i][j] = mma(nh, bfr[j][NB - 1][1], accr[i][j]);
-          accr[i][j] = mma(nl, bfr[j][NB - 1][0], accr[i][j]);
-        }
-        if (BC) {
-          acci[i][j] = mma(afr[0][0], bfr[j][NB - 1][0], acci[i][j]);
-          acci[i][j] = mma(afr[0][0], bfr[j][NB - 1][1], acci[i][j]);
-          acci[i][j] = mma(afr[0][1], bfr[j][NB - 1][0], acci[i][j]);
-        }
-        if (AC) {
-          acci[i][j] = mma(afr[NA - 1][0], bfr[j][0][0], acci[i][j]);
-          acci[i][j] = mma(afr[NA - 1][0], bfr[j][0][1], acci[i][j]);
-          acci[i][j] = mma(afr[NA - 1][1], bfr[j][0][0], acci[i][j]);
-        }
+    for (int t = 0; t < 3; ++t) {
+      const int ha = t == 2 ? 1 : 0, hb = t == 1 ? 1 : 0;
+      // Re(C) += Re(A) Re(B)
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) accr[i][j] = mma(afr[i][0][ha], bfr[j][0][hb], accr[i][j]);
+      // Im(C) += Re(A) Im(B)
+      if (BC) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acci[i][j] = mma(afr[i][0][ha], bfr[j][NB - 1][hb], acci[i][j]);
+      }
+      // Im(C) += Im(A) Re(B)
+      if (AC) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acci[i][j] = mma(afr[i][NA - 1][ha], bfr[j][0][hb], acci[i][j]);
+      }
+      // Re(C) -= Im(A) Im(B)
+      if (AC && BC) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) accr[i][j] = mma(neg(afr[i][NA - 1][ha]), bfr[j][NB - 1][hb], accr[i][j]);
       }
     }
     __syncthreads();
@@ -238,6 +256,9 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   Params p{A.re, A.im, A.ld, B.re, B.im, B.ld, Cre, Cim, ldc, (int)M, (int)N, (int)K, (float)alpha, (float)beta};
   auto al = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
   const int vec = al(A.re) && (!AC || al(A.im)) && al(B.re) && (!BC || al(B.im)) && A.ld % 4 == 0 && B.ld % 4 == 0;
+  // grids that cannot fill the chip go to the FP32 kernel, which can split over K (unless the
+  // split is forced onto every product by a zero threshold)
+  if (E.bf16_min_flops > 0 && cdiv(M, 64) * cdiv(N, 64) < 256) return false;
   // complex x complex products hold more fragments: narrower tiles
   const bool cc = AC && BC;
   const int64_t t128 = cdiv(M, 128) * cdiv(N, cc ? 64 : 128);

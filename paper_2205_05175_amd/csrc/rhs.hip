@@ -161,14 +161,15 @@ void build_work(Arena& A, int o, int v, Work<T>& w) {
   w.Px = A.cplx<T>({o, v, o, v});
   w.Bd = A.cplx<T>({o, v, o, v});
   w.Bx = A.cplx<T>({o, v, o, v});
-  w.WW = A.cplx<T>({2, o, v, o, v});
-  w.Wd = view(w.WW, 0, {o, v, o, v}, {v * ov, ov, v, 1});
-  w.Wx = view(w.WW, oovv, {o, v, o, v}, {v * ov, ov, v, 1});
-  // Hbar_mbej (s=0 direct, s=1 exchange) stored at (j,b,s,m,e)
-  w.HH = A.cplx<T>({o, v, 2, o, v});
+  // W_mbej (s=0 direct, s=1 exchange) stored at (j,b,s,m,e): the T ring GEMM reads it as [n][k]
+  w.WW = A.cplx<T>({o, v, 2, o, v});
+  w.Wd = view(w.WW, 0, {o, v, o, v}, {v, 1, 2 * ov * v, 2 * ov});
+  w.Wx = view(w.WW, ov, {o, v, o, v}, {v, 1, 2 * ov * v, 2 * ov});
+  // Hbar_mbej (s=0 direct, s=1 exchange) stored at (m,e,j,b,s): the Lambda ring GEMM reads it as [n][k]
+  w.HH = A.cplx<T>({o, v, o, v, 2});
   w.HH5 = w.HH;
-  w.HHd = view(w.HH, 0, {o, v, o, v}, {v, 1, 2 * ov * v, 2 * ov});
-  w.HHx = view(w.HH, ov, {o, v, o, v}, {v, 1, 2 * ov * v, 2 * ov});
+  w.HHd = view(w.HH, 0, {o, v, o, v}, {2 * ov * v, 2 * ov, 2 * v, 2});
+  w.HHx = view(w.HH, 1, {o, v, o, v}, {2 * ov * v, 2 * ov, 2 * v, 2});
   // stacked left operands of the ring GEMMs: (i,a,s,m,e) for T and (i,a,m,e,s) for Lambda
   w.T2R = A.cplx<T>({o, v, 2, o, v});
   w.T2R0 = view(w.T2R, 0, {o, o, v, v}, {2 * ov * v, v, 2 * ov, 1});
@@ -260,7 +261,7 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     {
       const int64_t rows = (lambda ? 2 : 1) * (int64_t)o * o, vv = (int64_t)v * v;
       GemmOp<T> a{w.X.re, w.X.im, vv, 0};
-      GemmOp<T> b{I.vvvv.re, nullptr, vv, 0};  // <ef|ab> = <ab|ef>
+      GemmOp<T> b{I.vvvv.re, nullptr, vv, 1};  // B(ef, ab) = <ab|ef> = <ef|ab>: V is symmetric
       if (E.mark) E.mark(E.mark_user, 0);
       gemm<T>(E, rows, vv, vv, 1.0, a, b, w.Lad.re, w.Lad.im, vv, 0.0);
       if (E.mark) E.mark(E.mark_user, 1);
@@ -295,7 +296,7 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   if (tb) {
     P(1, "imae->imae", w.t2s, w.T2R0, 0);
     P(1, "imae->imae", t2, w.T2R1, 0);
-    C(1, "iasme,smejb->iajb", w.T2R, w.WW, w.Zt, 0);
+    C(1, "iasme,jbsme->iajb", w.T2R, w.WW, w.Zt, 0);
     C(1, "mjae,meib->iajb", t2, w.Wx, w.Zt, 1);
     C(-1, "mb,ijam->ijab", t1, w.Z1, w.Z, 1);
     // t1 t1 ring pieces: S[m,b,i,j] = sum_e t_ie <mb|ej> + t_je <mb|ie>
@@ -331,7 +332,7 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     C(-1, "ma,ijmb->ijab", l1, w.Hooov, w.ZL, 1);
     P(1, "imae->imae", w.l2s, w.L2R0, 0);
     P(1, "imae->imae", l2, w.L2R1, 0);
-    C(1, "iames,mesjb->iajb", w.L2R, w.HH5, w.ZLt, 0);
+    C(1, "iames,jbmes->iajb", w.L2R, w.HH5, w.ZLt, 0);
     C(1, "mjae,ibme->iajb", l2, w.HHx, w.ZLt, 1);
     P(1, "iajb->ijab", w.ZLt, w.ZL, 1);
     C(1, "ijae,be->ijab", I.oovv, w.Gvv, w.ZL, 1);
