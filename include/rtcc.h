@@ -108,6 +108,28 @@ int rtcc_step_rk4(rtcc_ctx* ctx, void* y, double t, double h, const rtcc_field* 
 int rtcc_propagate_rk4(rtcc_ctx* ctx, void* y, double t0, double h, int nsteps, const rtcc_field* field,
                        double* mu_dev);
 
+/* Batched RK4 propagation of several systems, each with several members (polarisations, field
+ * strengths, pulses), as one graph per step.
+ *   ctxs[s], s < nsys (1 <= nsys <= 64): distinct contexts, one per system (each uses its own
+ *              precision); the call is ordered on the stream of ctxs[0] (the states must be ready
+ *              there) and returns asynchronously.
+ *   nprop[s]  : members of system s (1 ... 4096).
+ *   ys[s]     : DEVICE, nprop[s] consecutive states of system s (state layout above), advanced in place.
+ *   fields    : HOST, sum_s nprop[s] fields, system 0's members first; member m of system s uses
+ *               fields[nprop[0] + ... + nprop[s-1] + m]. A kick (kind 2) is applied beforehand with
+ *               rtcc_kick on the member's state; during the propagation it acts as no field.
+ *   t0, h, nsteps: nsteps RK4 steps of size h from t0 for every member.
+ *   mu_dev    : NULL, or per system NULL or DEVICE (nsteps+1) * nprop[s] * 6 doubles: the dipole of
+ *               every member (6 values as in rtcc_dipole) at t0 and after every step, [step][member][6].
+ * Each context's integrals are shared by its members: a contraction of an integral with the
+ * members' amplitudes is one GEMM over all members; a contraction of two amplitude tensors is a
+ * batched GEMM. Every member's result equals its own rtcc_propagate_rk4 up to the rounding order of
+ * those sums. One step of all systems (a branch per system) is captured once as a HIP graph and
+ * replayed; RTCC_NO_GRAPH=1 selects plain launches on each context's stream. Workspaces for the
+ * members are allocated by the first call with a given nprop[s] (a change reallocates them). */
+int rtcc_propagate_batch(rtcc_ctx* const* ctxs, int nsys, const int* nprop, void* const* ys,
+                         const rtcc_field* fields, double t0, double h, int nsteps, double* const* mu_dev);
+
 /* One Cash-Karp trial of size *h from *t with absolute tolerance eps on the largest complex
  * modulus of y5 - y4. If accepted (*accepted = 1) y advances by the fifth-order solution and
  * *t += h; otherwise y is unchanged. In both cases *h becomes the controller's next trial size

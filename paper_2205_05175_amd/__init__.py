@@ -53,6 +53,8 @@ def load_library(path: str = LIB_PATH):
     L.rtcc_rhs.argtypes = [vp, vp, d, dp, vp]
     L.rtcc_step_rk4.argtypes = [vp, vp, d, d, ctypes.POINTER(Field)]
     L.rtcc_propagate_rk4.argtypes = [vp, vp, d, d, i, ctypes.POINTER(Field), vp]
+    L.rtcc_propagate_batch.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(vp),
+                                       ctypes.POINTER(Field), d, d, i, ctypes.POINTER(vp)]
     L.rtcc_step_cashkarp.argtypes = [vp, vp, dp, dp, d, ctypes.POINTER(Field), ctypes.POINTER(i), dp]
     L.rtcc_dipole.argtypes = [vp, vp, dp]
     L.rtcc_dipole_dev.argtypes = [vp, vp, vp]
@@ -67,7 +69,7 @@ def load_library(path: str = LIB_PATH):
     L.rtcc_last_error.argtypes = [vp]
     L.rtcc_last_error.restype = ctypes.c_char_p
     for name in ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
-                 "rtcc_step_cashkarp", "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick",
+                 "rtcc_propagate_batch", "rtcc_step_cashkarp", "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick",
                  "rtcc_check_state", "rtcc_info", "rtcc_profile", "rtcc_profile_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -75,7 +77,7 @@ def load_library(path: str = LIB_PATH):
 
 
 EXPORTED = ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
-            "rtcc_step_cashkarp", "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick",
+            "rtcc_propagate_batch", "rtcc_step_cashkarp", "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick",
             "rtcc_check_state", "rtcc_info", "rtcc_profile", "rtcc_profile_read", "rtcc_destroy",
             "rtcc_last_error")
 
@@ -215,6 +217,46 @@ class RTCC:
             self.close()
         except Exception:
             pass
+
+
+def propagate_batch(systems, ys, fields, t0, h, nsteps, mu_out=None):
+    """Batched RK4 propagation (rtcc_propagate_batch).
+
+    systems: list of RTCC contexts (distinct); ys[s]: contiguous complex128 CUDA tensor of shape
+    (members_s, state_size); fields[s]: list of members_s Field; mu_out: None or a list with, per
+    system, None or a contiguous float64 CUDA tensor of (nsteps+1) * members_s * 6 entries.
+    Ordered on the stream of systems[0].
+    """
+    import torch
+    nsys = len(systems)
+    if nsys == 0 or len(ys) != nsys or len(fields) != nsys:
+        raise ValueError("systems, ys and fields must have one entry per system")
+    L = systems[0].L
+    nprop = []
+    for R, y, fl in zip(systems, ys, fields):
+        if not (isinstance(y, torch.Tensor) and y.is_cuda and y.dtype == torch.complex128 and y.is_contiguous()
+                and y.dim() == 2 and y.shape[1] == R.nstate and y.shape[0] == len(fl) and y.shape[0] > 0):
+            raise ValueError("ys[s] must be a contiguous complex128 CUDA tensor (members, state_size) "
+                             "matching fields[s]")
+        nprop.append(y.shape[0])
+    flat = [f for fl in fields for f in fl]
+    ctxs = (ctypes.c_void_p * nsys)(*[R.ctx.value for R in systems])
+    npa = (ctypes.c_int * nsys)(*nprop)
+    ypa = (ctypes.c_void_p * nsys)(*[y.data_ptr() for y in ys])
+    fa = (Field * len(flat))(*flat)
+    mpa = None
+    if mu_out is not None:
+        ptrs = []
+        for m, k in zip(mu_out, nprop):
+            if m is None:
+                ptrs.append(None)
+                continue
+            if not (m.is_cuda and m.dtype == torch.float64 and m.is_contiguous() and m.numel() >= 6 * k * (nsteps + 1)):
+                raise ValueError("mu_out[s] must be a contiguous float64 CUDA tensor of (nsteps+1)*members*6 entries")
+            ptrs.append(m.data_ptr())
+        mpa = (ctypes.c_void_p * nsys)(*ptrs)
+    rc = L.rtcc_propagate_batch(ctxs, nsys, npa, ypa, fa, float(t0), float(h), int(nsteps), mpa)
+    systems[0]._check(rc)
 
 
 def state_size(o, v):

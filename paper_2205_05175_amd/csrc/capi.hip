@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <memory>
 #include <string>
 #include <vector>
@@ -33,12 +34,39 @@ const double kCkA[6][5] = {
 const double kCkB5[6] = {37.0 / 378, 0.0, 250.0 / 621, 125.0 / 594, 0.0, 512.0 / 1771};
 const double kCkB4[6] = {2825.0 / 27648, 0.0, 18575.0 / 48384, 13525.0 / 55296, 277.0 / 14336, 1.0 / 4};
 const double kSafety = 0.84, kFacMin = 0.1, kFacMax = 5.0;
+const int kMaxBatchSystems = 64, kMaxBatchMembers = 4096;
 
 thread_local std::string g_init_error;
+std::atomic<uint64_t> g_serial{0};
 
 }  // namespace
 
+namespace rtcc {
+// Workspace of one context for a batch of nb propagations of its system (rtcc_propagate_batch).
+struct BatchWS {
+  int nb = 0;
+  uint64_t gen = 0;  // unique per allocation: a captured batch graph is keyed on it
+  bool has32 = false;
+  Arena arena;
+  Engine E;          // nb members, the context's stream
+  Work<double> W64;  // FP64 contractions and the density of every member
+  Work<float> W32;   // FP32 / split-BF16 contractions
+  void* k[4] = {nullptr, nullptr, nullptr, nullptr};  // RK4 stage derivatives, nb states each
+  void* ytmp = nullptr;
+  FieldDev* fdev = nullptr;  // the members' fields (device)
+  std::vector<FieldDev> fhost;
+  double* tdev = nullptr;     // start time of the current step (device)
+  double* mu_slot = nullptr;  // nb * 6 dipole values written by a captured step
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  ~BatchWS() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+  }
+};
+}  // namespace rtcc
+
 struct rtcc_ctx {
+  uint64_t id = 0;  // unique per context (never reused within a process)
   int o = 0, v = 0, n = 0, precision = RTCC_FP64;
   int64_t n1 = 0, n2 = 0, nstate = 0;  // complex entries
   hipStream_t stream = nullptr;
@@ -92,6 +120,11 @@ struct rtcc_ctx {
              n[1] == o.n[1] && n[2] == o.n[2];
     }
   } gkey{};
+  // batched propagation: this context's batch workspace, and the multi-context step graph of the
+  // calls in which this context comes first
+  std::unique_ptr<BatchWS> batch;
+  hipGraphExec_t bexec = nullptr;
+  std::vector<uint64_t> bkey;
 };
 
 namespace {
@@ -132,12 +165,14 @@ Planes4<T> planes(Work<T>& w, bool inputs) {
     for (int i = 0; i < 4; ++i) {
       P.re[i] = ts[i]->re;
       P.im[i] = ts[i]->im;
+      P.bs[i] = ts[i]->bs;
     }
   } else {
     Ten<T>* ts[4] = {&w.R1, &w.R2, &w.S1, &w.S2};
     for (int i = 0; i < 4; ++i) {
       P.re[i] = ts[i]->re;
       P.im[i] = ts[i]->im;
+      P.bs[i] = ts[i]->bs;
     }
   }
   return P;
@@ -293,6 +328,140 @@ void capture_step(rtcc_ctx* c, void* y, double h, const rtcc_field* field, bool 
   c->gkey = key;
 }
 
+// ---- batched propagation -------------------------------------------------------------------------
+std::atomic<uint64_t> g_batch_gen{0};
+
+void ensure_batch(rtcc_ctx* c, int nb) {
+  if (c->batch && c->batch->nb == nb && c->batch->has32 == c->have32) return;
+  // the old workspace may be in use by a step graph launched on another context's stream
+  if (c->batch) RTCC_HIP(hipDeviceSynchronize());
+  c->batch.reset();
+  auto B = std::make_unique<BatchWS>();
+  B->nb = nb;
+  B->gen = ++g_batch_gen;
+  B->has32 = c->have32;
+  B->E.stream = c->stream;
+  B->E.nb = nb;
+  B->E.trace = c->E.trace;
+  B->E.bf16_min_flops = c->E.bf16_min_flops;
+  B->E.scratch.cap = c->E.scratch.cap * (size_t)nb;
+  B->E.scratch.base = B->arena.alloc<char>(B->E.scratch.cap);
+  build_work<double>(B->arena, c->o, c->v, B->W64, nb);
+  if (c->have32) build_work<float>(B->arena, c->o, c->v, B->W32, nb);
+  const int64_t nst = (int64_t)nb * c->nstate;
+  for (auto& p : B->k) p = B->arena.alloc<double>(2 * nst);
+  B->ytmp = B->arena.alloc<double>(2 * nst);
+  B->fdev = (FieldDev*)B->arena.alloc<char>((int64_t)nb * sizeof(FieldDev));
+  B->fhost.resize(nb);
+  B->tdev = B->arena.alloc<double>(1);
+  B->mu_slot = B->arena.alloc<double>(6 * (int64_t)nb);
+  RTCC_HIP(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
+  RTCC_HIP(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
+  c->batch = std::move(B);
+}
+
+template <typename T>
+void eval_rhs_batch(rtcc_ctx* c, BatchWS& B, Ints<T>& I, Work<T>& w, const void* y, double toff, void* out) {
+  field_fock_tb<T>(B.E.stream, c->n, c->f0, c->mu, B.fdev, B.nb, B.tdev, toff, w.f.re, w.f.bs);
+  unpack_state<T>(B.E.stream, y, c->o, c->v, planes(w, true), B.nb);
+  residuals<T>(B.E, I, w, true, true);
+  pack_rhs<T>(B.E.stream, c->o, c->v, planes(w, false), out, 1.0, B.nb);
+}
+
+void rhs_batch(rtcc_ctx* c, const void* y, double toff, void* out) {
+  BatchWS& B = *c->batch;
+  if (c->precision == RTCC_FP64) {
+    eval_rhs_batch<double>(c, B, c->I64, B.W64, y, toff, out);
+  } else {
+    B.E.bf16x3 = c->precision == RTCC_BF16X3;
+    eval_rhs_batch<float>(c, B, c->I32, B.W32, y, toff, out);
+    B.E.bf16x3 = false;
+  }
+}
+
+// dipoles of all members of y (FP64 density) into out[6 * nb]
+void dipole_batch_dev(rtcc_ctx* c, const void* y, double* out) {
+  BatchWS& B = *c->batch;
+  Work<double>& w = B.W64;
+  unpack_state<double>(B.E.stream, y, c->o, c->v, planes(w, true), B.nb);
+  density<double>(B.E, w);
+  dipole_batch(B.E.stream, B.nb, (int64_t)c->n * c->n, w.rho.re, w.rho.im, w.rho.bs, c->mu, c->mu_ref_dev, out);
+}
+
+// One RK4 step of every member from t = *tdev (the members' own fields); advances *tdev by h.
+void rk4_step_batch(rtcc_ctx* c, void* y, double h, double* dip) {
+  BatchWS& B = *c->batch;
+  const int64_t nst = (int64_t)B.nb * c->nstate;
+  for (int s = 0; s < 4; ++s) {
+    const void* ys = y;
+    if (s > 0) {
+      const void* ks[3] = {B.k[0], B.k[1], B.k[2]};
+      double cs[3] = {h * kRk4A[s][0], h * kRk4A[s][1], h * kRk4A[s][2]};
+      state_combo(B.E.stream, nst, y, s, ks, cs, B.ytmp);
+      ys = B.ytmp;
+    }
+    rhs_batch(c, ys, kRk4C[s] * h, B.k[s]);
+  }
+  const void* ks[4] = {B.k[0], B.k[1], B.k[2], B.k[3]};
+  double cs[4] = {h * kRk4B[0], h * kRk4B[1], h * kRk4B[2], h * kRk4B[3]};
+  state_combo(B.E.stream, nst, y, 4, ks, cs, y);
+  if (dip) dipole_batch_dev(c, y, dip);
+  scalar_update(B.E.stream, B.tdev, h, true);
+}
+
+// Streams of ctxs[1..] wait for the work already on ctxs[0]'s stream.
+void batch_fork(rtcc_ctx* const* ctxs, int nsys) {
+  rtcc_ctx* c0 = ctxs[0];
+  RTCC_HIP(hipEventRecord(c0->batch->ev_fork, c0->stream));
+  for (int s = 1; s < nsys; ++s) RTCC_HIP(hipStreamWaitEvent(ctxs[s]->stream, c0->batch->ev_fork, 0));
+}
+// ctxs[0]'s stream waits for the work on the other contexts' streams.
+void batch_join(rtcc_ctx* const* ctxs, int nsys) {
+  for (int s = 1; s < nsys; ++s) {
+    RTCC_HIP(hipEventRecord(ctxs[s]->batch->ev_join, ctxs[s]->stream));
+    RTCC_HIP(hipStreamWaitEvent(ctxs[0]->stream, ctxs[s]->batch->ev_join, 0));
+  }
+}
+
+// One RK4 step of every member of every system captured as one graph (a branch per system),
+// replayed while the contexts, their workspaces, the states, h and the precisions are unchanged.
+void capture_batch(rtcc_ctx* const* ctxs, int nsys, void* const* ys, double h, const bool* dip) {
+  rtcc_ctx* c0 = ctxs[0];
+  std::vector<uint64_t> key;
+  uint64_t hb;
+  std::memcpy(&hb, &h, sizeof hb);
+  key.push_back((uint64_t)nsys);
+  key.push_back(hb);
+  for (int s = 0; s < nsys; ++s) {
+    key.push_back(ctxs[s]->id);
+    key.push_back(ctxs[s]->batch->gen);
+    key.push_back((uint64_t)(uintptr_t)ys[s]);
+    key.push_back((uint64_t)ctxs[s]->precision);
+    key.push_back(dip[s] ? 1 : 0);
+  }
+  if (c0->bexec && key == c0->bkey) return;
+  if (c0->bexec) {
+    RTCC_HIP(hipGraphExecDestroy(c0->bexec));
+    c0->bexec = nullptr;
+  }
+  RTCC_HIP(hipStreamBeginCapture(c0->stream, hipStreamCaptureModeRelaxed));
+  hipGraph_t g = nullptr;
+  try {
+    batch_fork(ctxs, nsys);
+    for (int s = 0; s < nsys; ++s) rk4_step_batch(ctxs[s], ys[s], h, dip[s] ? ctxs[s]->batch->mu_slot : nullptr);
+    batch_join(ctxs, nsys);
+  } catch (...) {
+    (void)hipStreamEndCapture(c0->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  RTCC_HIP(hipStreamEndCapture(c0->stream, &g));
+  hipError_t e = hipGraphInstantiate(&c0->bexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  RTCC_HIP(e);
+  c0->bkey = key;
+}
+
 void sync_read(rtcc_ctx* c, const double* dev, double* host, int n) {
   RTCC_HIP(hipMemcpyAsync(c->host_pinned, dev, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   RTCC_HIP(hipStreamSynchronize(c->stream));
@@ -341,6 +510,7 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
   }
   auto c = std::make_unique<rtcc_ctx>();
   int st = guarded(nullptr, [&] {
+    c->id = ++g_serial;
     c->o = o;
     c->v = v;
     c->n = o + v;
@@ -471,6 +641,73 @@ int rtcc_propagate_rk4(rtcc_ctx* c, void* y, double t0, double h, int nsteps, co
       } else {
         rk4_step(c, y, h, fd, mu_dev ? mu_dev + 6 * (int64_t)(s + 1) : nullptr);
       }
+    }
+  });
+}
+
+int rtcc_propagate_batch(rtcc_ctx* const* ctxs, int nsys, const int* nprop, void* const* ys,
+                         const rtcc_field* fields, double t0, double h, int nsteps, double* const* mu_dev) {
+  if (!ctxs || nsys < 1 || !ctxs[0]) {
+    g_init_error = "rtcc_propagate_batch: no contexts";
+    return RTCC_EINVAL;
+  }
+  rtcc_ctx* c0 = ctxs[0];
+  auto bad = [&](const char* why) {
+    c0->err = std::string("rtcc_propagate_batch: ") + why;
+    return RTCC_EINVAL;
+  };
+  if (nsys > kMaxBatchSystems) return bad("too many systems");
+  if (!nprop || !ys || !fields || nsteps < 0 || !std::isfinite(t0) || !std::isfinite(h)) return bad("invalid arguments");
+  int total = 0;
+  for (int s = 0; s < nsys; ++s) {
+    if (!ctxs[s] || !ys[s]) return bad("null context or state");
+    for (int r = 0; r < s; ++r)
+      if (ctxs[r] == ctxs[s]) return bad("a context appears twice");
+    if (nprop[s] < 1 || nprop[s] > kMaxBatchMembers) return bad("members per system out of range");
+    total += nprop[s];
+  }
+  for (int m = 0; m < total; ++m) {
+    const rtcc_field& f = fields[m];
+    if (f.kind < 0 || f.kind > 2 || !std::isfinite(f.E0) || !std::isfinite(f.omega) || !std::isfinite(f.t0) ||
+        !std::isfinite(f.n[0]) || !std::isfinite(f.n[1]) || !std::isfinite(f.n[2]) ||
+        (f.kind == 1 && !(f.sigma > 0)))
+      return bad("invalid field");
+  }
+  return guarded(c0, [&] {
+    bool dip[kMaxBatchSystems];
+    int off = 0;
+    for (int s = 0; s < nsys; ++s) {
+      rtcc_ctx* c = ctxs[s];
+      ensure_batch(c, nprop[s]);
+      BatchWS& B = *c->batch;
+      for (int m = 0; m < nprop[s]; ++m) B.fhost[m] = to_dev(&fields[off + m]);
+      off += nprop[s];
+      RTCC_HIP(hipMemcpyAsync(B.fdev, B.fhost.data(), nprop[s] * sizeof(FieldDev), hipMemcpyHostToDevice,
+                              c0->stream));
+      dip[s] = mu_dev && mu_dev[s];
+    }
+    // initial time and dipoles on every system's stream
+    batch_fork(ctxs, nsys);
+    for (int s = 0; s < nsys; ++s) {
+      rtcc_ctx* c = ctxs[s];
+      scalar_update(c->stream, c->batch->tdev, t0, false);
+      if (dip[s]) dipole_batch_dev(c, ys[s], mu_dev[s]);
+    }
+    if (!c0->use_graph) {
+      for (int st = 0; st < nsteps; ++st)
+        for (int s = 0; s < nsys; ++s)
+          rk4_step_batch(ctxs[s], ys[s], h, dip[s] ? mu_dev[s] + (int64_t)6 * nprop[s] * (st + 1) : nullptr);
+      batch_join(ctxs, nsys);
+      return;
+    }
+    batch_join(ctxs, nsys);
+    for (int st = 0; st < nsteps; ++st) {
+      capture_batch(ctxs, nsys, ys, h, dip);
+      RTCC_HIP(hipGraphLaunch(c0->bexec, c0->stream));
+      for (int s = 0; s < nsys; ++s)
+        if (dip[s])
+          RTCC_HIP(hipMemcpyAsync(mu_dev[s] + (int64_t)6 * nprop[s] * (st + 1), ctxs[s]->batch->mu_slot,
+                                  6 * nprop[s] * sizeof(double), hipMemcpyDeviceToDevice, c0->stream));
     }
   });
 }
@@ -718,8 +955,10 @@ int rtcc_info(rtcc_ctx* c, int64_t out[6]) {
 void rtcc_destroy(rtcc_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  if (c->batch) (void)hipDeviceSynchronize();  // batch buffers may be in use on another context's stream
   for (auto e : c->ev) (void)hipEventDestroy(e);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->bexec) (void)hipGraphExecDestroy(c->bexec);
   if (c->e_in) (void)hipEventDestroy(c->e_in);
   if (c->e_out) (void)hipEventDestroy(c->e_out);
   if (c->host_pinned) (void)hipHostFree(c->host_pinned);

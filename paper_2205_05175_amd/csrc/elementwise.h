@@ -4,15 +4,18 @@
 
 namespace rtcc {
 
+// Planar T1, T2, L1, L2 (or their residuals); member b of a batch at re[i] + b * bs[i] (same for im).
 template <typename T>
 struct Planes4 {
   T* re[4];
   T* im[4];
+  int64_t bs[4];
 };
+// y holds nb consecutive states (nb = 1 for a single state).
 template <typename T>
-void unpack_state(hipStream_t st, const void* y, int o, int v, Planes4<T> P);
+void unpack_state(hipStream_t st, const void* y, int o, int v, Planes4<T> P, int nb = 1);
 template <typename T>
-void pack_rhs(hipStream_t st, int o, int v, Planes4<T> P, void* out, double scale);
+void pack_rhs(hipStream_t st, int o, int v, Planes4<T> P, void* out, double scale, int nb = 1);
 template <typename T>
 void field_fock(hipStream_t st, int n, const double* f0, const double* mu, const double E[3], double s0, T* f);
 struct FieldDev {
@@ -22,6 +25,14 @@ struct FieldDev {
 template <typename T>
 void field_fock_t(hipStream_t st, int n, const double* f0, const double* mu, const FieldDev& fd, const double* tdev,
                   double toff, T* f);
+// Batched: member b uses fds[b] (DEVICE) and writes f + b * fbs.
+template <typename T>
+void field_fock_tb(hipStream_t st, int n, const double* f0, const double* mu, const FieldDev* fds, int nb,
+                   const double* tdev, double toff, T* f, int64_t fbs);
+// out[6 b + 2 a + (0, 1)] = (Re, Im) of mu_ref[a] + sum_pq rho_b[pq] mu_a[pq] for every member b;
+// rho_b at rho_re / rho_im + b * rbs (n*n entries). Fixed summation order.
+void dipole_batch(hipStream_t st, int nb, int64_t nn, const double* rho_re, const double* rho_im, int64_t rbs,
+                  const double* mu, const double* mu_ref, double* out);
 void scalar_update(hipStream_t st, double* p, double v, bool add);
 void state_combo(hipStream_t st, int64_t n, const void* y, int nk, const void* const* ks, const double* cs, void* out);
 template <typename T>

@@ -73,40 +73,47 @@ template void permute_axpby<float>(hipStream_t, int, const int64_t*, const float
 // ---- state vector <-> planar amplitudes ------------------------------------------------
 // y layout (complex128 interleaved): [T1 o*v | T2 o*o*v*v | L1 o*v | L2 o*o*v*v]
 template <typename T>
-__global__ void unpack_kernel(const double2* __restrict__ y, int64_t n1, int64_t n2, Planes4<T> P) {
-  int64_t ntot = 2 * (n1 + n2);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += (int64_t)gridDim.x * blockDim.x) {
+__device__ inline void state_segment(int64_t i, int64_t n1, int64_t n2, int64_t ntot, int* seg, int64_t* j,
+                                     int64_t* b) {
+  *b = i / ntot;
+  int64_t r = i - *b * ntot;
+  if (r < n1) { *seg = 0; *j = r; }
+  else if (r < n1 + n2) { *seg = 1; *j = r - n1; }
+  else if (r < 2 * n1 + n2) { *seg = 2; *j = r - n1 - n2; }
+  else { *seg = 3; *j = r - 2 * n1 - n2; }
+}
+
+template <typename T>
+__global__ void unpack_kernel(const double2* __restrict__ y, int64_t n1, int64_t n2, int64_t total, Planes4<T> P) {
+  const int64_t ntot = 2 * (n1 + n2);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     double2 z = y[i];
     int seg;
-    int64_t j;
-    if (i < n1) { seg = 0; j = i; }
-    else if (i < n1 + n2) { seg = 1; j = i - n1; }
-    else if (i < 2 * n1 + n2) { seg = 2; j = i - n1 - n2; }
-    else { seg = 3; j = i - 2 * n1 - n2; }
+    int64_t j, b;
+    state_segment<T>(i, n1, n2, ntot, &seg, &j, &b);
+    j += b * P.bs[seg];
     P.re[seg][j] = (T)z.x;
     P.im[seg][j] = (T)z.y;
   }
 }
 
 template <typename T>
-void unpack_state(hipStream_t st, const void* y, int o, int v, Planes4<T> P) {
-  int64_t n1 = (int64_t)o * v, n2 = n1 * n1;
-  int64_t blocks = std::min<int64_t>(cdiv(2 * (n1 + n2), 256), 65536);
-  hipLaunchKernelGGL(unpack_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, (const double2*)y, n1, n2, P);
+void unpack_state(hipStream_t st, const void* y, int o, int v, Planes4<T> P, int nb) {
+  int64_t n1 = (int64_t)o * v, n2 = n1 * n1, total = 2 * (n1 + n2) * nb;
+  int64_t blocks = std::min<int64_t>(cdiv(total, 256), 65536);
+  hipLaunchKernelGGL(unpack_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, (const double2*)y, n1, n2, total, P);
   RTCC_HIP(hipGetLastError());
 }
 
 // out = scale * (-i R_T, +i R_L)
 template <typename T>
-__global__ void pack_kernel(int64_t n1, int64_t n2, Planes4<T> P, double2* out, double scale) {
-  int64_t ntot = 2 * (n1 + n2);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += (int64_t)gridDim.x * blockDim.x) {
+__global__ void pack_kernel(int64_t n1, int64_t n2, int64_t total, Planes4<T> P, double2* out, double scale) {
+  const int64_t ntot = 2 * (n1 + n2);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     int seg;
-    int64_t j;
-    if (i < n1) { seg = 0; j = i; }
-    else if (i < n1 + n2) { seg = 1; j = i - n1; }
-    else if (i < 2 * n1 + n2) { seg = 2; j = i - n1 - n2; }
-    else { seg = 3; j = i - 2 * n1 - n2; }
+    int64_t j, b;
+    state_segment<T>(i, n1, n2, ntot, &seg, &j, &b);
+    j += b * P.bs[seg];
     double sgn = seg < 2 ? -1.0 : 1.0;
     double re = (double)P.re[seg][j], im = (double)P.im[seg][j];
     // (sgn i)(re + i im) = -sgn im + i sgn re
@@ -115,17 +122,18 @@ __global__ void pack_kernel(int64_t n1, int64_t n2, Planes4<T> P, double2* out, 
 }
 
 template <typename T>
-void pack_rhs(hipStream_t st, int o, int v, Planes4<T> P, void* out, double scale) {
-  int64_t n1 = (int64_t)o * v, n2 = n1 * n1;
-  int64_t blocks = std::min<int64_t>(cdiv(2 * (n1 + n2), 256), 65536);
-  hipLaunchKernelGGL(pack_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, n1, n2, P, (double2*)out, scale);
+void pack_rhs(hipStream_t st, int o, int v, Planes4<T> P, void* out, double scale, int nb) {
+  int64_t n1 = (int64_t)o * v, n2 = n1 * n1, total = 2 * (n1 + n2) * nb;
+  int64_t blocks = std::min<int64_t>(cdiv(total, 256), 65536);
+  hipLaunchKernelGGL(pack_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, n1, n2, total, P, (double2*)out,
+                     scale);
   RTCC_HIP(hipGetLastError());
 }
 
-template void unpack_state<double>(hipStream_t, const void*, int, int, Planes4<double>);
-template void unpack_state<float>(hipStream_t, const void*, int, int, Planes4<float>);
-template void pack_rhs<double>(hipStream_t, int, int, Planes4<double>, void*, double);
-template void pack_rhs<float>(hipStream_t, int, int, Planes4<float>, void*, double);
+template void unpack_state<double>(hipStream_t, const void*, int, int, Planes4<double>, int);
+template void unpack_state<float>(hipStream_t, const void*, int, int, Planes4<float>, int);
+template void pack_rhs<double>(hipStream_t, int, int, Planes4<double>, void*, double, int);
+template void pack_rhs<float>(hipStream_t, int, int, Planes4<float>, void*, double, int);
 
 // ---- field-dressed Fock matrix f(t) = f0 - sum_a E_a mu_a -------------------------------------
 template <typename T>
@@ -173,6 +181,71 @@ template void field_fock_t<double>(hipStream_t, int, const double*, const double
                                    double, double*);
 template void field_fock_t<float>(hipStream_t, int, const double*, const double*, const FieldDev&, const double*,
                                   double, float*);
+
+template <typename T>
+__global__ void fock_time_batch_kernel(int64_t nn, const double* f0, const double* mu, const FieldDev* fds,
+                                       const double* tdev, double toff, T* f, int64_t fbs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  const FieldDev& fd = fds[blockIdx.y];
+  double a = 0.0;
+  if (fd.kind == 1) {
+    double x = tdev[0] + toff - fd.t0;
+    a = -fd.E0 * exp(-0.5 * x * x / (fd.sigma * fd.sigma)) * cos(fd.omega * x);
+  }
+  f[blockIdx.y * fbs + i] = (T)(f0[i] - a * (fd.n[0] * mu[i] + fd.n[1] * mu[nn + i] + fd.n[2] * mu[2 * nn + i]));
+}
+
+template <typename T>
+void field_fock_tb(hipStream_t st, int n, const double* f0, const double* mu, const FieldDev* fds, int nb,
+                   const double* tdev, double toff, T* f, int64_t fbs) {
+  int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(fock_time_batch_kernel<T>, dim3((unsigned)cdiv(nn, 256), (unsigned)nb), dim3(256), 0, st, nn,
+                     f0, mu, fds, tdev, toff, f, fbs);
+  RTCC_HIP(hipGetLastError());
+}
+template void field_fock_tb<double>(hipStream_t, int, const double*, const double*, const FieldDev*, int,
+                                    const double*, double, double*, int64_t);
+template void field_fock_tb<float>(hipStream_t, int, const double*, const double*, const FieldDev*, int,
+                                   const double*, double, float*, int64_t);
+
+// One block per (component a, member b): strided per-thread sums, then the 256 thread sums
+// are combined in a fixed tree order through LDS.
+__global__ __launch_bounds__(256) void dipole_batch_kernel(int64_t nn, const double* rre, const double* rim,
+                                                           int64_t rbs, const double* mu, const double* mu_ref,
+                                                           double* out) {
+  __shared__ double sr[256], si[256];
+  const int a = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const double* pr = rre + b * rbs;
+  const double* pi = rim + b * rbs;
+  const double* m = mu + a * nn;
+  double xr = 0.0, xi = 0.0;
+  for (int64_t i = tid; i < nn; i += 256) {
+    xr += pr[i] * m[i];
+    xi += pi[i] * m[i];
+  }
+  sr[tid] = xr;
+  si[tid] = xi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      sr[tid] += sr[tid + w];
+      si[tid] += si[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[6 * b + 2 * a] = mu_ref[a] + sr[0];
+    out[6 * b + 2 * a + 1] = si[0];
+  }
+}
+
+void dipole_batch(hipStream_t st, int nb, int64_t nn, const double* rho_re, const double* rho_im, int64_t rbs,
+                  const double* mu, const double* mu_ref, double* out) {
+  hipLaunchKernelGGL(dipole_batch_kernel, dim3(3, (unsigned)nb), dim3(256), 0, st, nn, rho_re, rho_im, rbs, mu,
+                     mu_ref, out);
+  RTCC_HIP(hipGetLastError());
+}
 
 __global__ void scalar_kernel(double* p, double v, int add) { p[0] = add ? p[0] + v : v; }
 void scalar_update(hipStream_t st, double* p, double v, bool add) {

@@ -21,6 +21,9 @@ struct Ten {
   int nd = 0;
   int64_t d[kMaxDim] = {0};
   int64_t s[kMaxDim] = {0};  // element strides
+  // Batch stride: 0 for a tensor shared by every member of a batch (the integrals), else the
+  // element offset between consecutive members (both planes of a complex tensor).
+  int64_t bs = 0;
   bool cplx() const { return im != nullptr; }
   int64_t size() const {
     int64_t n = 1;
@@ -73,6 +76,10 @@ struct Engine {
   bool trace = false;         // print every contraction's layout decisions to stderr
   bool bf16x3 = false;        // FP32 GEMMs above bf16_min_flops use the split-BF16 three-term kernel
   double bf16_min_flops = 5e8;
+  // Batch size of the tensors with bs != 0. Every contraction then runs for all members: a
+  // member index carried by one operand only becomes part of the GEMM's M or N (one fat GEMM
+  // against the shared integrals); one carried by both becomes a batched GEMM.
+  int nb = 1;
 };
 
 
@@ -95,9 +102,15 @@ struct GemmOp {
   int64_t ld;
   int trans;
 };
+// Batched form: `n` independent products, operand X of product z at X + z * (batch stride of X);
+// a stride of 0 shares the operand.
+struct GemmBatch {
+  int n = 1;
+  int64_t a = 0, b = 0, c = 0;
+};
 template <typename T>
 void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A, GemmOp<T> B, T* Cre, T* Cim,
-          int64_t ldc, double beta);
+          int64_t ldc, double beta, GemmBatch bt = GemmBatch());
 
 bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<float> A, GemmOp<float> B,
                  float* Cre, float* Cim, int64_t ldc, double beta);

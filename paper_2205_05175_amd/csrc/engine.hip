@@ -112,112 +112,182 @@ std::string ordered(const std::string& from, const std::string& keep) {
   return r;
 }
 
+// The operand with the batch axis (letter 'Z', outermost) prepended when it is batched.
+template <typename T>
+Ten<T> batch_ext(const Ten<T>& X, int nb, std::string* spec) {
+  RTCC_CHECK(X.nd < kMaxDim, kEInval, "batched tensor of too many dimensions");
+  Ten<T> Y = X;
+  Y.nd = X.nd + 1;
+  Y.d[0] = nb;
+  Y.s[0] = X.bs;
+  for (int i = 0; i < X.nd; ++i) {
+    Y.d[i + 1] = X.d[i];
+    Y.s[i + 1] = X.s[i];
+  }
+  *spec = "Z" + *spec;
+  return Y;
+}
+
+struct Plan {
+  std::string m, n, k;  // letter groups of the GEMM (outer to inner)
+  std::string h;        // batch letter ("Z") or empty
+  int64_t cost = -1;    // elements that must be permuted
+};
+
+// Best letter orders for one choice of batch letters H (letters of H are neither M, N nor K).
+template <typename T>
+Plan plan_for(const Ten<T>& A, const std::string& sa, const Ten<T>& B, const std::string& sb, const Ten<T>& C,
+              const std::string& sc, const std::string& H) {
+  auto drop = [&](const std::string& x) {
+    std::string r;
+    for (char c : x)
+      if (H.find(c) == std::string::npos) r += c;
+    return r;
+  };
+  const std::string a = drop(sa), b = drop(sb), c = drop(sc);
+  std::string Kfrom[2] = {ordered(a, b), ordered(b, a)};
+  for (auto& k : Kfrom) {
+    std::string kk;
+    for (char x : k)
+      if (c.find(x) == std::string::npos) kk += x;
+    k = kk;
+  }
+  std::string Mfrom[2] = {ordered(c, a), ordered(a, c)};
+  std::string Nfrom[2] = {ordered(c, b), ordered(b, c)};
+  Plan best;
+  best.h = H;
+  for (int im = 0; im < 2; ++im)
+    for (int in = 0; in < 2; ++in)
+      for (int ik = 0; ik < 2; ++ik) {
+        GemmOp<T> oa, ob, oc;
+        int64_t cost = 0;
+        if (!view2d(A, sa, Mfrom[im], Kfrom[ik], &oa)) cost += A.size() * (A.cplx() ? 2 : 1);
+        if (!view2d(B, sb, Kfrom[ik], Nfrom[in], &ob)) cost += B.size() * (B.cplx() ? 2 : 1);
+        if (!view2d(C, sc, Mfrom[im], Nfrom[in], &oc)) cost += 3 * C.size() * (C.cplx() ? 2 : 1);
+        if (best.cost < 0 || cost < best.cost) {
+          best.cost = cost;
+          best.m = Mfrom[im];
+          best.n = Nfrom[in];
+          best.k = Kfrom[ik];
+        }
+      }
+  return best;
+}
+
 }  // namespace
 
 template <typename T>
-void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A, const Ten<T>& B, const Ten<T>& C,
+void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const Ten<T>& B0, const Ten<T>& C0,
          double beta) {
   Spec sp = parse3(specstr);
-  RTCC_CHECK((int)sp.a.size() == A.nd && (int)sp.b.size() == B.nd && (int)sp.c.size() == C.nd, kEInval,
+  RTCC_CHECK((int)sp.a.size() == A0.nd && (int)sp.b.size() == B0.nd && (int)sp.c.size() == C0.nd, kEInval,
              std::string("rank mismatch in ") + specstr);
+  for (const std::string* x : {&sp.a, &sp.b, &sp.c})
+    RTCC_CHECK(x->find('Z') == std::string::npos, kEInval, std::string("reserved index Z in ") + specstr);
   // letter classes
-  std::string Ml, Nl, Kl;
   for (char c : sp.c) {
     bool ina = sp.a.find(c) != std::string::npos, inb = sp.b.find(c) != std::string::npos;
     RTCC_CHECK(ina != inb, kEInval, std::string("batch/unknown index in ") + specstr);
-    RTCC_CHECK(dim_of(C, sp.c, c) == (ina ? dim_of(A, sp.a, c) : dim_of(B, sp.b, c)), kEInval,
+    RTCC_CHECK(dim_of(C0, sp.c, c) == (ina ? dim_of(A0, sp.a, c) : dim_of(B0, sp.b, c)), kEInval,
                std::string("extent mismatch in ") + specstr);
   }
   for (char c : sp.a) {
     bool inb = sp.b.find(c) != std::string::npos, inc = sp.c.find(c) != std::string::npos;
     RTCC_CHECK(inb || inc, kEInval, std::string("summed-only index in ") + specstr);
     if (inb && !inc) {
-      RTCC_CHECK(dim_of(A, sp.a, c) == dim_of(B, sp.b, c), kEInval, std::string("extent mismatch in ") + specstr);
+      RTCC_CHECK(dim_of(A0, sp.a, c) == dim_of(B0, sp.b, c), kEInval, std::string("extent mismatch in ") + specstr);
     }
   }
   for (char c : sp.b) {
     bool ina = sp.a.find(c) != std::string::npos, inc = sp.c.find(c) != std::string::npos;
     RTCC_CHECK(ina || inc, kEInval, std::string("summed-only index in ") + specstr);
   }
-  RTCC_CHECK(C.cplx() || (!A.cplx() && !B.cplx()), kEInval, std::string("complex into real in ") + specstr);
+  RTCC_CHECK(C0.cplx() || (!A0.cplx() && !B0.cplx()), kEInval, std::string("complex into real in ") + specstr);
 
-  std::string Kfrom[2] = {ordered(sp.a, sp.b + ""), ordered(sp.b, sp.a)};
-  for (auto& k : Kfrom) {
-    std::string kk;
-    for (char c : k)
-      if (sp.c.find(c) == std::string::npos) kk += c;
-    k = kk;
+  // batch axis: prepended as letter Z to every batched operand
+  const bool bA = E.nb > 1 && A0.bs != 0, bB = E.nb > 1 && B0.bs != 0, bC = E.nb > 1 && C0.bs != 0;
+  RTCC_CHECK(bC || (!bA && !bB), kEInval, std::string("batched operand into a shared output in ") + specstr);
+  std::string sa = sp.a, sb = sp.b, sc = sp.c;
+  Ten<T> A = bA ? batch_ext(A0, E.nb, &sa) : A0;
+  Ten<T> B = bB ? batch_ext(B0, E.nb, &sb) : B0;
+  Ten<T> C = bC ? batch_ext(C0, E.nb, &sc) : C0;
+
+  // Z in both inputs: a batched GEMM. Z in one input: folded into M (or N) -- one GEMM against
+  // the shared operand -- unless that needs more permuting than a batched GEMM with the shared
+  // operand at batch stride 0. Z in the output only (both inputs shared): a batched GEMM.
+  Plan pl;
+  if (bC && bA == bB) {
+    pl = plan_for(A, sa, B, sb, C, sc, "Z");
+  } else {
+    pl = plan_for(A, sa, B, sb, C, sc, "");
+    if (bC && pl.cost > 0) {
+      Plan pz = plan_for(A, sa, B, sb, C, sc, "Z");
+      if (pz.cost < pl.cost) pl = pz;
+    }
   }
-  std::string Mfrom[2] = {ordered(sp.c, sp.a), ordered(sp.a, sp.c)};
-  std::string Nfrom[2] = {ordered(sp.c, sp.b), ordered(sp.b, sp.c)};
-
-  // choose letter orders that minimise permuted bytes
-  int64_t best = -1;
-  std::string bm, bn, bk;
-  for (int im = 0; im < 2; ++im)
-    for (int in = 0; in < 2; ++in)
-      for (int ik = 0; ik < 2; ++ik) {
-        GemmOp<T> oa, ob, oc;
-        int64_t cost = 0;
-        if (!view2d(A, sp.a, Mfrom[im], Kfrom[ik], &oa)) cost += A.size() * (A.cplx() ? 2 : 1);
-        if (!view2d(B, sp.b, Kfrom[ik], Nfrom[in], &ob)) cost += B.size() * (B.cplx() ? 2 : 1);
-        if (!view2d(C, sp.c, Mfrom[im], Nfrom[in], &oc)) cost += 3 * C.size() * (C.cplx() ? 2 : 1);
-        if (best < 0 || cost < best) {
-          best = cost;
-          bm = Mfrom[im];
-          bn = Nfrom[in];
-          bk = Kfrom[ik];
-        }
-      }
+  const std::string &bm = pl.m, &bn = pl.n, &bk = pl.k;
+  const bool hb = !pl.h.empty();
   int64_t M = 1, N = 1, K = 1;
-  for (char c : bm) M *= dim_of(C, sp.c, c);
-  for (char c : bn) N *= dim_of(C, sp.c, c);
-  for (char c : bk) K *= dim_of(A, sp.a, c);
+  for (char c : bm) M *= dim_of(C, sc, c);
+  for (char c : bn) N *= dim_of(C, sc, c);
+  for (char c : bk) K *= dim_of(A, sa, c);
+  const int nbt = hb ? E.nb : 1;
 
   if (E.trace) {
     GemmOp<T> xa, xb, xc;
-    bool pa = !view2d(A, sp.a, bm, bk, &xa), pb = !view2d(B, sp.b, bk, bn, &xb), pc = !view2d(C, sp.c, bm, bn, &xc);
-    fprintf(stderr, "[rtcc] ein %-22s M=%lld N=%lld K=%lld permute:%s%s%s (A %lld, B %lld, C %lld elems)\n", specstr,
-            (long long)M, (long long)N, (long long)K, pa ? " A" : "", pb ? " B" : "", pc ? " C" : "",
+    bool pa = !view2d(A, sa, bm, bk, &xa), pb = !view2d(B, sb, bk, bn, &xb), pc = !view2d(C, sc, bm, bn, &xc);
+    fprintf(stderr, "[rtcc] ein %-22s M=%lld N=%lld K=%lld batch=%d permute:%s%s%s (A %lld, B %lld, C %lld elems)\n",
+            specstr, (long long)M, (long long)N, (long long)K, nbt, pa ? " A" : "", pb ? " B" : "", pc ? " C" : "",
             (long long)A.size(), (long long)B.size(), (long long)C.size());
   }
   size_t mark = E.scratch.used;
   GemmOp<T> oa, ob, oc;
   Ten<T> Ap = A, Bp = B;
-  std::string sa = sp.a, sb = sp.b;
-  if (!view2d(A, sp.a, bm, bk, &oa)) {
-    Ap = permuted_copy(E, A, sp.a, bm + bk);
-    sa = bm + bk;
+  const std::string ha = (hb && bA) ? "Z" : "", hbb = (hb && bB) ? "Z" : "";
+  if (!view2d(A, sa, bm, bk, &oa)) {
+    Ap = permuted_copy(E, A, sa, ha + bm + bk);
+    sa = ha + bm + bk;
     view2d(Ap, sa, bm, bk, &oa);
   }
-  if (!view2d(B, sp.b, bk, bn, &ob)) {
-    Bp = permuted_copy(E, B, sp.b, bk + bn);
-    sb = bk + bn;
+  if (!view2d(B, sb, bk, bn, &ob)) {
+    Bp = permuted_copy(E, B, sb, hbb + bk + bn);
+    sb = hbb + bk + bn;
     view2d(Bp, sb, bk, bn, &ob);
   }
-  if (view2d(C, sp.c, bm, bn, &oc)) {
+  GemmBatch gb;
+  gb.n = nbt;
+  if (hb) {
+    gb.a = bA ? str_of(Ap, sa, 'Z') : 0;
+    gb.b = bB ? str_of(Bp, sb, 'Z') : 0;
+    gb.c = str_of(C, sc, 'Z');
+  }
+  if (view2d(C, sc, bm, bn, &oc)) {
     if (oc.trans == 0) {
-      gemm<T>(E, M, N, K, alpha, oa, ob, C.re, C.im, oc.ld, beta);
+      gemm<T>(E, M, N, K, alpha, oa, ob, C.re, C.im, oc.ld, beta, gb);
     } else {
       // C^T(n,m) = B^T(n,k) A^T(k,m)
       GemmOp<T> bt = ob, at = oa;
       bt.trans ^= 1;
       at.trans ^= 1;
-      gemm<T>(E, N, M, K, alpha, bt, at, C.re, C.im, oc.ld, beta);
+      std::swap(gb.a, gb.b);
+      gemm<T>(E, N, M, K, alpha, bt, at, C.re, C.im, oc.ld, beta, gb);
     }
   } else {
-    T* tre = E.scratch.get<T>(std::max<int64_t>(M * N, 1));
-    T* tim = C.im ? E.scratch.get<T>(std::max<int64_t>(M * N, 1)) : nullptr;
-    gemm<T>(E, M, N, K, 1.0, oa, ob, tre, tim, N, 0.0);
-    // temp is row-major over letters bm+bn; add into C
-    std::string tl = bm + bn;
+    const int64_t nt = std::max<int64_t>(M * N * nbt, 1);
+    T* tre = E.scratch.get<T>(nt);
+    T* tim = C.im ? E.scratch.get<T>(nt) : nullptr;
+    GemmBatch gt = gb;
+    gt.c = M * N;
+    gemm<T>(E, M, N, K, 1.0, oa, ob, tre, tim, N, 0.0, gt);
+    // temp is row-major over letters (Z) bm bn; add into C
+    std::string tl = pl.h + bm + bn;
     int64_t d[kMaxDim], is[kMaxDim], os[kMaxDim];
     int64_t st = 1;
     for (int i = (int)tl.size() - 1; i >= 0; --i) {
-      d[i] = dim_of(C, sp.c, tl[i]);
+      d[i] = dim_of(C, sc, tl[i]);
       is[i] = st;
       st *= d[i];
-      os[i] = str_of(C, sp.c, tl[i]);
+      os[i] = str_of(C, sc, tl[i]);
     }
     permute_axpby<T>(E.stream, (int)tl.size(), d, tre, tim, is, C.re, C.im, os, alpha, beta);
   }
@@ -233,19 +303,30 @@ void padd(Engine& E, double alpha, const char* specstr, const Ten<T>& A, const T
   RTCC_CHECK((int)sa.size() == A.nd && (int)sc.size() == C.nd && sa.size() == sc.size(), kEInval,
              std::string("rank mismatch in ") + specstr);
   RTCC_CHECK(C.cplx() || !A.cplx(), kEInval, std::string("complex into real in ") + specstr);
+  const bool bA = E.nb > 1 && A.bs != 0, bC = E.nb > 1 && C.bs != 0;
+  RTCC_CHECK(bC || !bA, kEInval, std::string("batched operand into a shared output in ") + specstr);
   int64_t d[kMaxDim], is[kMaxDim], os[kMaxDim];
+  int nd = 0;
+  if (bC) {  // batch axis; a shared input is broadcast (stride 0)
+    RTCC_CHECK(C.nd < kMaxDim, kEInval, std::string("batched permute of too many dimensions: ") + specstr);
+    d[0] = E.nb;
+    is[0] = bA ? A.bs : 0;
+    os[0] = C.bs;
+    nd = 1;
+  }
   for (size_t i = 0; i < sc.size(); ++i) {
     size_t j = sa.find(sc[i]);
     RTCC_CHECK(j != std::string::npos && A.d[j] == C.d[i], kEInval, std::string("bad permute spec: ") + specstr);
-    d[i] = C.d[i];
-    is[i] = A.s[j];
-    os[i] = C.s[i];
+    d[nd] = C.d[i];
+    is[nd] = A.s[j];
+    os[nd] = C.s[i];
+    ++nd;
   }
   if (A.cplx() || !C.cplx()) {
-    permute_axpby<T>(E.stream, C.nd, d, A.re, A.im, is, C.re, C.im, os, alpha, beta);
+    permute_axpby<T>(E.stream, nd, d, A.re, A.im, is, C.re, C.im, os, alpha, beta);
   } else {
     // real input into complex output: imaginary plane is scaled by beta only
-    permute_axpby<T>(E.stream, C.nd, d, A.re, (const T*)nullptr, is, C.re, C.im, os, alpha, beta);
+    permute_axpby<T>(E.stream, nd, d, A.re, (const T*)nullptr, is, C.re, C.im, os, alpha, beta);
   }
 }
 

@@ -49,8 +49,10 @@ struct GemmParams {
   T* Cim;
   int64_t ldc;
   int M, N, K;
-  int kchunk;            // K range handled by one blockIdx.z
+  int kchunk;            // K range handled by one split
+  int splits;            // blockIdx.z = member * splits + split
   int64_t split_stride;  // elements between partial planes (split-K); 0 = write C directly
+  int64_t sa, sb, sc;    // batch strides of A, B and C (elements; 0 = shared)
   T alpha, beta;
 };
 
@@ -128,7 +130,8 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int kbeg = blockIdx.z * p.kchunk;
+  const int zb = blockIdx.z / p.splits, zs = blockIdx.z - zb * p.splits;
+  const int kbeg = zs * p.kchunk;
   const int kend = min(p.K, kbeg + p.kchunk);
 
   V4 accr[FM][FN], acci[FM][FN];
@@ -139,8 +142,9 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
       accr[i][j] = V4{0, 0, 0, 0};
       acci[i][j] = V4{0, 0, 0, 0};
     }
-  const T* Ap[2] = {p.Are, p.Aim};
-  const T* Bp[2] = {p.Bre, p.Bim};
+  const int64_t oa = (int64_t)zb * p.sa, ob = (int64_t)zb * p.sb;
+  const T* Ap[2] = {p.Are + oa, AC ? p.Aim + oa : nullptr};
+  const T* Bp[2] = {p.Bre + ob, BC ? p.Bim + ob : nullptr};
 
   // A tile: TA ? (rows k, cols m) : (rows m, cols k);  B tile: TB ? (rows n, cols k) : (rows k, cols n)
   TileRegs<T, TA ? kBK : BM, TA ? BM : kBK, VEC, NA> ra;
@@ -221,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
           p.Cre[off] = vr;
           if (CC) p.Cim[off] = vi;
         } else {
-          int64_t off = (int64_t)row * p.ldc + col;
+          int64_t off = (int64_t)zb * p.sc + (int64_t)row * p.ldc + col;
           T outr = p.alpha * vr, outi = p.alpha * vi;
           if (p.beta != T(0)) {
             outr += p.beta * p.Cre[off];
@@ -238,9 +242,15 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
 // so the result does not depend on scheduling.
 template <typename T>
 __global__ __launch_bounds__(256) void splitk_reduce(const T* Pre, const T* Pim, int splits, int64_t stride, int M,
-                                                     int N, T* Cre, T* Cim, int64_t ldc, T alpha, T beta) {
+                                                     int N, T* Cre, T* Cim, int64_t ldc, int64_t sc, T alpha,
+                                                     T beta) {
   __shared__ T shr[16][17], shi[16][17];
   const int ol = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  // member blockIdx.y: partial planes y * splits ... y * splits + splits - 1
+  Pre += (int64_t)blockIdx.y * splits * stride;
+  if (Pim) Pim += (int64_t)blockIdx.y * splits * stride;
+  Cre += (int64_t)blockIdx.y * sc;
+  if (Cim) Cim += (int64_t)blockIdx.y * sc;
   const int64_t idx = (int64_t)blockIdx.x * 16 + ol;
   const bool ok = idx < (int64_t)M * N;
   T sr = 0, si = 0;
@@ -271,8 +281,8 @@ __global__ __launch_bounds__(256) void splitk_reduce(const T* Pre, const T* Pim,
 }
 
 template <typename T, int BM, int BN, int AC, int BC, int TA, int TB, int VEC>
-static void launch_one(hipStream_t st, const GemmParams<T>& p, int splits) {
-  dim3 grid((unsigned)cdiv(p.N, BN), (unsigned)cdiv(p.M, BM), (unsigned)splits);
+static void launch_one(hipStream_t st, const GemmParams<T>& p, int zdim) {
+  dim3 grid((unsigned)cdiv(p.N, BN), (unsigned)cdiv(p.M, BM), (unsigned)zdim);
   hipLaunchKernelGGL((gemm_kernel<T, BM, BN, AC, BC, TA, TB, VEC>), grid, dim3(kThreads), 0, st, p);
   RTCC_HIP(hipGetLastError());
 }
@@ -313,24 +323,26 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 template <typename T>
 void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A, GemmOp<T> B, T* Cre, T* Cim,
-          int64_t ldc, double beta) {
-  if (M <= 0 || N <= 0) return;
+          int64_t ldc, double beta, GemmBatch bt) {
+  if (M <= 0 || N <= 0 || bt.n <= 0) return;
   RTCC_CHECK(M < (1LL << 31) && N < (1LL << 31) && K < (1LL << 31), kEInval, "gemm: dimension too large");
+  RTCC_CHECK(bt.n <= 65535, kEInval, "gemm: batch too large");
   const bool AC = A.im != nullptr, BC = B.im != nullptr, CC = Cim != nullptr;
   RTCC_CHECK(CC || (!AC && !BC), kEInval, "gemm: complex product into a real output");
+  const int nbt = bt.n;
   if (K <= 0) {
-    int64_t d[2] = {M, N}, s[2] = {ldc, 1};
-    permute_axpby<T>(E.stream, 2, d, Cre, Cim, s, Cre, Cim, s, 0.0, beta);
+    int64_t d[3] = {nbt, M, N}, s[3] = {bt.c, ldc, 1};
+    permute_axpby<T>(E.stream, 3, d, Cre, Cim, s, Cre, Cim, s, 0.0, beta);
     return;
   }
   if (!AC && !BC && CC) {
     // real product into a complex output: the imaginary plane is only scaled
-    int64_t d[2] = {M, N}, s[2] = {ldc, 1};
-    permute_axpby<T>(E.stream, 2, d, Cim, (T*)nullptr, s, Cim, (T*)nullptr, s, 0.0, beta);
+    int64_t d[3] = {nbt, M, N}, s[3] = {bt.c, ldc, 1};
+    permute_axpby<T>(E.stream, 3, d, Cim, (T*)nullptr, s, Cim, (T*)nullptr, s, 0.0, beta);
     Cim = nullptr;
   }
   if constexpr (sizeof(T) == 4) {
-    if (E.bf16x3 && 2.0 * (double)M * (double)N * (double)K >= E.bf16_min_flops &&
+    if (nbt == 1 && E.bf16x3 && 2.0 * (double)M * (double)N * (double)K >= E.bf16_min_flops &&
         gemm_bf16x3(E, M, N, K, alpha, A, B, Cre, Cim, ldc, beta))
       return;
   }
@@ -346,34 +358,38 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
   p.M = (int)M;
   p.N = (int)N;
   p.K = (int)K;
+  p.sa = bt.a;
+  p.sb = bt.b;
+  p.sc = bt.c;
   p.alpha = (T)alpha;
   p.beta = (T)beta;
-  // 16-byte vector loads need every plane pointer and leading dimension VEC-aligned
+  // 16-byte vector loads need every plane pointer, leading dimension and batch stride VEC-aligned
   constexpr int V = 16 / sizeof(T);
   const bool vec = aligned16(A.re) && (!AC || aligned16(A.im)) && aligned16(B.re) && (!BC || aligned16(B.im)) &&
-                   A.ld % V == 0 && B.ld % V == 0;
+                   A.ld % V == 0 && B.ld % V == 0 && bt.a % V == 0 && bt.b % V == 0;
   // FP32: 128 x 128 tiles when the grid still holds >= 2 tiles per CU; FP64 (longer MFMA,
   // more registers per tile): always 64 x 64 for occupancy. Small grids split over K.
   constexpr int LBM = 128, LBN = 128;
-  const bool large = sizeof(T) == 4 && cdiv(M, LBM) * cdiv(N, LBN) >= 512;
+  const bool large = sizeof(T) == 4 && cdiv(M, LBM) * cdiv(N, LBN) * nbt >= 512;
   const int BM = large ? LBM : 64, BN = large ? LBN : 64;
-  const int64_t tiles = cdiv(M, BM) * cdiv(N, BN);
+  const int64_t tiles = cdiv(M, BM) * cdiv(N, BN) * nbt;
   // fewer than ~2 workgroups per CU: split K (chunks of >= 256) toward ~1024 workgroups
   int splits = 1;
   if (!large && tiles < 512 && K >= 512) {
     int64_t want = std::max<int64_t>(1, 1024 / tiles);
-    splits = (int)std::min<int64_t>({want, cdiv(K, 256), 1024});
+    splits = (int)std::min<int64_t>({want, cdiv(K, 256), 1024, 65535 / nbt});
   }
   int64_t kchunk = cdiv(cdiv(K, splits), kBK) * kBK;
   splits = (int)cdiv(K, kchunk);
   p.kchunk = (int)kchunk;
+  p.splits = splits;
   size_t mark = E.scratch.used;
   T* Pre = nullptr;
   T* Pim = nullptr;
   if (splits > 1) {
     p.split_stride = M * N;
-    Pre = E.scratch.get<T>(splits * M * N);
-    if (AC || BC) Pim = E.scratch.get<T>(splits * M * N);
+    Pre = E.scratch.get<T>((int64_t)nbt * splits * M * N);
+    if (AC || BC) Pim = E.scratch.get<T>((int64_t)nbt * splits * M * N);
     p.Cre = Pre;
     p.Cim = Pim;
     p.ldc = N;
@@ -383,25 +399,25 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
     p.Cim = Cim;
     p.ldc = ldc;
   }
-  if (large) launch_typed<T, LBM, LBN>(E.stream, p, splits, vec);
-  else launch_typed<T, 64, 64>(E.stream, p, splits, vec);
+  if (large) launch_typed<T, LBM, LBN>(E.stream, p, nbt * splits, vec);
+  else launch_typed<T, 64, 64>(E.stream, p, nbt * splits, vec);
   if (splits > 1) {
     int64_t n = M * N;
-    hipLaunchKernelGGL(splitk_reduce<T>, dim3((unsigned)cdiv(n, 16)), dim3(256), 0, E.stream, Pre, Pim, splits,
-                       M * N, (int)M, (int)N, Cre, Cim, ldc, (T)alpha, (T)beta);
+    hipLaunchKernelGGL(splitk_reduce<T>, dim3((unsigned)cdiv(n, 16), (unsigned)nbt), dim3(256), 0, E.stream, Pre,
+                       Pim, splits, M * N, (int)M, (int)N, Cre, Cim, ldc, bt.c, (T)alpha, (T)beta);
     RTCC_HIP(hipGetLastError());
   }
   E.scratch.reset(mark);
-  E.gemm_flops += 2 * M * N * K * ((AC && BC) ? 4 : (AC || BC) ? 2 : 1);
+  E.gemm_flops += 2 * M * N * K * nbt * ((AC && BC) ? 4 : (AC || BC) ? 2 : 1);
   if (E.trace)
-    fprintf(stderr, "[rtcc] gemm M=%lld N=%lld K=%lld %s%s ta=%d tb=%d tile=%dx%d splits=%d vec=%d\n",
-            (long long)M, (long long)N, (long long)K, AC ? "c" : "r", BC ? "c" : "r", A.trans, B.trans, BM, BN,
-            splits, (int)vec);
+    fprintf(stderr, "[rtcc] gemm M=%lld N=%lld K=%lld batch=%d %s%s ta=%d tb=%d tile=%dx%d splits=%d vec=%d\n",
+            (long long)M, (long long)N, (long long)K, nbt, AC ? "c" : "r", BC ? "c" : "r", A.trans, B.trans, BM,
+            BN, splits, (int)vec);
 }
 
 template void gemm<double>(Engine&, int64_t, int64_t, int64_t, double, GemmOp<double>, GemmOp<double>, double*,
-                           double*, int64_t, double);
+                           double*, int64_t, double, GemmBatch);
 template void gemm<float>(Engine&, int64_t, int64_t, int64_t, double, GemmOp<float>, GemmOp<float>, float*, float*,
-                          int64_t, double);
+                          int64_t, double, GemmBatch);
 
 }  // namespace rtcc

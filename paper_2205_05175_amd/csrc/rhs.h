@@ -10,6 +10,7 @@ namespace rtcc {
 // Device arena for long-lived tensors of one context.
 struct Arena {
   std::vector<void*> blocks;
+  int nb = 1;  // members per tensor allocated by real() / cplx() (batch stride = one member)
   ~Arena() { release(); }
   void release() {
     for (void* p : blocks) (void)hipFree(p);
@@ -27,14 +28,19 @@ struct Arena {
   Ten<T> real(std::initializer_list<int64_t> dims) {
     int64_t n = 1;
     for (auto d : dims) n *= d;
-    return make_ten<T>(alloc<T>(n), nullptr, dims);
+    Ten<T> t = make_ten<T>(alloc<T>(nb * n), nullptr, dims);
+    t.bs = nb > 1 ? n : 0;
+    return t;
   }
+  // planar complex: all real planes of the batch, then all imaginary planes
   template <typename T>
   Ten<T> cplx(std::initializer_list<int64_t> dims) {
     int64_t n = 1;
     for (auto d : dims) n *= d;
-    T* p = alloc<T>(2 * n);
-    return make_ten<T>(p, p + n, dims);
+    T* p = alloc<T>(2 * nb * n);
+    Ten<T> t = make_ten<T>(p, p + nb * n, dims);
+    t.bs = nb > 1 ? n : 0;
+    return t;
   }
 };
 
@@ -60,8 +66,9 @@ struct Work {
 
 template <typename T>
 void build_ints(Engine& E, Arena& A, int o, int v, const double* eri_dev, Ints<T>& I);
+// Workspace for nb members (nb > 1: every tensor batched, see Engine::nb).
 template <typename T>
-void build_work(Arena& A, int o, int v, Work<T>& w);
+void build_work(Arena& A, int o, int v, Work<T>& w, int nb = 1);
 // Residuals at the amplitudes held in w (t1, t2, l1, l2) and the Fock matrix w.f.
 // twobody=false evaluates the residuals of the one-body operator w.f alone.
 template <typename T>

@@ -24,6 +24,7 @@ Ten<T> view(const Ten<T>& base, int64_t off, std::initializer_list<int64_t> dims
   for (auto d : dims) t.d[i++] = d;
   i = 0;
   for (auto s : strides) t.s[i++] = s;
+  t.bs = base.bs;
   return t;
 }
 
@@ -110,8 +111,13 @@ void build_ints<float>(Engine& E, Arena& A, int o, int v, const double* eri, Int
 }
 
 template <typename T>
-void build_work(Arena& A, int o, int v, Work<T>& w) {
+void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
   const int64_t n = o + v, ov = (int64_t)o * v, oovv = ov * ov;
+  struct Restore {
+    Arena& a;
+    ~Restore() { a.nb = 1; }
+  } restore{A};
+  A.nb = nb;
   w.o = o;
   w.v = v;
   w.n = (int)n;
@@ -259,7 +265,9 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     }
     // particle-particle ladder: one GEMM over the stacked [tau; lambda2] rows
     {
-      const int64_t rows = (lambda ? 2 : 1) * (int64_t)o * o, vv = (int64_t)v * v;
+      // batched: the members' [tau; lambda2] blocks are consecutive rows of one operand
+      const int64_t rows = E.nb * (lambda || E.nb > 1 ? 2 : 1) * (int64_t)o * o, vv = (int64_t)v * v;
+      RTCC_CHECK(E.nb == 1 || w.X.bs == 2 * (int64_t)o * o * vv, kEInval, "ladder operand is not member-contiguous");
       GemmOp<T> a{w.X.re, w.X.im, vv, 0};
       GemmOp<T> b{I.vvvv.re, nullptr, vv, 1};  // B(ef, ab) = <ab|ef> = <ef|ab>: V is symmetric
       if (E.mark) E.mark(E.mark_user, 0);
@@ -448,8 +456,8 @@ void density(Engine& E, Work<T>& w) {
   P(2, "be->be", w.Dvv, rvv, 1);
 }
 
-template void build_work<double>(Arena&, int, int, Work<double>&);
-template void build_work<float>(Arena&, int, int, Work<float>&);
+template void build_work<double>(Arena&, int, int, Work<double>&, int);
+template void build_work<float>(Arena&, int, int, Work<float>&, int);
 template void residuals<double>(Engine&, const Ints<double>&, Work<double>&, bool, bool);
 template void residuals<float>(Engine&, const Ints<float>&, Work<float>&, bool, bool);
 template void density<double>(Engine&, Work<double>&);
