@@ -161,9 +161,11 @@ int rtcc_check_state(rtcc_ctx* ctx, const void* y, int64_t* nonfinite);
  * resets the statistics and brackets every subsequent ladder launch with HIP events recorded on
  * the context stream; rtcc_profile(ctx, 0) stops. While profiling is on, rtcc_propagate_rk4 issues
  * its kernels one by one instead of replaying the captured step graph (events recorded inside a
- * captured graph cannot be timed). rtcc_profile_read synchronises and returns the
- * number of timed launches, their summed duration in ms and the algorithmic real flops of one
- * launch (4 * rows * v^2 * v^2 for rows = 2 o^2 complex rows times the real <ab|ef> matrix). */
+ * captured graph cannot be timed); rtcc_propagate_batch does the same when any of its contexts
+ * is profiling, and times that context's batched ladder. rtcc_profile_read synchronises and returns
+ * the number of timed launches, their summed duration in ms and the algorithmic real flops of the
+ * last timed launch (4 * rows * v^2 * v^2 for rows = 2 o^2 complex rows per member times the real
+ * <ab|ef> matrix). */
 int rtcc_profile(rtcc_ctx* ctx, int enable);
 int rtcc_profile_read(rtcc_ctx* ctx, int64_t* launches, double* total_ms, double* flops_per_launch);
 

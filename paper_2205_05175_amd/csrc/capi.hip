@@ -209,9 +209,10 @@ void prof_flush(rtcc_ctx* c) {
   c->ev_used = 0;
 }
 
-void prof_mark(void* user, int phase) {
+void prof_mark(void* user, int phase, double flops) {
   rtcc_ctx* c = (rtcc_ctx*)user;
   if (!c->prof) return;
+  c->prof_flops = flops;
   if (phase == 0 && c->ev_used + 2 > (int)c->ev.size()) prof_flush(c);
   RTCC_HIP(hipEventRecord(c->ev[c->ev_used++], c->stream));
   if (phase == 1) c->prof_launches++;
@@ -675,6 +676,7 @@ int rtcc_propagate_batch(rtcc_ctx* const* ctxs, int nsys, const int* nprop, void
   }
   return guarded(c0, [&] {
     bool dip[kMaxBatchSystems];
+    bool profiling = false;
     int off = 0;
     for (int s = 0; s < nsys; ++s) {
       rtcc_ctx* c = ctxs[s];
@@ -685,6 +687,9 @@ int rtcc_propagate_batch(rtcc_ctx* const* ctxs, int nsys, const int* nprop, void
       RTCC_HIP(hipMemcpyAsync(B.fdev, B.fhost.data(), nprop[s] * sizeof(FieldDev), hipMemcpyHostToDevice,
                               c0->stream));
       dip[s] = mu_dev && mu_dev[s];
+      B.E.mark = c->E.mark;  // ladder timing of a profiling context
+      B.E.mark_user = c;
+      if (c->prof) profiling = true;
     }
     // initial time and dipoles on every system's stream
     batch_fork(ctxs, nsys);
@@ -693,7 +698,8 @@ int rtcc_propagate_batch(rtcc_ctx* const* ctxs, int nsys, const int* nprop, void
       scalar_update(c->stream, c->batch->tdev, t0, false);
       if (dip[s]) dipole_batch_dev(c, ys[s], mu_dev[s]);
     }
-    if (!c0->use_graph) {
+    // HIP cannot time events recorded inside a captured graph: profiling runs the eager launches
+    if (!c0->use_graph || profiling) {
       for (int st = 0; st < nsteps; ++st)
         for (int s = 0; s < nsys; ++s)
           rk4_step_batch(ctxs[s], ys[s], h, dip[s] ? mu_dev[s] + (int64_t)6 * nprop[s] * (st + 1) : nullptr);
@@ -935,7 +941,7 @@ int rtcc_profile_read(rtcc_ctx* c, int64_t* launches, double* total_ms, double* 
     prof_flush(c);
     *launches = c->prof_launches;
     *total_ms = c->prof_ms;
-    *flops_per_launch = c->E.ladder_flops;
+    *flops_per_launch = c->prof_flops;
   });
 }
 

@@ -69,8 +69,9 @@ struct Engine {
   hipStream_t stream = nullptr;
   Scratch scratch;
   int64_t gemm_flops = 0;  // algorithmic real flops issued (accounting)
-  // optional hook called before (phase 0) and after (phase 1) the ladder GEMM launch
-  void (*mark)(void*, int) = nullptr;
+  // optional hook called before (phase 0) and after (phase 1) the ladder GEMM launch; the
+  // third argument is the launch's algorithmic real flops
+  void (*mark)(void*, int, double) = nullptr;
   void* mark_user = nullptr;
   double ladder_flops = 0.0;  // algorithmic real flops of the last ladder GEMM
   bool trace = false;         // print every contraction's layout decisions to stderr

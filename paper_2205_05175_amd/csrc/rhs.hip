@@ -270,10 +270,10 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
       RTCC_CHECK(E.nb == 1 || w.X.bs == 2 * (int64_t)o * o * vv, kEInval, "ladder operand is not member-contiguous");
       GemmOp<T> a{w.X.re, w.X.im, vv, 0};
       GemmOp<T> b{I.vvvv.re, nullptr, vv, 1};  // B(ef, ab) = <ab|ef> = <ef|ab>: V is symmetric
-      if (E.mark) E.mark(E.mark_user, 0);
-      gemm<T>(E, rows, vv, vv, 1.0, a, b, w.Lad.re, w.Lad.im, vv, 0.0);
-      if (E.mark) E.mark(E.mark_user, 1);
       E.ladder_flops = 4.0 * (double)rows * (double)vv * (double)vv;  // real x complex: 2 MACs per entry
+      if (E.mark) E.mark(E.mark_user, 0, E.ladder_flops);
+      gemm<T>(E, rows, vv, vv, 1.0, a, b, w.Lad.re, w.Lad.im, vv, 0.0);
+      if (E.mark) E.mark(E.mark_user, 1, E.ladder_flops);
     }
     C(1, "ijef,mafe->ijam", tau, I.ovvv, w.Z1, 0);
     // ring intermediates (element X_mbej at (m,e,j,b))
