@@ -137,6 +137,37 @@ int rtcc_propagate_batch(rtcc_ctx* const* ctxs, int nsys, const int* nprop, void
 int rtcc_step_cashkarp(rtcc_ctx* ctx, void* y, double* t, double* h, double eps, const rtcc_field* field,
                        int* accepted, double* delta);
 
+/* ---- Adjoint (vector-Jacobian products) -------------------------------------------------------
+ * Gradients follow the convention for a real loss L of complex variables z: zbar = dL/dRe z + i dL/dIm z
+ * (PyTorch's), so a map z -> w(z) holomorphic in z sends wbar to J^H wbar.
+ *
+ * Structure used (equations of motion Eqs. derivT/derivL): with the Lagrangian L = <0|(1+Lambda)Hbar|0>,
+ * dt/dt = -i dL/dlambda and dlambda/dt = +i dL/dt; in the closed-shell variables of this ABI this reads
+ * F = S grad L with S = [[0, -i G^-1], [i G^-1, 0]], G the closed-shell metric (singles: 2 x_ia; doubles:
+ * 2 x_ijab - x_ijba). Hence the bilinear transpose of the Jacobian is J^T w = -S^-1 J (S w), and J u is
+ * evaluated exactly as the first Taylor coefficient of the degree-4 polynomial F(y + eps u) from four
+ * points on a circle in the complex eps plane (one batched evaluation of four right-hand sides).
+ * All three calls run the right-hand sides in the context's precision (the dipole gradient in FP64) and
+ * accumulate in FP64. The cotangents are DEVICE states (layout above) and must not overlap y. */
+
+/* ybar_out = J^H ybar with J = dF/dy at (y, field E); if Ebar (HOST) is not NULL, Ebar[a] = d/dE_a of
+ * Re <ybar, F> = -Re sum conj(ybar) F[mu_a, 0](y) (synchronises). ybar_out must not overlap ybar or y. */
+int rtcc_rhs_vjp(rtcc_ctx* ctx, const void* y, double t, const double E[3], const void* ybar, void* ybar_out,
+                 double Ebar[3]);
+
+/* ybar += gradient of Re sum_a conj(mubar_a) mu_a(y) (mubar_a = mubar[2a] + i mubar[2a+1], HOST), i.e.
+ * the adjoint of rtcc_dipole: with mu_a = mu_ref_a + L[mu_a, 0](y) its bilinear gradient is
+ * S^-1 F[mu_a, 0](y), F[mu_a, 0] the right-hand side of the operator mu_a alone. Asynchronous. */
+int rtcc_dipole_vjp(rtcc_ctx* ctx, const void* y, const double mubar[6], void* ybar);
+
+/* Adjoint of one rtcc_step_rk4 from (y, t) with step h: on entry ybar is the gradient with respect to the
+ * step's result, on return with respect to y (the discrete adjoint of the RK4 map: the four stage states
+ * are recomputed from y, then J^H is applied stage by stage in reverse). For a Gaussian pulse (kind 1),
+ * pbar[0..3] (HOST) += the gradient with respect to (E0, omega, sigma, t0) through
+ * dF/dp = -(de/dp) F[n . mu, 0], e(t) the pulse amplitude (synchronises); other kinds leave pbar alone. */
+int rtcc_step_rk4_vjp(rtcc_ctx* ctx, const void* y, double t, double h, const rtcc_field* field, void* ybar,
+                      double pbar[4]);
+
 /* Complex dipole expectation value (Eq. dipole), reference part included, into mu[6] (HOST):
  * (Re mu_x, Im mu_x, Re mu_y, Im mu_y, Re mu_z, Im mu_z). Computed in FP64. Synchronises. */
 int rtcc_dipole(rtcc_ctx* ctx, const void* y, double mu[6]);

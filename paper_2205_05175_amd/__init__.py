@@ -55,6 +55,9 @@ def load_library(path: str = LIB_PATH):
     L.rtcc_propagate_rk4.argtypes = [vp, vp, d, d, i, ctypes.POINTER(Field), vp]
     L.rtcc_propagate_batch.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(vp),
                                        ctypes.POINTER(Field), d, d, i, ctypes.POINTER(vp)]
+    L.rtcc_rhs_vjp.argtypes = [vp, vp, d, dp, vp, vp, dp]
+    L.rtcc_dipole_vjp.argtypes = [vp, vp, dp, vp]
+    L.rtcc_step_rk4_vjp.argtypes = [vp, vp, d, d, ctypes.POINTER(Field), vp, dp]
     L.rtcc_step_cashkarp.argtypes = [vp, vp, dp, dp, d, ctypes.POINTER(Field), ctypes.POINTER(i), dp]
     L.rtcc_dipole.argtypes = [vp, vp, dp]
     L.rtcc_dipole_dev.argtypes = [vp, vp, vp]
@@ -69,7 +72,7 @@ def load_library(path: str = LIB_PATH):
     L.rtcc_last_error.argtypes = [vp]
     L.rtcc_last_error.restype = ctypes.c_char_p
     for name in ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
-                 "rtcc_propagate_batch", "rtcc_step_cashkarp", "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick",
+                 "rtcc_propagate_batch", "rtcc_rhs_vjp", "rtcc_dipole_vjp", "rtcc_step_rk4_vjp", "rtcc_step_cashkarp", "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick",
                  "rtcc_check_state", "rtcc_info", "rtcc_profile", "rtcc_profile_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -77,9 +80,9 @@ def load_library(path: str = LIB_PATH):
 
 
 EXPORTED = ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
-            "rtcc_propagate_batch", "rtcc_step_cashkarp", "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick",
-            "rtcc_check_state", "rtcc_info", "rtcc_profile", "rtcc_profile_read", "rtcc_destroy",
-            "rtcc_last_error")
+            "rtcc_propagate_batch", "rtcc_rhs_vjp", "rtcc_dipole_vjp", "rtcc_step_rk4_vjp", "rtcc_step_cashkarp",
+            "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick", "rtcc_check_state", "rtcc_info",
+            "rtcc_profile", "rtcc_profile_read", "rtcc_destroy", "rtcc_last_error")
 
 
 class RTCCError(RuntimeError):
@@ -170,6 +173,30 @@ class RTCC:
         self._check(self.L.rtcc_step_cashkarp(self.ctx, self._state(y), ctypes.byref(tt), ctypes.byref(hh),
                                               float(eps), ctypes.byref(f), ctypes.byref(acc), ctypes.byref(delta)))
         return tt.value, hh.value, bool(acc.value), delta.value
+
+    def rhs_vjp(self, y, E, ybar, out=None, t=0.0, want_E=False):
+        """J^H ybar at (y, E); with want_E also the gradient with respect to the field vector E."""
+        if out is None:
+            out = self.new_state()
+        Ea = (ctypes.c_double * 3)(*[float(x) for x in E])
+        Eb = np.zeros(3) if want_E else None
+        self._check(self.L.rtcc_rhs_vjp(self.ctx, self._state(y), float(t), Ea, self._state(ybar, "ybar"),
+                                        self._state(out, "out"), _dptr(Eb) if want_E else None))
+        return (out, Eb) if want_E else out
+
+    def dipole_vjp(self, y, mubar, ybar):
+        """ybar += gradient of Re sum_a conj(mubar_a) mu_a(y); mubar: 3 complex numbers."""
+        mb = np.asarray(mubar, dtype=np.complex128).reshape(3)
+        arr = np.ascontiguousarray(np.stack([mb.real, mb.imag], axis=1).reshape(6))
+        self._check(self.L.rtcc_dipole_vjp(self.ctx, self._state(y), _dptr(arr), self._state(ybar, "ybar")))
+
+    def step_rk4_vjp(self, y, t, h, field, ybar, pbar=None):
+        """Adjoint of step_rk4 from (y, t): ybar in/out; returns pbar (+= pulse-parameter gradient)."""
+        f = field if field is not None else Field.none()
+        pb = np.zeros(4) if pbar is None else pbar
+        self._check(self.L.rtcc_step_rk4_vjp(self.ctx, self._state(y), float(t), float(h), ctypes.byref(f),
+                                             self._state(ybar, "ybar"), _dptr(pb)))
+        return pb
 
     def dipole(self, y):
         out = np.zeros(6)

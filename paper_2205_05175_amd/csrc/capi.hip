@@ -57,6 +57,7 @@ struct BatchWS {
   std::vector<FieldDev> fhost;
   double* tdev = nullptr;     // start time of the current step (device)
   double* mu_slot = nullptr;  // nb * 6 dipole values written by a captured step
+  double* red = nullptr;      // reduction partials (2 * 1024) and results
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~BatchWS() {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -123,6 +124,8 @@ struct rtcc_ctx {
   // batched propagation: this context's batch workspace, and the multi-context step graph of the
   // calls in which this context comes first
   std::unique_ptr<BatchWS> batch;
+  std::unique_ptr<BatchWS> adj;  // 4 members: the circle points of the Jacobian-vector product
+  void* abuf[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // adjoint state buffers
   hipGraphExec_t bexec = nullptr;
   std::vector<uint64_t> bkey;
 };
@@ -332,11 +335,11 @@ void capture_step(rtcc_ctx* c, void* y, double h, const rtcc_field* field, bool 
 // ---- batched propagation -------------------------------------------------------------------------
 std::atomic<uint64_t> g_batch_gen{0};
 
-void ensure_batch(rtcc_ctx* c, int nb) {
-  if (c->batch && c->batch->nb == nb && c->batch->has32 == c->have32) return;
+void ensure_batch(rtcc_ctx* c, std::unique_ptr<BatchWS>& slot, int nb) {
+  if (slot && slot->nb == nb && slot->has32 == c->have32) return;
   // the old workspace may be in use by a step graph launched on another context's stream
-  if (c->batch) RTCC_HIP(hipDeviceSynchronize());
-  c->batch.reset();
+  if (slot) RTCC_HIP(hipDeviceSynchronize());
+  slot.reset();
   auto B = std::make_unique<BatchWS>();
   B->nb = nb;
   B->gen = ++g_batch_gen;
@@ -356,10 +359,12 @@ void ensure_batch(rtcc_ctx* c, int nb) {
   B->fhost.resize(nb);
   B->tdev = B->arena.alloc<double>(1);
   B->mu_slot = B->arena.alloc<double>(6 * (int64_t)nb);
+  B->red = B->arena.alloc<double>(2 * 1024 + 16);
   RTCC_HIP(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
   RTCC_HIP(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
-  c->batch = std::move(B);
+  slot = std::move(B);
 }
+void ensure_batch(rtcc_ctx* c, int nb) { ensure_batch(c, c->batch, nb); }
 
 template <typename T>
 void eval_rhs_batch(rtcc_ctx* c, BatchWS& B, Ints<T>& I, Work<T>& w, const void* y, double toff, void* out) {
@@ -369,8 +374,7 @@ void eval_rhs_batch(rtcc_ctx* c, BatchWS& B, Ints<T>& I, Work<T>& w, const void*
   pack_rhs<T>(B.E.stream, c->o, c->v, planes(w, false), out, 1.0, B.nb);
 }
 
-void rhs_batch(rtcc_ctx* c, const void* y, double toff, void* out) {
-  BatchWS& B = *c->batch;
+void rhs_batch(rtcc_ctx* c, BatchWS& B, const void* y, double toff, void* out) {
   if (c->precision == RTCC_FP64) {
     eval_rhs_batch<double>(c, B, c->I64, B.W64, y, toff, out);
   } else {
@@ -401,7 +405,7 @@ void rk4_step_batch(rtcc_ctx* c, void* y, double h, double* dip) {
       state_combo(B.E.stream, nst, y, s, ks, cs, B.ytmp);
       ys = B.ytmp;
     }
-    rhs_batch(c, ys, kRk4C[s] * h, B.k[s]);
+    rhs_batch(c, B, ys, kRk4C[s] * h, B.k[s]);
   }
   const void* ks[4] = {B.k[0], B.k[1], B.k[2], B.k[3]};
   double cs[4] = {h * kRk4B[0], h * kRk4B[1], h * kRk4B[2], h * kRk4B[3]};
@@ -461,6 +465,64 @@ void capture_batch(rtcc_ctx* const* ctxs, int nsys, void* const* ys, double h, c
   (void)hipGraphDestroy(g);
   RTCC_HIP(e);
   c0->bkey = key;
+}
+
+// ---- adjoint ----------------------------------------------------------------------------------------
+// The right-hand side F = S_hat grad L of the Lagrangian L = <0|(1+Lambda) Hbar|0> in closed-shell
+// variables, S_hat = [[0, -i G^-1], [i G^-1, 0]] with the closed-shell metric G (singles 2, doubles
+// 2 x_ijab - x_ijba), so the Jacobian J = S_hat Hess(L) has the bilinear transpose
+// J^T w = -S_hat^-1 J (S_hat w): a vector-Jacobian product is a Jacobian-vector product between two
+// swaps. F is a polynomial of degree 4 in the state, so J u is the first Taylor coefficient of
+// F(y + eps u), extracted exactly from four points on a circle in the complex eps plane.
+const int kCircleM = 4;
+const double kCircleRho = 0.1;  // circle radius in units of 1 / max|u|
+
+void ensure_adj(rtcc_ctx* c) {
+  ensure_batch(c, c->adj, kCircleM);
+  if (!c->abuf[0])
+    for (auto& p : c->abuf) p = c->arena.alloc<double>(2 * c->nstate);
+}
+
+void set_adj_field(rtcc_ctx* c, const FieldDev& fd, double t) {
+  BatchWS& A = *c->adj;
+  for (auto& f : A.fhost) f = fd;
+  upload_fields(c->stream, A.fhost.data(), A.nb, A.fdev);
+  scalar_update(c->stream, A.tdev, t, false);
+}
+
+// out = J^H ybar (the gradient convention of a real loss: Re-part + i Im-part derivatives), J = dF/dy at y
+// for the adjoint workspace's field at time *tdev + toff. out must not overlap ybar or y.
+void rhs_vjp_dev(rtcc_ctx* c, const void* y, double toff, const void* ybar, void* out) {
+  BatchWS& A = *c->adj;
+  hipStream_t st = c->stream;
+  void* u = c->abuf[0];
+  void* Ju = c->abuf[1];
+  double* maxu = A.red + 2048;
+  // J^H ybar = conj(J^T conj(ybar)) = conj(-S_hat^-1 J S_hat conj(ybar))
+  hamil_apply(st, c->o, c->v, ybar, nullptr, nullptr, false, true, false, 1.0, false, u);
+  max_abs(st, c->nstate, u, A.red, maxu);
+  circle_points(st, c->nstate, y, u, maxu, kCircleRho, kCircleM, A.ytmp);
+  rhs_batch(c, A, A.ytmp, toff, A.k[0]);
+  circle_coef1(st, c->nstate, A.k[0], maxu, kCircleRho, kCircleM, Ju);
+  hamil_apply(st, c->o, c->v, Ju, nullptr, nullptr, true, false, true, -1.0, false, out);
+}
+
+// out = F[m . mu, 0](y): the right-hand side of the one-body operator m . mu alone (context precision)
+void one_body_rhs(rtcc_ctx* c, const void* y, const double m[3], void* out, bool fp64) {
+  const double E[3] = {-m[0], -m[1], -m[2]};
+  if (fp64 || c->precision == RTCC_FP64) eval_rhs<double>(c, c->I64, c->W64, y, E, 0.0, false, out, 1.0);
+  else eval_rhs<float>(c, c->I32, c->W32, y, E, 0.0, false, out, 1.0);
+}
+
+// Derivatives of the Gaussian pulse amplitude e(t) = -E0 exp(-x^2 / (2 sigma^2)) cos(omega x), x = t - t0,
+// with respect to (E0, omega, sigma, t0).
+void pulse_grad(const FieldDev& fd, double t, double g[4]) {
+  const double x = t - fd.t0, s2 = fd.sigma * fd.sigma;
+  const double env = std::exp(-0.5 * x * x / s2), cs = std::cos(fd.omega * x), sn = std::sin(fd.omega * x);
+  g[0] = -env * cs;
+  g[1] = fd.E0 * env * sn * x;
+  g[2] = -fd.E0 * env * cs * x * x / (s2 * fd.sigma);
+  g[3] = -fd.E0 * env * (x * cs / s2 + fd.omega * sn);
 }
 
 void sync_read(rtcc_ctx* c, const double* dev, double* host, int n) {
@@ -684,8 +746,7 @@ int rtcc_propagate_batch(rtcc_ctx* const* ctxs, int nsys, const int* nprop, void
       BatchWS& B = *c->batch;
       for (int m = 0; m < nprop[s]; ++m) B.fhost[m] = to_dev(&fields[off + m]);
       off += nprop[s];
-      RTCC_HIP(hipMemcpyAsync(B.fdev, B.fhost.data(), nprop[s] * sizeof(FieldDev), hipMemcpyHostToDevice,
-                              c0->stream));
+      upload_fields(c0->stream, B.fhost.data(), nprop[s], B.fdev);
       dip[s] = mu_dev && mu_dev[s];
       B.E.mark = c->E.mark;  // ladder timing of a profiling context
       B.E.mark_user = c;
@@ -714,6 +775,114 @@ int rtcc_propagate_batch(rtcc_ctx* const* ctxs, int nsys, const int* nprop, void
         if (dip[s])
           RTCC_HIP(hipMemcpyAsync(mu_dev[s] + (int64_t)6 * nprop[s] * (st + 1), ctxs[s]->batch->mu_slot,
                                   6 * nprop[s] * sizeof(double), hipMemcpyDeviceToDevice, c0->stream));
+    }
+  });
+}
+
+int rtcc_rhs_vjp(rtcc_ctx* c, const void* y, double t, const double E[3], const void* ybar, void* ybar_out,
+                 double Ebar[3]) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !E || !ybar || !ybar_out || ybar_out == ybar || ybar_out == y || !std::isfinite(t) ||
+      !std::isfinite(E[0]) || !std::isfinite(E[1]) || !std::isfinite(E[2])) {
+    c->err = "rtcc_rhs_vjp: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] {
+    ensure_adj(c);
+    FieldDev fd{};
+    fd.kind = kFieldConstant;
+    for (int a = 0; a < 3; ++a) fd.n[a] = E[a];
+    set_adj_field(c, fd, t);
+    rhs_vjp_dev(c, y, 0.0, ybar, ybar_out);
+    if (Ebar) {
+      // dF/dE_a = -F[mu_a, 0](y)
+      for (int a = 0; a < 3; ++a) {
+        double m[3] = {0, 0, 0};
+        m[a] = 1.0;
+        one_body_rhs(c, y, m, c->abuf[2], false);
+        vdot(c->stream, c->nstate, ybar, c->abuf[2], c->red, c->redout + 40 + 2 * a);
+      }
+      double d[6];
+      sync_read(c, c->redout + 40, d, 6);
+      for (int a = 0; a < 3; ++a) Ebar[a] = -d[2 * a];
+    }
+  });
+}
+
+int rtcc_dipole_vjp(rtcc_ctx* c, const void* y, const double mubar[6], void* ybar) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !mubar || !ybar || ybar == y) {
+    c->err = "rtcc_dipole_vjp: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(mubar[i])) {
+      c->err = "rtcc_dipole_vjp: non-finite cotangent";
+      return RTCC_EINVAL;
+    }
+  return guarded(c, [&] {
+    ensure_adj(c);
+    // mu_a = mu_ref_a + L[mu_a, 0](y), so its bilinear gradient is S_hat^-1 F[mu_a, 0](y). With
+    // g_a = mubar_a: ybar += sum_a conj(S_hat^-1 F[mu_a, 0]) g_a = conj(S_hat^-1 F[sum_a conj(g_a) mu_a, 0]),
+    // F linear in the operator: F[Re c . mu] + i F[Im c . mu] with c = conj(g).
+    const double mr[3] = {mubar[0], mubar[2], mubar[4]}, mi[3] = {-mubar[1], -mubar[3], -mubar[5]};
+    one_body_rhs(c, y, mr, c->abuf[2], true);
+    one_body_rhs(c, y, mi, c->abuf[3], true);
+    const double ci[2] = {0.0, 1.0};
+    hamil_apply(c->stream, c->o, c->v, c->abuf[2], c->abuf[3], ci, true, false, true, 1.0, true, ybar);
+  });
+}
+
+int rtcc_step_rk4_vjp(rtcc_ctx* c, const void* y, double t, double h, const rtcc_field* field, void* ybar,
+                      double pbar[4]) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !ybar || ybar == y || !std::isfinite(t) || !std::isfinite(h)) {
+    c->err = "rtcc_step_rk4_vjp: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] {
+    ensure_adj(c);
+    const FieldDev fd = to_dev(field);
+    const bool pulse = fd.kind == 1;
+    hipStream_t st = c->stream;
+    const int64_t nst = c->nstate;
+    // stage states of the step (recomputed): Y1 = y, Y2, Y3, Y4
+    void* Ys[4] = {const_cast<void*>(y), c->y4, c->y5, c->ytmp};
+    scalar_update(st, c->tdev, t, false);
+    for (int s = 0; s < 3; ++s) {
+      rhs_t(c, Ys[s], fd, kRk4C[s] * h, c->k[s]);
+      const void* ks[1] = {c->k[s]};
+      double cs[1] = {h * kRk4A[s + 1][s]};
+      state_combo(st, nst, y, 1, ks, cs, Ys[s + 1]);
+    }
+    // reverse sweep: kbar_s = h b_s ybar + h a_{s+1,s} g_{s+1}, g_s = J_s^H kbar_s, ybar += sum_s g_s
+    void* yb0 = c->k[5];
+    void* kbar = c->k[4];
+    void* g = c->k[3];
+    void* Fn = c->k[0];
+    RTCC_HIP(hipMemcpyAsync(yb0, ybar, nst * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    set_adj_field(c, fd, t);
+    for (int s = 3; s >= 0; --s) {
+      const void* ks[2] = {yb0, g};
+      double cs[2] = {h * kRk4B[s], s < 3 ? h * kRk4A[s + 1][s] : 0.0};
+      state_combo(st, nst, nullptr, 2, ks, cs, kbar);
+      if (pulse) {
+        one_body_rhs(c, Ys[s], fd.n, Fn, false);
+        vdot(st, nst, kbar, Fn, c->red, c->redout + 48 + 2 * s);
+      }
+      rhs_vjp_dev(c, Ys[s], kRk4C[s] * h, kbar, g);
+      const void* kg[1] = {g};
+      double one[1] = {1.0};
+      state_combo(st, nst, ybar, 1, kg, one, ybar);
+    }
+    if (pulse && pbar) {
+      double d[8];
+      sync_read(c, c->redout + 48, d, 8);
+      for (int s = 0; s < 4; ++s) {
+        double gp[4];
+        pulse_grad(fd, t + kRk4C[s] * h, gp);
+        for (int j = 0; j < 4; ++j) pbar[j] -= gp[j] * d[2 * s];
+      }
     }
   });
 }

@@ -18,6 +18,9 @@ template <typename T>
 void pack_rhs(hipStream_t st, int o, int v, Planes4<T> P, void* out, double scale, int nb = 1);
 template <typename T>
 void field_fock(hipStream_t st, int n, const double* f0, const double* mu, const double E[3], double s0, T* f);
+// Field on the device: the rtcc_field kinds (0 none, 1 Gaussian pulse, 2 kick = none while
+// stepping) and kFieldConstant, the constant field vector n (E0 and the pulse shape unused).
+constexpr int kFieldConstant = 3;
 struct FieldDev {
   int kind;
   double E0, omega, sigma, t0, n[3];
@@ -29,6 +32,8 @@ void field_fock_t(hipStream_t st, int n, const double* f0, const double* mu, con
 template <typename T>
 void field_fock_tb(hipStream_t st, int n, const double* f0, const double* mu, const FieldDev* fds, int nb,
                    const double* tdev, double toff, T* f, int64_t fbs);
+// dev[0..n) = host[0..n), enqueued as kernel arguments (the host array may change right after the call).
+void upload_fields(hipStream_t st, const FieldDev* host, int n, FieldDev* dev);
 // out[6 b + 2 a + (0, 1)] = (Re, Im) of mu_ref[a] + sum_pq rho_b[pq] mu_a[pq] for every member b;
 // rho_b at rho_re / rho_im + b * rbs (n*n entries). Fixed summation order.
 void dipole_batch(hipStream_t st, int nb, int64_t nn, const double* rho_re, const double* rho_im, int64_t rbs,
@@ -41,6 +46,13 @@ void dot_planar_real(hipStream_t st, int64_t n, const T* are, const T* aim, cons
 void max_abs_diff(hipStream_t st, int64_t n, const void* a, const void* b, double* partial, double* out2);
 void vdot(hipStream_t st, int64_t n, const void* a, const void* b, double* partial, double* out2);
 void count_nonfinite(hipStream_t st, int64_t n, const void* a, double* partial, double* out2);
+// Adjoint helpers (interleaved complex states of o, v): see elementwise.hip.
+void hamil_apply(hipStream_t st, int o, int v, const void* a, const void* b, const double cb[2], bool inverse,
+                 bool conj_in, bool conj_out, double scale, bool accumulate, void* out);
+void circle_points(hipStream_t st, int64_t nst, const void* y, const void* u, const double* maxu, double rho, int m,
+                   void* out);
+void circle_coef1(hipStream_t st, int64_t nst, const void* F, const double* maxu, double rho, int m, void* out);
+void max_abs(hipStream_t st, int64_t n, const void* a, double* partial, double* out2);
 template <typename T>
 void jacobi_update(hipStream_t st, int o, int v, const double* fdiag, const T* r1, const T* r2, void* x1, void* x2,
                    void* e1, void* e2);

@@ -192,6 +192,8 @@ __global__ void fock_time_batch_kernel(int64_t nn, const double* f0, const doubl
   if (fd.kind == 1) {
     double x = tdev[0] + toff - fd.t0;
     a = -fd.E0 * exp(-0.5 * x * x / (fd.sigma * fd.sigma)) * cos(fd.omega * x);
+  } else if (fd.kind == kFieldConstant) {
+    a = 1.0;
   }
   f[blockIdx.y * fbs + i] = (T)(f0[i] - a * (fd.n[0] * mu[i] + fd.n[1] * mu[nn + i] + fd.n[2] * mu[2 * nn + i]));
 }
@@ -208,6 +210,24 @@ template void field_fock_tb<double>(hipStream_t, int, const double*, const doubl
                                     const double*, double, double*, int64_t);
 template void field_fock_tb<float>(hipStream_t, int, const double*, const double*, const FieldDev*, int,
                                    const double*, double, float*, int64_t);
+
+// Fields reach the device as kernel arguments (copied at launch), never through a host staging buffer.
+struct FieldChunk {
+  FieldDev f[8];
+  int n;
+};
+__global__ void store_fields_kernel(FieldChunk ch, FieldDev* out) {
+  if ((int)threadIdx.x < ch.n) out[threadIdx.x] = ch.f[threadIdx.x];
+}
+void upload_fields(hipStream_t st, const FieldDev* host, int n, FieldDev* dev) {
+  for (int b = 0; b < n; b += 8) {
+    FieldChunk ch;
+    ch.n = std::min(8, n - b);
+    for (int i = 0; i < ch.n; ++i) ch.f[i] = host[b + i];
+    hipLaunchKernelGGL(store_fields_kernel, dim3(1), dim3(64), 0, st, ch, dev + b);
+    RTCC_HIP(hipGetLastError());
+  }
+}
 
 // One block per (component a, member b): strided per-thread sums, then the 256 thread sums
 // are combined in a fixed tree order through LDS.
@@ -322,7 +342,7 @@ __global__ void reduce_stage1(int64_t n, const void* a, const void* b, const voi
       s0 += (double)ar[i] * bv;
       s1 += (double)ai[i] * bv;
     } else if (MODE == 1) {
-      double2 p = ((const double2*)a)[i], q = ((const double2*)b)[i];
+      double2 p = ((const double2*)a)[i], q = b ? ((const double2*)b)[i] : make_double2(0.0, 0.0);
       double dx = p.x - q.x, dy = p.y - q.y;
       s0 = fmax(s0, sqrt(dx * dx + dy * dy));
     } else if (MODE == 2) {
@@ -402,6 +422,120 @@ void vdot(hipStream_t st, int64_t n, const void* a, const void* b, double* parti
 }
 void count_nonfinite(hipStream_t st, int64_t n, const void* a, double* partial, double* out2) {
   reduce<double, 3>(st, n, a, nullptr, nullptr, partial, out2);
+}
+
+// ---- adjoint helpers on the interleaved state ---------------------------------------------------
+// out (= or +=) scale * post( M( pre(a + cb * b) ) ) with M = Shat or Shat^-1:
+//   Shat   (x_T, x_L) = (-i Ginv x_L, +i Ginv x_T),   Ginv: singles x/2, doubles (2 x_ijab + x_ijba)/3
+//   Shat^-1(x_T, x_L) = (-i G x_L,    +i G x_T),      G:    singles 2 x, doubles 2 x_ijab - x_ijba
+// pre / post: complex conjugation when requested. a, b and out must not overlap.
+__global__ void hamil_kernel(int o, int v, const double2* __restrict__ a, const double2* __restrict__ b, double2 cb,
+                             int inverse, int conj_in, int conj_out, double scale, int accumulate,
+                             double2* __restrict__ out) {
+  const int64_t n1 = (int64_t)o * v, n2 = n1 * n1, nst = 2 * (n1 + n2);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nst; i += (int64_t)gridDim.x * blockDim.x) {
+    const bool tpart = i < n1 + n2;
+    const int64_t r = tpart ? i : i - (n1 + n2);  // offset inside the T or L half
+    const int64_t src = tpart ? i + (n1 + n2) : i - (n1 + n2);  // same offset in the other half
+    auto load = [&](int64_t k) {
+      double2 x = a[k];
+      if (b) {
+        double2 y = b[k];
+        x.x += cb.x * y.x - cb.y * y.y;
+        x.y += cb.x * y.y + cb.y * y.x;
+      }
+      if (conj_in) x.y = -x.y;
+      return x;
+    };
+    double2 x;
+    if (r < n1) {
+      double2 z = load(src);
+      double f = inverse ? 2.0 : 0.5;
+      x = make_double2(f * z.x, f * z.y);
+    } else {
+      const int64_t d = r - n1, bb = d % v, aa = (d / v) % v, pre = d / (v * (int64_t)v);
+      const int64_t sw = src - d + (pre * v + bb) * v + aa;  // (i j b a) in the other half
+      double2 z = load(src), zs = load(sw);
+      if (inverse) x = make_double2(2.0 * z.x - zs.x, 2.0 * z.y - zs.y);
+      else x = make_double2((2.0 * z.x + zs.x) / 3.0, (2.0 * z.y + zs.y) / 3.0);
+    }
+    // multiply by -i (T half of the output) or +i (L half): (-i)(x + iy) = y - ix
+    double2 res = tpart ? make_double2(x.y, -x.x) : make_double2(-x.y, x.x);
+    if (conj_out) res.y = -res.y;
+    res.x *= scale;
+    res.y *= scale;
+    if (accumulate) {
+      res.x += out[i].x;
+      res.y += out[i].y;
+    }
+    out[i] = res;
+  }
+}
+
+void hamil_apply(hipStream_t st, int o, int v, const void* a, const void* b, const double cb[2], bool inverse,
+                 bool conj_in, bool conj_out, double scale, bool accumulate, void* out) {
+  const int64_t n1 = (int64_t)o * v, nst = 2 * (n1 + n1 * n1);
+  int64_t blocks = std::min<int64_t>(cdiv(nst, 256), 8192);
+  hipLaunchKernelGGL(hamil_kernel, dim3((unsigned)blocks), dim3(256), 0, st, o, v, (const double2*)a,
+                     (const double2*)b, make_double2(cb ? cb[0] : 0.0, cb ? cb[1] : 0.0), inverse ? 1 : 0,
+                     conj_in ? 1 : 0, conj_out ? 1 : 0, scale, accumulate ? 1 : 0, (double2*)out);
+  RTCC_HIP(hipGetLastError());
+}
+
+// Radius of the evaluation circle: rho / max|u| (rho when u = 0).
+__device__ inline double circle_radius(const double* maxu, double rho) {
+  return maxu[0] > 0.0 ? rho / maxu[0] : rho;
+}
+
+// out[j] = y + r w^j u for the m points w^j = exp(2 pi i j / m)
+__global__ void circle_points_kernel(int64_t nst, const double2* __restrict__ y, const double2* __restrict__ u,
+                                     const double* maxu, double rho, int m, double2* __restrict__ out) {
+  const double r = circle_radius(maxu, rho);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nst * m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(i / nst);
+    const int64_t k = i - (int64_t)j * nst;
+    double sn, cs;
+    sincospi(2.0 * j / m, &sn, &cs);
+    const double2 uu = u[k], yy = y[k];
+    out[i] = make_double2(yy.x + r * (cs * uu.x - sn * uu.y), yy.y + r * (cs * uu.y + sn * uu.x));
+  }
+}
+
+void circle_points(hipStream_t st, int64_t nst, const void* y, const void* u, const double* maxu, double rho, int m,
+                   void* out) {
+  int64_t blocks = std::min<int64_t>(cdiv(nst * m, 256), 8192);
+  hipLaunchKernelGGL(circle_points_kernel, dim3((unsigned)blocks), dim3(256), 0, st, nst, (const double2*)y,
+                     (const double2*)u, maxu, rho, m, (double2*)out);
+  RTCC_HIP(hipGetLastError());
+}
+
+// out = (1 / (m r)) sum_j conj(w^j) F_j: the first-order Taylor coefficient of a polynomial of degree < m + 1
+// sampled on the circle (exact, no truncation error)
+__global__ void circle_coef1_kernel(int64_t nst, const double2* __restrict__ F, const double* maxu, double rho, int m,
+                                    double2* __restrict__ out) {
+  const double r = circle_radius(maxu, rho);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nst; k += (int64_t)gridDim.x * blockDim.x) {
+    double sx = 0.0, sy = 0.0;
+    for (int j = 0; j < m; ++j) {
+      double sn, cs;
+      sincospi(2.0 * j / m, &sn, &cs);
+      const double2 f = F[(int64_t)j * nst + k];
+      sx += cs * f.x + sn * f.y;  // conj(w) f = (cs - i sn)(fx + i fy)
+      sy += cs * f.y - sn * f.x;
+    }
+    out[k] = make_double2(sx / (m * r), sy / (m * r));
+  }
+}
+
+void circle_coef1(hipStream_t st, int64_t nst, const void* F, const double* maxu, double rho, int m, void* out) {
+  int64_t blocks = std::min<int64_t>(cdiv(nst, 256), 8192);
+  hipLaunchKernelGGL(circle_coef1_kernel, dim3((unsigned)blocks), dim3(256), 0, st, nst, (const double2*)F, maxu, rho,
+                     m, (double2*)out);
+  RTCC_HIP(hipGetLastError());
+}
+
+void max_abs(hipStream_t st, int64_t n, const void* a, double* partial, double* out2) {
+  reduce<double, 1>(st, n, a, nullptr, nullptr, partial, out2);
 }
 
 // ---- ground-state Jacobi update on the interleaved state: x += R / D ---------------------------
