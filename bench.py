@@ -152,11 +152,86 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_adjoint(args):
+    """Gradient of L = dt * trapezoid(Re mu_z) over 200 RK4 steps (dt = 0.05) at (10,38) with respect
+    to the Gaussian pulse (E0, omega, sigma, t0) = (0.01, 0.5, 5, 15) along z: complex-FP32 forward
+    with segment checkpoints every 20 steps, then the adjoint sweep (FP64 adjoint state). Checked
+    against central differences (h = 1e-5) of the GPU FP64 loss."""
+    import torch
+    from paper_2205_05175_amd import RTCC, Field
+    from paper_2205_05175_amd.adjoint import integrated_dipole, pulse_dipole_trajectory
+    from synth import make_system
+
+    o, v, dt, N, every = 10, 38, 0.05, args.steps, 20
+    n = [0.0, 0.0, 1.0]
+    p0 = np.array([0.01, 0.5, 5.0, 15.0])
+    eri, fock, mu = make_system(o, v, 0)
+    R = RTCC(eri, fock, mu, o, v, "fp32")
+    y0 = R.new_state()
+    R.set_precision("fp64")
+    R.ground_state(y0, 1e-12, 200)
+    R.set_precision("fp32")
+
+    def grad_once():
+        params = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        L = integrated_dipole(pulse_dipole_trajectory(R, params, y0, n, 0.0, dt, N, every=every), dt)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        return params.grad.numpy().copy(), L.item(), tb - ta, tc - tb
+
+    for _ in range(max(args.warmup, 1)):
+        grad_once()
+    reps = 3
+    runs = [grad_once() for _ in range(reps)]
+    g, L, tf, tbk = runs[-1]
+    tf = min(r[2] for r in runs)
+    tbk = min(r[3] for r in runs)
+    log(f"[bench] adjoint: forward {tf:.3f} s, backward {tbk:.3f} s, grad {g}")
+
+    def loss64(pp):
+        R.set_precision("fp64")
+        y = y0.clone()
+        m = torch.zeros((N + 1, 6), dtype=torch.float64, device="cuda")
+        R.propagate_rk4(y, 0.0, dt, N, Field.gaussian(*pp, n), m)
+        x = m[:, 4].cpu().numpy()
+        return dt * (x.sum() - 0.5 * (x[0] + x[-1]))
+
+    fd = np.zeros(4)
+    for j in range(4):
+        st = 1e-5 * (1.0 if j == 0 else abs(p0[j]))
+        e = np.zeros(4)
+        e[j] = st
+        fd[j] = (loss64(p0 + e) - loss64(p0 - e)) / (2 * st)
+    R.set_precision("fp32")
+    err = float(np.abs(g - fd).max() / np.abs(fd).max())
+    line = {
+        "metric": "adjoint gradient of the time-integrated dipole w.r.t. the pulse parameters, (10,38), 200 RK4 steps",
+        "value": 1.0 / (tf + tbk), "unit": "gradients/s", "n_gpus": 1, "steps": N, "warmup": args.warmup,
+        "ms_per_step": 1e3 * (tf + tbk) / N, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "rt-ccsd adjoint: synthetic water-shaped (10,38) seed 0, Gaussian pulse E0=0.01 "
+                               "omega=0.5 sigma=5 t0=15 along z, RK4 dt=0.05, loss dt*trapz(Re mu_z), "
+                               "checkpoints every 20 steps",
+                   "precision": "complex fp32 contractions, fp64 state and adjoint", "parallelism": "single GPU"},
+        "forward_s": tf, "backward_s": tbk, "backward_over_forward": tbk / tf,
+        "gradient": g.tolist(), "fd_gradient_fp64": fd.tolist(), "max_rel_err_vs_fd": err,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["single", "batch"], default="single",
-                    help="single: the o=20 v=76 propagation (default); batch: 24 batched propagations")
+    ap.add_argument("--workload", choices=["single", "batch", "adjoint"], default="single",
+                    help="single: the o=20 v=76 propagation (default); batch: 24 batched propagations; "
+                         "adjoint: pulse-parameter gradient at (10,38)")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--o", type=int, default=20)
@@ -172,6 +247,10 @@ def main():
         if args.steps is None:
             args.steps = 500
         return bench_batch(args)
+    if args.workload == "adjoint":
+        if args.steps is None:
+            args.steps = 200
+        return bench_adjoint(args)
     if args.steps is None:
         args.steps = 20
 
