@@ -310,6 +310,8 @@ void capture_step(rtcc_ctx* c, void* y, double h, const rtcc_field* field, bool 
   for (int i = 0; i < 3; ++i) key.n[i] = fd.n[i];
   if (c->gexec && key == c->gkey) return;
   if (c->gexec) {
+    // launches of the old graph may still be executing on this stream: let them finish first
+    RTCC_HIP(hipStreamSynchronize(c->stream));
     RTCC_HIP(hipGraphExecDestroy(c->gexec));
     c->gexec = nullptr;
   }
@@ -345,6 +347,7 @@ void ensure_batch(rtcc_ctx* c, std::unique_ptr<BatchWS>& slot, int nb) {
   B->gen = ++g_batch_gen;
   B->has32 = c->have32;
   B->E.stream = c->stream;
+  B->E.cache = c->E.cache;
   B->E.nb = nb;
   B->E.trace = c->E.trace;
   B->E.bf16_min_flops = c->E.bf16_min_flops;
@@ -446,6 +449,8 @@ void capture_batch(rtcc_ctx* const* ctxs, int nsys, void* const* ys, double h, c
   }
   if (c0->bexec && key == c0->bkey) return;
   if (c0->bexec) {
+    // launches of the old graph may still be executing on this stream: let them finish first
+    RTCC_HIP(hipStreamSynchronize(c0->stream));
     RTCC_HIP(hipGraphExecDestroy(c0->bexec));
     c0->bexec = nullptr;
   }
@@ -586,6 +591,7 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     RTCC_HIP(hipEventCreateWithFlags(&c->e_in, hipEventDisableTiming));
     RTCC_HIP(hipEventCreateWithFlags(&c->e_out, hipEventDisableTiming));
     c->E.stream = c->stream;
+    c->E.cache = const_cache_create();
     const char* bm = std::getenv("RTCC_BF16_MIN_FLOPS");
     if (bm && bm[0]) c->E.bf16_min_flops = std::atof(bm);
     const char* ng = std::getenv("RTCC_NO_GRAPH");
@@ -635,6 +641,8 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     RTCC_HIP(hipStreamSynchronize(c->stream));
   });
   if (st != RTCC_OK) {
+    const_cache_destroy(c->E.cache);
+    c->E.cache = nullptr;
     if (c->stream) (void)hipStreamDestroy(c->stream);
     if (c->e_in) (void)hipEventDestroy(c->e_in);
     if (c->e_out) (void)hipEventDestroy(c->e_out);
@@ -1138,7 +1146,9 @@ void rtcc_destroy(rtcc_ctx* c) {
   if (c->e_out) (void)hipEventDestroy(c->e_out);
   if (c->host_pinned) (void)hipHostFree(c->host_pinned);
   hipStream_t st = c->stream;
+  ConstCache* cache = c->E.cache;
   delete c;  // frees device memory first
+  const_cache_destroy(cache);
   if (st) (void)hipStreamDestroy(st);
 }
 

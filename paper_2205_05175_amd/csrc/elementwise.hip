@@ -1,38 +1,138 @@
 // Memory-bound kernels: strided permute-axpby, state (un)packing, RK stage updates, field,
 // and fixed-order wavefront reductions.
+#include <cstdio>
+#include <cstdlib>
+
 #include "elementwise.h"
 
 namespace rtcc {
 
+// ---- strided permute-axpby: out = alpha * permute(in) + beta * out -------------------------------
+// Dimensions that are contiguous on both sides are merged first. If the output's fastest dimension x
+// is also the input's fastest, every thread handles V consecutive elements along x (16-byte vectors
+// when aligned). Otherwise (a transpose) 32 x 32 tiles over x and p, the input's fastest dimension,
+// go through LDS: read with p across lanes, written with x across lanes. Indices are decoded with
+// 32-bit multiply-shift division (exact for numerators below 2^31).
+struct FDiv {
+  uint32_t m, s, d;
+};
+static FDiv make_fdiv(int64_t d) {
+  // Granlund-Montgomery: l = ceil(log2 d), m = floor(2^(31+l) / d) + 1, n / d = (n * m) >> (31 + l)
+  int l = 0;
+  while ((1LL << l) < d) ++l;
+  FDiv f;
+  f.m = (uint32_t)(((uint64_t)1 << (31 + l)) / (uint64_t)d + 1);
+  f.s = 31 + l;
+  f.d = (uint32_t)d;
+  return f;
+}
+__device__ inline uint32_t fdiv(uint32_t n, const FDiv& f) { return (uint32_t)(((uint64_t)n * f.m) >> f.s); }
+
+constexpr int kPT = 32;
 struct PermGeom {
-  int nd;
-  int64_t d[kMaxDim];
-  int64_t is[kMaxDim];
-  int64_t os[kMaxDim];
+  int nout;  // outer dimensions (<= kMaxDim - 1), outermost first
+  FDiv od[kMaxDim];
+  int64_t ois[kMaxDim], oos[kMaxDim];
+  FDiv dx, dp;  // tile dims (transpose) or x and x / V (element kernel: dp = groups per row)
+  int64_t isp, isx, osp, osx;
+  FDiv tx;      // tiles along x (transpose kernel)
+  FDiv tp;      // tiles along p
+  uint32_t nwork;  // tiles or element groups
+  int load_x_fast;
 };
 
+__device__ inline void decode_outer(const PermGeom& g, uint32_t rem, int64_t* ib, int64_t* ob) {
+  int64_t a = 0, b = 0;
+  for (int k = g.nout - 1; k >= 0; --k) {
+    const uint32_t q = fdiv(rem, g.od[k]);
+    const uint32_t c = rem - q * g.od[k].d;
+    rem = q;
+    a += (int64_t)c * g.ois[k];
+    b += (int64_t)c * g.oos[k];
+  }
+  *ib = a;
+  *ob = b;
+}
+
+template <typename T, int V>
+__global__ __launch_bounds__(256) void permute_elem_kernel(PermGeom g, const T* __restrict__ inre,
+                                                           const T* __restrict__ inim, T* outre, T* outim, T alpha,
+                                                           T beta) {
+  typedef T vt __attribute__((ext_vector_type(V)));
+  for (uint32_t w = blockIdx.x * 256 + threadIdx.x; w < g.nwork; w += gridDim.x * 256) {
+    const uint32_t row = fdiv(w, g.dp);            // dp = groups of V per row
+    const uint32_t x = (w - row * g.dp.d) * V;
+    int64_t ib, ob;
+    decode_outer(g, row, &ib, &ob);
+    ib += (int64_t)x * g.isx;
+    ob += (int64_t)x * g.osx;
+    if constexpr (V > 1) {
+      vt r = inre ? *reinterpret_cast<const vt*>(inre + ib) : vt{};
+      vt o = r * alpha;
+      if (beta != T(0)) o += beta * *reinterpret_cast<const vt*>(outre + ob);
+      *reinterpret_cast<vt*>(outre + ob) = o;
+      if (outim) {
+        vt ri = (inre && inim) ? *reinterpret_cast<const vt*>(inim + ib) : vt{};
+        vt oi = ri * alpha;
+        if (beta != T(0)) oi += beta * *reinterpret_cast<const vt*>(outim + ob);
+        *reinterpret_cast<vt*>(outim + ob) = oi;
+      }
+    } else {
+      T vr = inre ? alpha * inre[ib] : T(0);
+      if (beta != T(0)) vr += beta * outre[ob];
+      outre[ob] = vr;
+      if (outim) {
+        T vi = (inre && inim) ? alpha * inim[ib] : T(0);
+        if (beta != T(0)) vi += beta * outim[ob];
+        outim[ob] = vi;
+      }
+    }
+  }
+}
+
 template <typename T>
-__global__ void permute_kernel(PermGeom g, int64_t total, const T* __restrict__ inre, const T* __restrict__ inim,
-                               T* outre, T* outim, T alpha, T beta) {
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    int64_t rem = idx, io = 0, oo = 0;
+__global__ __launch_bounds__(256) void permute_tile_kernel(PermGeom g, const T* __restrict__ inre,
+                                                           const T* __restrict__ inim, T* outre, T* outim, T alpha,
+                                                           T beta) {
+  __shared__ T sre[kPT][kPT + 1];
+  __shared__ T sim[kPT][kPT + 1];
+  const int t = threadIdx.x;
+  for (uint32_t tile = blockIdx.x; tile < g.nwork; tile += gridDim.x) {
+    uint32_t rem = fdiv(tile, g.tx);
+    const int bx = (int)(tile - rem * g.tx.d);
+    const uint32_t r2 = fdiv(rem, g.tp);
+    const int bp = (int)(rem - r2 * g.tp.d);
+    int64_t ib, ob;
+    decode_outer(g, r2, &ib, &ob);
+    const int p0 = bp * kPT, x0 = bx * kPT;
+    const int dpn = (int)g.dp.d, dxn = (int)g.dx.d;
 #pragma unroll
-    for (int k = kMaxDim - 1; k >= 0; --k) {
-      if (k >= g.nd) continue;
-      int64_t c = rem % g.d[k];
-      rem /= g.d[k];
-      io += c * g.is[k];
-      oo += c * g.os[k];
+    for (int r = 0; r < kPT * kPT / 256; ++r) {
+      const int f = t & (kPT - 1), sidx = (t >> 5) + r * (256 / kPT);
+      const int ip = g.load_x_fast ? sidx : f, ix = g.load_x_fast ? f : sidx;
+      if (p0 + ip < dpn && x0 + ix < dxn) {
+        const int64_t off = ib + (int64_t)(p0 + ip) * g.isp + (int64_t)(x0 + ix) * g.isx;
+        sre[ix][ip] = inre[off];
+        if (outim) sim[ix][ip] = inim ? inim[off] : T(0);
+      }
     }
-    T vr = inre ? alpha * inre[io] : T(0);
-    if (beta != T(0)) vr += beta * outre[oo];
-    outre[oo] = vr;
-    if (outim) {
-      T vi = inim ? alpha * inim[io] : T(0);
-      if (beta != T(0)) vi += beta * outim[oo];
-      outim[oo] = vi;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPT * kPT / 256; ++r) {
+      const int ix = t & (kPT - 1), ip = (t >> 5) + r * (256 / kPT);
+      if (p0 + ip < dpn && x0 + ix < dxn) {
+        const int64_t off = ob + (int64_t)(p0 + ip) * g.osp + (int64_t)(x0 + ix) * g.osx;
+        T vr = alpha * sre[ix][ip];
+        if (beta != T(0)) vr += beta * outre[off];
+        outre[off] = vr;
+        if (outim) {
+          T vi = alpha * sim[ix][ip];
+          if (beta != T(0)) vi += beta * outim[off];
+          outim[off] = vi;
+        }
+      }
     }
+    __syncthreads();
   }
 }
 
@@ -40,29 +140,121 @@ template <typename T>
 void permute_axpby(hipStream_t st, int nd, const int64_t* dims, const T* inre, const T* inim, const int64_t* instr,
                    T* outre, T* outim, const int64_t* outstr, double alpha, double beta) {
   RTCC_CHECK(nd >= 0 && nd <= kMaxDim, kEInval, "permute: too many dimensions");
-  // order loops so the fastest-running index is the output's unit-stride one
-  int ord[kMaxDim];
-  for (int i = 0; i < nd; ++i) ord[i] = i;
-  for (int i = 0; i < nd; ++i)
-    for (int j = i + 1; j < nd; ++j)
-      if (outstr[ord[j]] > outstr[ord[i]]) std::swap(ord[i], ord[j]);
-  PermGeom g;
-  g.nd = nd;
-  int64_t total = 1;
-  for (int i = 0; i < nd; ++i) {
-    g.d[i] = dims[ord[i]];
-    g.is[i] = instr[ord[i]];
-    g.os[i] = outstr[ord[i]];
-    total *= g.d[i];
-  }
-  if (total == 0) return;
   if (alpha == 0.0) {
     inre = nullptr;
     inim = nullptr;
   }
-  int64_t blocks = std::min<int64_t>(cdiv(total, 256), 65536);
-  hipLaunchKernelGGL(permute_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, g, total, inre, inim, outre, outim,
-                     (T)alpha, (T)beta);
+  auto absl = [](int64_t x) { return x < 0 ? -x : x; };
+  // drop unit dimensions; an empty tensor is a no-op
+  int64_t d[kMaxDim], is[kMaxDim], os[kMaxDim];
+  int n = 0;
+  int64_t total = 1;
+  for (int i = 0; i < nd; ++i) {
+    if (dims[i] == 0) return;
+    if (dims[i] == 1) continue;
+    d[n] = dims[i];
+    is[n] = inre ? instr[i] : 0;
+    os[n] = outstr[i];
+    total *= dims[i];
+    ++n;
+  }
+  RTCC_CHECK(total < (1LL << 31), kEInval, "permute: tensor too large");
+  // order by output stride, outermost first, then merge dimensions contiguous on both sides
+  for (int a = 0; a < n; ++a)
+    for (int b = a + 1; b < n; ++b)
+      if (absl(os[b]) > absl(os[a])) {
+        std::swap(d[a], d[b]);
+        std::swap(is[a], is[b]);
+        std::swap(os[a], os[b]);
+      }
+  {
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+      if (m > 0 && os[m - 1] == os[i] * d[i] && is[m - 1] == is[i] * d[i]) {
+        d[m - 1] *= d[i];
+        is[m - 1] = is[i];
+        os[m - 1] = os[i];
+      } else {
+        d[m] = d[i];
+        is[m] = is[i];
+        os[m] = os[i];
+        ++m;
+      }
+    }
+    n = m;
+  }
+  PermGeom g;
+  const int ix = n - 1;  // output-fastest (ix = -1: a scalar)
+  int ip = -1;
+  if (inre && ix >= 0)
+    for (int i = 0; i < ix; ++i)
+      if (is[i] != 0 && absl(is[i]) < absl(is[ix]) && (ip < 0 || absl(is[i]) < absl(is[ip]))) ip = i;
+  static const bool trace = [] {
+    const char* t = std::getenv("RTCC_TRACE");
+    return t && t[0] == '1';
+  }();
+  const int64_t dxv = ix >= 0 ? d[ix] : 1;
+  g.isx = ix >= 0 ? is[ix] : 0;
+  g.osx = ix >= 0 ? os[ix] : 0;
+  if (ip < 0) {
+    // element kernel over (outer..., x)
+    constexpr int VW = 16 / sizeof(T);
+    bool vec = dxv % VW == 0 && g.osx == 1 && (g.isx == 1 || !inre) && ((uintptr_t)outre % 16) == 0 &&
+               (!outim || (uintptr_t)outim % 16 == 0) && (!inre || (uintptr_t)inre % 16 == 0) &&
+               (!inim || (uintptr_t)inim % 16 == 0);
+    for (int i = 0; i < ix; ++i) vec = vec && is[i] % VW == 0 && os[i] % VW == 0;
+    const int V = vec ? VW : 1;
+    g.nout = ix > 0 ? ix : 0;
+    for (int k = 0; k < g.nout; ++k) {
+      g.od[k] = make_fdiv(d[k]);
+      g.ois[k] = is[k];
+      g.oos[k] = os[k];
+    }
+    g.dp = make_fdiv(dxv / V);
+    g.nwork = (uint32_t)(total / V);
+    if (trace)
+      fprintf(stderr, "[rtcc] permute %s elem x=%lld(is %lld os %lld) V=%d outer=%d groups=%u cplx=%d beta=%g\n",
+              sizeof(T) == 8 ? "f64" : "f32", (long long)dxv, (long long)g.isx, (long long)g.osx, V, g.nout, g.nwork,
+              outim ? 1 : 0, beta);
+    const unsigned blocks = (unsigned)std::min<int64_t>(cdiv((int64_t)g.nwork, 256), 16384);
+    if (V > 1)
+      hipLaunchKernelGGL((permute_elem_kernel<T, VW>), dim3(blocks), dim3(256), 0, st, g, inre, inim, outre, outim,
+                         (T)alpha, (T)beta);
+    else
+      hipLaunchKernelGGL((permute_elem_kernel<T, 1>), dim3(blocks), dim3(256), 0, st, g, inre, inim, outre, outim,
+                         (T)alpha, (T)beta);
+    RTCC_HIP(hipGetLastError());
+    return;
+  }
+  // transpose: tiles over (p, x), outer = the rest
+  g.dx = make_fdiv(dxv);
+  g.dp = make_fdiv(d[ip]);
+  g.isp = is[ip];
+  g.osp = os[ip];
+  g.load_x_fast = 0;
+  g.nout = 0;
+  int64_t outer = 1;
+  for (int i = 0; i < ix; ++i) {
+    if (i == ip) continue;
+    g.od[g.nout] = make_fdiv(d[i]);
+    g.ois[g.nout] = is[i];
+    g.oos[g.nout] = os[i];
+    outer *= d[i];
+    ++g.nout;
+  }
+  const int64_t tx = cdiv(dxv, kPT), tp = cdiv(d[ip], kPT);
+  g.tx = make_fdiv(tx);
+  g.tp = make_fdiv(tp);
+  const int64_t ntiles = outer * tx * tp;
+  RTCC_CHECK(ntiles < (1LL << 31), kEInval, "permute: too many tiles");
+  g.nwork = (uint32_t)ntiles;
+  if (trace)
+    fprintf(stderr, "[rtcc] permute %s tile x=%lld(is %lld os %lld) p=%lld(is %lld os %lld) outer=%lld tiles=%lld cplx=%d beta=%g\n",
+            sizeof(T) == 8 ? "f64" : "f32", (long long)dxv, (long long)g.isx, (long long)g.osx, (long long)d[ip],
+            (long long)g.isp, (long long)g.osp, (long long)outer, (long long)ntiles, outim ? 1 : 0, beta);
+  const unsigned blocks = (unsigned)std::min<int64_t>(ntiles, 16384);
+  hipLaunchKernelGGL(permute_tile_kernel<T>, dim3(blocks), dim3(256), 0, st, g, inre, inim, outre, outim, (T)alpha,
+                     (T)beta);
   RTCC_HIP(hipGetLastError());
 }
 template void permute_axpby<double>(hipStream_t, int, const int64_t*, const double*, const double*, const int64_t*,

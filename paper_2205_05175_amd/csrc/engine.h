@@ -24,6 +24,8 @@ struct Ten {
   // Batch stride: 0 for a tensor shared by every member of a batch (the integrals), else the
   // element offset between consecutive members (both planes of a complex tensor).
   int64_t bs = 0;
+  // A constant operand (an integral block): permuted layouts of it are cached by the engine.
+  bool konst = false;
   bool cplx() const { return im != nullptr; }
   int64_t size() const {
     int64_t n = 1;
@@ -65,8 +67,15 @@ struct Scratch {
   void reset(size_t mark = 0) { used = mark; }
 };
 
+// Permuted copies of constant operands, made once and kept (shared by the engines of a context).
+struct ConstCache;
+ConstCache* const_cache_create();
+void const_cache_destroy(ConstCache* c);
+size_t const_cache_bytes(const ConstCache* c);
+
 struct Engine {
   hipStream_t stream = nullptr;
+  ConstCache* cache = nullptr;
   Scratch scratch;
   int64_t gemm_flops = 0;  // algorithmic real flops issued (accounting)
   // optional hook called before (phase 0) and after (phase 1) the ladder GEMM launch; the

@@ -2,7 +2,9 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <vector>
 
 #include "engine.h"
 
@@ -105,6 +107,93 @@ Ten<T> permuted_copy(Engine& E, const Ten<T>& X, const std::string& sx, const st
   return Y;
 }
 
+}  // namespace
+
+struct ConstCache {
+  struct Entry {
+    void* re = nullptr;
+    void* im = nullptr;
+    int nd = 0;
+    int64_t d[kMaxDim] = {0}, s[kMaxDim] = {0};
+  };
+  std::map<std::string, Entry> entries;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  hipStream_t side = nullptr;
+};
+
+ConstCache* const_cache_create() { return new ConstCache(); }
+void const_cache_destroy(ConstCache* c) {
+  if (!c) return;
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  for (void* p : c->allocs) (void)hipFree(p);
+  delete c;
+}
+size_t const_cache_bytes(const ConstCache* c) { return c ? c->bytes : 0; }
+
+namespace {
+
+// A constant operand permuted into letter order `order`, made on first use and kept. The copy is
+// made on the cache's own stream and waited for, so it is complete before any later work (also when
+// the first use happens while the engine's stream is being captured into a graph).
+template <typename T>
+Ten<T> cached_permute(Engine& E, const Ten<T>& X, const std::string& sx, const std::string& order) {
+  ConstCache& cc = *E.cache;
+  char head[64];
+  snprintf(head, sizeof head, "%p/%p/%d:", (const void*)X.re, (const void*)X.im, (int)sizeof(T));
+  std::string key(head);
+  for (char c : order) key += std::to_string(dim_of(X, sx, c)) + "," + std::to_string(str_of(X, sx, c)) + ";";
+  auto it = cc.entries.find(key);
+  Ten<T> Y;
+  Y.nd = (int)order.size();
+  Y.konst = true;
+  if (it != cc.entries.end()) {
+    const auto& e = it->second;
+    Y.re = (T*)e.re;
+    Y.im = (T*)e.im;
+    for (int i = 0; i < Y.nd; ++i) {
+      Y.d[i] = e.d[i];
+      Y.s[i] = e.s[i];
+    }
+    return Y;
+  }
+  int64_t n = 1;
+  for (int i = 0; i < Y.nd; ++i) {
+    Y.d[i] = dim_of(X, sx, order[i]);
+    n *= Y.d[i];
+  }
+  int64_t st = 1;
+  for (int i = Y.nd - 1; i >= 0; --i) {
+    Y.s[i] = st;
+    st *= Y.d[i];
+  }
+  const int planes = X.im ? 2 : 1;
+  void* p = nullptr;
+  RTCC_HIP(hipMalloc(&p, (size_t)std::max<int64_t>(n, 1) * planes * sizeof(T)));
+  cc.allocs.push_back(p);
+  cc.bytes += (size_t)std::max<int64_t>(n, 1) * planes * sizeof(T);
+  Y.re = (T*)p;
+  Y.im = X.im ? Y.re + std::max<int64_t>(n, 1) : nullptr;
+  if (!cc.side) RTCC_HIP(hipStreamCreateWithFlags(&cc.side, hipStreamNonBlocking));
+  int64_t d[kMaxDim], is[kMaxDim];
+  strides_for(X, sx, order, d, is);
+  permute_axpby<T>(cc.side, Y.nd, d, X.re, X.im, is, Y.re, Y.im, Y.s, 1.0, 0.0);
+  RTCC_HIP(hipStreamSynchronize(cc.side));
+  ConstCache::Entry e;
+  e.re = Y.re;
+  e.im = Y.im;
+  e.nd = Y.nd;
+  for (int i = 0; i < Y.nd; ++i) {
+    e.d[i] = Y.d[i];
+    e.s[i] = Y.s[i];
+  }
+  cc.entries[key] = e;
+  return Y;
+}
+
 std::string ordered(const std::string& from, const std::string& keep) {
   std::string r;
   for (char c : from)
@@ -161,8 +250,9 @@ Plan plan_for(const Ten<T>& A, const std::string& sa, const Ten<T>& B, const std
       for (int ik = 0; ik < 2; ++ik) {
         GemmOp<T> oa, ob, oc;
         int64_t cost = 0;
-        if (!view2d(A, sa, Mfrom[im], Kfrom[ik], &oa)) cost += A.size() * (A.cplx() ? 2 : 1);
-        if (!view2d(B, sb, Kfrom[ik], Nfrom[in], &ob)) cost += B.size() * (B.cplx() ? 2 : 1);
+        // a constant operand's permuted layouts are cached: free after the first use
+        if (!view2d(A, sa, Mfrom[im], Kfrom[ik], &oa) && !A.konst) cost += A.size() * (A.cplx() ? 2 : 1);
+        if (!view2d(B, sb, Kfrom[ik], Nfrom[in], &ob) && !B.konst) cost += B.size() * (B.cplx() ? 2 : 1);
         if (!view2d(C, sc, Mfrom[im], Nfrom[in], &oc)) cost += 3 * C.size() * (C.cplx() ? 2 : 1);
         if (best.cost < 0 || cost < best.cost) {
           best.cost = cost;
@@ -245,12 +335,12 @@ void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const T
   Ten<T> Ap = A, Bp = B;
   const std::string ha = (hb && bA) ? "Z" : "", hbb = (hb && bB) ? "Z" : "";
   if (!view2d(A, sa, bm, bk, &oa)) {
-    Ap = permuted_copy(E, A, sa, ha + bm + bk);
+    Ap = (A.konst && !bA && E.cache) ? cached_permute(E, A, sa, bm + bk) : permuted_copy(E, A, sa, ha + bm + bk);
     sa = ha + bm + bk;
     view2d(Ap, sa, bm, bk, &oa);
   }
   if (!view2d(B, sb, bk, bn, &ob)) {
-    Bp = permuted_copy(E, B, sb, hbb + bk + bn);
+    Bp = (B.konst && !bB && E.cache) ? cached_permute(E, B, sb, bk + bn) : permuted_copy(E, B, sb, hbb + bk + bn);
     sb = hbb + bk + bn;
     view2d(Bp, sb, bk, bn, &ob);
   }

@@ -146,9 +146,12 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
   const T* Ap[2] = {p.Are + oa, AC ? p.Aim + oa : nullptr};
   const T* Bp[2] = {p.Bre + ob, BC ? p.Bim + ob : nullptr};
 
-  // A tile: TA ? (rows k, cols m) : (rows m, cols k);  B tile: TB ? (rows n, cols k) : (rows k, cols n)
-  TileRegs<T, TA ? kBK : BM, TA ? BM : kBK, VEC, NA> ra;
-  TileRegs<T, TB ? BN : kBK, TB ? kBK : BN, VEC, NB> rb;
+  // A tile: TA ? (rows k, cols m) : (rows m, cols k);  B tile: TB ? (rows n, cols k) : (rows k, cols n).
+  // A narrow tile (32 rows or columns) has fewer elements than VEC per thread: use shorter vectors.
+  constexpr int VA = VEC < (kBK * BM) / kThreads ? VEC : (kBK * BM) / kThreads;
+  constexpr int VB = VEC < (kBK * BN) / kThreads ? VEC : (kBK * BN) / kThreads;
+  TileRegs<T, TA ? kBK : BM, TA ? BM : kBK, VA, NA> ra;
+  TileRegs<T, TB ? BN : kBK, TB ? kBK : BN, VB, NB> rb;
   auto fetch = [&](int k0) {
     if (TA) ra.load(Ap, p.lda, k0, m0, kend, p.M, tid);
     else ra.load(Ap, p.lda, m0, k0, p.M, kend, tid);
@@ -370,12 +373,16 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
   // FP32: 128 x 128 tiles when the grid still holds >= 2 tiles per CU; FP64 (longer MFMA,
   // more registers per tile): always 64 x 64 for occupancy. Small grids split over K.
   constexpr int LBM = 128, LBN = 128;
-  const bool large = sizeof(T) == 4 && cdiv(M, LBM) * cdiv(N, LBN) * nbt >= 512;
-  const int BM = large ? LBM : 64, BN = large ? LBN : 64;
+  // short K, one side of at most 32 against a long other side: a 32 x 256 (or 256 x 32) tile wastes
+  // little (long K goes to split-K instead)
+  const int narrow = K > 256 ? 0 : (M <= 32 && N >= 256) ? 1 : (N <= 32 && M >= 256) ? 2 : 0;
+  const bool large = !narrow && sizeof(T) == 4 && cdiv(M, LBM) * cdiv(N, LBN) * nbt >= 512;
+  const int BM = narrow == 1 ? 32 : narrow == 2 ? 256 : large ? LBM : 64;
+  const int BN = narrow == 1 ? 256 : narrow == 2 ? 32 : large ? LBN : 64;
   const int64_t tiles = cdiv(M, BM) * cdiv(N, BN) * nbt;
   // fewer than ~2 workgroups per CU: split K (chunks of >= 256) toward ~1024 workgroups
   int splits = 1;
-  if (!large && tiles < 512 && K >= 512) {
+  if (!large && !narrow && tiles < 512 && K >= 512) {
     int64_t want = std::max<int64_t>(1, 1024 / tiles);
     splits = (int)std::min<int64_t>({want, cdiv(K, 256), 1024, 65535 / nbt});
   }
@@ -399,7 +406,9 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
     p.Cim = Cim;
     p.ldc = ldc;
   }
-  if (large) launch_typed<T, LBM, LBN>(E.stream, p, nbt * splits, vec);
+  if (narrow == 1) launch_typed<T, 32, 256>(E.stream, p, nbt * splits, vec);
+  else if (narrow == 2) launch_typed<T, 256, 32>(E.stream, p, nbt * splits, vec);
+  else if (large) launch_typed<T, LBM, LBN>(E.stream, p, nbt * splits, vec);
   else launch_typed<T, 64, 64>(E.stream, p, nbt * splits, vec);
   if (splits > 1) {
     int64_t n = M * N;

@@ -37,6 +37,13 @@ void extract(Engine& E, const double* eri, int n, int p0, int q0, int r0, int s0
   permute_axpby<double>(E.stream, 4, out.d, base, nullptr, is, out.re, nullptr, out.s, 1.0, 0.0);
 }
 
+template <typename T>
+void mark_constant(Ints<T>& I) {
+  for (Ten<T>* t : {&I.oooo, &I.ooov, &I.oovv, &I.ovov, &I.ovvo, &I.ovvv, &I.vvvv, &I.Loovv, &I.Looov, &I.Lovvv,
+                    &I.Lovvo})
+    t->konst = true;
+}
+
 __global__ void convert_kernel(int64_t n, const double* in, float* out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     out[i] = (float)in[i];
@@ -76,6 +83,7 @@ void build_ints<double>(Engine& E, Arena& A, int o, int v, const double* eri, In
   padd<double>(E, -1.0, "mafe->maef", I.ovvv, I.Lovvv, 1.0);
   padd<double>(E, 2.0, "nafi->nafi", I.ovvo, I.Lovvo, 0.0);
   padd<double>(E, -1.0, "naif->nafi", I.ovov, I.Lovvo, 1.0);
+  mark_constant(I);
 }
 
 template <>
@@ -107,6 +115,7 @@ void build_ints<float>(Engine& E, Arena& A, int o, int v, const double* eri, Int
   I.Looov = cvt(D.Looov);
   I.Lovvv = cvt(D.Lovvv);
   I.Lovvo = cvt(D.Lovvo);
+  mark_constant(I);
   RTCC_HIP(hipStreamSynchronize(E.stream));  // tmp is freed on return
 }
 
