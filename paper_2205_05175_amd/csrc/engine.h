@@ -7,6 +7,8 @@
 // MFMA GEMM as a strided view; otherwise it is permuted into scratch first. Complex
 // tensors are planar: separate real and imaginary planes.
 #pragma once
+#include <functional>
+#include <string>
 #include <vector>
 #include "common.h"
 
@@ -72,6 +74,10 @@ struct ConstCache;
 ConstCache* const_cache_create();
 void const_cache_destroy(ConstCache* c);
 size_t const_cache_bytes(const ConstCache* c);
+// The buffer cached under `key`; on a miss `bytes` are allocated and fill(buffer, stream) is run on
+// the cache's own stream and waited for.
+void* const_cache_get(ConstCache* c, const std::string& key, size_t bytes,
+                      const std::function<void(void*, hipStream_t)>& fill);
 
 struct Engine {
   hipStream_t stream = nullptr;
@@ -111,6 +117,7 @@ struct GemmOp {
   const T* im;
   int64_t ld;
   int trans;
+  bool konst = false;  // constant operand: derived layouts of it may be cached
 };
 // Batched form: `n` independent products, operand X of product z at X + z * (batch stride of X);
 // a stride of 0 shares the operand.
@@ -124,6 +131,12 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
 
 bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<float> A, GemmOp<float> B,
                  float* Cre, float* Cim, int64_t ldc, double beta);
+
+// Sum `splits` partial planes P[s][m][n] (plane stride M * N) into C = alpha * sum + beta * C, in a
+// fixed order; nbatch members (member z's planes start at z * splits * M * N, its C at Cre + z * sc).
+template <typename T>
+void splitk_reduce_launch(hipStream_t st, const T* Pre, const T* Pim, int splits, int64_t M, int64_t N, T* Cre,
+                          T* Cim, int64_t ldc, int64_t sc, int nbatch, double alpha, double beta);
 
 // General strided permute-axpby on planar complex or real data (nd <= 6).
 template <typename T>

@@ -63,6 +63,7 @@ bool view2d(const Ten<T>& X, const std::string& sx, const std::string& g1, const
   if (!mergeable(X, sx, g1, &i1, &e1) || !mergeable(X, sx, g2, &i2, &e2)) return false;
   op->re = X.re;
   op->im = X.im;
+  op->konst = X.konst;
   if (e2 == 1 || i2 == 1) {  // row-major: X(r, c) = X[r*ld + c]
     op->trans = 0;
     op->ld = (e1 == 1) ? std::max<int64_t>(e2, 1) : i1;
@@ -133,6 +134,23 @@ void const_cache_destroy(ConstCache* c) {
   delete c;
 }
 size_t const_cache_bytes(const ConstCache* c) { return c ? c->bytes : 0; }
+
+void* const_cache_get(ConstCache* c, const std::string& key, size_t bytes,
+                      const std::function<void(void*, hipStream_t)>& fill) {
+  auto it = c->entries.find(key);
+  if (it != c->entries.end()) return it->second.re;
+  void* p = nullptr;
+  RTCC_HIP(hipMalloc(&p, std::max<size_t>(bytes, 1)));
+  c->allocs.push_back(p);
+  c->bytes += bytes;
+  if (!c->side) RTCC_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  fill(p, c->side);
+  RTCC_HIP(hipStreamSynchronize(c->side));
+  ConstCache::Entry e;
+  e.re = p;
+  c->entries[key] = e;
+  return p;
+}
 
 namespace {
 

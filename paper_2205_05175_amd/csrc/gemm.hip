@@ -283,6 +283,52 @@ __global__ __launch_bounds__(256) void splitk_reduce(const T* Pre, const T* Pim,
   }
 }
 
+// Few splits: one thread per output sums the partial planes in split order.
+template <typename T>
+__global__ __launch_bounds__(256) void splitk_reduce_few(const T* Pre, const T* Pim, int splits, int64_t stride,
+                                                         int M, int N, T* Cre, T* Cim, int64_t ldc, int64_t sc,
+                                                         T alpha, T beta) {
+  Pre += (int64_t)blockIdx.y * splits * stride;
+  if (Pim) Pim += (int64_t)blockIdx.y * splits * stride;
+  Cre += (int64_t)blockIdx.y * sc;
+  if (Cim) Cim += (int64_t)blockIdx.y * sc;
+  const int64_t n = (int64_t)M * N;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * 256) {
+    T ar = 0, ai = 0;
+    for (int s = 0; s < splits; ++s) {
+      ar += Pre[s * stride + idx];
+      if (Pim) ai += Pim[s * stride + idx];
+    }
+    const int row = (int)(idx / N), col = (int)(idx - (int64_t)row * N);
+    const int64_t off = (int64_t)row * ldc + col;
+    T outr = alpha * ar, outi = alpha * ai;
+    if (beta != T(0)) {
+      outr += beta * Cre[off];
+      if (Cim) outi += beta * Cim[off];
+    }
+    Cre[off] = outr;
+    if (Cim && Pim) Cim[off] = outi;
+  }
+}
+
+template <typename T>
+void splitk_reduce_launch(hipStream_t st, const T* Pre, const T* Pim, int splits, int64_t M, int64_t N, T* Cre,
+                          T* Cim, int64_t ldc, int64_t sc, int nbatch, double alpha, double beta) {
+  const int64_t n = M * N;
+  if (splits <= 24) {
+    hipLaunchKernelGGL(splitk_reduce_few<T>, dim3((unsigned)std::min<int64_t>(cdiv(n, 256), 8192), (unsigned)nbatch),
+                       dim3(256), 0, st, Pre, Pim, splits, n, (int)M, (int)N, Cre, Cim, ldc, sc, (T)alpha, (T)beta);
+  } else {
+    hipLaunchKernelGGL(splitk_reduce<T>, dim3((unsigned)cdiv(n, 16), (unsigned)nbatch), dim3(256), 0, st, Pre, Pim,
+                       splits, n, (int)M, (int)N, Cre, Cim, ldc, sc, (T)alpha, (T)beta);
+  }
+  RTCC_HIP(hipGetLastError());
+}
+template void splitk_reduce_launch<float>(hipStream_t, const float*, const float*, int, int64_t, int64_t, float*,
+                                          float*, int64_t, int64_t, int, double, double);
+template void splitk_reduce_launch<double>(hipStream_t, const double*, const double*, int, int64_t, int64_t, double*,
+                                           double*, int64_t, int64_t, int, double, double);
+
 template <typename T, int BM, int BN, int AC, int BC, int TA, int TB, int VEC>
 static void launch_one(hipStream_t st, const GemmParams<T>& p, int zdim) {
   dim3 grid((unsigned)cdiv(p.N, BN), (unsigned)cdiv(p.M, BM), (unsigned)zdim);
@@ -375,7 +421,10 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
   constexpr int LBM = 128, LBN = 128;
   // short K, one side of at most 32 against a long other side: a 32 x 256 (or 256 x 32) tile wastes
   // little (long K goes to split-K instead)
-  const int narrow = K > 256 ? 0 : (M <= 32 && N >= 256) ? 1 : (N <= 32 && M >= 256) ? 2 : 0;
+  const int narrow = K > 256                                            ? 0
+                     : (M <= 32 && N >= 256) || (M <= 96 && N >= 8192)   ? 1
+                     : (N <= 32 && M >= 256) || (N <= 96 && M >= 8192)   ? 2
+                                                                         : 0;
   const bool large = !narrow && sizeof(T) == 4 && cdiv(M, LBM) * cdiv(N, LBN) * nbt >= 512;
   const int BM = narrow == 1 ? 32 : narrow == 2 ? 256 : large ? LBM : 64;
   const int BN = narrow == 1 ? 256 : narrow == 2 ? 32 : large ? LBN : 64;
@@ -410,12 +459,7 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
   else if (narrow == 2) launch_typed<T, 256, 32>(E.stream, p, nbt * splits, vec);
   else if (large) launch_typed<T, LBM, LBN>(E.stream, p, nbt * splits, vec);
   else launch_typed<T, 64, 64>(E.stream, p, nbt * splits, vec);
-  if (splits > 1) {
-    int64_t n = M * N;
-    hipLaunchKernelGGL(splitk_reduce<T>, dim3((unsigned)cdiv(n, 16), (unsigned)nbt), dim3(256), 0, E.stream, Pre,
-                       Pim, splits, M * N, (int)M, (int)N, Cre, Cim, ldc, bt.c, (T)alpha, (T)beta);
-    RTCC_HIP(hipGetLastError());
-  }
+  if (splits > 1) splitk_reduce_launch<T>(E.stream, Pre, Pim, splits, M, N, Cre, Cim, ldc, bt.c, nbt, alpha, beta);
   E.scratch.reset(mark);
   E.gemm_flops += 2 * M * N * K * nbt * ((AC && BC) ? 4 : (AC || BC) ? 2 : 1);
   if (E.trace)

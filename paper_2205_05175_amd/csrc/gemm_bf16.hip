@@ -1,12 +1,23 @@
 // Split-BF16 three-term MFMA GEMM on FP32 planar-complex / real operands (gfx950).
 //
-// Every FP32 operand element x is split while it is staged into LDS as hi = bf16(x) and
-// lo = bf16(x - hi), and each real product is formed as hi*hi' + hi*lo' + lo*hi' with
-// v_mfma_f32_16x16x32_bf16, accumulated in FP32 (the dropped lo*lo' term is ~2^-16 of the
-// product). Operand tiles live in LDS as [row][k] with k contiguous so that each lane reads its
-// eight consecutive k values of a fragment with one 16-byte load. Same operand descriptors and
-// epilogue as the FP32 kernel; no split over K (used for the large products only).
+// Each FP32 operand element x is split as hi = bf16(x), lo = bf16(x - hi), and every real product
+// is formed as hi*hi' + hi*lo' + lo*hi' with v_mfma_f32_32x32x16_bf16, accumulated in FP32 (the
+// dropped lo*lo' term is ~2^-16 of the product). The split is a separate pass that also brings both
+// operands into one layout, "packed": per plane (Re hi, Re lo[, Im hi, Im lo]) a row-major
+// [rows][K] bf16 matrix with K contiguous, rows padded to a multiple of 128 and K to a multiple of
+// 32 with zeros, so the GEMM reads whole 16-byte chunks without bounds checks. Packed layouts of
+// constant operands (the integrals) are made once and cached.
+//
+// GEMM: 256 threads, a 128 x 128 output tile per workgroup, 2 x 2 waves of 64 x 64 (2 x 2 MFMA
+// blocks of 32 x 32). Per 32-wide k stage the packed tiles are copied to LDS through registers (the
+// next stage's global loads are in flight while the current one is multiplied). Lane l of a 32x32x16
+// MFMA holds A[l%32][8(l/32)+j] and B[8(l/32)+j][l%32] and its output r lies at row
+// 8(r/4) + 4(l/32) + r%4, column l%32. Small grids split K into fixed-order partial sums. Workgroups
+// are numbered so that each of the eight XCDs (which take workgroups round-robin) works on a
+// contiguous band of tiles.
 #include <cstdint>
+#include <cstdio>
+#include <string>
 
 #include "engine.h"
 
@@ -15,24 +26,102 @@ namespace rtcc {
 namespace {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16 __attribute__((ext_vector_type(16)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThr = 256;
-constexpr int kBK = 32;           // one MFMA k-step
-constexpr int kLDK = kBK + 8;     // padded LDS row (80 bytes)
+constexpr int kBM = 128, kBN = 128;  // output tile
+constexpr int kBK = 32;              // k stage
+constexpr int kLDK = 40;             // LDS row (bf16): 80 bytes, conflict-free 16-byte fragment reads
+constexpr int kRowPad = 128;         // packed rows are a multiple of this
+constexpr int kKPad = 32;            // packed K is a multiple of this
 
+// ---- packing ------------------------------------------------------------------------------------
+// dst plane (2 c + h) = h ? lo : hi of plane c of the source, as [Rp][Kp]; element (r, k) of the
+// source is src[r * ld + k] (trans = 0) or src[k * ld + r] (trans = 1). 32 x 32 tiles via LDS.
+__global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ sre, const float* __restrict__ sim,
+                                                   int64_t ld, int trans, int R, int K, int Rp, int Kp,
+                                                   __bf16* __restrict__ dst) {
+  __shared__ float t[2][32][33];
+  const int tid = threadIdx.x;
+  const int tk = Kp / 32;
+  const int r0 = (blockIdx.x / tk) * 32, k0 = (blockIdx.x % tk) * 32;
+  const int np = sim ? 2 : 1;
+  // load: lanes along the source's contiguous index
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int f = tid & 31, s = (tid >> 5) + 8 * i;
+    const int r = trans ? f : s, k = trans ? s : f;  // tile coordinates
+    const int gr = r0 + r, gk = k0 + k;
+    const bool ok = gr < R && gk < K;
+    const int64_t off = trans ? (int64_t)gk * ld + gr : (int64_t)gr * ld + gk;
+    t[0][r][k] = ok ? sre[off] : 0.f;
+    if (np == 2) t[1][r][k] = ok ? sim[off] : 0.f;
+  }
+  __syncthreads();
+  // store: lanes along k
+  const int64_t plane = (int64_t)Rp * Kp;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int k = tid & 31, r = (tid >> 5) + 8 * i;
+    const int64_t off = (int64_t)(r0 + r) * Kp + k0 + k;
+    for (int c = 0; c < np; ++c) {
+      const float x = t[c][r][k];
+      const __bf16 hi = (__bf16)x;
+      const __bf16 lo = (__bf16)(x - (float)hi);
+      dst[(2 * c) * plane + off] = hi;
+      dst[(2 * c + 1) * plane + off] = lo;
+    }
+  }
+}
+
+struct Packed {
+  const __bf16* p = nullptr;
+  int64_t plane = 0;  // elements per plane
+  int Rp = 0, Kp = 0, np = 1;
+};
+
+Packed pack_operand(Engine& E, const float* re, const float* im, int64_t ld, int trans, int64_t R, int64_t K,
+                    bool konst) {
+  Packed P;
+  P.Rp = (int)(cdiv(R, kRowPad) * kRowPad);
+  P.Kp = (int)(cdiv(K, kKPad) * kKPad);
+  P.np = im ? 2 : 1;
+  P.plane = (int64_t)P.Rp * P.Kp;
+  const size_t bytes = (size_t)P.plane * 2 * P.np * sizeof(__bf16);
+  const unsigned blocks = (unsigned)((P.Rp / 32) * (P.Kp / 32));
+  auto fill = [&](void* dst, hipStream_t st) {
+    hipLaunchKernelGGL(pack_kernel, dim3(blocks), dim3(256), 0, st, re, im, ld, trans, (int)R, (int)K, P.Rp, P.Kp,
+                       (__bf16*)dst);
+    RTCC_HIP(hipGetLastError());
+  };
+  if (konst && E.cache) {
+    char key[160];
+    snprintf(key, sizeof key, "bf16x3:%p/%p/%lld/%d/%lld/%lld", (const void*)re, (const void*)im, (long long)ld, trans,
+             (long long)R, (long long)K);
+    P.p = (const __bf16*)const_cache_get(E.cache, key, bytes, fill);
+  } else {
+    void* dst = E.scratch.get<char>((int64_t)bytes);
+    fill(dst, E.stream);
+    P.p = (const __bf16*)dst;
+  }
+  return P;
+}
+
+// ---- GEMM ---------------------------------------------------------------------------------------
 struct Params {
-  const float* Are;
-  const float* Aim;
-  int64_t lda;
-  const float* Bre;
-  const float* Bim;
-  int64_t ldb;
+  const __bf16* A;  // packed [NA * 2][Mp][Kp]
+  const __bf16* B;  // packed [NB * 2][Np][Kp]
+  int64_t pa, pb;   // plane strides
+  int Kp;
+  int M, N;
+  int tiles_m, tiles_n, ntiles;
+  int kchunk, splits;
   float* Cre;
   float* Cim;
   int64_t ldc;
-  int M, N, K;
+  int64_t split_stride;  // > 0: write partial planes [split][M][N]
   float alpha, beta;
 };
 
@@ -42,158 +131,127 @@ __device__ inline bf8 neg(bf8 x) {
   return __builtin_bit_cast(bf8, u);
 }
 
-__device__ inline f4 mma(bf8 a, bf8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+__device__ inline f16 mma(bf8 a, bf8 b, f16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
 
-// Register-staged FP32 tile: ROWS x COLS with COLS contiguous in memory.
-template <int ROWS, int COLS, int NPL>
-struct Regs {
-  static constexpr int NV = ROWS * COLS / 4 / kThr;
-  static_assert(NV >= 1 && NV * 4 * kThr == ROWS * COLS, "tile not divisible among threads");
-  float r[NPL][NV][4];
-  __device__ inline void load(const float* const* base, int64_t ld, bool vec, int row0, int col0, int rowLim,
-                              int colLim, int tid) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int idx = v * kThr + tid;
-      const int row = idx / (COLS / 4), col = (idx % (COLS / 4)) * 4;
-      const int gr = row0 + row, gc = col0 + col;
-      const int64_t off = (int64_t)gr * ld + gc;
-      if (vec && gr < rowLim && gc + 4 <= colLim) {
-#pragma unroll
-        for (int pl = 0; pl < NPL; ++pl) {
-          f4 x = *reinterpret_cast<const f4*>(base[pl] + off);
-          r[pl][v][0] = x[0];
-          r[pl][v][1] = x[1];
-          r[pl][v][2] = x[2];
-          r[pl][v][3] = x[3];
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool ok = gr < rowLim && gc + e < colLim;
-#pragma unroll
-          for (int pl = 0; pl < NPL; ++pl) r[pl][v][e] = ok ? base[pl][off + e] : 0.f;
-        }
-      }
-    }
-  }
-  // S[pl][h][x][k]; ROWS_ARE_K: memory rows are k (else memory rows are x)
-  template <bool ROWS_ARE_K, int XDIM>
-  __device__ inline void store(__bf16* S, int tid) const {
-    typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int idx = v * kThr + tid;
-      const int row = idx / (COLS / 4), col = (idx % (COLS / 4)) * 4;
-#pragma unroll
-      for (int pl = 0; pl < NPL; ++pl) {
-        bf4 hi, lo;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float x = r[pl][v][e];
-          hi[e] = (__bf16)x;
-          lo[e] = (__bf16)(x - (float)hi[e]);
-        }
-        __bf16* base = S + (size_t)pl * 2 * XDIM * kLDK;
-        if (!ROWS_ARE_K) {
-          // four consecutive k of one row: one 8-byte store per half
-          *reinterpret_cast<bf4*>(&base[row * kLDK + col]) = hi;
-          *reinterpret_cast<bf4*>(&base[XDIM * kLDK + row * kLDK + col]) = lo;
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            base[(col + e) * kLDK + row] = hi[e];
-            base[XDIM * kLDK + (col + e) * kLDK + row] = lo[e];
-          }
-        }
-      }
-    }
-  }
-};
+// Tile (tm, tn) of workgroup b: the eight XCDs take workgroups round-robin; renumber so XCD x owns a
+// contiguous range, then walk that range in bands of 8 tile rows (tiles of a band share B columns).
+__device__ inline void tile_of(int b, const Params& p, int* tm, int* tn) {
+  const int n = p.ntiles, q = n / 8, r = n % 8, x = b % 8, j = b / 8;
+  const int id = x * q + min(x, r) + j;
+  constexpr int G = 8;
+  const int band = id / (G * p.tiles_n);
+  const int first = band * G;
+  const int rows = min(G, p.tiles_m - first);
+  const int in = id - band * G * p.tiles_n;
+  *tm = first + in % rows;
+  *tn = in / rows;
+}
 
-template <int BM, int BN, int AC, int BC, int TA, int TB>
-__global__ __launch_bounds__(kThr) void gemm_bf16x3_kernel(Params p, int vec) {
-  constexpr int NA = AC ? 2 : 1, NB = BC ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) __bf16 As[NA * 2 * BM * kLDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[NB * 2 * BN * kLDK];
-  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+template <int AC, int BC>
+__global__ __launch_bounds__(kThr) void gemm_bf16x3_nt(Params p) {
+  constexpr int NA = AC ? 2 : 1, NB = BC ? 2 : 1;        // complex planes
+  constexpr int PA = 2 * NA, PB = 2 * NB;                  // packed planes (hi, lo per complex plane)
+  __shared__ __attribute__((aligned(16))) __bf16 As[PA * kBM * kLDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[PB * kBN * kLDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int split = blockIdx.x % p.splits;
+  int tm, tn;
+  tile_of(blockIdx.x / p.splits, p, &tm, &tn);
+  const int m0 = tm * kBM, n0 = tn * kBN;
+  const int kbeg = split * p.kchunk, kend = min(p.Kp, kbeg + p.kchunk);
 
-  f4 accr[FM][FN], acci[FM][FN];
+  f16 accr[2][2], acci[2][2];
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      accr[i][j] = f4{0, 0, 0, 0};
-      acci[i][j] = f4{0, 0, 0, 0};
-    }
-  const float* Ap[2] = {p.Are, p.Aim};
-  const float* Bp[2] = {p.Bre, p.Bim};
-  Regs<TA ? kBK : BM, TA ? BM : kBK, NA> ra;
-  Regs<TB ? BN : kBK, TB ? kBK : BN, NB> rb;
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        accr[i][j][e] = 0.f;
+        acci[i][j][e] = 0.f;
+      }
+
+  // stage copy: each plane tile is 128 rows x 32 k = 512 chunks of 16 bytes, two per thread
+  u4 ra[PA][2], rb[PB][2];
   auto fetch = [&](int k0) {
-    if (TA) ra.load(Ap, p.lda, vec, k0, m0, p.K, p.M, tid);
-    else ra.load(Ap, p.lda, vec, m0, k0, p.M, p.K, tid);
-    if (TB) rb.load(Bp, p.ldb, vec, n0, k0, p.N, p.K, tid);
-    else rb.load(Bp, p.ldb, vec, k0, n0, p.K, p.N, tid);
+#pragma unroll
+    for (int pl = 0; pl < PA; ++pl)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int c = tid + 256 * v, row = c >> 2, q = c & 3;
+        ra[pl][v] = *reinterpret_cast<const u4*>(p.A + pl * p.pa + (int64_t)(m0 + row) * p.Kp + k0 + 8 * q);
+      }
+#pragma unroll
+    for (int pl = 0; pl < PB; ++pl)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int c = tid + 256 * v, row = c >> 2, q = c & 3;
+        rb[pl][v] = *reinterpret_cast<const u4*>(p.B + pl * p.pb + (int64_t)(n0 + row) * p.Kp + k0 + 8 * q);
+      }
   };
-  fetch(0);
-  const int g = lane >> 4, c16 = lane & 15;
-  for (int k0 = 0; k0 < p.K; k0 += kBK) {
-    ra.template store<TA != 0, BM>(As, tid);
-    rb.template store<TB == 0, BN>(Bs, tid);
+  auto stash = [&]() {
+#pragma unroll
+    for (int pl = 0; pl < PA; ++pl)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int c = tid + 256 * v, row = c >> 2, q = c & 3;
+        *reinterpret_cast<u4*>(&As[(pl * kBM + row) * kLDK + 8 * q]) = ra[pl][v];
+      }
+#pragma unroll
+    for (int pl = 0; pl < PB; ++pl)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int c = tid + 256 * v, row = c >> 2, q = c & 3;
+        *reinterpret_cast<u4*>(&Bs[(pl * kBN + row) * kLDK + 8 * q]) = rb[pl][v];
+      }
+  };
+
+  const int l32 = lane & 31, hk = 8 * (lane >> 5);
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += kBK) {
+    stash();
     __syncthreads();
-    if (k0 + kBK < p.K) fetch(k0 + kBK);
-    // all fragments of this wave (hi, lo for each plane), then term-major MFMA issue so that
-    // consecutive MFMAs update different accumulators
-    bf8 bfr[FN][NB][2], afr[FM][NA][2];
+    if (k0 + kBK < kend) fetch(k0 + kBK);  // next stage in flight during this one
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+    for (int kk = 0; kk < kBK; kk += 16) {
+      bf8 af[2][PA], bfr[2][PB];
 #pragma unroll
-      for (int pl = 0; pl < NB; ++pl)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-          bfr[j][pl][h] = *reinterpret_cast<const bf8*>(
-              &Bs[((pl * 2 + h) * BN + wn * WN + j * 16 + c16) * kLDK + 8 * g]);
+        for (int pl = 0; pl < PA; ++pl)
+          af[i][pl] = *reinterpret_cast<const bf8*>(&As[(pl * kBM + wm * 64 + i * 32 + l32) * kLDK + kk + hk]);
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int pl = 0; pl < NA; ++pl)
+        for (int pl = 0; pl < PB; ++pl)
+          bfr[j][pl] = *reinterpret_cast<const bf8*>(&Bs[(pl * kBN + wn * 64 + j * 32 + l32) * kLDK + kk + hk]);
+      // three split products: (hi, hi), (hi, lo), (lo, hi); planes: 2c + h
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-          afr[i][pl][h] = *reinterpret_cast<const bf8*>(
-              &As[((pl * 2 + h) * BM + wm * WM + i * 16 + c16) * kLDK + 8 * g]);
-    // (ha, hb): the three split products hi*hi, hi*lo, lo*hi
+      for (int t = 0; t < 3; ++t) {
+        const int ha = t == 2 ? 1 : 0, hb = t == 1 ? 1 : 0;
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const int ha = t == 2 ? 1 : 0, hb = t == 1 ? 1 : 0;
-      // Re(C) += Re(A) Re(B)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+          for (int j = 0; j < 2; ++j) accr[i][j] = mma(af[i][ha], bfr[j][hb], accr[i][j]);
+        if (BC) {
 #pragma unroll
-        for (int j = 0; j < FN; ++j) accr[i][j] = mma(afr[i][0][ha], bfr[j][0][hb], accr[i][j]);
-      // Im(C) += Re(A) Im(B)
-      if (BC) {
+          for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+            for (int j = 0; j < 2; ++j) acci[i][j] = mma(af[i][ha], bfr[j][2 + hb], acci[i][j]);
+        }
+        if (AC) {
 #pragma unroll
-          for (int j = 0; j < FN; ++j) acci[i][j] = mma(afr[i][0][ha], bfr[j][NB - 1][hb], acci[i][j]);
-      }
-      // Im(C) += Im(A) Re(B)
-      if (AC) {
+          for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+            for (int j = 0; j < 2; ++j) acci[i][j] = mma(af[i][2 + ha], bfr[j][hb], acci[i][j]);
+        }
+        if (AC && BC) {
 #pragma unroll
-          for (int j = 0; j < FN; ++j) acci[i][j] = mma(afr[i][NA - 1][ha], bfr[j][0][hb], acci[i][j]);
-      }
-      // Re(C) -= Im(A) Im(B)
-      if (AC && BC) {
+          for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) accr[i][j] = mma(neg(afr[i][NA - 1][ha]), bfr[j][NB - 1][hb], accr[i][j]);
+            for (int j = 0; j < 2; ++j) accr[i][j] = mma(neg(af[i][2 + ha]), bfr[j][2 + hb], accr[i][j]);
+        }
       }
     }
     __syncthreads();
@@ -201,47 +259,30 @@ __global__ __launch_bounds__(kThr) void gemm_bf16x3_kernel(Params p, int vec) {
 
   constexpr bool CC = AC || BC;
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WM + i * 16 + 4 * g + r;
-        const int col = n0 + wn * WN + j * 16 + c16;
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = n0 + wn * 64 + j * 32 + l32;
         if (row >= p.M || col >= p.N) continue;
-        const int64_t off = (int64_t)row * p.ldc + col;
-        float outr = p.alpha * accr[i][j][r], outi = p.alpha * acci[i][j][r];
-        if (p.beta != 0.f) {
-          outr += p.beta * p.Cre[off];
-          if (CC) outi += p.beta * p.Cim[off];
+        const float vr = accr[i][j][r], vi = acci[i][j][r];
+        if (p.split_stride) {
+          const int64_t off = (int64_t)split * p.split_stride + (int64_t)row * p.N + col;
+          p.Cre[off] = vr;
+          if (CC) p.Cim[off] = vi;
+        } else {
+          const int64_t off = (int64_t)row * p.ldc + col;
+          float outr = p.alpha * vr, outi = p.alpha * vi;
+          if (p.beta != 0.f) {
+            outr += p.beta * p.Cre[off];
+            if (CC) outi += p.beta * p.Cim[off];
+          }
+          p.Cre[off] = outr;
+          if (CC) p.Cim[off] = outi;
         }
-        p.Cre[off] = outr;
-        if (CC) p.Cim[off] = outi;
       }
-}
-
-template <int BM, int BN, int AC, int BC>
-void launch(hipStream_t st, const Params& p, int ta, int tb, int vec) {
-  dim3 grid((unsigned)cdiv(p.N, BN), (unsigned)cdiv(p.M, BM));
-  const int sel = ta * 2 + tb;
-  switch (sel) {
-    case 0: hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN, AC, BC, 0, 0>), grid, dim3(kThr), 0, st, p, vec); break;
-    case 1: hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN, AC, BC, 0, 1>), grid, dim3(kThr), 0, st, p, vec); break;
-    case 2: hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN, AC, BC, 1, 0>), grid, dim3(kThr), 0, st, p, vec); break;
-    default: hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN, AC, BC, 1, 1>), grid, dim3(kThr), 0, st, p, vec); break;
-  }
-  RTCC_HIP(hipGetLastError());
-}
-
-template <int BM, int BN>
-void launch_typed(hipStream_t st, const Params& p, int ta, int tb, int vec) {
-  const int sel = (p.Aim ? 2 : 0) + (p.Bim ? 1 : 0);
-  switch (sel) {
-    case 1: launch<BM, BN, 0, 1>(st, p, ta, tb, vec); break;
-    case 2: launch<BM, BN, 1, 0>(st, p, ta, tb, vec); break;
-    case 3: launch<BM, BN, 1, 1>(st, p, ta, tb, vec); break;
-    default: launch<BM, BN, 0, 0>(st, p, ta, tb, vec); break;
-  }
 }
 
 }  // namespace
@@ -253,25 +294,70 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   const bool AC = A.im != nullptr, BC = B.im != nullptr;
   if (!Cim && (AC || BC)) return false;
   if (!AC && !BC) return false;
-  Params p{A.re, A.im, A.ld, B.re, B.im, B.ld, Cre, Cim, ldc, (int)M, (int)N, (int)K, (float)alpha, (float)beta};
-  auto al = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
-  const int vec = al(A.re) && (!AC || al(A.im)) && al(B.re) && (!BC || al(B.im)) && A.ld % 4 == 0 && B.ld % 4 == 0;
-  // grids that cannot fill the chip go to the FP32 kernel, which can split over K (unless the
-  // split is forced onto every product by a zero threshold)
-  if (E.bf16_min_flops > 0 && cdiv(M, 64) * cdiv(N, 64) < 256) return false;
-  // complex x complex products hold more fragments: narrower tiles
-  const bool cc = AC && BC;
-  const int64_t t128 = cdiv(M, 128) * cdiv(N, cc ? 64 : 128);
-  if (t128 >= 384) {
-    if (cc) launch_typed<128, 64>(E.stream, p, A.trans, B.trans, vec);
-    else launch_typed<128, 128>(E.stream, p, A.trans, B.trans, vec);
-  } else {
-    launch_typed<64, 64>(E.stream, p, A.trans, B.trans, vec);
+  RTCC_CHECK(M < (1LL << 30) && N < (1LL << 30) && K < (1LL << 30), kEInval, "gemm_bf16x3: dimension too large");
+  size_t mark = E.scratch.used;
+  // A as [M][K] rows; B as [N][K] rows (B(k, n) = trans ? b[n * ld + k] : b[k * ld + n])
+  const Packed pa = pack_operand(E, A.re, A.im, A.ld, A.trans, M, K, A.konst);
+  const Packed pb = pack_operand(E, B.re, B.im, B.ld, B.trans ? 0 : 1, N, K, B.konst);
+  Params p;
+  p.A = pa.p;
+  p.B = pb.p;
+  p.pa = pa.plane;
+  p.pb = pb.plane;
+  p.Kp = pa.Kp;
+  p.M = (int)M;
+  p.N = (int)N;
+  p.tiles_m = (int)cdiv(M, kBM);
+  p.tiles_n = (int)cdiv(N, kBN);
+  p.ntiles = p.tiles_m * p.tiles_n;
+  p.alpha = (float)alpha;
+  p.beta = (float)beta;
+  // Split K when it shortens the estimated time: workgroups run in rounds of one per CU (256), a
+  // tile takes ~tile_flops / (half the per-CU split-BF16 rate), and s > 1 splits add a reduction
+  // that streams s partial planes and C at ~5 TB/s.
+  const int stages = p.Kp / kBK;
+  const double tile_time = 2.0 * kBM * kBN * (double)p.Kp * ((AC && BC) ? 4 : 2) / (0.5 * 2516.6e12 / 3 / 256);
+  const double plane_bytes = (double)M * N * 4.0 * 2.0;
+  int splits = 1;
+  double best = 1e300;
+  for (int sp = 1; sp <= 16 && (sp == 1 || stages / sp >= 4); ++sp) {
+    const double rounds = (double)cdiv((int64_t)p.ntiles * sp, 256);
+    const double t = rounds * tile_time / sp + (sp > 1 ? (2.0 * sp + 2.0) * plane_bytes / 5e12 : 0.0);
+    if (t < best * 0.97) {
+      best = t;
+      splits = sp;
+    }
   }
-  E.gemm_flops += 2 * M * N * K * (cc ? 4 : 2);
+  const int per = (int)cdiv(stages, splits);
+  p.kchunk = per * kBK;
+  splits = (int)cdiv(stages, per);
+  p.splits = splits;
+  float *Pre = nullptr, *Pim = nullptr;
+  if (splits > 1) {
+    p.split_stride = M * N;
+    Pre = E.scratch.get<float>(splits * M * N);
+    Pim = E.scratch.get<float>(splits * M * N);
+    p.Cre = Pre;
+    p.Cim = Pim;
+    p.ldc = N;
+  } else {
+    p.split_stride = 0;
+    p.Cre = Cre;
+    p.Cim = Cim;
+    p.ldc = ldc;
+  }
+  const dim3 grid((unsigned)(p.ntiles * splits));
+  if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1>), grid, dim3(kThr), 0, E.stream, p);
+  else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0>), grid, dim3(kThr), 0, E.stream, p);
+  else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1>), grid, dim3(kThr), 0, E.stream, p);
+  RTCC_HIP(hipGetLastError());
+  if (splits > 1) splitk_reduce_launch<float>(E.stream, Pre, Pim, splits, M, N, Cre, Cim, ldc, 0, 1, alpha, beta);
+  E.scratch.reset(mark);
+  E.gemm_flops += 2 * M * N * K * ((AC && BC) ? 4 : 2);
   if (E.trace)
-    fprintf(stderr, "[rtcc] gemm-bf16x3 M=%lld N=%lld K=%lld %s%s ta=%d tb=%d vec=%d\n", (long long)M, (long long)N,
-            (long long)K, AC ? "c" : "r", BC ? "c" : "r", A.trans, B.trans, vec);
+    fprintf(stderr, "[rtcc] gemm-bf16x3 M=%lld N=%lld K=%lld %s%s ta=%d tb=%d splits=%d konst=%d%d\n", (long long)M,
+            (long long)N, (long long)K, AC ? "c" : "r", BC ? "c" : "r", A.trans, B.trans, splits, (int)A.konst,
+            (int)B.konst);
   return true;
 }
 

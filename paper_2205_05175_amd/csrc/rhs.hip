@@ -278,7 +278,7 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
       const int64_t rows = E.nb * (lambda || E.nb > 1 ? 2 : 1) * (int64_t)o * o, vv = (int64_t)v * v;
       RTCC_CHECK(E.nb == 1 || w.X.bs == 2 * (int64_t)o * o * vv, kEInval, "ladder operand is not member-contiguous");
       GemmOp<T> a{w.X.re, w.X.im, vv, 0};
-      GemmOp<T> b{I.vvvv.re, nullptr, vv, 1};  // B(ef, ab) = <ab|ef> = <ef|ab>: V is symmetric
+      GemmOp<T> b{I.vvvv.re, nullptr, vv, 1, true};  // B(ef, ab) = <ab|ef> = <ef|ab>: V is symmetric
       E.ladder_flops = 4.0 * (double)rows * (double)vv * (double)vv;  // real x complex: 2 MACs per entry
       if (E.mark) E.mark(E.mark_user, 0, E.ladder_flops);
       gemm<T>(E, rows, vv, vv, 1.0, a, b, w.Lad.re, w.Lad.im, vv, 0.0);
