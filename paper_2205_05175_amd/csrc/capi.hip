@@ -73,6 +73,7 @@ struct rtcc_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   Engine E;
+  Engine EB[2];  // branch engines of E (own streams and scratch)
   Arena arena;        // integrals and workspaces
   Arena arena32;      // FP32 integrals and workspace (allocated on demand)
   bool have32 = false;
@@ -598,6 +599,8 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     c->use_graph = !(ng && ng[0] == '1');
     const char* tr = std::getenv("RTCC_TRACE");
     c->E.trace = tr && tr[0] == '1';
+    const char* nbr = std::getenv("RTCC_NO_BRANCH");
+    const bool branches = !(nbr && nbr[0] == '1');
     const int64_t n = c->n, nn = n * n, n4 = nn * nn;
     for (int64_t i = 0; i < nn; ++i)
       RTCC_CHECK(std::isfinite(fock[i]) && std::isfinite(dipole[i]) && std::isfinite(dipole[nn + i]) &&
@@ -625,6 +628,17 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     int64_t big = std::max<int64_t>({(int64_t)o * v * v * v, 2 * c->n2, (int64_t)o * o * o * o, c->n2 * 2});
     c->E.scratch.cap = (size_t)(8 * big + (1 << 22)) * sizeof(double) * 2;
     c->E.scratch.base = c->arena.alloc<char>(c->E.scratch.cap);
+    if (branches) {
+      RTCC_HIP(hipEventCreateWithFlags(&c->E.ev_fork, hipEventDisableTiming));
+      for (int k = 0; k < 2; ++k) {
+        Engine& b = c->EB[k];
+        RTCC_HIP(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));
+        RTCC_HIP(hipEventCreateWithFlags(&c->E.ev_join[k], hipEventDisableTiming));
+        b.scratch.cap = c->E.scratch.cap;
+        b.scratch.base = c->arena.alloc<char>(b.scratch.cap);
+        c->E.br[k] = &b;
+      }
+    }
     build_ints<double>(c->E, c->arena, o, v, eri_dev, c->I64);
     build_work<double>(c->arena, o, v, c->W64);
     if (precision != RTCC_FP64) ensure32(c.get(), eri_dev);
@@ -643,6 +657,11 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
   if (st != RTCC_OK) {
     const_cache_destroy(c->E.cache);
     c->E.cache = nullptr;
+    for (int k = 0; k < 2; ++k) {
+      if (c->EB[k].stream) (void)hipStreamDestroy(c->EB[k].stream);
+      if (c->E.ev_join[k]) (void)hipEventDestroy(c->E.ev_join[k]);
+    }
+    if (c->E.ev_fork) (void)hipEventDestroy(c->E.ev_fork);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     if (c->e_in) (void)hipEventDestroy(c->e_in);
     if (c->e_out) (void)hipEventDestroy(c->e_out);
@@ -1147,8 +1166,16 @@ void rtcc_destroy(rtcc_ctx* c) {
   if (c->host_pinned) (void)hipHostFree(c->host_pinned);
   hipStream_t st = c->stream;
   ConstCache* cache = c->E.cache;
+  hipStream_t bst[2] = {c->EB[0].stream, c->EB[1].stream};
+  for (int k = 0; k < 2; ++k) {
+    if (bst[k]) (void)hipStreamSynchronize(bst[k]);
+    if (c->E.ev_join[k]) (void)hipEventDestroy(c->E.ev_join[k]);
+  }
+  if (c->E.ev_fork) (void)hipEventDestroy(c->E.ev_fork);
   delete c;  // frees device memory first
   const_cache_destroy(cache);
+  for (hipStream_t b : bst)
+    if (b) (void)hipStreamDestroy(b);
   if (st) (void)hipStreamDestroy(st);
 }
 

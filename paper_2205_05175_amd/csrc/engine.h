@@ -96,7 +96,17 @@ struct Engine {
   // member index carried by one operand only becomes part of the GEMM's M or N (one fat GEMM
   // against the shared integrals); one carried by both becomes a batched GEMM.
   int nb = 1;
+  // Optional branch engines (own stream and scratch): independent parts of the right-hand side run
+  // on them concurrently between fork() and join().
+  Engine* br[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[2] = {nullptr, nullptr};
 };
+
+// Branch engines take this engine's settings and wait for the work already on its stream.
+void fork_branches(Engine& E);
+// This engine's stream waits for the branches; their flop counts are added to this engine's.
+void join_branches(Engine& E);
 
 
 // C = alpha * contraction(A, B) + beta * C   (beta 0 or 1)

@@ -284,6 +284,27 @@ Plan plan_for(const Ten<T>& A, const std::string& sa, const Ten<T>& B, const std
 
 }  // namespace
 
+void fork_branches(Engine& E) {
+  RTCC_HIP(hipEventRecord(E.ev_fork, E.stream));
+  for (Engine* b : E.br) {
+    b->cache = E.cache;
+    b->trace = E.trace;
+    b->bf16x3 = E.bf16x3;
+    b->bf16_min_flops = E.bf16_min_flops;
+    b->nb = E.nb;
+    b->gemm_flops = 0;
+    RTCC_HIP(hipStreamWaitEvent(b->stream, E.ev_fork, 0));
+  }
+}
+
+void join_branches(Engine& E) {
+  for (int k = 0; k < 2; ++k) {
+    RTCC_HIP(hipEventRecord(E.ev_join[k], E.br[k]->stream));
+    RTCC_HIP(hipStreamWaitEvent(E.stream, E.ev_join[k], 0));
+    E.gemm_flops += E.br[k]->gemm_flops;
+  }
+}
+
 template <typename T>
 void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const Ten<T>& B0, const Ten<T>& C0,
          double beta) {

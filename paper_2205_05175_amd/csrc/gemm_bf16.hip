@@ -3,14 +3,16 @@
 // Each FP32 operand element x is split as hi = bf16(x), lo = bf16(x - hi), and every real product
 // is formed as hi*hi' + hi*lo' + lo*hi' with v_mfma_f32_32x32x16_bf16, accumulated in FP32 (the
 // dropped lo*lo' term is ~2^-16 of the product). The split is a separate pass that also brings both
-// operands into one layout, "packed": per plane (Re hi, Re lo[, Im hi, Im lo]) a row-major
-// [rows][K] bf16 matrix with K contiguous, rows padded to a multiple of 128 and K to a multiple of
-// 32 with zeros, so the GEMM reads whole 16-byte chunks without bounds checks. Packed layouts of
-// constant operands (the integrals) are made once and cached.
+// operands into one layout, "packed": per plane (Re hi, Re lo[, Im hi, Im lo]) a bf16 matrix of
+// [rows][K] stored k-blocked as [K / 16][rows][16] (16 consecutive k of a row contiguous), rows
+// padded to a multiple of 128 and K to a multiple of 32 with zeros, so the GEMM copies whole
+// contiguous stage tiles without bounds checks. Packed layouts of constant operands (the
+// integrals) are made once and cached.
 //
 // GEMM: 256 threads, a 128 x 128 output tile per workgroup, 2 x 2 waves of 64 x 64 (2 x 2 MFMA
-// blocks of 32 x 32). Per 32-wide k stage the packed tiles are copied to LDS through registers (the
-// next stage's global loads are in flight while the current one is multiplied). Lane l of a 32x32x16
+// blocks of 32 x 32). Per 16-wide k stage the packed tiles pass through registers into one of two
+// LDS buffers: stage s + 1 is written and stage s + 2 fetched while stage s is multiplied, with
+// one barrier per stage. Lane l of a 32x32x16
 // MFMA holds A[l%32][8(l/32)+j] and B[8(l/32)+j][l%32] and its output r lies at row
 // 8(r/4) + 4(l/32) + r%4, column l%32. Small grids split K into fixed-order partial sums. Workgroups
 // are numbered so that each of the eight XCDs (which take workgroups round-robin) works on a
@@ -33,13 +35,13 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 constexpr int kThr = 256;
 constexpr int kBM = 128, kBN = 128;  // output tile
 constexpr int kBK = 32;              // k stage
-constexpr int kLDK = 40;             // LDS row (bf16): 80 bytes, conflict-free 16-byte fragment reads
 constexpr int kRowPad = 128;         // packed rows are a multiple of this
 constexpr int kKPad = 32;            // packed K is a multiple of this
 
 // ---- packing ------------------------------------------------------------------------------------
-// dst plane (2 c + h) = h ? lo : hi of plane c of the source, as [Rp][Kp]; element (r, k) of the
-// source is src[r * ld + k] (trans = 0) or src[k * ld + r] (trans = 1). 32 x 32 tiles via LDS.
+// dst plane (2 c + h) = h ? lo : hi of plane c of the source, k-blocked as [Kp / 16][Rp][16]: one
+// 16-wide k stage of 128 rows is a contiguous 4 KB. Element (r, k) of the source is src[r * ld + k]
+// (trans = 0) or src[k * ld + r] (trans = 1). 32 x 32 tiles via LDS.
 __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ sre, const float* __restrict__ sim,
                                                    int64_t ld, int trans, int R, int K, int Rp, int Kp,
                                                    __bf16* __restrict__ dst) {
@@ -60,12 +62,13 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ sre
     if (np == 2) t[1][r][k] = ok ? sim[off] : 0.f;
   }
   __syncthreads();
-  // store: lanes along k
+  // store: lanes along k; k-blocked layout [Kp / 16][Rp][16]
   const int64_t plane = (int64_t)Rp * Kp;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int k = tid & 31, r = (tid >> 5) + 8 * i;
-    const int64_t off = (int64_t)(r0 + r) * Kp + k0 + k;
+    const int gk = k0 + k;
+    const int64_t off = (int64_t)(gk >> 4) * Rp * 16 + (int64_t)(r0 + r) * 16 + (gk & 15);
     for (int c = 0; c < np; ++c) {
       const float x = t[c][r][k];
       const __bf16 hi = (__bf16)x;
@@ -114,7 +117,7 @@ struct Params {
   const __bf16* A;  // packed [NA * 2][Mp][Kp]
   const __bf16* B;  // packed [NB * 2][Np][Kp]
   int64_t pa, pb;   // plane strides
-  int Kp;
+  int Kp, Mp, Np;   // padded K and rows
   int M, N;
   int tiles_m, tiles_n, ntiles;
   int kchunk, splits;
@@ -149,10 +152,13 @@ __device__ inline void tile_of(int b, const Params& p, int* tm, int* tn) {
 
 template <int AC, int BC>
 __global__ __launch_bounds__(kThr) void gemm_bf16x3_nt(Params p) {
-  constexpr int NA = AC ? 2 : 1, NB = BC ? 2 : 1;        // complex planes
-  constexpr int PA = 2 * NA, PB = 2 * NB;                  // packed planes (hi, lo per complex plane)
-  __shared__ __attribute__((aligned(16))) __bf16 As[PA * kBM * kLDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[PB * kBN * kLDK];
+  constexpr int NA = AC ? 2 : 1, NB = BC ? 2 : 1;  // complex planes
+  constexpr int PA = 2 * NA, PB = 2 * NB;            // packed planes (hi, lo per complex plane)
+  constexpr int SK = 16;                             // k per LDS stage (one MFMA step)
+  constexpr int LDK = 24;                            // LDS row: 48 bytes, 16-byte aligned rows
+  // two LDS buffers: stage s + 1 is written while stage s is multiplied
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][PA * kBM * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][PB * kBN * LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int split = blockIdx.x % p.splits;
@@ -172,87 +178,79 @@ __global__ __launch_bounds__(kThr) void gemm_bf16x3_nt(Params p) {
         acci[i][j][e] = 0.f;
       }
 
-  // stage copy: each plane tile is 128 rows x 32 k = 512 chunks of 16 bytes, two per thread
-  u4 ra[PA][2], rb[PB][2];
+  // a plane tile of one stage: 128 rows x 16 k = 256 chunks of 16 bytes, one per thread
+  const int crow = tid >> 1, cq = tid & 1;
+  u4 ra[PA], rb[PB];
+  // k-blocked planes: stage k0 of rows r0.. is the contiguous run at (k0 / 16) * R * 16 + r0 * 16
+  const int64_t sa = (int64_t)p.Mp * SK, sb = (int64_t)p.Np * SK;
   auto fetch = [&](int k0) {
+    const int64_t kb = k0 / SK;
 #pragma unroll
     for (int pl = 0; pl < PA; ++pl)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int c = tid + 256 * v, row = c >> 2, q = c & 3;
-        ra[pl][v] = *reinterpret_cast<const u4*>(p.A + pl * p.pa + (int64_t)(m0 + row) * p.Kp + k0 + 8 * q);
-      }
+      ra[pl] = *reinterpret_cast<const u4*>(p.A + pl * p.pa + kb * sa + (int64_t)m0 * SK + 8 * tid);
 #pragma unroll
     for (int pl = 0; pl < PB; ++pl)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int c = tid + 256 * v, row = c >> 2, q = c & 3;
-        rb[pl][v] = *reinterpret_cast<const u4*>(p.B + pl * p.pb + (int64_t)(n0 + row) * p.Kp + k0 + 8 * q);
-      }
+      rb[pl] = *reinterpret_cast<const u4*>(p.B + pl * p.pb + kb * sb + (int64_t)n0 * SK + 8 * tid);
   };
-  auto stash = [&]() {
+  auto stash = [&](int buf) {
 #pragma unroll
-    for (int pl = 0; pl < PA; ++pl)
+    for (int pl = 0; pl < PA; ++pl) *reinterpret_cast<u4*>(&As[buf][(pl * kBM + crow) * LDK + 8 * cq]) = ra[pl];
 #pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int c = tid + 256 * v, row = c >> 2, q = c & 3;
-        *reinterpret_cast<u4*>(&As[(pl * kBM + row) * kLDK + 8 * q]) = ra[pl][v];
-      }
-#pragma unroll
-    for (int pl = 0; pl < PB; ++pl)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int c = tid + 256 * v, row = c >> 2, q = c & 3;
-        *reinterpret_cast<u4*>(&Bs[(pl * kBN + row) * kLDK + 8 * q]) = rb[pl][v];
-      }
+    for (int pl = 0; pl < PB; ++pl) *reinterpret_cast<u4*>(&Bs[buf][(pl * kBN + crow) * LDK + 8 * cq]) = rb[pl];
   };
 
   const int l32 = lane & 31, hk = 8 * (lane >> 5);
-  if (kbeg < kend) fetch(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += kBK) {
-    stash();
+  const int nst = (kend - kbeg) / SK;
+  if (nst > 0) {
+    fetch(kbeg);
+    stash(0);
+    if (nst > 1) fetch(kbeg + SK);
     __syncthreads();
-    if (k0 + kBK < kend) fetch(k0 + kBK);  // next stage in flight during this one
+  }
+  for (int s = 0; s < nst; ++s) {
+    const int buf = s & 1;
+    bf8 af[2][PA], bfr[2][PB];
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 16) {
-      bf8 af[2][PA], bfr[2][PB];
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int pl = 0; pl < PA; ++pl)
+        af[i][pl] = *reinterpret_cast<const bf8*>(&As[buf][(pl * kBM + wm * 64 + i * 32 + l32) * LDK + hk]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int pl = 0; pl < PB; ++pl)
+        bfr[j][pl] = *reinterpret_cast<const bf8*>(&Bs[buf][(pl * kBN + wn * 64 + j * 32 + l32) * LDK + hk]);
+    // three split products: (hi, hi), (hi, lo), (lo, hi); packed plane index 2c + h
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int ha = t == 2 ? 1 : 0, hb = t == 1 ? 1 : 0;
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int pl = 0; pl < PA; ++pl)
-          af[i][pl] = *reinterpret_cast<const bf8*>(&As[(pl * kBM + wm * 64 + i * 32 + l32) * kLDK + kk + hk]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int pl = 0; pl < PB; ++pl)
-          bfr[j][pl] = *reinterpret_cast<const bf8*>(&Bs[(pl * kBN + wn * 64 + j * 32 + l32) * kLDK + kk + hk]);
-      // three split products: (hi, hi), (hi, lo), (lo, hi); planes: 2c + h
-#pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        const int ha = t == 2 ? 1 : 0, hb = t == 1 ? 1 : 0;
+        for (int j = 0; j < 2; ++j) accr[i][j] = mma(af[i][ha], bfr[j][hb], accr[i][j]);
+      if (BC) {
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) accr[i][j] = mma(af[i][ha], bfr[j][hb], accr[i][j]);
-        if (BC) {
-#pragma unroll
-          for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acci[i][j] = mma(af[i][ha], bfr[j][2 + hb], acci[i][j]);
-        }
-        if (AC) {
-#pragma unroll
-          for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acci[i][j] = mma(af[i][2 + ha], bfr[j][hb], acci[i][j]);
-        }
-        if (AC && BC) {
-#pragma unroll
-          for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) accr[i][j] = mma(neg(af[i][2 + ha]), bfr[j][2 + hb], accr[i][j]);
-        }
+          for (int j = 0; j < 2; ++j) acci[i][j] = mma(af[i][ha], bfr[j][2 + hb], acci[i][j]);
       }
+      if (AC) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acci[i][j] = mma(af[i][2 + ha], bfr[j][hb], acci[i][j]);
+      }
+      if (AC && BC) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) accr[i][j] = mma(neg(af[i][2 + ha]), bfr[j][2 + hb], accr[i][j]);
+      }
+    }
+    // next stage into the other buffer (last read before the previous barrier), then prefetch
+    if (s + 1 < nst) {
+      stash(buf ^ 1);
+      if (s + 2 < nst) fetch(kbeg + (s + 2) * SK);
     }
     __syncthreads();
   }
@@ -305,6 +303,8 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   p.pa = pa.plane;
   p.pb = pb.plane;
   p.Kp = pa.Kp;
+  p.Mp = pa.Rp;
+  p.Np = pb.Rp;
   p.M = (int)M;
   p.N = (int)N;
   p.tiles_m = (int)cdiv(M, kBM);

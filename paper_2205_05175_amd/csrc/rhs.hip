@@ -212,10 +212,17 @@ void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
 
 template <typename T>
 void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
+  // Contractions go to engine `cur`. With branch engines, the T2, Lambda2 and Lambda1 residuals
+  // (which share only intermediates finished before the fork, and each write their own outputs and
+  // temporaries) run concurrently on three streams.
+  Engine* cur = &E;
   auto C = [&](double a, const char* s, const Ten<T>& x, const Ten<T>& y, const Ten<T>& z, double b) {
-    ein<T>(E, a, s, x, y, z, b);
+    ein<T>(*cur, a, s, x, y, z, b);
   };
-  auto P = [&](double a, const char* s, const Ten<T>& x, const Ten<T>& z, double b) { padd<T>(E, a, s, x, z, b); };
+  auto P = [&](double a, const char* s, const Ten<T>& x, const Ten<T>& z, double b) {
+    padd<T>(*cur, a, s, x, z, b);
+  };
+  const bool par = tb && lambda && E.br[0] && E.br[1];
   const int o = w.o, v = w.v;
   const Ten<T>&t1 = w.t1, &t2 = w.t2, &l1 = w.l1, &l2 = w.l2, &tau = w.tau;
 
@@ -307,6 +314,13 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     }
   }
 
+  // Lambda one-body intermediates used by both Lambda residuals
+  if (lambda && tb) {
+    C(-1, "mnef,mnaf->ae", w.t2s, w.l2, w.Gvv, 0);
+    C(1, "mnef,inef->mi", w.t2s, w.l2, w.Goo, 0);
+  }
+  if (par) fork_branches(E);
+
   // ---- T2 residual: R2 = <ij|ab> + tau.W + ladder + (1 + P(ia,jb)) Z
   C(1, "ijae,be->ijab", t2, w.Hvv, w.Z, 0);
   C(-1, "imab,mj->ijab", t2, w.Hoo, w.Z, 1);
@@ -337,12 +351,11 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   if (!lambda) return;
 
   // ---- Lambda2 residual
+  if (par) cur = E.br[0];
   C(1, "ijae,eb->ijab", l2, w.Hvv, w.ZL, 0);
   C(-1, "imab,jm->ijab", l2, w.Hoo, w.ZL, 1);
   C(1, "ia,jb->ijab", l1, w.Fme, w.ZL, 1);
   if (tb) {
-    C(-1, "mnef,mnaf->ae", w.t2s, l2, w.Gvv, 0);
-    C(1, "mnef,inef->mi", w.t2s, l2, w.Goo, 0);
     C(1, "ijef,mf->ijem", l2, t1, w.Y, 0);
     C(1, "ijef,mnef->ijmn", l2, tau, w.M, 0);
     C(1, "ie,ejab->ijab", l1, w.Hvovv, w.ZL, 1);
@@ -366,6 +379,7 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   P(1, "ijab->jiba", w.ZL, w.S2, 1);
 
   // ---- Lambda1 residual: S1 = Fme + l1.Hvv - l1.Hoo + ... + A1 - A2
+  if (par) cur = E.br[1];
   P(1, "ia->ia", w.Fme, w.S1, 0);
   C(1, "ie,ea->ia", l1, w.Hvv, w.S1, 1);
   C(-1, "ma,im->ia", l1, w.Hoo, w.S1, 1);
@@ -431,6 +445,7 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   C(-1, "mnae,mnei->ia", w.l2s, w.D, w.S1, 1);
   C(1, "nf,iemf->niem", t1, I.ovov, w.B7, 0);
   C(-1, "mnae,niem->ia", w.l2s, w.B7, w.S1, 1);
+  if (par) join_branches(E);
 }
 
 template <typename T>
