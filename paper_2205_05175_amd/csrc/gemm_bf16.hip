@@ -178,8 +178,9 @@ __global__ __launch_bounds__(kThr) void gemm_bf16x3_nt(Params p) {
         acci[i][j][e] = 0.f;
       }
 
-  // a plane tile of one stage: 128 rows x 16 k = 256 chunks of 16 bytes, one per thread
-  const int crow = tid >> 1, cq = tid & 1;
+  // a plane tile of one stage: 128 rows x 16 k = 256 chunks of 16 bytes, one per thread; thread t
+  // moves row t % 128, half t / 128 (consecutive lanes write consecutive LDS rows: conflict-free)
+  const int crow = tid & 127, cq = tid >> 7;
   u4 ra[PA], rb[PB];
   // k-blocked planes: stage k0 of rows r0.. is the contiguous run at (k0 / 16) * R * 16 + r0 * 16
   const int64_t sa = (int64_t)p.Mp * SK, sb = (int64_t)p.Np * SK;
@@ -187,10 +188,10 @@ __global__ __launch_bounds__(kThr) void gemm_bf16x3_nt(Params p) {
     const int64_t kb = k0 / SK;
 #pragma unroll
     for (int pl = 0; pl < PA; ++pl)
-      ra[pl] = *reinterpret_cast<const u4*>(p.A + pl * p.pa + kb * sa + (int64_t)m0 * SK + 8 * tid);
+      ra[pl] = *reinterpret_cast<const u4*>(p.A + pl * p.pa + kb * sa + (int64_t)(m0 + crow) * SK + 8 * cq);
 #pragma unroll
     for (int pl = 0; pl < PB; ++pl)
-      rb[pl] = *reinterpret_cast<const u4*>(p.B + pl * p.pb + kb * sb + (int64_t)n0 * SK + 8 * tid);
+      rb[pl] = *reinterpret_cast<const u4*>(p.B + pl * p.pb + kb * sb + (int64_t)(n0 + crow) * SK + 8 * cq);
   };
   auto stash = [&](int buf) {
 #pragma unroll
@@ -313,16 +314,16 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   p.alpha = (float)alpha;
   p.beta = (float)beta;
   // Split K when it shortens the estimated time: workgroups run in rounds of one per CU (256), a
-  // tile takes ~tile_flops / (half the per-CU split-BF16 rate), and s > 1 splits add a reduction
-  // that streams s partial planes and C at ~5 TB/s.
+  // tile takes ~tile_flops / (35% of the per-CU split-BF16 rate, as measured), and s > 1 splits add
+  // a reduction that streams s partial planes and C (cache-resident: ~12 TB/s measured).
   const int stages = p.Kp / kBK;
-  const double tile_time = 2.0 * kBM * kBN * (double)p.Kp * ((AC && BC) ? 4 : 2) / (0.5 * 2516.6e12 / 3 / 256);
+  const double tile_time = 2.0 * kBM * kBN * (double)p.Kp * ((AC && BC) ? 4 : 2) / (0.35 * 2516.6e12 / 3 / 256);
   const double plane_bytes = (double)M * N * 4.0 * 2.0;
   int splits = 1;
   double best = 1e300;
   for (int sp = 1; sp <= 16 && (sp == 1 || stages / sp >= 4); ++sp) {
     const double rounds = (double)cdiv((int64_t)p.ntiles * sp, 256);
-    const double t = rounds * tile_time / sp + (sp > 1 ? (2.0 * sp + 2.0) * plane_bytes / 5e12 : 0.0);
+    const double t = rounds * tile_time / sp + (sp > 1 ? (2.0 * sp + 2.0) * plane_bytes / 12e12 : 0.0);
     if (t < best * 0.97) {
       best = t;
       splits = sp;
