@@ -61,6 +61,7 @@ struct Work {
   Ten<T> Pd, Px, Bd, Bx, WW, Wd, Wx, HH, HHd, HHx, HH5, T2R, T2R0, T2R1, L2R, L2R0, L2R1, Zt, ZLt, B2, B3, Wr;
   Ten<T> Z, ZL, S1t;                               // (1+P) brackets; t1-t1 ring piece
   Ten<T> R1, R2, S1, S2;                           // residuals: R_T (T1,T2), R_L (L1,L2)
+  Ten<T> S1b, S1c, Wr2;                            // partial Lambda1 sums of the concurrent groups
   Ten<T> rho, Dvv, Doo, P1;                        // one-particle density
 };
 

@@ -203,6 +203,9 @@ void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
   w.R1 = A.cplx<T>({o, v});
   w.R2 = A.cplx<T>({o, o, v, v});
   w.S1 = A.cplx<T>({o, v});
+  w.S1b = A.cplx<T>({o, v});
+  w.S1c = A.cplx<T>({o, v});
+  w.Wr2 = A.cplx<T>({o, o, v, v});
   w.S2 = A.cplx<T>({o, o, v, v});
   w.rho = A.cplx<T>({n, n});
   w.Dvv = A.cplx<T>({v, v});
@@ -314,10 +317,12 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     }
   }
 
-  // Lambda one-body intermediates used by both Lambda residuals
+  // Lambda intermediates used by more than one of the concurrent parts
   if (lambda && tb) {
     C(-1, "mnef,mnaf->ae", w.t2s, w.l2, w.Gvv, 0);
     C(1, "mnef,inef->mi", w.t2s, w.l2, w.Goo, 0);
+    C(1, "imef,kf->imek", w.l2s, t1, w.U, 0);
+    C(1, "imef,ke->imkf", w.l2s, t1, w.U2, 0);
   }
   if (par) fork_branches(E);
 
@@ -378,8 +383,10 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   }
   P(1, "ijab->jiba", w.ZL, w.S2, 1);
 
-  // ---- Lambda1 residual: S1 = Fme + l1.Hvv - l1.Hoo + ... + A1 - A2
-  if (par) cur = E.br[1];
+  // ---- Lambda1 residual: S1 = Fme + l1.Hvv - l1.Hoo + ... + A1 - A2, in three groups with their
+  // own partial sums (S1, S1b, S1c): group A after the T2 residual on the main engine, groups B
+  // (the Wr / Y3 parts of A1) and C (A2) on the second branch; summed after the join.
+  if (par) cur = &E;
   P(1, "ia->ia", w.Fme, w.S1, 0);
   C(1, "ie,ea->ia", l1, w.Hvv, w.S1, 1);
   C(-1, "ma,im->ia", l1, w.Hoo, w.S1, 1);
@@ -389,6 +396,7 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   C(1, "mnae,mnfe->af", w.l2s, t2, w.Gx, 0);
   C(-1, "if,af->ia", w.Fme, w.Gx, w.S1, 1);
   if (!tb) return;
+  // group A
   C(2, "me,iame->ia", l1, w.HHd, w.S1, 1);
   C(1, "me,iame->ia", l1, w.HHx, w.S1, 1);
   C(-2, "ef,eifa->ia", w.Gvv, w.Hvovv, w.S1, 1);
@@ -399,8 +407,6 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   C(1, "imef,mafe->ia", w.l2s, I.ovvv, w.S1, 1);
   C(2, "mg,imag->ia", t1, w.LadL, w.S1, 1);
   C(-1, "mg,imga->ia", t1, w.LadL, w.S1, 1);
-  C(1, "imef,kf->imek", w.l2s, t1, w.U, 0);
-  C(1, "imef,ke->imkf", w.l2s, t1, w.U2, 0);
   C(1, "mg,kega->meka", t1, I.ovvv, w.B2, 0);
   C(-1, "imek,meka->ia", w.U, w.B2, w.S1, 1);
   C(1, "mg,kfag->mfka", t1, I.ovvv, w.B3, 0);
@@ -409,43 +415,48 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   C(1, "mg,klag->klma", t1, I.oovv, w.Nn, 0);
   C(1, "imkl,klma->ia", w.Mp, w.Nn, w.S1, 1);
   C(1, "imnk,knma->ia", w.Mp, I.ooov, w.S1, 1);
-  C(1, "imef,nmeg->infg", w.l2s, t2, w.Wr, 0);
-  C(-1, "infg,nfag->ia", w.Wr, I.ovvv, w.S1, 1);
-  C(1, "imef,nmgf->ineg", w.l2s, t2, w.Wr, 0);
-  C(1, "ineg,nega->ia", w.Wr, I.Lovvv, w.S1, 1);
-  C(1, "imef,nmfg->ineg", w.l2s, t2, w.Wr, 0);
-  C(-1, "ineg,nega->ia", w.Wr, I.ovvv, w.S1, 1);
   C(-1, "imnf,nfam->ia", w.U2, I.ovvo, w.S1, 1);
-  C(1, "imnf,kmfg->inkg", w.U2, t2, w.Y3, 0);
-  C(1, "inkg,nkag->ia", w.Y3, I.oovv, w.S1, 1);
-  C(1, "imnf,kmgf->inkg", w.U2, t2, w.Y3, 0);
-  C(-1, "inkg,nkag->ia", w.Y3, I.Loovv, w.S1, 1);
   C(-1, "imen,nema->ia", w.U, I.ovov, w.S1, 1);
+  // group B: the Wr and Y3 parts of A1
+  if (par) cur = E.br[1];
+  C(1, "imef,nmeg->infg", w.l2s, t2, w.Wr, 0);
+  C(-1, "infg,nfag->ia", w.Wr, I.ovvv, w.S1b, 0);
+  C(1, "imef,nmgf->ineg", w.l2s, t2, w.Wr, 0);
+  C(1, "ineg,nega->ia", w.Wr, I.Lovvv, w.S1b, 1);
+  C(1, "imef,nmfg->ineg", w.l2s, t2, w.Wr, 0);
+  C(-1, "ineg,nega->ia", w.Wr, I.ovvv, w.S1b, 1);
+  C(1, "imnf,kmfg->inkg", w.U2, t2, w.Y3, 0);
+  C(1, "inkg,nkag->ia", w.Y3, I.oovv, w.S1b, 1);
+  C(1, "imnf,kmgf->inkg", w.U2, t2, w.Y3, 0);
+  C(-1, "inkg,nkag->ia", w.Y3, I.Loovv, w.S1b, 1);
   C(1, "imen,kmeg->inkg", w.U, t2, w.Y3, 0);
-  C(1, "inkg,nkga->ia", w.Y3, I.oovv, w.S1, 1);
-  // -A2 = -sum_mne l2s_mn^ae Hbar_iemn
-  C(-1, "mnae,mnie->ia", w.l2s, I.ooov, w.S1, 1);
+  C(1, "inkg,nkga->ia", w.Y3, I.oovv, w.S1b, 1);
+  // group C: -A2 = -sum_mne l2s_mn^ae Hbar_iemn
+  C(-1, "mnae,mnie->ia", w.l2s, I.ooov, w.S1c, 0);
   C(1, "mnae,ke->mnak", w.l2s, t1, w.Y6, 0);
-  C(1, "mnak,ikmn->ia", w.Y6, w.W, w.S1, 1);
-  C(-1, "mnae,nmei->ia", w.l2s, w.Z1, w.S1, 1);
-  C(1, "mnae,nkef->mkaf", w.l2s, t2, w.Wr, 0);
-  C(-1, "mkaf,ikmf->ia", w.Wr, I.Looov, w.S1, 1);
-  C(1, "mnae,nkfe->mkaf", w.l2s, t2, w.Wr, 0);
-  C(1, "mkaf,ikmf->ia", w.Wr, I.ooov, w.S1, 1);
-  C(1, "mnae,mkfe->nkaf", w.l2s, t2, w.Wr, 0);
-  C(1, "nkaf,kinf->ia", w.Wr, I.ooov, w.S1, 1);
+  C(1, "mnak,ikmn->ia", w.Y6, w.W, w.S1c, 1);
+  C(-1, "mnae,nmei->ia", w.l2s, w.Z1, w.S1c, 1);
+  C(1, "mnae,nkef->mkaf", w.l2s, t2, w.Wr2, 0);
+  C(-1, "mkaf,ikmf->ia", w.Wr2, I.Looov, w.S1c, 1);
+  C(1, "mnae,nkfe->mkaf", w.l2s, t2, w.Wr2, 0);
+  C(1, "mkaf,ikmf->ia", w.Wr2, I.ooov, w.S1c, 1);
+  C(1, "mnae,mkfe->nkaf", w.l2s, t2, w.Wr2, 0);
+  C(1, "nkaf,kinf->ia", w.Wr2, I.ooov, w.S1c, 1);
   C(1, "mf,iefn->mien", t1, I.ovvo, w.B4, 0);
-  C(-1, "mnae,mien->ia", w.l2s, w.B4, w.S1, 1);
+  C(-1, "mnae,mien->ia", w.l2s, w.B4, w.S1c, 1);
   C(1, "mf,ikfg->mikg", t1, I.oovv, w.B5, 0);
   C(-1, "kneg,mikg->mnei", t2, w.B5, w.D, 0);
   C(1, "mf,ikfg->mikg", t1, I.Loovv, w.B5, 0);
   C(1, "knge,mikg->mnei", t2, w.B5, w.D, 1);
   C(1, "nf,ikgf->nikg", t1, I.oovv, w.B5, 0);
   C(-1, "mkge,nikg->mnei", t2, w.B5, w.D, 1);
-  C(-1, "mnae,mnei->ia", w.l2s, w.D, w.S1, 1);
+  C(-1, "mnae,mnei->ia", w.l2s, w.D, w.S1c, 1);
   C(1, "nf,iemf->niem", t1, I.ovov, w.B7, 0);
-  C(-1, "mnae,niem->ia", w.l2s, w.B7, w.S1, 1);
+  C(-1, "mnae,niem->ia", w.l2s, w.B7, w.S1c, 1);
   if (par) join_branches(E);
+  cur = &E;
+  P(1, "ia->ia", w.S1b, w.S1, 1);
+  P(1, "ia->ia", w.S1c, w.S1, 1);
 }
 
 template <typename T>
