@@ -213,12 +213,12 @@ void prof_flush(rtcc_ctx* c) {
   c->ev_used = 0;
 }
 
-void prof_mark(void* user, int phase, double flops) {
+void prof_mark(void* user, int phase, double flops, hipStream_t st) {
   rtcc_ctx* c = (rtcc_ctx*)user;
   if (!c->prof) return;
   c->prof_flops = flops;
   if (phase == 0 && c->ev_used + 2 > (int)c->ev.size()) prof_flush(c);
-  RTCC_HIP(hipEventRecord(c->ev[c->ev_used++], c->stream));
+  RTCC_HIP(hipEventRecord(c->ev[c->ev_used++], st));
   if (phase == 1) c->prof_launches++;
 }
 

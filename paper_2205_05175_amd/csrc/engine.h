@@ -84,9 +84,9 @@ struct Engine {
   ConstCache* cache = nullptr;
   Scratch scratch;
   int64_t gemm_flops = 0;  // algorithmic real flops issued (accounting)
-  // optional hook called before (phase 0) and after (phase 1) the ladder GEMM launch; the
-  // third argument is the launch's algorithmic real flops
-  void (*mark)(void*, int, double) = nullptr;
+  // optional hook called before (phase 0) and after (phase 1) the ladder GEMM launch with the
+  // launch's algorithmic real flops and the stream it is issued on
+  void (*mark)(void*, int, double, hipStream_t) = nullptr;
   void* mark_user = nullptr;
   double ladder_flops = 0.0;  // algorithmic real flops of the last ladder GEMM
   bool trace = false;         // print every contraction's layout decisions to stderr

@@ -215,9 +215,9 @@ void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
 
 template <typename T>
 void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
-  // Contractions go to engine `cur`. With branch engines, the T2, Lambda2 and Lambda1 residuals
-  // (which share only intermediates finished before the fork, and each write their own outputs and
-  // temporaries) run concurrently on three streams.
+  // Contractions go to engine `cur`. With branch engines, independent parts (which share only
+  // intermediates finished before their fork, and each write their own outputs and temporaries)
+  // run concurrently on three streams, in two fork/join sections.
   Engine* cur = &E;
   auto C = [&](double a, const char* s, const Ten<T>& x, const Ten<T>& y, const Ten<T>& z, double b) {
     ein<T>(*cur, a, s, x, y, z, b);
@@ -240,6 +240,12 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     P(2, "ijab->ijab", l2, w.l2s, 0);
     P(-1, "ijab->ijba", l2, w.l2s, 1);
   }
+
+  // Concurrent part 1 (with branch engines): the main engine builds the one-body intermediates,
+  // the T1 residual, W and Hbar_mnie; branch 0 the ladder, Z1 and Hbar_amef; branch 1 the
+  // t2-integral ring pieces and the Lambda intermediates G, U. Then the main engine completes the
+  // ring intermediates (which need Hbar_mnie) and part 2 forks the residuals.
+  if (par) fork_branches(E);
 
   // ---- one-body intermediates
   P(1, "ae->ae", w.fvv, w.Fae, 0);
@@ -278,6 +284,8 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     C(1, "ijef,mnef->mnij", tau, I.oovv, w.W, 1);
     P(1, "mnie->mnie", I.ooov, w.Hooov, 0);
     C(1, "if,mnfe->mnie", t1, I.oovv, w.Hooov, 1);
+
+    if (par) cur = E.br[0];
     if (lambda) {
       P(1, "mafe->amef", I.ovvv, w.Hvovv, 0);
       C(-1, "na,nmef->amef", t1, I.oovv, w.Hvovv, 1);
@@ -290,15 +298,28 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
       GemmOp<T> a{w.X.re, w.X.im, vv, 0};
       GemmOp<T> b{I.vvvv.re, nullptr, vv, 1, true};  // B(ef, ab) = <ab|ef> = <ef|ab>: V is symmetric
       E.ladder_flops = 4.0 * (double)rows * (double)vv * (double)vv;  // real x complex: 2 MACs per entry
-      if (E.mark) E.mark(E.mark_user, 0, E.ladder_flops);
-      gemm<T>(E, rows, vv, vv, 1.0, a, b, w.Lad.re, w.Lad.im, vv, 0.0);
-      if (E.mark) E.mark(E.mark_user, 1, E.ladder_flops);
+      if (E.mark) E.mark(E.mark_user, 0, E.ladder_flops, cur->stream);
+      gemm<T>(*cur, rows, vv, vv, 1.0, a, b, w.Lad.re, w.Lad.im, vv, 0.0);
+      if (E.mark) E.mark(E.mark_user, 1, E.ladder_flops, cur->stream);
     }
     C(1, "ijef,mafe->ijam", tau, I.ovvv, w.Z1, 0);
+
     // ring intermediates (element X_mbej at (m,e,j,b))
+    if (par) cur = E.br[1];
     C(1, "njfb,mnef->mejb", t2, I.Loovv, w.Pd, 0);
     C(-1, "jnfb,mnef->mejb", t2, I.oovv, w.Pd, 1);
     C(1, "jnfb,mnfe->mejb", t2, I.oovv, w.Px, 0);
+  }
+  // Lambda intermediates used by more than one of the concurrent parts
+  if (lambda && tb) {
+    C(-1, "mnef,mnaf->ae", w.t2s, w.l2, w.Gvv, 0);
+    C(1, "mnef,inef->mi", w.t2s, w.l2, w.Goo, 0);
+    C(1, "imef,kf->imek", w.l2s, t1, w.U, 0);
+    C(1, "imef,ke->imkf", w.l2s, t1, w.U2, 0);
+  }
+  if (par) join_branches(E);
+  cur = &E;
+  if (tb) {
     P(1, "mbej->mejb", I.ovvo, w.Bd, 0);
     C(1, "jf,mbef->mejb", t1, I.ovvv, w.Bd, 1);
     C(-1, "nb,nmje->mejb", t1, w.Hooov, w.Bd, 1);
@@ -315,14 +336,6 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
       P(1, "mejb->mejb", w.Bx, w.HHx, 0);
       P(1, "mejb->mejb", w.Px, w.HHx, 1);
     }
-  }
-
-  // Lambda intermediates used by more than one of the concurrent parts
-  if (lambda && tb) {
-    C(-1, "mnef,mnaf->ae", w.t2s, w.l2, w.Gvv, 0);
-    C(1, "mnef,inef->mi", w.t2s, w.l2, w.Goo, 0);
-    C(1, "imef,kf->imek", w.l2s, t1, w.U, 0);
-    C(1, "imef,ke->imkf", w.l2s, t1, w.U2, 0);
   }
   if (par) fork_branches(E);
 
