@@ -190,7 +190,8 @@ int rtcc_check_state(rtcc_ctx* ctx, const void* y, int64_t* nonfinite);
 
 /* Live timing of the dominant kernel, the particle-particle ladder GEMM. rtcc_profile(ctx, 1)
  * resets the statistics and brackets every subsequent ladder launch with HIP events recorded on
- * the context stream; rtcc_profile(ctx, 0) stops. While profiling is on, rtcc_propagate_rk4 issues
+ * the stream it is issued on (with RTCC_BF16X3 the split-BF16 GEMM kernel alone, which runs under
+ * a name of its own; otherwise the whole GEMM call); rtcc_profile(ctx, 0) stops. While profiling is on, rtcc_propagate_rk4 issues
  * its kernels one by one instead of replaying the captured step graph (events recorded inside a
  * captured graph cannot be timed); rtcc_propagate_batch does the same when any of its contexts
  * is profiling, and times that context's batched ladder. rtcc_profile_read synchronises and returns

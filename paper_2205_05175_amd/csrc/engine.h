@@ -88,6 +88,9 @@ struct Engine {
   // launch's algorithmic real flops and the stream it is issued on
   void (*mark)(void*, int, double, hipStream_t) = nullptr;
   void* mark_user = nullptr;
+  // 1 while the ladder GEMM is issued: the split-BF16 path then launches its kernel under a name of
+  // its own and calls `mark` around that kernel alone (other paths: around the whole GEMM call)
+  int ladder = 0;
   double ladder_flops = 0.0;  // algorithmic real flops of the last ladder GEMM
   bool trace = false;         // print every contraction's layout decisions to stderr
   bool bf16x3 = false;        // FP32 GEMMs above bf16_min_flops use the split-BF16 three-term kernel

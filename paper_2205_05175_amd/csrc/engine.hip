@@ -288,6 +288,8 @@ void fork_branches(Engine& E) {
   RTCC_HIP(hipEventRecord(E.ev_fork, E.stream));
   for (Engine* b : E.br) {
     b->cache = E.cache;
+    b->mark = E.mark;
+    b->mark_user = E.mark_user;
     b->trace = E.trace;
     b->bf16x3 = E.bf16x3;
     b->bf16_min_flops = E.bf16_min_flops;

@@ -136,11 +136,14 @@ __device__ inline bf8 neg(bf8 x) {
 
 __device__ inline f16 mma(bf8 a, bf8 b, f16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
 
-// Tile (tm, tn) of workgroup b: the eight XCDs take workgroups round-robin; renumber so XCD x owns a
-// contiguous range, then walk that range in bands of 8 tile rows (tiles of a band share B columns).
-__device__ inline void tile_of(int b, const Params& p, int* tm, int* tn) {
-  const int n = p.ntiles, q = n / 8, r = n % 8, x = b % 8, j = b / 8;
-  const int id = x * q + min(x, r) + j;
+// Split and tile (tm, tn) of workgroup b: the eight XCDs take workgroups round-robin; renumber so
+// XCD x owns a contiguous range of (split, tile) pairs, split slowest, and walk the tiles of one
+// split in bands of 8 tile rows (tiles of a band share B columns, all share the split's k range).
+__device__ inline void tile_of(int b, const Params& p, int* split, int* tm, int* tn) {
+  const int n = p.ntiles * p.splits, q = n / 8, r = n % 8, x = b % 8, j = b / 8;
+  const int lin = x * q + min(x, r) + j;
+  *split = lin / p.ntiles;
+  const int id = lin - *split * p.ntiles;
   constexpr int G = 8;
   const int band = id / (G * p.tiles_n);
   const int first = band * G;
@@ -150,7 +153,8 @@ __device__ inline void tile_of(int b, const Params& p, int* tm, int* tn) {
   *tn = in / rows;
 }
 
-template <int AC, int BC>
+// LADDER = 1: the same kernel under a name of its own for the particle-particle ladder.
+template <int AC, int BC, int LADDER>
 __global__ __launch_bounds__(kThr) void gemm_bf16x3_nt(Params p) {
   constexpr int NA = AC ? 2 : 1, NB = BC ? 2 : 1;  // complex planes
   constexpr int PA = 2 * NA, PB = 2 * NB;            // packed planes (hi, lo per complex plane)
@@ -161,9 +165,8 @@ __global__ __launch_bounds__(kThr) void gemm_bf16x3_nt(Params p) {
   __shared__ __attribute__((aligned(16))) __bf16 Bs[2][PB * kBN * LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int split = blockIdx.x % p.splits;
-  int tm, tn;
-  tile_of(blockIdx.x / p.splits, p, &tm, &tn);
+  int split, tm, tn;
+  tile_of(blockIdx.x, p, &split, &tm, &tn);
   const int m0 = tm * kBM, n0 = tn * kBN;
   const int kbeg = split * p.kchunk, kend = min(p.Kp, kbeg + p.kchunk);
 
@@ -348,10 +351,14 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
     p.ldc = ldc;
   }
   const dim3 grid((unsigned)(p.ntiles * splits));
-  if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1>), grid, dim3(kThr), 0, E.stream, p);
-  else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0>), grid, dim3(kThr), 0, E.stream, p);
-  else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1>), grid, dim3(kThr), 0, E.stream, p);
+  const bool lad = E.ladder != 0;
+  if (lad && E.mark) E.mark(E.mark_user, 0, E.ladder_flops, E.stream);
+  if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 1>), grid, dim3(kThr), 0, E.stream, p);
+  else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1, 0>), grid, dim3(kThr), 0, E.stream, p);
+  else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 0>), grid, dim3(kThr), 0, E.stream, p);
+  else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1, 0>), grid, dim3(kThr), 0, E.stream, p);
   RTCC_HIP(hipGetLastError());
+  if (lad && E.mark) E.mark(E.mark_user, 1, E.ladder_flops, E.stream);
   if (splits > 1) splitk_reduce_launch<float>(E.stream, Pre, Pim, splits, M, N, Cre, Cim, ldc, 0, 1, alpha, beta);
   E.scratch.reset(mark);
   E.gemm_flops += 2 * M * N * K * ((AC && BC) ? 4 : 2);

@@ -298,9 +298,13 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
       GemmOp<T> a{w.X.re, w.X.im, vv, 0};
       GemmOp<T> b{I.vvvv.re, nullptr, vv, 1, true};  // B(ef, ab) = <ab|ef> = <ef|ab>: V is symmetric
       E.ladder_flops = 4.0 * (double)rows * (double)vv * (double)vv;  // real x complex: 2 MACs per entry
-      if (E.mark) E.mark(E.mark_user, 0, E.ladder_flops, cur->stream);
+      cur->ladder_flops = E.ladder_flops;
+      cur->ladder = 1;
+      const bool split16 = sizeof(T) == 4 && cur->bf16x3;  // the split-BF16 path marks its kernel itself
+      if (E.mark && !split16) E.mark(E.mark_user, 0, E.ladder_flops, cur->stream);
       gemm<T>(*cur, rows, vv, vv, 1.0, a, b, w.Lad.re, w.Lad.im, vv, 0.0);
-      if (E.mark) E.mark(E.mark_user, 1, E.ladder_flops, cur->stream);
+      if (E.mark && !split16) E.mark(E.mark_user, 1, E.ladder_flops, cur->stream);
+      cur->ladder = 0;
     }
     C(1, "ijef,mafe->ijam", tau, I.ovvv, w.Z1, 0);
 
