@@ -453,6 +453,7 @@ void padd(Engine& E, double alpha, const char* specstr, const Ten<T>& A, const T
     os[nd] = C.s[i];
     ++nd;
   }
+  if (E.trace) fprintf(stderr, "[rtcc] padd %s\n", specstr);
   if (A.cplx() || !C.cplx()) {
     permute_axpby<T>(E.stream, nd, d, A.re, A.im, is, C.re, C.im, os, alpha, beta);
   } else {

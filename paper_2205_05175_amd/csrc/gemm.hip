@@ -118,12 +118,12 @@ struct TileRegs {
 };
 
 // TA: A stored as [k][m] (else [m][k]); TB: B stored as [n][k] (else [k][n]).
-template <typename T, int BM, int BN, int AC, int BC, int TA, int TB, int VEC>
+template <typename T, int BM, int BN, int AC, int BC, int TA, int TB, int VEC, int BK = kBK>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
   constexpr int NA = AC ? 2 : 1, NB = BC ? 2 : 1;
   constexpr int LDA = BM + 1, LDB = BN + 1;  // padded LDS rows
-  __shared__ T As[NA * kBK * LDA];
-  __shared__ T Bs[NB * kBK * LDB];
+  __shared__ T As[NA * BK * LDA];
+  __shared__ T Bs[NB * BK * LDB];
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
   using V4 = typename Mfma<T>::v4;
 
@@ -148,10 +148,10 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
 
   // A tile: TA ? (rows k, cols m) : (rows m, cols k);  B tile: TB ? (rows n, cols k) : (rows k, cols n).
   // A narrow tile (32 rows or columns) has fewer elements than VEC per thread: use shorter vectors.
-  constexpr int VA = VEC < (kBK * BM) / kThreads ? VEC : (kBK * BM) / kThreads;
-  constexpr int VB = VEC < (kBK * BN) / kThreads ? VEC : (kBK * BN) / kThreads;
-  TileRegs<T, TA ? kBK : BM, TA ? BM : kBK, VA, NA> ra;
-  TileRegs<T, TB ? BN : kBK, TB ? kBK : BN, VB, NB> rb;
+  constexpr int VA = VEC < (BK * BM) / kThreads ? VEC : (BK * BM) / kThreads;
+  constexpr int VB = VEC < (BK * BN) / kThreads ? VEC : (BK * BN) / kThreads;
+  TileRegs<T, TA ? BK : BM, TA ? BM : BK, VA, NA> ra;
+  TileRegs<T, TB ? BN : BK, TB ? BK : BN, VB, NB> rb;
   auto fetch = [&](int k0) {
     if (TA) ra.load(Ap, p.lda, k0, m0, kend, p.M, tid);
     else ra.load(Ap, p.lda, m0, k0, p.M, kend, tid);
@@ -159,24 +159,24 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
     else rb.load(Bp, p.ldb, k0, n0, kend, p.N, tid);
   };
   if (kbeg < kend) fetch(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += kBK) {
-    ra.template store<TA != 0, LDA>(As, kBK * LDA, tid);
-    rb.template store<TB == 0, LDB>(Bs, kBK * LDB, tid);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    ra.template store<TA != 0, LDA>(As, BK * LDA, tid);
+    rb.template store<TB == 0, LDB>(Bs, BK * LDB, tid);
     __syncthreads();
-    if (k0 + kBK < kend) fetch(k0 + kBK);  // next tile in flight while this one is multiplied
+    if (k0 + BK < kend) fetch(k0 + BK);  // next tile in flight while this one is multiplied
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 4) {
+    for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4), col = lane & 15;
       T ar[FM], ai[FM], br[FN], bi[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
         ar[i] = As[kr * LDA + wm * WM + i * 16 + col];
-        if (AC) ai[i] = As[kBK * LDA + kr * LDA + wm * WM + i * 16 + col];
+        if (AC) ai[i] = As[BK * LDA + kr * LDA + wm * WM + i * 16 + col];
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         br[j] = Bs[kr * LDB + wn * WN + j * 16 + col];
-        if (BC) bi[j] = Bs[kBK * LDB + kr * LDB + wn * WN + j * 16 + col];
+        if (BC) bi[j] = Bs[BK * LDB + kr * LDB + wn * WN + j * 16 + col];
       }
       T nai[FM];
       if (AC && BC) {
@@ -257,11 +257,27 @@ __global__ __launch_bounds__(256) void splitk_reduce(const T* Pre, const T* Pim,
   const int64_t idx = (int64_t)blockIdx.x * 16 + ol;
   const bool ok = idx < (int64_t)M * N;
   T sr = 0, si = 0;
-  if (ok)
-    for (int s = sl; s < splits; s += 16) {
-      sr += Pre[s * stride + idx];
-      if (Pim) si += Pim[s * stride + idx];
+  if (ok) {
+    // eight partial loads in flight per step, added in split order
+    int s = sl;
+    for (; s + 7 * 16 < splits; s += 8 * 16) {
+      T vr[8], vi[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        vr[u] = Pre[(int64_t)(s + 16 * u) * stride + idx];
+        vi[u] = Pim ? Pim[(int64_t)(s + 16 * u) * stride + idx] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        sr += vr[u];
+        si += vi[u];
+      }
     }
+    for (; s < splits; s += 16) {
+      sr += Pre[(int64_t)s * stride + idx];
+      if (Pim) si += Pim[(int64_t)s * stride + idx];
+    }
+  }
   shr[sl][ol] = sr;
   shi[sl][ol] = si;
   __syncthreads();
@@ -295,9 +311,23 @@ __global__ __launch_bounds__(256) void splitk_reduce_few(const T* Pre, const T* 
   const int64_t n = (int64_t)M * N;
   for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * 256) {
     T ar = 0, ai = 0;
-    for (int s = 0; s < splits; ++s) {
-      ar += Pre[s * stride + idx];
-      if (Pim) ai += Pim[s * stride + idx];
+    int s = 0;
+    for (; s + 4 <= splits; s += 4) {
+      T vr[4], vi[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        vr[u] = Pre[(int64_t)(s + u) * stride + idx];
+        vi[u] = Pim ? Pim[(int64_t)(s + u) * stride + idx] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ar += vr[u];
+        ai += vi[u];
+      }
+    }
+    for (; s < splits; ++s) {
+      ar += Pre[(int64_t)s * stride + idx];
+      if (Pim) ai += Pim[(int64_t)s * stride + idx];
     }
     const int row = (int)(idx / N), col = (int)(idx - (int64_t)row * N);
     const int64_t off = (int64_t)row * ldc + col;
@@ -329,42 +359,300 @@ template void splitk_reduce_launch<float>(hipStream_t, const float*, const float
 template void splitk_reduce_launch<double>(hipStream_t, const double*, const double*, int, int64_t, int64_t, double*,
                                            double*, int64_t, int64_t, int, double, double);
 
-template <typename T, int BM, int BN, int AC, int BC, int TA, int TB, int VEC>
+// ---- tiny products ------------------------------------------------------------------------------
+// M * N and K small: too few tiles to hide a tile kernel's stage latency. A workgroup takes 16
+// consecutive outputs of member blockIdx.y; 16 threads share the k range of each output (thread
+// slice s takes k = s, s + 16, ...) and the 16 slice sums are added in slice order.
+template <typename T, int AC, int BC>
+__global__ __launch_bounds__(256) void gemm_dot_kernel(GemmParams<T> p) {
+  __shared__ T shr[16][17], shi[16][17];
+  const int ol = threadIdx.x & 15, ks = threadIdx.x >> 4;
+  const int64_t o = (int64_t)blockIdx.x * 16 + ol;
+  const bool ok = o < (int64_t)p.M * p.N;
+  const int m = ok ? (int)(o / p.N) : 0, n = ok ? (int)(o - (int64_t)m * p.N) : 0;
+  const int64_t zb = blockIdx.y;
+  const T* Ar = p.Are + zb * p.sa;
+  const T* Ai = AC ? p.Aim + zb * p.sa : nullptr;
+  const T* Br = p.Bre + zb * p.sb;
+  const T* Bi = BC ? p.Bim + zb * p.sb : nullptr;
+  // element (m, k) of A at am + k * ak; element (k, n) of B at bn + k * bk
+  const int64_t am = p.ta ? m : (int64_t)m * p.lda, ak = p.ta ? p.lda : 1;
+  const int64_t bn = p.tb ? (int64_t)n * p.ldb : n, bk = p.tb ? 1 : p.ldb;
+  T ar = 0, ai = 0;
+  auto madd = [&](T xr, T xi, T yr, T yi) {
+    ar = fma(xr, yr, ar);
+    if (AC && BC) ar = fma(-xi, yi, ar);
+    if (BC) ai = fma(xr, yi, ai);
+    if (AC) ai = fma(xi, yr, ai);
+  };
+  if (ok) {
+    int k = ks;
+    for (; k + 3 * 16 < p.K; k += 4 * 16) {
+      T xr[4], xi[4], yr[4], yi[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t kk = k + 16 * u;
+        xr[u] = Ar[am + kk * ak];
+        xi[u] = AC ? Ai[am + kk * ak] : T(0);
+        yr[u] = Br[bn + kk * bk];
+        yi[u] = BC ? Bi[bn + kk * bk] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) madd(xr[u], xi[u], yr[u], yi[u]);
+    }
+    for (; k < p.K; k += 16)
+      madd(Ar[am + (int64_t)k * ak], AC ? Ai[am + (int64_t)k * ak] : T(0), Br[bn + (int64_t)k * bk],
+           BC ? Bi[bn + (int64_t)k * bk] : T(0));
+  }
+  shr[ks][ol] = ar;
+  shi[ks][ol] = ai;
+  __syncthreads();
+  if (ks != 0 || !ok) return;
+  T sr = 0, si = 0;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    sr += shr[s][ol];
+    si += shi[s][ol];
+  }
+  constexpr bool CC = AC || BC;
+  const int64_t off = zb * p.sc + (int64_t)m * p.ldc + n;
+  T outr = p.alpha * sr, outi = p.alpha * si;
+  if (p.beta != T(0)) {
+    outr += p.beta * p.Cre[off];
+    if (CC) outi += p.beta * p.Cim[off];
+  }
+  p.Cre[off] = outr;
+  if (CC) p.Cim[off] = outi;
+}
+
+// ---- matrix-vector products (one of M, N is 1) -------------------------------------------------
+// y(n) = alpha * sum_k x(k) W(k, n) + beta * y(n), x with element stride incx, y with stride incy.
+// With split_stride != 0 the k-range of split s goes to the partial plane y + s * split_stride
+// (unit stride) and splitk_reduce_launch finishes the sum.
+template <typename T>
+struct GemvParams {
+  const T* xre;
+  const T* xim;
+  int64_t incx;
+  const T* wre;
+  const T* wim;
+  int64_t ldw;
+  T* yre;
+  T* yim;
+  int64_t incy;
+  int N, K, kchunk;
+  int64_t split_stride;
+  T alpha, beta;
+};
+
+// Row layout W(k, n) = W[k * ldw + n]: consecutive lanes take consecutive n (coalesced rows of W);
+// each thread walks its k-range with eight rows of loads in flight and sums in k order.
+template <typename T, int XC, int WC>
+__global__ __launch_bounds__(256) void gemv_row_kernel(GemvParams<T> p) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= p.N) return;  // no barriers below
+  const int s = blockIdx.y;
+  const int kb = s * p.kchunk, ke = min(p.K, kb + p.kchunk);
+  T ar = 0, ai = 0;
+  auto madd = [&](T xr, T xi, T wr, T wi) {
+    ar = fma(xr, wr, ar);
+    if (XC && WC) ar = fma(-xi, wi, ar);
+    if (WC) ai = fma(xr, wi, ai);
+    if (XC) ai = fma(xi, wr, ai);
+  };
+  int k = kb;
+  for (; k + 8 <= ke; k += 8) {
+    T wr[8], wi[8], xr[8], xi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t o = (int64_t)(k + u) * p.ldw + n;
+      wr[u] = p.wre[o];
+      wi[u] = WC ? p.wim[o] : T(0);
+      xr[u] = p.xre[(int64_t)(k + u) * p.incx];
+      xi[u] = XC ? p.xim[(int64_t)(k + u) * p.incx] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) madd(xr[u], xi[u], wr[u], wi[u]);
+  }
+  for (; k < ke; ++k) {
+    const int64_t o = (int64_t)k * p.ldw + n;
+    madd(p.xre[(int64_t)k * p.incx], XC ? p.xim[(int64_t)k * p.incx] : T(0), p.wre[o], WC ? p.wim[o] : T(0));
+  }
+  constexpr bool CC = XC || WC;
+  if (p.split_stride) {
+    const int64_t o = (int64_t)s * p.split_stride + n;
+    p.yre[o] = ar;
+    if (CC) p.yim[o] = ai;
+  } else {
+    const int64_t o = (int64_t)n * p.incy;
+    T outr = p.alpha * ar, outi = p.alpha * ai;
+    if (p.beta != T(0)) {
+      outr += p.beta * p.yre[o];
+      if (CC) outi += p.beta * p.yim[o];
+    }
+    p.yre[o] = outr;
+    if (CC) p.yim[o] = outi;
+  }
+}
+
+// Column layout W(k, n) = W[n * ldw + k]: one wave per n, lanes stride over k (coalesced), four
+// loads in flight per lane; the 64 lane sums are combined in a fixed butterfly order.
+template <typename T, int XC, int WC>
+__global__ __launch_bounds__(256) void gemv_col_kernel(GemvParams<T> p) {
+  const int lane = threadIdx.x & 63;
+  const int n = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= p.N) return;  // whole waves leave together; no barriers below
+  const int s = blockIdx.y;
+  const int kb = s * p.kchunk, ke = min(p.K, kb + p.kchunk);
+  const T* wr = p.wre + (int64_t)n * p.ldw;
+  const T* wi = WC ? p.wim + (int64_t)n * p.ldw : nullptr;
+  T ar = 0, ai = 0;
+  auto madd = [&](T xr, T xi, T vr, T vi) {
+    ar = fma(xr, vr, ar);
+    if (XC && WC) ar = fma(-xi, vi, ar);
+    if (WC) ai = fma(xr, vi, ai);
+    if (XC) ai = fma(xi, vr, ai);
+  };
+  int k = kb + lane;
+  for (; k + 3 * 64 < ke; k += 4 * 64) {
+    T vr[4], vi[4], xr[4], xi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k + 64 * u;
+      vr[u] = wr[kk];
+      vi[u] = WC ? wi[kk] : T(0);
+      xr[u] = p.xre[(int64_t)kk * p.incx];
+      xi[u] = XC ? p.xim[(int64_t)kk * p.incx] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) madd(xr[u], xi[u], vr[u], vi[u]);
+  }
+  for (; k < ke; k += 64)
+    madd(p.xre[(int64_t)k * p.incx], XC ? p.xim[(int64_t)k * p.incx] : T(0), wr[k], WC ? wi[k] : T(0));
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    ar += __shfl_xor(ar, off);
+    ai += __shfl_xor(ai, off);
+  }
+  if (lane != 0) return;
+  constexpr bool CC = XC || WC;
+  if (p.split_stride) {
+    const int64_t o = (int64_t)s * p.split_stride + n;
+    p.yre[o] = ar;
+    if (CC) p.yim[o] = ai;
+  } else {
+    const int64_t o = (int64_t)n * p.incy;
+    T outr = p.alpha * ar, outi = p.alpha * ai;
+    if (p.beta != T(0)) {
+      outr += p.beta * p.yre[o];
+      if (CC) outi += p.beta * p.yim[o];
+    }
+    p.yre[o] = outr;
+    if (CC) p.yim[o] = outi;
+  }
+}
+
+// x(k), W(k, n) as described above; y complex when x or W is. Returns the number of splits used.
+template <typename T>
+static int gemv(Engine& E, bool col, int64_t N, int64_t K, double alpha, const T* xre, const T* xim, int64_t incx,
+                const T* wre, const T* wim, int64_t ldw, T* yre, T* yim, int64_t incy, double beta) {
+  GemvParams<T> p;
+  p.xre = xre;
+  p.xim = xim;
+  p.incx = incx;
+  p.wre = wre;
+  p.wim = wim;
+  p.ldw = ldw;
+  p.N = (int)N;
+  p.K = (int)K;
+  p.alpha = (T)alpha;
+  p.beta = (T)beta;
+  // enough independent k-ranges for ~2048 workgroups of row threads / ~8192 column waves
+  int64_t kchunk;
+  unsigned gx;
+  if (col) {
+    gx = (unsigned)cdiv(N, 4);
+    const int64_t want = std::max<int64_t>(1, 8192 / N);
+    kchunk = cdiv(cdiv(K, std::min<int64_t>(want, cdiv(K, 256))), 64) * 64;
+  } else {
+    gx = (unsigned)cdiv(N, 256);
+    kchunk = cdiv(std::max<int64_t>({16, cdiv(K * gx, 2048), cdiv(K, 65535)}), 8) * 8;
+  }
+  const int splits = (int)cdiv(K, kchunk);
+  p.kchunk = (int)kchunk;
+  size_t mark = E.scratch.used;
+  T* Pre = nullptr;
+  T* Pim = nullptr;
+  const bool CC = xim || wim;
+  if (splits > 1) {
+    Pre = E.scratch.get<T>((int64_t)splits * N);
+    if (CC) Pim = E.scratch.get<T>((int64_t)splits * N);
+    p.yre = Pre;
+    p.yim = Pim;
+    p.incy = 1;
+    p.split_stride = N;
+  } else {
+    p.yre = yre;
+    p.yim = yim;
+    p.incy = incy;
+    p.split_stride = 0;
+  }
+  const dim3 grid(gx, (unsigned)splits);
+  const int sel = (xim ? 2 : 0) + (wim ? 1 : 0);
+#define RTCC_GEMV(XC, WC)                                                                             \
+  if (col) hipLaunchKernelGGL((gemv_col_kernel<T, XC, WC>), grid, dim3(256), 0, E.stream, p);          \
+  else hipLaunchKernelGGL((gemv_row_kernel<T, XC, WC>), grid, dim3(256), 0, E.stream, p);
+  switch (sel) {
+    case 0: RTCC_GEMV(0, 0) break;
+    case 1: RTCC_GEMV(0, 1) break;
+    case 2: RTCC_GEMV(1, 0) break;
+    default: RTCC_GEMV(1, 1) break;
+  }
+#undef RTCC_GEMV
+  RTCC_HIP(hipGetLastError());
+  // partial planes [split][n] -> y(n) at stride incy (an N x 1 "matrix" with row stride incy)
+  if (splits > 1) splitk_reduce_launch<T>(E.stream, Pre, Pim, splits, N, 1, yre, yim, incy, 0, 1, alpha, beta);
+  E.scratch.reset(mark);
+  return splits;
+}
+
+template <typename T, int BM, int BN, int AC, int BC, int TA, int TB, int VEC, int BK = kBK>
 static void launch_one(hipStream_t st, const GemmParams<T>& p, int zdim) {
   dim3 grid((unsigned)cdiv(p.N, BN), (unsigned)cdiv(p.M, BM), (unsigned)zdim);
-  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, AC, BC, TA, TB, VEC>), grid, dim3(kThreads), 0, st, p);
+  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, AC, BC, TA, TB, VEC, BK>), grid, dim3(kThreads), 0, st, p);
   RTCC_HIP(hipGetLastError());
 }
 
-template <typename T, int BM, int BN, int AC, int BC>
+template <typename T, int BM, int BN, int AC, int BC, int BK, bool VECONLY>
 static void launch_gemm(hipStream_t st, const GemmParams<T>& p, int splits, bool vec) {
   constexpr int V = 16 / sizeof(T);
   const int sel = (p.ta ? 2 : 0) + (p.tb ? 1 : 0);
-  if (vec) {
+  if (vec || VECONLY) {
     switch (sel) {
-      case 0: launch_one<T, BM, BN, AC, BC, 0, 0, V>(st, p, splits); break;
-      case 1: launch_one<T, BM, BN, AC, BC, 0, 1, V>(st, p, splits); break;
-      case 2: launch_one<T, BM, BN, AC, BC, 1, 0, V>(st, p, splits); break;
-      default: launch_one<T, BM, BN, AC, BC, 1, 1, V>(st, p, splits); break;
+      case 0: launch_one<T, BM, BN, AC, BC, 0, 0, V, BK>(st, p, splits); break;
+      case 1: launch_one<T, BM, BN, AC, BC, 0, 1, V, BK>(st, p, splits); break;
+      case 2: launch_one<T, BM, BN, AC, BC, 1, 0, V, BK>(st, p, splits); break;
+      default: launch_one<T, BM, BN, AC, BC, 1, 1, V, BK>(st, p, splits); break;
     }
   } else {
     switch (sel) {
-      case 0: launch_one<T, BM, BN, AC, BC, 0, 0, 1>(st, p, splits); break;
-      case 1: launch_one<T, BM, BN, AC, BC, 0, 1, 1>(st, p, splits); break;
-      case 2: launch_one<T, BM, BN, AC, BC, 1, 0, 1>(st, p, splits); break;
-      default: launch_one<T, BM, BN, AC, BC, 1, 1, 1>(st, p, splits); break;
+      case 0: launch_one<T, BM, BN, AC, BC, 0, 0, 1, BK>(st, p, splits); break;
+      case 1: launch_one<T, BM, BN, AC, BC, 0, 1, 1, BK>(st, p, splits); break;
+      case 2: launch_one<T, BM, BN, AC, BC, 1, 0, 1, BK>(st, p, splits); break;
+      default: launch_one<T, BM, BN, AC, BC, 1, 1, 1, BK>(st, p, splits); break;
     }
   }
 }
 
-template <typename T, int BM, int BN>
+// VECONLY: instantiated for 16-byte-aligned operands only (the caller falls back to 64 x 64 tiles)
+template <typename T, int BM, int BN, int BK = kBK, bool VECONLY = false>
 static void launch_typed(hipStream_t st, const GemmParams<T>& p, int splits, bool vec) {
   const int sel = (p.Aim ? 2 : 0) + (p.Bim ? 1 : 0);
   switch (sel) {
-    case 0: launch_gemm<T, BM, BN, 0, 0>(st, p, splits, vec); break;
-    case 1: launch_gemm<T, BM, BN, 0, 1>(st, p, splits, vec); break;
-    case 2: launch_gemm<T, BM, BN, 1, 0>(st, p, splits, vec); break;
-    default: launch_gemm<T, BM, BN, 1, 1>(st, p, splits, vec); break;
+    case 0: launch_gemm<T, BM, BN, 0, 0, BK, VECONLY>(st, p, splits, vec); break;
+    case 1: launch_gemm<T, BM, BN, 0, 1, BK, VECONLY>(st, p, splits, vec); break;
+    case 2: launch_gemm<T, BM, BN, 1, 0, BK, VECONLY>(st, p, splits, vec); break;
+    default: launch_gemm<T, BM, BN, 1, 1, BK, VECONLY>(st, p, splits, vec); break;
   }
 }
 
@@ -395,6 +683,20 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
         gemm_bf16x3(E, M, N, K, alpha, A, B, Cre, Cim, ldc, beta))
       return;
   }
+  if (nbt == 1 && (M == 1 || N == 1)) {
+    int splits;
+    if (M == 1)  // x(k) = A(0, k), W(k, n) = B(k, n), y(n) = C(0, n)
+      splits = gemv<T>(E, B.trans != 0, N, K, alpha, A.re, A.im, A.trans ? A.ld : 1, B.re, B.im, B.ld, Cre, Cim, 1,
+                       beta);
+    else  // x(k) = B(k, 0), W(k, m) = A(m, k), y(m) = C(m, 0)
+      splits = gemv<T>(E, A.trans == 0, M, K, alpha, B.re, B.im, B.trans ? 1 : B.ld, A.re, A.im, A.ld, Cre, Cim, ldc,
+                       beta);
+    E.gemm_flops += 2 * M * N * K * ((AC && BC) ? 4 : (AC || BC) ? 2 : 1);
+    if (E.trace)
+      fprintf(stderr, "[rtcc] gemv M=%lld N=%lld K=%lld %s%s ta=%d tb=%d splits=%d\n", (long long)M, (long long)N,
+              (long long)K, AC ? "c" : "r", BC ? "c" : "r", A.trans, B.trans, splits);
+    return;
+  }
   GemmParams<T> p;
   p.Are = A.re;
   p.Aim = A.im;
@@ -416,26 +718,74 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
   constexpr int V = 16 / sizeof(T);
   const bool vec = aligned16(A.re) && (!AC || aligned16(A.im)) && aligned16(B.re) && (!BC || aligned16(B.im)) &&
                    A.ld % V == 0 && B.ld % V == 0 && bt.a % V == 0 && bt.b % V == 0;
-  // FP32: 128 x 128 tiles when the grid still holds >= 2 tiles per CU; FP64 (longer MFMA,
-  // more registers per tile): always 64 x 64 for occupancy. Small grids split over K.
-  constexpr int LBM = 128, LBN = 128;
-  // short K, one side of at most 32 against a long other side: a 32 x 256 (or 256 x 32) tile wastes
-  // little (long K goes to split-K instead)
+  // Tile choice (measured on skinny shapes, which are latency- and bandwidth-bound):
+  //  - short K (<= 256) with one side of at most 32 (96 against a very long other side): a thin tile
+  //    along the long side; the whole K of a tile is a few stages;
+  //  - an output of at most 128 x 128 with long K: a tile fitted to the output and K split into
+  //    ~512-2048 fixed-order partial sums;
+  //  - FP32 with >= 512 tiles of 128 x 128: those; otherwise 64 x 64, K split when the grid is small.
+  if (M * N <= 8192 && K <= 256) {
+    p.kchunk = (int)K;
+    p.splits = 1;
+    p.split_stride = 0;
+    p.Cre = Cre;
+    p.Cim = Cim;
+    p.ldc = ldc;
+    const dim3 grid((unsigned)cdiv(M * N, 16), (unsigned)nbt);
+    const int sel = (AC ? 2 : 0) + (BC ? 1 : 0);
+    switch (sel) {
+      case 0: hipLaunchKernelGGL((gemm_dot_kernel<T, 0, 0>), grid, dim3(256), 0, E.stream, p); break;
+      case 1: hipLaunchKernelGGL((gemm_dot_kernel<T, 0, 1>), grid, dim3(256), 0, E.stream, p); break;
+      case 2: hipLaunchKernelGGL((gemm_dot_kernel<T, 1, 0>), grid, dim3(256), 0, E.stream, p); break;
+      default: hipLaunchKernelGGL((gemm_dot_kernel<T, 1, 1>), grid, dim3(256), 0, E.stream, p); break;
+    }
+    RTCC_HIP(hipGetLastError());
+    E.gemm_flops += 2 * M * N * K * nbt * ((AC && BC) ? 4 : (AC || BC) ? 2 : 1);
+    if (E.trace)
+      fprintf(stderr, "[rtcc] gemm M=%lld N=%lld K=%lld batch=%d %s%s ta=%d tb=%d dot\n", (long long)M, (long long)N,
+              (long long)K, nbt, AC ? "c" : "r", BC ? "c" : "r", A.trans, B.trans);
+    return;
+  }
   const int narrow = K > 256                                            ? 0
                      : (M <= 32 && N >= 256) || (M <= 96 && N >= 8192)   ? 1
                      : (N <= 32 && M >= 256) || (N <= 96 && M >= 8192)   ? 2
                                                                          : 0;
-  const bool large = !narrow && sizeof(T) == 4 && cdiv(M, LBM) * cdiv(N, LBN) * nbt >= 512;
-  const int BM = narrow == 1 ? 32 : narrow == 2 ? 256 : large ? LBM : 64;
-  const int BN = narrow == 1 ? 256 : narrow == 2 ? 32 : large ? LBN : 64;
+  const bool skinny = !narrow && M <= 128 && N <= 128 && K >= 512 && vec;
+  const bool large = !narrow && !skinny && sizeof(T) == 4 && cdiv(M, 128) * cdiv(N, 128) * nbt >= 512;
+  int BM = 64, BN = 64, BK = kBK, target = 1024;
+  if (narrow == 1) {
+    BM = 32;
+    BN = K <= 32 ? 64 : 128;
+    BK = K <= 32 ? 32 : 16;
+  } else if (narrow == 2) {
+    BM = 64;
+    BN = N <= 32 ? 32 : 96;
+    BK = 32;
+  } else if (skinny) {
+    if (M <= N || M <= 32) {
+      BM = 32;
+      BN = N <= 32 ? 32 : N <= 64 ? 64 : N <= 96 ? 96 : 128;
+    } else {
+      BN = 32;
+      BM = M <= 64 ? 64 : 96;
+    }
+    BK = BM == 32 && BN == 32 ? 64 : BN == 128 ? 16 : 32;
+    target = BM * BN <= 1024 ? 2048 : BM * BN <= 2048 ? 1024 : 512;
+  } else if (large) {
+    BM = BN = 128;
+  }
+  const bool fixed = narrow || large;
+  if (narrow && !vec) BM = BN = 64, BK = kBK;  // thin tiles are built for aligned operands only
   const int64_t tiles = cdiv(M, BM) * cdiv(N, BN) * nbt;
-  // fewer than ~2 workgroups per CU: split K (chunks of >= 256) toward ~1024 workgroups
   int splits = 1;
-  if (!large && !narrow && tiles < 512 && K >= 512) {
+  if (skinny) {
+    splits = (int)std::max<int64_t>(1, std::min<int64_t>({target / tiles, cdiv(K, 64), 65535 / nbt}));
+  } else if (!fixed && tiles < 512 && K >= 512) {
+    // fewer than ~2 workgroups per CU: split K (chunks of >= 256) toward ~1024 workgroups
     int64_t want = std::max<int64_t>(1, 1024 / tiles);
     splits = (int)std::min<int64_t>({want, cdiv(K, 256), 1024, 65535 / nbt});
   }
-  int64_t kchunk = cdiv(cdiv(K, splits), kBK) * kBK;
+  int64_t kchunk = cdiv(cdiv(K, splits), BK) * BK;
   splits = (int)cdiv(K, kchunk);
   p.kchunk = (int)kchunk;
   p.splits = splits;
@@ -455,17 +805,26 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
     p.Cim = Cim;
     p.ldc = ldc;
   }
-  if (narrow == 1) launch_typed<T, 32, 256>(E.stream, p, nbt * splits, vec);
-  else if (narrow == 2) launch_typed<T, 256, 32>(E.stream, p, nbt * splits, vec);
-  else if (large) launch_typed<T, LBM, LBN>(E.stream, p, nbt * splits, vec);
-  else launch_typed<T, 64, 64>(E.stream, p, nbt * splits, vec);
+  const int z = nbt * splits;
+  const int cfg = BM * 1000 + BN;
+  if (BK == kBK && BM == 64 && BN == 64) launch_typed<T, 64, 64>(E.stream, p, z, vec);
+  else if (cfg == 128128) {
+    if constexpr (sizeof(T) == 4) launch_typed<T, 128, 128>(E.stream, p, z, vec);
+  } else if (cfg == 32064) launch_typed<T, 32, 64, 32, true>(E.stream, p, z, vec);
+  else if (cfg == 32128) launch_typed<T, 32, 128, 16, true>(E.stream, p, z, vec);
+  else if (cfg == 64032) launch_typed<T, 64, 32, 32, true>(E.stream, p, z, vec);
+  else if (cfg == 64096) launch_typed<T, 64, 96, 32, true>(E.stream, p, z, vec);
+  else if (cfg == 32032) launch_typed<T, 32, 32, 64, true>(E.stream, p, z, vec);
+  else if (cfg == 32096) launch_typed<T, 32, 96, 32, true>(E.stream, p, z, vec);
+  else if (cfg == 96032) launch_typed<T, 96, 32, 32, true>(E.stream, p, z, vec);
+  else RTCC_CHECK(false, kEInval, "gemm: no kernel for the chosen tile");
   if (splits > 1) splitk_reduce_launch<T>(E.stream, Pre, Pim, splits, M, N, Cre, Cim, ldc, bt.c, nbt, alpha, beta);
   E.scratch.reset(mark);
   E.gemm_flops += 2 * M * N * K * nbt * ((AC && BC) ? 4 : (AC || BC) ? 2 : 1);
   if (E.trace)
-    fprintf(stderr, "[rtcc] gemm M=%lld N=%lld K=%lld batch=%d %s%s ta=%d tb=%d tile=%dx%d splits=%d vec=%d\n",
+    fprintf(stderr, "[rtcc] gemm M=%lld N=%lld K=%lld batch=%d %s%s ta=%d tb=%d tile=%dx%dx%d splits=%d vec=%d\n",
             (long long)M, (long long)N, (long long)K, nbt, AC ? "c" : "r", BC ? "c" : "r", A.trans, B.trans, BM,
-            BN, splits, (int)vec);
+            BN, BK, splits, (int)vec);
 }
 
 template void gemm<double>(Engine&, int64_t, int64_t, int64_t, double, GemmOp<double>, GemmOp<double>, double*,
