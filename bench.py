@@ -27,13 +27,13 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6}
 
-# HBM bytes per launch of the split-BF16 ladder kernel (gemm_bf16x3_nt<1, 0, 1>, o=20 v=76),
+# HBM bytes per launch of the split-BF16 ladder kernel (gemm_bf16x3_nt<1, 0, 1, 4>, o=20 v=76),
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by the
 # same counter on a plain device copy of the same run (the 72,247.5 KiB state clone: FETCH_SIZE
-# 36,139.8 KiB, x2.0; WRITE_SIZE 72,247.5 KiB, x1.0). Commands and raw figures:
+# 36,139.2 KiB, x2.0; WRITE_SIZE 72,247.5 KiB, x1.0). Commands and raw figures:
 # profiles/ladder_traffic_o20v76.md. To be re-measured whenever that kernel changes.
-LADDER_TRAFFIC_BF16X3 = {"fetch_bytes": 310154.2 * 1024 * 2.0, "write_bytes": 110746.5 * 1024 * 1.0,
-                         "kernel": "gemm_bf16x3_nt<1, 0, 1>"}
+LADDER_TRAFFIC_BF16X3 = {"fetch_bytes": 246295.6 * 1024 * 2.0, "write_bytes": 38162.9 * 1024 * 1.0,
+                         "kernel": "gemm_bf16x3_nt<1, 0, 1, 4>"}
 
 
 def log(*a):
@@ -363,8 +363,8 @@ def main():
                                  if measured_traffic else None),
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      # packed operands read once (X: 896 x 5792 x 4 bf16 planes, V: 5888 x 5792 x 2) and
-                     # three split-K partial planes written (800 x 5776 complex FP32 each)
-                     "traffic_algorithmic_min": (2 * 896 * 5792 * 4 + 2 * 5888 * 5792 * 2 + 800 * 5776 * 8 * 3
+                     # the 800 x 5776 complex FP32 output written once (one K split at this size)
+                     "traffic_algorithmic_min": (2 * 896 * 5792 * 4 + 2 * 5888 * 5792 * 2 + 800 * 5776 * 8
                                                  if measured_traffic else None),
                      "avg_ms": rh["ladder_ms"], "flops_per_launch": rh["ladder_flops"],
                      "fp32": {"achieved": r32["ladder_tflops"], "peak": PEAK_TFLOPS["fp32"],

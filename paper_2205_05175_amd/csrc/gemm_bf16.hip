@@ -5,18 +5,19 @@
 // dropped lo*lo' term is ~2^-16 of the product). The split is a separate pass that also brings both
 // operands into one layout, "packed": per plane (Re hi, Re lo[, Im hi, Im lo]) a bf16 matrix of
 // [rows][K] stored k-blocked as [K / 16][rows][16] (16 consecutive k of a row contiguous), rows
-// padded to a multiple of 128 and K to a multiple of 32 with zeros, so the GEMM copies whole
-// contiguous stage tiles without bounds checks. Packed layouts of constant operands (the
-// integrals) are made once and cached.
+// padded to a multiple of the tile's rows (128 for A, 256 for B) and K to a multiple of 32 with
+// zeros, so the GEMM copies whole contiguous stage tiles without bounds checks. Packed layouts of
+// constant operands (the integrals) are made once and cached.
 //
-// GEMM: 256 threads, a 128 x 128 output tile per workgroup, 2 x 2 waves of 64 x 64 (2 x 2 MFMA
-// blocks of 32 x 32). Per 16-wide k stage the packed tiles pass through registers into one of two
-// LDS buffers: stage s + 1 is written and stage s + 2 fetched while stage s is multiplied, with
-// one barrier per stage. Lane l of a 32x32x16
-// MFMA holds A[l%32][8(l/32)+j] and B[8(l/32)+j][l%32] and its output r lies at row
-// 8(r/4) + 4(l/32) + r%4, column l%32. Small grids split K into fixed-order partial sums. Workgroups
-// are numbered so that each of the eight XCDs (which take workgroups round-robin) works on a
-// contiguous band of tiles.
+// GEMM: 512 threads, a 128 x 256 output tile per workgroup, 2 x 4 waves of 64 x 64 (2 x 2 MFMA
+// blocks of 32 x 32 each), two waves per SIMD so that one wave's MFMAs cover the other's LDS and
+// barrier waits; the wide N side halves the B-plane traffic per flop. Per 16-wide k stage the
+// packed tiles pass through registers into one of two LDS buffers: stage s + 1 is written and
+// stage s + 2 fetched while stage s is multiplied, with one barrier per stage. Lane l of a
+// 32x32x16 MFMA holds A[l%32][8(l/32)+j] and B[8(l/32)+j][l%32] and its output r lies at row
+// 8(r/4) + 4(l/32) + r%4, column l%32. Small grids split K into fixed-order partial sums.
+// Workgroups are numbered so that each of the eight XCDs (which take workgroups round-robin) works
+// on a contiguous band of tiles.
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -32,10 +33,9 @@ typedef float f16 __attribute__((ext_vector_type(16)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
-constexpr int kThr = 256;
-constexpr int kBM = 128, kBN = 128;  // output tile
+constexpr int kBM = 128;             // output tile rows; columns 64 * WN (WN waves along N)
 constexpr int kBK = 32;              // k stage
-constexpr int kRowPad = 128;         // packed rows are a multiple of this
+constexpr int kRowPad = 128;         // packed rows are a multiple of this (of 256 for wide B tiles)
 constexpr int kKPad = 32;            // packed K is a multiple of this
 
 // ---- packing ------------------------------------------------------------------------------------
@@ -86,9 +86,9 @@ struct Packed {
 };
 
 Packed pack_operand(Engine& E, const float* re, const float* im, int64_t ld, int trans, int64_t R, int64_t K,
-                    bool konst) {
+                    bool konst, int rowpad) {
   Packed P;
-  P.Rp = (int)(cdiv(R, kRowPad) * kRowPad);
+  P.Rp = (int)(cdiv(R, rowpad) * rowpad);
   P.Kp = (int)(cdiv(K, kKPad) * kKPad);
   P.np = im ? 2 : 1;
   P.plane = (int64_t)P.Rp * P.Kp;
@@ -101,8 +101,8 @@ Packed pack_operand(Engine& E, const float* re, const float* im, int64_t ld, int
   };
   if (konst && E.cache) {
     char key[160];
-    snprintf(key, sizeof key, "bf16x3:%p/%p/%lld/%d/%lld/%lld", (const void*)re, (const void*)im, (long long)ld, trans,
-             (long long)R, (long long)K);
+    snprintf(key, sizeof key, "bf16x3:%p/%p/%lld/%d/%lld/%lld/%d", (const void*)re, (const void*)im, (long long)ld,
+             trans, (long long)R, (long long)K, P.Rp);
     P.p = (const __bf16*)const_cache_get(E.cache, key, bytes, fill);
   } else {
     void* dst = E.scratch.get<char>((int64_t)bytes);
@@ -154,8 +154,10 @@ __device__ inline void tile_of(int b, const Params& p, int* split, int* tm, int*
 }
 
 // LADDER = 1: the same kernel under a name of its own for the particle-particle ladder.
-template <int AC, int BC, int LADDER>
-__global__ __launch_bounds__(kThr) void gemm_bf16x3_nt(Params p) {
+// WN waves along N (2 or 4): a 128 x 64 WN tile, 128 WN threads.
+template <int AC, int BC, int LADDER, int WN>
+__global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p) {
+  constexpr int kThr = 128 * WN, kBN = 64 * WN;
   constexpr int NA = AC ? 2 : 1, NB = BC ? 2 : 1;  // complex planes
   constexpr int PA = 2 * NA, PB = 2 * NB;            // packed planes (hi, lo per complex plane)
   constexpr int SK = 16;                             // k per LDS stage (one MFMA step)
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(kThr) void gemm_bf16x3_nt(Params p) {
   __shared__ __attribute__((aligned(16))) __bf16 As[2][PA * kBM * LDK];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[2][PB * kBN * LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   int split, tm, tn;
   tile_of(blockIdx.x, p, &split, &tm, &tn);
   const int m0 = tm * kBM, n0 = tn * kBN;
@@ -181,26 +183,30 @@ __global__ __launch_bounds__(kThr) void gemm_bf16x3_nt(Params p) {
         acci[i][j][e] = 0.f;
       }
 
-  // a plane tile of one stage: 128 rows x 16 k = 256 chunks of 16 bytes, one per thread; thread t
-  // moves row t % 128, half t / 128 (consecutive lanes write consecutive LDS rows: conflict-free)
-  const int crow = tid & 127, cq = tid >> 7;
-  u4 ra[PA], rb[PB];
+  // a plane tile of one stage: rows x 16 k = 2 chunks of 16 bytes per row. B: one chunk per plane
+  // and thread (row t % kBN, half t / kBN); A (128 rows): planes (t / 256) + kThr / 256 * q, row
+  // t % 128, half (t / 128) % 2. Consecutive lanes write consecutive LDS rows (conflict-free).
+  constexpr int AST = kThr / 256, NRA = PA / AST;  // A planes per thread
+  const int brow = tid % kBN, bq = tid / kBN;
+  const int arow = tid & 127, aq = (tid >> 7) & 1, apl = tid >> 8;
+  u4 ra[NRA], rb[PB];
   // k-blocked planes: stage k0 of rows r0.. is the contiguous run at (k0 / 16) * R * 16 + r0 * 16
   const int64_t sa = (int64_t)p.Mp * SK, sb = (int64_t)p.Np * SK;
   auto fetch = [&](int k0) {
     const int64_t kb = k0 / SK;
 #pragma unroll
-    for (int pl = 0; pl < PA; ++pl)
-      ra[pl] = *reinterpret_cast<const u4*>(p.A + pl * p.pa + kb * sa + (int64_t)(m0 + crow) * SK + 8 * cq);
+    for (int q = 0; q < NRA; ++q)
+      ra[q] = *reinterpret_cast<const u4*>(p.A + (apl + AST * q) * p.pa + kb * sa + (int64_t)(m0 + arow) * SK + 8 * aq);
 #pragma unroll
     for (int pl = 0; pl < PB; ++pl)
-      rb[pl] = *reinterpret_cast<const u4*>(p.B + pl * p.pb + kb * sb + (int64_t)(n0 + crow) * SK + 8 * cq);
+      rb[pl] = *reinterpret_cast<const u4*>(p.B + pl * p.pb + kb * sb + (int64_t)(n0 + brow) * SK + 8 * bq);
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int pl = 0; pl < PA; ++pl) *reinterpret_cast<u4*>(&As[buf][(pl * kBM + crow) * LDK + 8 * cq]) = ra[pl];
+    for (int q = 0; q < NRA; ++q)
+      *reinterpret_cast<u4*>(&As[buf][((apl + AST * q) * kBM + arow) * LDK + 8 * aq]) = ra[q];
 #pragma unroll
-    for (int pl = 0; pl < PB; ++pl) *reinterpret_cast<u4*>(&Bs[buf][(pl * kBN + crow) * LDK + 8 * cq]) = rb[pl];
+    for (int pl = 0; pl < PB; ++pl) *reinterpret_cast<u4*>(&Bs[buf][(pl * kBN + brow) * LDK + 8 * bq]) = rb[pl];
   };
 
   const int l32 = lane & 31, hk = 8 * (lane >> 5);
@@ -298,9 +304,10 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   if (!AC && !BC) return false;
   RTCC_CHECK(M < (1LL << 30) && N < (1LL << 30) && K < (1LL << 30), kEInval, "gemm_bf16x3: dimension too large");
   size_t mark = E.scratch.used;
+  constexpr int WN = 4, kBN = 64 * WN;
   // A as [M][K] rows; B as [N][K] rows (B(k, n) = trans ? b[n * ld + k] : b[k * ld + n])
-  const Packed pa = pack_operand(E, A.re, A.im, A.ld, A.trans, M, K, A.konst);
-  const Packed pb = pack_operand(E, B.re, B.im, B.ld, B.trans ? 0 : 1, N, K, B.konst);
+  const Packed pa = pack_operand(E, A.re, A.im, A.ld, A.trans, M, K, A.konst, kRowPad);
+  const Packed pb = pack_operand(E, B.re, B.im, B.ld, B.trans ? 0 : 1, N, K, B.konst, kBN);
   Params p;
   p.A = pa.p;
   p.B = pb.p;
@@ -318,13 +325,18 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   p.beta = (float)beta;
   // Split K when it shortens the estimated time: workgroups run in rounds of one per CU (256), a
   // tile takes ~tile_flops / (35% of the per-CU split-BF16 rate, as measured), and s > 1 splits add
-  // a reduction that streams s partial planes and C (cache-resident: ~12 TB/s measured).
+  // a reduction that streams s partial planes and C (cache-resident: ~12 TB/s measured). A split
+  // grid stays within kSplitWG workgroups: the right-hand side issues its large products from
+  // three concurrent streams, and a split product that claims every CU holds the others back
+  // longer than its split gains (measured: ~160-192 of 256 is best for the o=20, v=76 step).
   const int stages = p.Kp / kBK;
   const double tile_time = 2.0 * kBM * kBN * (double)p.Kp * ((AC && BC) ? 4 : 2) / (0.35 * 2516.6e12 / 3 / 256);
   const double plane_bytes = (double)M * N * 4.0 * 2.0;
   int splits = 1;
   double best = 1e300;
+  constexpr int kSplitWG = 192;
   for (int sp = 1; sp <= 16 && (sp == 1 || stages / sp >= 4); ++sp) {
+    if (sp > 1 && p.ntiles * sp > kSplitWG) break;
     const double rounds = (double)cdiv((int64_t)p.ntiles * sp, 256);
     const double t = rounds * tile_time / sp + (sp > 1 ? (2.0 * sp + 2.0) * plane_bytes / 12e12 : 0.0);
     if (t < best * 0.97) {
@@ -353,10 +365,11 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   const dim3 grid((unsigned)(p.ntiles * splits));
   const bool lad = E.ladder != 0;
   if (lad && E.mark) E.mark(E.mark_user, 0, E.ladder_flops, E.stream);
-  if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 1>), grid, dim3(kThr), 0, E.stream, p);
-  else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1, 0>), grid, dim3(kThr), 0, E.stream, p);
-  else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 0>), grid, dim3(kThr), 0, E.stream, p);
-  else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1, 0>), grid, dim3(kThr), 0, E.stream, p);
+  const dim3 block(128 * WN);
+  if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 1, WN>), grid, block, 0, E.stream, p);
+  else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1, 0, WN>), grid, block, 0, E.stream, p);
+  else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 0, WN>), grid, block, 0, E.stream, p);
+  else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1, 0, WN>), grid, block, 0, E.stream, p);
   RTCC_HIP(hipGetLastError());
   if (lad && E.mark) E.mark(E.mark_user, 1, E.ladder_flops, E.stream);
   if (splits > 1) splitk_reduce_launch<float>(E.stream, Pre, Pim, splits, M, N, Cre, Cim, ldc, 0, 1, alpha, beta);
