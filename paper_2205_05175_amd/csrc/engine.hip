@@ -104,6 +104,7 @@ Ten<T> permuted_copy(Engine& E, const Ten<T>& X, const std::string& sx, const st
   Y.im = X.im ? E.scratch.get<T>(std::max<int64_t>(n, 1)) : nullptr;
   int64_t d[kMaxDim], is[kMaxDim];
   strides_for(X, sx, order, d, is);
+  if (E.trace) fprintf(stderr, "[rtcc] permute-operand src=%p %s->%s n=%lld\n", (const void*)X.re, sx.c_str(), order.c_str(), (long long)n);
   permute_axpby<T>(E.stream, Y.nd, d, X.re, X.im, is, Y.re, Y.im, Y.s, 1.0, 0.0);
   return Y;
 }

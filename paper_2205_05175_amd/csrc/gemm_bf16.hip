@@ -105,6 +105,9 @@ Packed pack_operand(Engine& E, const float* re, const float* im, int64_t ld, int
              trans, (long long)R, (long long)K, P.Rp);
     P.p = (const __bf16*)const_cache_get(E.cache, key, bytes, fill);
   } else {
+    if (E.trace)
+      fprintf(stderr, "[rtcc] pack-operand src=%p ld=%lld trans=%d R=%lld K=%lld\n", (const void*)re, (long long)ld, trans,
+              (long long)R, (long long)K);
     void* dst = E.scratch.get<char>((int64_t)bytes);
     fill(dst, E.stream);
     P.p = (const __bf16*)dst;

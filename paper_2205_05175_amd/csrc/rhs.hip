@@ -226,6 +226,10 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     padd<T>(*cur, a, s, x, z, b);
   };
   const bool par = tb && lambda && E.br[0] && E.br[1];
+  if (E.trace)
+    fprintf(stderr, "[rtcc] tensors t1=%p t2=%p l1=%p l2=%p tau=%p taut=%p t2s=%p l2s=%p W=%p Hooov=%p Hvovv=%p\n",
+            (void*)w.t1.re, (void*)w.t2.re, (void*)w.l1.re, (void*)w.l2.re, (void*)w.tau.re, (void*)w.taut.re,
+            (void*)w.t2s.re, (void*)w.l2s.re, (void*)w.W.re, (void*)w.Hooov.re, (void*)w.Hvovv.re);
   const int o = w.o, v = w.v;
   const Ten<T>&t1 = w.t1, &t2 = w.t2, &l1 = w.l1, &l2 = w.l2, &tau = w.tau;
 
@@ -401,8 +405,18 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   P(1, "ijab->jiba", w.ZL, w.S2, 1);
 
   // ---- Lambda1 residual: S1 = Fme + l1.Hvv - l1.Hoo + ... + A1 - A2, in three groups with their
-  // own partial sums (S1, S1b, S1c): group A after the T2 residual on the main engine, groups B
-  // (the Wr / Y3 parts of A1) and C (A2) on the second branch; summed after the join.
+  // own partial sums (S1, S1b, S1c), balanced over the three streams: group B (the Wr part of A1)
+  // on the first branch after the Lambda2 residual, group A after the T2 residual on the main
+  // engine, group C (the Y3 part of A1 and A2) on the second branch; summed after the join.
+  if (tb) {
+    // group B (the Wr part of A1)
+    C(1, "imef,nmeg->infg", w.l2s, t2, w.Wr, 0);
+    C(-1, "infg,nfag->ia", w.Wr, I.ovvv, w.S1b, 0);
+    C(1, "imef,nmgf->ineg", w.l2s, t2, w.Wr, 0);
+    C(1, "ineg,nega->ia", w.Wr, I.Lovvv, w.S1b, 1);
+    C(1, "imef,nmfg->ineg", w.l2s, t2, w.Wr, 0);
+    C(-1, "ineg,nega->ia", w.Wr, I.ovvv, w.S1b, 1);
+  }
   if (par) cur = &E;
   P(1, "ia->ia", w.Fme, w.S1, 0);
   C(1, "ie,ea->ia", l1, w.Hvv, w.S1, 1);
@@ -434,22 +448,15 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   C(1, "imnk,knma->ia", w.Mp, I.ooov, w.S1, 1);
   C(-1, "imnf,nfam->ia", w.U2, I.ovvo, w.S1, 1);
   C(-1, "imen,nema->ia", w.U, I.ovov, w.S1, 1);
-  // group B: the Wr and Y3 parts of A1
+  // group C: the Y3 part of A1, then -A2 = -sum_mne l2s_mn^ae Hbar_iemn
   if (par) cur = E.br[1];
-  C(1, "imef,nmeg->infg", w.l2s, t2, w.Wr, 0);
-  C(-1, "infg,nfag->ia", w.Wr, I.ovvv, w.S1b, 0);
-  C(1, "imef,nmgf->ineg", w.l2s, t2, w.Wr, 0);
-  C(1, "ineg,nega->ia", w.Wr, I.Lovvv, w.S1b, 1);
-  C(1, "imef,nmfg->ineg", w.l2s, t2, w.Wr, 0);
-  C(-1, "ineg,nega->ia", w.Wr, I.ovvv, w.S1b, 1);
   C(1, "imnf,kmfg->inkg", w.U2, t2, w.Y3, 0);
-  C(1, "inkg,nkag->ia", w.Y3, I.oovv, w.S1b, 1);
+  C(1, "inkg,nkag->ia", w.Y3, I.oovv, w.S1c, 0);
   C(1, "imnf,kmgf->inkg", w.U2, t2, w.Y3, 0);
-  C(-1, "inkg,nkag->ia", w.Y3, I.Loovv, w.S1b, 1);
+  C(-1, "inkg,nkag->ia", w.Y3, I.Loovv, w.S1c, 1);
   C(1, "imen,kmeg->inkg", w.U, t2, w.Y3, 0);
-  C(1, "inkg,nkga->ia", w.Y3, I.oovv, w.S1b, 1);
-  // group C: -A2 = -sum_mne l2s_mn^ae Hbar_iemn
-  C(-1, "mnae,mnie->ia", w.l2s, I.ooov, w.S1c, 0);
+  C(1, "inkg,nkga->ia", w.Y3, I.oovv, w.S1c, 1);
+  C(-1, "mnae,mnie->ia", w.l2s, I.ooov, w.S1c, 1);
   C(1, "mnae,ke->mnak", w.l2s, t1, w.Y6, 0);
   C(1, "mnak,ikmn->ia", w.Y6, w.W, w.S1c, 1);
   C(-1, "mnae,nmei->ia", w.l2s, w.Z1, w.S1c, 1);
