@@ -59,4 +59,9 @@ void jacobi_update(hipStream_t st, int o, int v, const double* fdiag, const T* r
 template <typename T>
 void maxabs_planar(hipStream_t st, int64_t n, const T* re, const T* im, double* partial, double* out2);
 
+// W = (Bd + Pd / 2 | Bx + Px / 2) transposed into [q][2][p], H = (Bd + Pd, Bx + Px) interleaved into [p][q][2]
+// (H skipped when hre is null); x = {Bd, Pd, Bx, Px} as (re, im) pairs, each [p][q] contiguous.
+template <typename T>
+void ring_combo(hipStream_t st, int64_t P, int64_t Q, int nb, const T* const x[8], int64_t xbs, T* wre, T* wim,
+                int64_t wbs, T* hre, T* him, int64_t hbs);
 }  // namespace rtcc

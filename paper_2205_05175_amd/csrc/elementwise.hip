@@ -804,4 +804,86 @@ void maxabs_planar(hipStream_t st, int64_t n, const T* re, const T* im, double* 
 }
 template void maxabs_planar<double>(hipStream_t, int64_t, const double*, const double*, double*, double*);
 
+// ---- ring-intermediate combinations --------------------------------------------------------------
+// With p = (m,e), q = (j,b) and X(p,q) = X[p * Q + q] for X in {Bd, Pd, Bx, Px} (planar complex):
+//   W[q * 2P + p] = Bd + Pd / 2,   W[q * 2P + P + p] = Bx + Px / 2      (transposed, via LDS)
+//   H[p * 2Q + 2q] = Bd + Pd,      H[p * 2Q + 2q + 1] = Bx + Px          (optional)
+// 32 x 32 tiles of (p, q); member blockIdx.z of a batch at the given batch strides.
+template <typename T>
+struct RingArgs {
+  const T* x[8];  // Bd, Pd, Bx, Px: re, im
+  T* w[2];        // W re, im
+  T* h[2];        // H re, im (nullptr: not formed)
+  int64_t P, Q, tiles_q;
+  int64_t xbs, wbs, hbs;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void ring_combo_kernel(RingArgs<T> a) {
+  __shared__ T sw[4][32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t p0 = (blockIdx.x / a.tiles_q) * 32, q0 = (blockIdx.x % a.tiles_q) * 32;
+  const int64_t z = blockIdx.z;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t p = p0 + ty + 8 * k, q = q0 + tx;
+    if (p < a.P && q < a.Q) {
+      const int64_t i = z * a.xbs + p * a.Q + q;
+      T v[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[c] = a.x[c][i];
+      // v: Bd re, Bd im, Pd re, Pd im, Bx re, Bx im, Px re, Px im
+      sw[0][ty + 8 * k][tx] = v[0] + T(0.5) * v[2];
+      sw[1][ty + 8 * k][tx] = v[1] + T(0.5) * v[3];
+      sw[2][ty + 8 * k][tx] = v[4] + T(0.5) * v[6];
+      sw[3][ty + 8 * k][tx] = v[5] + T(0.5) * v[7];
+      if (a.h[0]) {
+        const int64_t o = z * a.hbs + p * 2 * a.Q + 2 * q;
+        a.h[0][o] = v[0] + v[2];
+        a.h[0][o + 1] = v[4] + v[6];
+        a.h[1][o] = v[1] + v[3];
+        a.h[1][o + 1] = v[5] + v[7];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t q = q0 + ty + 8 * k, p = p0 + tx;
+    if (p < a.P && q < a.Q) {
+      const int64_t o = z * a.wbs + q * 2 * a.P + p;
+      a.w[0][o] = sw[0][tx][ty + 8 * k];
+      a.w[1][o] = sw[1][tx][ty + 8 * k];
+      a.w[0][o + a.P] = sw[2][tx][ty + 8 * k];
+      a.w[1][o + a.P] = sw[3][tx][ty + 8 * k];
+    }
+  }
+}
+
+template <typename T>
+void ring_combo(hipStream_t st, int64_t P, int64_t Q, int nb, const T* const x[8], int64_t xbs, T* wre, T* wim,
+                int64_t wbs, T* hre, T* him, int64_t hbs) {
+  RTCC_CHECK(P > 0 && Q > 0 && nb >= 1 && nb <= 65535, kEInval, "ring_combo: bad extents");
+  RingArgs<T> a;
+  for (int c = 0; c < 8; ++c) a.x[c] = x[c];
+  a.w[0] = wre;
+  a.w[1] = wim;
+  a.h[0] = hre;
+  a.h[1] = him;
+  a.P = P;
+  a.Q = Q;
+  a.tiles_q = cdiv(Q, 32);
+  a.xbs = xbs;
+  a.wbs = wbs;
+  a.hbs = hbs;
+  const int64_t tiles = cdiv(P, 32) * a.tiles_q;
+  RTCC_CHECK(tiles < (1LL << 31), kEInval, "ring_combo: too many tiles");
+  hipLaunchKernelGGL(ring_combo_kernel<T>, dim3((unsigned)tiles, 1, (unsigned)nb), dim3(256), 0, st, a);
+  RTCC_HIP(hipGetLastError());
+}
+template void ring_combo<double>(hipStream_t, int64_t, int64_t, int, const double* const[8], int64_t, double*,
+                                 double*, int64_t, double*, double*, int64_t);
+template void ring_combo<float>(hipStream_t, int64_t, int64_t, int, const float* const[8], int64_t, float*, float*,
+                                int64_t, float*, float*, int64_t);
+
 }  // namespace rtcc

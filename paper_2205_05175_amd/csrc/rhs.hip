@@ -246,9 +246,10 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   }
 
   // Concurrent part 1 (with branch engines): the main engine builds the one-body intermediates,
-  // the T1 residual, W and Hbar_mnie; branch 0 the ladder, Z1 and Hbar_amef; branch 1 the
-  // t2-integral ring pieces and the Lambda intermediates G, U. Then the main engine completes the
-  // ring intermediates (which need Hbar_mnie) and part 2 forks the residuals.
+  // the T1 residual, W, Hbar_mnie and the Hbar_mnie-free parts of the ring intermediates; branch 0
+  // the ladder, Z1 and Hbar_amef; branch 1 the t2-integral ring pieces and the Lambda
+  // intermediates G, U. Then the main engine completes the ring intermediates (the Hbar_mnie
+  // terms and the combinations) and part 2 forks the residuals.
   if (par) fork_branches(E);
 
   // ---- one-body intermediates
@@ -288,6 +289,11 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     C(1, "ijef,mnef->mnij", tau, I.oovv, w.W, 1);
     P(1, "mnie->mnie", I.ooov, w.Hooov, 0);
     C(1, "if,mnfe->mnie", t1, I.oovv, w.Hooov, 1);
+    // the parts of the ring intermediates that do not need Hbar_mnie
+    P(1, "mbej->mejb", I.ovvo, w.Bd, 0);
+    C(1, "jf,mbef->mejb", t1, I.ovvv, w.Bd, 1);
+    P(-1, "mbje->mejb", I.ovov, w.Bx, 0);
+    C(-1, "jf,mbfe->mejb", t1, I.ovvv, w.Bx, 1);
 
     if (par) cur = E.br[0];
     if (lambda) {
@@ -328,22 +334,14 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   if (par) join_branches(E);
   cur = &E;
   if (tb) {
-    P(1, "mbej->mejb", I.ovvo, w.Bd, 0);
-    C(1, "jf,mbef->mejb", t1, I.ovvv, w.Bd, 1);
     C(-1, "nb,nmje->mejb", t1, w.Hooov, w.Bd, 1);
-    P(-1, "mbje->mejb", I.ovov, w.Bx, 0);
-    C(-1, "jf,mbfe->mejb", t1, I.ovvv, w.Bx, 1);
     C(1, "nb,mnje->mejb", t1, w.Hooov, w.Bx, 1);
-    P(1, "mejb->mejb", w.Bd, w.Wd, 0);
-    P(0.5, "mejb->mejb", w.Pd, w.Wd, 1);
-    P(1, "mejb->mejb", w.Bx, w.Wx, 0);
-    P(0.5, "mejb->mejb", w.Px, w.Wx, 1);
-    if (lambda) {
-      P(1, "mejb->mejb", w.Bd, w.HHd, 0);
-      P(1, "mejb->mejb", w.Pd, w.HHd, 1);
-      P(1, "mejb->mejb", w.Bx, w.HHx, 0);
-      P(1, "mejb->mejb", w.Px, w.HHx, 1);
-    }
+    // Wd = Bd + Pd/2, Wx = Bx + Px/2 (the T side) and Hd = Bd + Pd, Hx = Bx + Px (the Lambda side)
+    // in one pass, written straight into the stacked layouts the ring GEMMs read
+    const T* x[8] = {w.Bd.re, w.Bd.im, w.Pd.re, w.Pd.im, w.Bx.re, w.Bx.im, w.Px.re, w.Px.im};
+    const int64_t ov = (int64_t)o * v;
+    ring_combo<T>(E.stream, ov, ov, E.nb, x, w.Bd.bs, w.WW.re, w.WW.im, w.WW.bs, lambda ? w.HH.re : nullptr,
+                  lambda ? w.HH.im : nullptr, w.HH.bs);
   }
   if (par) fork_branches(E);
 
