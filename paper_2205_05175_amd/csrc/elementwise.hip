@@ -66,26 +66,21 @@ __global__ __launch_bounds__(256) void permute_elem_kernel(PermGeom g, const T* 
     decode_outer(g, row, &ib, &ob);
     ib += (int64_t)x * g.isx;
     ob += (int64_t)x * g.osx;
+    // every load (input and, for beta != 0, output planes) is issued before the first store
     if constexpr (V > 1) {
-      vt r = inre ? *reinterpret_cast<const vt*>(inre + ib) : vt{};
-      vt o = r * alpha;
-      if (beta != T(0)) o += beta * *reinterpret_cast<const vt*>(outre + ob);
-      *reinterpret_cast<vt*>(outre + ob) = o;
-      if (outim) {
-        vt ri = (inre && inim) ? *reinterpret_cast<const vt*>(inim + ib) : vt{};
-        vt oi = ri * alpha;
-        if (beta != T(0)) oi += beta * *reinterpret_cast<const vt*>(outim + ob);
-        *reinterpret_cast<vt*>(outim + ob) = oi;
-      }
+      const vt r = inre ? *reinterpret_cast<const vt*>(inre + ib) : vt{};
+      const vt ri = (outim && inre && inim) ? *reinterpret_cast<const vt*>(inim + ib) : vt{};
+      const vt cr = beta != T(0) ? *reinterpret_cast<const vt*>(outre + ob) : vt{};
+      const vt ci = (outim && beta != T(0)) ? *reinterpret_cast<const vt*>(outim + ob) : vt{};
+      *reinterpret_cast<vt*>(outre + ob) = r * alpha + beta * cr;
+      if (outim) *reinterpret_cast<vt*>(outim + ob) = ri * alpha + beta * ci;
     } else {
-      T vr = inre ? alpha * inre[ib] : T(0);
-      if (beta != T(0)) vr += beta * outre[ob];
-      outre[ob] = vr;
-      if (outim) {
-        T vi = (inre && inim) ? alpha * inim[ib] : T(0);
-        if (beta != T(0)) vi += beta * outim[ob];
-        outim[ob] = vi;
-      }
+      const T r = inre ? inre[ib] : T(0);
+      const T ri = (outim && inre && inim) ? inim[ib] : T(0);
+      const T cr = beta != T(0) ? outre[ob] : T(0);
+      const T ci = (outim && beta != T(0)) ? outim[ob] : T(0);
+      outre[ob] = alpha * r + beta * cr;
+      if (outim) outim[ob] = alpha * ri + beta * ci;
     }
   }
 }
@@ -117,18 +112,97 @@ __global__ __launch_bounds__(256) void permute_tile_kernel(PermGeom g, const T* 
       }
     }
     __syncthreads();
+    constexpr int R = kPT * kPT / 256;
+    T cr[R], ci[R];  // old output values (beta != 0), all loaded before the stores
 #pragma unroll
-    for (int r = 0; r < kPT * kPT / 256; ++r) {
+    for (int r = 0; r < R; ++r) {
+      const int ix = t & (kPT - 1), ip = (t >> 5) + r * (256 / kPT);
+      cr[r] = T(0);
+      ci[r] = T(0);
+      if (beta != T(0) && p0 + ip < dpn && x0 + ix < dxn) {
+        const int64_t off = ob + (int64_t)(p0 + ip) * g.osp + (int64_t)(x0 + ix) * g.osx;
+        cr[r] = outre[off];
+        if (outim) ci[r] = outim[off];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
       const int ix = t & (kPT - 1), ip = (t >> 5) + r * (256 / kPT);
       if (p0 + ip < dpn && x0 + ix < dxn) {
         const int64_t off = ob + (int64_t)(p0 + ip) * g.osp + (int64_t)(x0 + ix) * g.osx;
-        T vr = alpha * sre[ix][ip];
-        if (beta != T(0)) vr += beta * outre[off];
-        outre[off] = vr;
-        if (outim) {
-          T vi = alpha * sim[ix][ip];
-          if (beta != T(0)) vi += beta * outim[off];
-          outim[off] = vi;
+        outre[off] = alpha * sre[ix][ip] + beta * cr[r];
+        if (outim) outim[off] = alpha * sim[ix][ip] + beta * ci[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Transposes of small matrices (both transposed extents <= 128, e.g. 76 x 76): 32 x 32 tiles would
+// leave up to 40% of their slots empty, so a workgroup moves one whole dx x dp matrix through LDS
+// (dynamic size; rows padded to an odd length), reading with p (the input's fastest dimension)
+// across lanes and writing with x (the output's) across lanes, eight elements in flight per thread.
+template <typename T>
+__global__ __launch_bounds__(256) void permute_mat_kernel(PermGeom g, int ld, const T* __restrict__ inre,
+                                                          const T* __restrict__ inim, T* outre, T* outim, T alpha,
+                                                          T beta) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* sre = reinterpret_cast<T*>(lds_raw);
+  const int dxn = (int)g.dx.d, dpn = (int)g.dp.d, n = dxn * dpn;
+  T* sim = sre + dxn * ld;
+  const int t = threadIdx.x;
+  constexpr int U = 8;
+  for (uint32_t w = blockIdx.x; w < g.nwork; w += gridDim.x) {
+    int64_t ib, ob;
+    decode_outer(g, w, &ib, &ob);
+    for (int e0 = 0; e0 < n; e0 += 256 * U) {
+      T vr[U], vi[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + t + 256 * u;
+        vr[u] = T(0);
+        vi[u] = T(0);
+        if (e < n) {
+          const int x = (int)fdiv((uint32_t)e, g.dp), p = e - x * dpn;
+          const int64_t off = ib + (int64_t)p * g.isp + (int64_t)x * g.isx;
+          vr[u] = inre[off];
+          if (inim) vi[u] = inim[off];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + t + 256 * u;
+        if (e < n) {
+          const int x = (int)fdiv((uint32_t)e, g.dp), p = e - x * dpn;
+          sre[x * ld + p] = vr[u];
+          if (outim) sim[x * ld + p] = vi[u];
+        }
+      }
+    }
+    __syncthreads();
+    for (int e0 = 0; e0 < n; e0 += 256 * U) {
+      // the outputs' old values (beta != 0) are all loaded before any of the U stores
+      T cr[U], ci[U];
+      int64_t offs[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + t + 256 * u;
+        const int p = (int)fdiv((uint32_t)e, g.dx), x = e - p * dxn;
+        offs[u] = ob + (int64_t)p * g.osp + (int64_t)x * g.osx;
+        cr[u] = T(0);
+        ci[u] = T(0);
+        if (e < n && beta != T(0)) {
+          cr[u] = outre[offs[u]];
+          if (outim) ci[u] = outim[offs[u]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + t + 256 * u;
+        if (e < n) {
+          const int p = (int)fdiv((uint32_t)e, g.dx), x = e - p * dxn;
+          outre[offs[u]] = alpha * sre[x * ld + p] + beta * cr[u];
+          if (outim) outim[offs[u]] = alpha * sim[x * ld + p] + beta * ci[u];
         }
       }
     }
@@ -241,6 +315,22 @@ void permute_axpby(hipStream_t st, int nd, const int64_t* dims, const T* inre, c
     g.oos[g.nout] = os[i];
     outer *= d[i];
     ++g.nout;
+  }
+  // whole small matrices when 32 x 32 tiles would be partly empty and the matrix fits in LDS
+  const int64_t dpv = d[ip];
+  const int ldm = (int)(dpv % 2 == 0 ? dpv + 1 : dpv + 2);  // odd row length: conflict-free column reads
+  const int64_t mat_bytes = dxv * ldm * (int64_t)sizeof(T) * (outim ? 2 : 1);
+  if (dxv <= 128 && dpv <= 128 && (dxv % kPT != 0 || dpv % kPT != 0) && mat_bytes <= 65536 && outer >= 256) {
+    g.nwork = (uint32_t)outer;
+    if (trace)
+      fprintf(stderr, "[rtcc] permute %s mat x=%lld(is %lld os %lld) p=%lld(is %lld os %lld) outer=%lld cplx=%d beta=%g\n",
+              sizeof(T) == 8 ? "f64" : "f32", (long long)dxv, (long long)g.isx, (long long)g.osx, (long long)dpv,
+              (long long)g.isp, (long long)g.osp, (long long)outer, outim ? 1 : 0, beta);
+    const unsigned blocks = (unsigned)std::min<int64_t>(outer, 16384);
+    hipLaunchKernelGGL(permute_mat_kernel<T>, dim3(blocks), dim3(256), (size_t)mat_bytes, st, g, ldm, inre, inim, outre,
+                       outim, (T)alpha, (T)beta);
+    RTCC_HIP(hipGetLastError());
+    return;
   }
   const int64_t tx = cdiv(dxv, kPT), tp = cdiv(d[ip], kPT);
   g.tx = make_fdiv(tx);
