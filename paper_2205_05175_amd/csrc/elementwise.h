@@ -64,4 +64,10 @@ void maxabs_planar(hipStream_t st, int64_t n, const T* re, const T* im, double* 
 template <typename T>
 void ring_combo(hipStream_t st, int64_t P, int64_t Q, int nb, const T* const x[8], int64_t xbs, T* wre, T* wim,
                 int64_t wbs, T* hre, T* him, int64_t hbs);
+// tau = t2 + t1 t1, taut = t2 + t1 t1 / 2, t2s = 2 t2 - t2[ijba], l2s = 2 l2 - l2[ijba] (l2 may be null),
+// planar (re, im) pointer pairs; t1 at batch stride bs1, the doubles (t2, l2, tau, taut, t2s, l2s) at bs[k].
+template <typename T>
+void amp_combo(hipStream_t st, int o, int v, int nb, const T* const t1[2], int64_t bs1, const T* const t2[2],
+               const T* const l2[2], const int64_t bs[6], T* const tau[2], T* const taut[2], T* const t2s[2],
+               T* const l2s[2]);
 }  // namespace rtcc

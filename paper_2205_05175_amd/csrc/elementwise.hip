@@ -976,4 +976,118 @@ template void ring_combo<double>(hipStream_t, int64_t, int64_t, int, const doubl
 template void ring_combo<float>(hipStream_t, int64_t, int64_t, int, const float* const[8], int64_t, float*, float*,
                                 int64_t, float*, float*, int64_t);
 
+// ---- amplitude combinations ------------------------------------------------------------------------
+// For every (i,j): tau = t2 + t1_ia t1_jb, taut = t2 + t1_ia t1_jb / 2, t2s = 2 t2 - t2[b,a] and (if l2)
+// l2s = 2 l2 - l2[b,a], planar complex, [i][j][a][b] row-major. A workgroup takes one (i,j) and one
+// pair of mirrored 32 x 32 (a,b) tiles (ta <= tb), so the transposed partner of every element is in
+// LDS and each element of t2 and l2 is read once. Member blockIdx.z at batch stride bs1 for t1 and
+// bs[k] for the doubles (t2, l2, tau, taut, t2s, l2s).
+template <typename T>
+struct AmpArgs {
+  const T* t1[2];
+  const T* t2[2];
+  const T* l2[2];
+  T* tau[2];
+  T* taut[2];
+  T* t2s[2];
+  T* l2s[2];
+  int o, v, nt;
+  int64_t bs1, bs[6];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void amp_combo_kernel(AmpArgs<T> g) {
+  __shared__ T s[2][2][32][33];  // [tile A / mirror tile B][re / im]
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // pair index -> (ta, tb), ta <= tb: row ta holds nt - ta pairs
+  int q = blockIdx.x, ta = 0;
+  while (q >= g.nt - ta) {
+    q -= g.nt - ta;
+    ++ta;
+  }
+  const int tb = ta + q;
+  const int ij = blockIdx.y, i = ij / g.o, j = ij - i * g.o;
+  const int64_t z = blockIdx.z, vv = (int64_t)g.v * g.v;
+  const int64_t base = (int64_t)ij * vv;  // (i,j) block; member offsets per tensor below
+  const int a0 = ta * 32, b0 = tb * 32;
+  const bool mirror = ta != tb;
+  const T* t1r = g.t1[0] + z * g.bs1 + (int64_t)i * g.v;
+  const T* t1i = g.t1[1] + z * g.bs1 + (int64_t)i * g.v;
+  const T* u1r = g.t1[0] + z * g.bs1 + (int64_t)j * g.v;
+  const T* u1i = g.t1[1] + z * g.bs1 + (int64_t)j * g.v;
+  for (int which = 0; which < 2; ++which) {
+    const T* const* X = which == 0 ? g.t2 : g.l2;
+    if (which == 1 && !X[0]) break;
+    T* const* XS = which == 0 ? g.t2s : g.l2s;
+    const int64_t xo = z * g.bs[which], so = z * g.bs[which == 0 ? 4 : 5];
+    const int64_t to = z * g.bs[2], uo = z * g.bs[3];
+    // tile A = X[a0 + r][b0 + c], tile B = X[b0 + r][a0 + c]
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = ty + 8 * k;
+      for (int c = 0; c < 2; ++c) {
+        s[0][c][r][tx] = (a0 + r < g.v && b0 + tx < g.v) ? X[c][xo + base + (int64_t)(a0 + r) * g.v + b0 + tx] : T(0);
+        if (mirror)
+          s[1][c][r][tx] =
+              (b0 + r < g.v && a0 + tx < g.v) ? X[c][xo + base + (int64_t)(b0 + r) * g.v + a0 + tx] : T(0);
+      }
+    }
+    __syncthreads();
+    for (int h = 0; h < (mirror ? 2 : 1); ++h) {
+      const int ra = h == 0 ? a0 : b0, cb = h == 0 ? b0 : a0;  // this tile's row (a) and column (b) origins
+      const int ht = mirror ? 1 - h : 0;                        // the tile holding the transposed partners
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = ty + 8 * k, a = ra + r, b = cb + tx;
+        if (a >= g.v || b >= g.v) continue;
+        const int64_t off = base + (int64_t)a * g.v + b;
+        const T xr = s[h][0][r][tx], xi = s[h][1][r][tx];
+        const T yr = s[ht][0][tx][r], yi = s[ht][1][tx][r];  // X[b][a]
+        XS[0][so + off] = T(2) * xr - yr;
+        XS[1][so + off] = T(2) * xi - yi;
+        if (which == 0) {
+          const T pr = t1r[a] * u1r[b] - t1i[a] * u1i[b];
+          const T pi = t1r[a] * u1i[b] + t1i[a] * u1r[b];
+          g.tau[0][to + off] = xr + pr;
+          g.tau[1][to + off] = xi + pi;
+          g.taut[0][uo + off] = xr + T(0.5) * pr;
+          g.taut[1][uo + off] = xi + T(0.5) * pi;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+void amp_combo(hipStream_t st, int o, int v, int nb, const T* const t1[2], int64_t bs1, const T* const t2[2],
+               const T* const l2[2], const int64_t bs[6], T* const tau[2], T* const taut[2], T* const t2s[2],
+               T* const l2s[2]) {
+  RTCC_CHECK(o > 0 && v > 0 && nb >= 1 && nb <= 65535 && (int64_t)o * o <= 65535, kEInval, "amp_combo: bad extents");
+  AmpArgs<T> g;
+  for (int c = 0; c < 2; ++c) {
+    g.t1[c] = t1[c];
+    g.t2[c] = t2[c];
+    g.l2[c] = l2 ? l2[c] : nullptr;
+    g.tau[c] = tau[c];
+    g.taut[c] = taut[c];
+    g.t2s[c] = t2s[c];
+    g.l2s[c] = l2 ? l2s[c] : nullptr;
+  }
+  g.o = o;
+  g.v = v;
+  g.nt = (int)cdiv(v, 32);
+  g.bs1 = bs1;
+  for (int k = 0; k < 6; ++k) g.bs[k] = bs[k];
+  const unsigned pairs = (unsigned)(g.nt * (g.nt + 1) / 2);
+  hipLaunchKernelGGL(amp_combo_kernel<T>, dim3(pairs, (unsigned)(o * o), (unsigned)nb), dim3(256), 0, st, g);
+  RTCC_HIP(hipGetLastError());
+}
+template void amp_combo<double>(hipStream_t, int, int, int, const double* const[2], int64_t, const double* const[2],
+                                const double* const[2], const int64_t[6], double* const[2], double* const[2],
+                                double* const[2], double* const[2]);
+template void amp_combo<float>(hipStream_t, int, int, int, const float* const[2], int64_t, const float* const[2],
+                               const float* const[2], const int64_t[6], float* const[2], float* const[2],
+                               float* const[2], float* const[2]);
+
 }  // namespace rtcc

@@ -233,16 +233,18 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   const int o = w.o, v = w.v;
   const Ten<T>&t1 = w.t1, &t2 = w.t2, &l1 = w.l1, &l2 = w.l2, &tau = w.tau;
 
-  // ---- amplitude combinations
-  P(1, "ijab->ijab", t2, tau, 0);
-  C(1, "ia,jb->ijab", t1, t1, tau, 1);
-  P(1, "ijab->ijab", t2, w.taut, 0);
-  C(0.5, "ia,jb->ijab", t1, t1, w.taut, 1);
-  P(2, "ijab->ijab", t2, w.t2s, 0);
-  P(-1, "ijab->ijba", t2, w.t2s, 1);
-  if (lambda) {
-    P(2, "ijab->ijab", l2, w.l2s, 0);
-    P(-1, "ijab->ijba", l2, w.l2s, 1);
+  // ---- amplitude combinations: tau = t2 + t1 t1, taut = t2 + t1 t1 / 2, t2s = 2 t2 - t2[ijba] and
+  // l2s = 2 l2 - l2[ijba], one pass over t2 and l2
+  {
+    const T* a1[2] = {t1.re, t1.im};
+    const T* a2[2] = {t2.re, t2.im};
+    const T* b2[2] = {l2.re, l2.im};
+    T* o_tau[2] = {tau.re, tau.im};
+    T* o_taut[2] = {w.taut.re, w.taut.im};
+    T* o_t2s[2] = {w.t2s.re, w.t2s.im};
+    T* o_l2s[2] = {w.l2s.re, w.l2s.im};
+    const int64_t bs[6] = {t2.bs, l2.bs, tau.bs, w.taut.bs, w.t2s.bs, w.l2s.bs};
+    amp_combo<T>(E.stream, o, v, E.nb, a1, t1.bs, a2, lambda ? b2 : nullptr, bs, o_tau, o_taut, o_t2s, o_l2s);
   }
 
   // Concurrent part 1 (with branch engines): the main engine builds the one-body intermediates,
