@@ -980,8 +980,9 @@ template void ring_combo<float>(hipStream_t, int64_t, int64_t, int, const float*
 // For every (i,j): tau = t2 + t1_ia t1_jb, taut = t2 + t1_ia t1_jb / 2, t2s = 2 t2 - t2[b,a] and (if l2)
 // l2s = 2 l2 - l2[b,a], planar complex, [i][j][a][b] row-major. A workgroup takes one (i,j) and one
 // pair of mirrored 32 x 32 (a,b) tiles (ta <= tb), so the transposed partner of every element is in
-// LDS and each element of t2 and l2 is read once. Member blockIdx.z at batch stride bs1 for t1 and
-// bs[k] for the doubles (t2, l2, tau, taut, t2s, l2s).
+// LDS and each element of t2 and l2 is read once; t2 and l2 go to separate workgroups (blockIdx.z =
+// 2 member + which). Member at batch stride bs1 for t1 and bs[k] for the doubles (t2, l2, tau, taut,
+// t2s, l2s).
 template <typename T>
 struct AmpArgs {
   const T* t1[2];
@@ -1007,7 +1008,8 @@ __global__ __launch_bounds__(256) void amp_combo_kernel(AmpArgs<T> g) {
   }
   const int tb = ta + q;
   const int ij = blockIdx.y, i = ij / g.o, j = ij - i * g.o;
-  const int64_t z = blockIdx.z, vv = (int64_t)g.v * g.v;
+  const int64_t z = blockIdx.z >> 1, vv = (int64_t)g.v * g.v;
+  const int which = blockIdx.z & 1;
   const int64_t base = (int64_t)ij * vv;  // (i,j) block; member offsets per tensor below
   const int a0 = ta * 32, b0 = tb * 32;
   const bool mirror = ta != tb;
@@ -1015,9 +1017,9 @@ __global__ __launch_bounds__(256) void amp_combo_kernel(AmpArgs<T> g) {
   const T* t1i = g.t1[1] + z * g.bs1 + (int64_t)i * g.v;
   const T* u1r = g.t1[0] + z * g.bs1 + (int64_t)j * g.v;
   const T* u1i = g.t1[1] + z * g.bs1 + (int64_t)j * g.v;
-  for (int which = 0; which < 2; ++which) {
+  {
     const T* const* X = which == 0 ? g.t2 : g.l2;
-    if (which == 1 && !X[0]) break;
+    if (which == 1 && !X[0]) return;  // uniform over the workgroup
     T* const* XS = which == 0 ? g.t2s : g.l2s;
     const int64_t xo = z * g.bs[which], so = z * g.bs[which == 0 ? 4 : 5];
     const int64_t to = z * g.bs[2], uo = z * g.bs[3];
@@ -1063,7 +1065,7 @@ template <typename T>
 void amp_combo(hipStream_t st, int o, int v, int nb, const T* const t1[2], int64_t bs1, const T* const t2[2],
                const T* const l2[2], const int64_t bs[6], T* const tau[2], T* const taut[2], T* const t2s[2],
                T* const l2s[2]) {
-  RTCC_CHECK(o > 0 && v > 0 && nb >= 1 && nb <= 65535 && (int64_t)o * o <= 65535, kEInval, "amp_combo: bad extents");
+  RTCC_CHECK(o > 0 && v > 0 && nb >= 1 && nb <= 32767 && (int64_t)o * o <= 65535, kEInval, "amp_combo: bad extents");
   AmpArgs<T> g;
   for (int c = 0; c < 2; ++c) {
     g.t1[c] = t1[c];
@@ -1080,7 +1082,7 @@ void amp_combo(hipStream_t st, int o, int v, int nb, const T* const t1[2], int64
   g.bs1 = bs1;
   for (int k = 0; k < 6; ++k) g.bs[k] = bs[k];
   const unsigned pairs = (unsigned)(g.nt * (g.nt + 1) / 2);
-  hipLaunchKernelGGL(amp_combo_kernel<T>, dim3(pairs, (unsigned)(o * o), (unsigned)nb), dim3(256), 0, st, g);
+  hipLaunchKernelGGL(amp_combo_kernel<T>, dim3(pairs, (unsigned)(o * o), (unsigned)(2 * nb)), dim3(256), 0, st, g);
   RTCC_HIP(hipGetLastError());
 }
 template void amp_combo<double>(hipStream_t, int, int, int, const double* const[2], int64_t, const double* const[2],
