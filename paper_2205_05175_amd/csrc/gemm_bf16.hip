@@ -41,41 +41,51 @@ constexpr int kKPad = 32;            // packed K is a multiple of this
 // ---- packing ------------------------------------------------------------------------------------
 // dst plane (2 c + h) = h ? lo : hi of plane c of the source, k-blocked as [Kp / 16][Rp][16]: one
 // 16-wide k stage of 128 rows is a contiguous 4 KB. Element (r, k) of the source is src[r * ld + k]
-// (trans = 0) or src[k * ld + r] (trans = 1). 32 x 32 tiles via LDS.
+// (trans = 0) or src[k * ld + r] (trans = 1). A thread makes one row's 16-wide k block: consecutive
+// threads take consecutive rows, so the 32-byte hi and lo chunks they store are contiguous; the
+// loads are four 16-byte vectors (trans = 0, aligned) or 16 loads coalesced across rows (trans = 1).
 __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ sre, const float* __restrict__ sim,
-                                                   int64_t ld, int trans, int R, int K, int Rp, int Kp,
+                                                   int64_t ld, int trans, int R, int K, int Rp, int Kp, int vec,
                                                    __bf16* __restrict__ dst) {
-  __shared__ float t[2][32][33];
-  const int tid = threadIdx.x;
-  const int tk = Kp / 32;
-  const int r0 = (blockIdx.x / tk) * 32, k0 = (blockIdx.x % tk) * 32;
-  const int np = sim ? 2 : 1;
-  // load: lanes along the source's contiguous index
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int f = tid & 31, s = (tid >> 5) + 8 * i;
-    const int r = trans ? f : s, k = trans ? s : f;  // tile coordinates
-    const int gr = r0 + r, gk = k0 + k;
-    const bool ok = gr < R && gk < K;
-    const int64_t off = trans ? (int64_t)gk * ld + gr : (int64_t)gr * ld + gk;
-    t[0][r][k] = ok ? sre[off] : 0.f;
-    if (np == 2) t[1][r][k] = ok ? sim[off] : 0.f;
-  }
-  __syncthreads();
-  // store: lanes along k; k-blocked layout [Kp / 16][Rp][16]
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= Rp) return;
+  const int kb = blockIdx.y, k0 = kb * 16;
   const int64_t plane = (int64_t)Rp * Kp;
+  const int64_t o = ((int64_t)kb * Rp + r) * 16;
+  const int np = sim ? 2 : 1;
+  for (int c = 0; c < np; ++c) {
+    const float* src = c ? sim : sre;
+    float x[16];
+    if (r < R && vec && k0 + 16 <= K) {
+      const float4* p4 = reinterpret_cast<const float4*>(src + (int64_t)r * ld + k0);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int k = tid & 31, r = (tid >> 5) + 8 * i;
-    const int gk = k0 + k;
-    const int64_t off = (int64_t)(gk >> 4) * Rp * 16 + (int64_t)(r0 + r) * 16 + (gk & 15);
-    for (int c = 0; c < np; ++c) {
-      const float x = t[c][r][k];
-      const __bf16 hi = (__bf16)x;
-      const __bf16 lo = (__bf16)(x - (float)hi);
-      dst[(2 * c) * plane + off] = hi;
-      dst[(2 * c + 1) * plane + off] = lo;
+      for (int q = 0; q < 4; ++q) {
+        const float4 f = p4[q];
+        x[4 * q] = f.x;
+        x[4 * q + 1] = f.y;
+        x[4 * q + 2] = f.z;
+        x[4 * q + 3] = f.w;
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const int k = k0 + kk;
+        x[kk] = (r < R && k < K) ? src[trans ? (int64_t)k * ld + r : (int64_t)r * ld + k] : 0.f;
+      }
     }
+    bf8 hi[2], lo[2];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const __bf16 h = (__bf16)x[kk];
+      hi[kk >> 3][kk & 7] = h;
+      lo[kk >> 3][kk & 7] = (__bf16)(x[kk] - (float)h);
+    }
+    bf8* dh = reinterpret_cast<bf8*>(dst + (2 * c) * plane + o);
+    bf8* dl = reinterpret_cast<bf8*>(dst + (2 * c + 1) * plane + o);
+    dh[0] = hi[0];
+    dh[1] = hi[1];
+    dl[0] = lo[0];
+    dl[1] = lo[1];
   }
 }
 
@@ -93,9 +103,11 @@ Packed pack_operand(Engine& E, const float* re, const float* im, int64_t ld, int
   P.np = im ? 2 : 1;
   P.plane = (int64_t)P.Rp * P.Kp;
   const size_t bytes = (size_t)P.plane * 2 * P.np * sizeof(__bf16);
-  const unsigned blocks = (unsigned)((P.Rp / 32) * (P.Kp / 32));
+  RTCC_CHECK(P.Kp / 16 <= 65535, kEInval, "gemm_bf16x3: K too large");
+  const bool vec = !trans && ld % 4 == 0 && ((uintptr_t)re % 16) == 0 && (!im || ((uintptr_t)im % 16) == 0);
+  const dim3 grid((unsigned)cdiv(P.Rp, 256), (unsigned)(P.Kp / 16));
   auto fill = [&](void* dst, hipStream_t st) {
-    hipLaunchKernelGGL(pack_kernel, dim3(blocks), dim3(256), 0, st, re, im, ld, trans, (int)R, (int)K, P.Rp, P.Kp,
+    hipLaunchKernelGGL(pack_kernel, grid, dim3(256), 0, st, re, im, ld, trans, (int)R, (int)K, P.Rp, P.Kp, (int)vec,
                        (__bf16*)dst);
     RTCC_HIP(hipGetLastError());
   };
