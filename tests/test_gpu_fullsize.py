@@ -1,0 +1,121 @@
+"""The production size o = 20, v = 76 (2.3 million complex doubles amplitudes per T2 / Lambda2), in
+the launch configuration the benchmark times: captured RK4 steps, the right-hand side on three streams.
+
+The spin-orbital oracle cannot evaluate a right-hand side at this size inside a test (its
+antisymmetrised integrals alone take ~11 GB), so these tests check what holds at any size:
+
+* the FP64 path (pinned to the oracle element by element at the smaller sizes) against the same
+  right-hand side in FP32 and split-BF16, to the rounding bounds the parity tests use (3e-5 and 3e-4
+  relative to the largest entry);
+* the closed-shell pair symmetry x[i,j,a,b] = x[j,i,b,a] of the doubles derivatives;
+* linearity in the field: the Hamiltonian is linear in E, so F(y, E) - F(y, 0) is linear in E;
+* the dipole of the propagated FP64 state against the oracle's dipole, which needs no two-electron
+  integrals and so is evaluated by the oracle at full size;
+* the benchmark's acceptance bound: split-BF16 and FP32 trajectories within 1e-6 au of FP64.
+"""
+import numpy as np
+import pytest
+
+from oracle import ccsd
+from synth import make_system, pack_state, random_state, unpack_state
+
+pytestmark = pytest.mark.gpu
+
+O, V = 20, 76
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu(require_gpu):
+    yield
+
+
+@pytest.fixture(scope="module")
+def system():
+    return make_system(O, V, 0)
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(1.0, np.abs(b).max())
+
+
+def _pair_asym(d, scale):
+    t2, l2 = d[1], d[3]
+    return max(np.abs(t2 - t2.transpose(1, 0, 3, 2)).max(), np.abs(l2 - l2.transpose(1, 0, 3, 2)).max()) / scale
+
+
+def test_fullsize_rhs_precisions_and_pair_symmetry(system):
+    import torch
+    from paper_2205_05175_amd import RTCC
+    print("full-size rhs: fp64 / fp32 / bf16x3", flush=True)
+    eri, fock, mu = system
+    R = RTCC(eri, fock, mu, O, V, "fp32")  # holds the FP64 integrals too
+    y = torch.tensor(pack_state(*random_state(O, V, 3, 0.05, 0.02)), device="cuda")
+    E = np.array([0.003, -0.002, 0.01])
+    out = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        R.set_precision(prec)
+        out[prec] = R.rhs(y, E).cpu().numpy()
+    ref = out["fp64"]
+    scale = max(1.0, np.abs(ref).max())
+    e32, ebf = _rel(out["fp32"], ref), _rel(out["bf16x3"], ref)
+    print(f"full-size rhs vs fp64: fp32 {e32:.3e}, bf16x3 {ebf:.3e}")
+    assert e32 < 3e-5
+    assert ebf < 3e-4
+    assert np.abs(out["bf16x3"] - out["fp32"]).max() > 0  # the split kernels really ran
+    for prec, tol in (("fp64", 1e-11), ("fp32", 3e-5), ("bf16x3", 3e-4)):
+        asym = _pair_asym(unpack_state(out[prec], O, V), scale)
+        print(f"  {prec}: pair asymmetry {asym:.3e}")
+        assert asym < 10 * tol
+    R.close()
+
+
+def test_fullsize_rhs_linear_in_field(system):
+    import torch
+    from paper_2205_05175_amd import RTCC
+    print("full-size rhs: linearity in the field (fp64)", flush=True)
+    eri, fock, mu = system
+    R = RTCC(eri, fock, mu, O, V, "fp64")
+    y = torch.tensor(pack_state(*random_state(O, V, 5, 0.05, 0.02)), device="cuda")
+    E1, E2 = np.array([0.01, 0.0, -0.004]), np.array([-0.002, 0.007, 0.003])
+    f0 = R.rhs(y, np.zeros(3)).cpu().numpy()
+    d1 = R.rhs(y, E1).cpu().numpy() - f0
+    d2 = R.rhs(y, E2).cpu().numpy() - f0
+    d12 = R.rhs(y, E1 + E2).cpu().numpy() - f0
+    err = np.abs(d12 - d1 - d2).max() / np.abs(d1).max()
+    print(f"  nonlinearity {err:.3e} (field part {np.abs(d1).max():.3e})")
+    assert np.abs(d1).max() > 1e-4
+    assert err < 1e-9
+    R.close()
+
+
+def test_fullsize_trajectories_in_bench_configuration(system):
+    """Ground state, delta kick 1e-3 au along z, 5 captured RK4 steps of dt = 0.02 per precision."""
+    import torch
+    from paper_2205_05175_amd import RTCC
+    print("full-size trajectories: fp64 / fp32 / bf16x3, 5 RK4 steps", flush=True)
+    eri, fock, mu = system
+    R = RTCC(eri, fock, mu, O, V, "fp32")
+    y0 = R.new_state()
+    R.ground_state(y0, 1e-10, 200)
+    R.kick(y0, 1e-3, [0.0, 0.0, 1.0])
+    steps = 5
+    mus, finals = {}, {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        R.set_precision(prec)
+        y = y0.clone()
+        m = torch.zeros((steps + 1, 6), dtype=torch.float64, device="cuda")
+        R.propagate_rk4(y, 0.0, 0.02, steps, None, m)
+        torch.cuda.synchronize()
+        assert R.check_state(y) == 0
+        mus[prec], finals[prec] = m.cpu().numpy(), y
+    cm = lambda a: a[:, 0::2] + 1j * a[:, 1::2]
+    for prec in ("fp32", "bf16x3"):
+        d = np.abs(cm(mus[prec]) - cm(mus["fp64"])).max()
+        print(f"  dipole {prec} vs fp64 over the run: {d:.3e} au")
+        assert d < 1e-6
+    S = ccsd.SpinOrbitalSystem(None, fock, mu, O, V)
+    ref = ccsd.dipole(S, *unpack_state(finals["fp64"].cpu().numpy(), O, V))
+    got = R.dipole(finals["fp64"])
+    print(f"  fp64 GPU dipole vs oracle: {np.abs(got - ref).max():.3e} au")
+    assert np.abs(got - ref).max() < 1e-12
+    R.close()

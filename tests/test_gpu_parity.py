@@ -3,7 +3,8 @@
 Every case uses seeded synthetic inputs from ``synth``: the water-cluster-shaped
 Hamiltonian plus a random symmetric Fock perturbation (non-canonical, f_ov != 0),
 and random NON-stationary complex amplitudes. Sizes span several 64-wide GEMM
-tiles with ragged tails: (6, 25) has ov = 150 and v^2 = 625.
+tiles with ragged tails: (6, 25) has ov = 150 and v^2 = 625; (7, 36) puts v above 32, so the
+(a,b) blocks span several 32-wide tiles (mirrored tile pairs, whole-matrix transposes).
 
 Tolerances: FP64 contractions 1e-11 (relative to the largest entry); FP32
 contractions 3e-5 relative (single-precision rounding accumulated over sums of
@@ -20,7 +21,7 @@ from synth import make_system, pack_state, random_state, random_symmetric, unpac
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [(1, 1), (1, 4), (2, 3), (4, 16), (5, 19), (6, 25)]
+SIZES = [(1, 1), (1, 4), (2, 3), (4, 16), (5, 19), (6, 25), (7, 36)]
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -240,7 +241,7 @@ def _ctx_env(eri, fock, mu, o, v, precision, **env):
                 os.environ[k] = x
 
 
-@pytest.mark.parametrize("o,v", [(2, 3), (5, 19), (6, 25)])
+@pytest.mark.parametrize("o,v", [(2, 3), (5, 19), (6, 25), (7, 36)])
 def test_rhs_bf16x3_matches_oracle(o, v):
     """Split-BF16 three-term products (forced onto every eligible GEMM): ~2^-16 relative per product."""
     eri, fock, mu = _system(o, v, 1)
