@@ -11,7 +11,8 @@
 //
 // GEMM: 512 threads, a 128 x 256 output tile per workgroup, 2 x 4 waves of 64 x 64 (2 x 2 MFMA
 // blocks of 32 x 32 each), two waves per SIMD so that one wave's MFMAs cover the other's LDS and
-// barrier waits; the wide N side halves the B-plane traffic per flop. Per 16-wide k stage the
+// barrier waits; the wide N side halves the B-plane traffic per flop (outputs too small for 16 such
+// tiles take 2 x 2 waves of 256 threads and 128 x 128 tiles instead). Per 16-wide k stage the
 // packed tiles pass through registers into one of two LDS buffers: stage s + 1 is written and
 // stage s + 2 fetched while stage s is multiplied, with one barrier per stage. Lane l of a
 // 32x32x16 MFMA holds A[l%32][8(l/32)+j] and B[8(l/32)+j][l%32] and its output r lies at row
@@ -319,7 +320,9 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   if (!AC && !BC) return false;
   RTCC_CHECK(M < (1LL << 30) && N < (1LL << 30) && K < (1LL << 30), kEInval, "gemm_bf16x3: dimension too large");
   size_t mark = E.scratch.used;
-  constexpr int WN = 4, kBN = 64 * WN;
+  // 2 x 4 waves (128 x 256 tiles); outputs too small for 16 such tiles (e.g. 400 x 400) use 2 x 2 waves
+  // (128 x 128), which doubles their tile count (measured: 41-55 -> 28-41 us at 400 x 400 x 5776)
+  const int WN = cdiv(M, kBM) * cdiv(N, 256) < 16 ? 2 : 4, kBN = 64 * WN;
   // A as [M][K] rows; B as [N][K] rows (B(k, n) = trans ? b[n * ld + k] : b[k * ld + n])
   const Packed pa = pack_operand(E, A.re, A.im, A.ld, A.trans, M, K, A.konst, kRowPad);
   const Packed pb = pack_operand(E, B.re, B.im, B.ld, B.trans ? 0 : 1, N, K, B.konst, kBN);
@@ -381,10 +384,17 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   const bool lad = E.ladder != 0;
   if (lad && E.mark) E.mark(E.mark_user, 0, E.ladder_flops, E.stream);
   const dim3 block(128 * WN);
-  if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 1, WN>), grid, block, 0, E.stream, p);
-  else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1, 0, WN>), grid, block, 0, E.stream, p);
-  else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 0, WN>), grid, block, 0, E.stream, p);
-  else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1, 0, WN>), grid, block, 0, E.stream, p);
+  if (WN == 4) {
+    if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 1, 4>), grid, block, 0, E.stream, p);
+    else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1, 0, 4>), grid, block, 0, E.stream, p);
+    else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 0, 4>), grid, block, 0, E.stream, p);
+    else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1, 0, 4>), grid, block, 0, E.stream, p);
+  } else {
+    if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 1, 2>), grid, block, 0, E.stream, p);
+    else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1, 0, 2>), grid, block, 0, E.stream, p);
+    else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 0, 2>), grid, block, 0, E.stream, p);
+    else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1, 0, 2>), grid, block, 0, E.stream, p);
+  }
   RTCC_HIP(hipGetLastError());
   if (lad && E.mark) E.mark(E.mark_user, 1, E.ladder_flops, E.stream);
   if (splits > 1) splitk_reduce_launch<float>(E.stream, Pre, Pim, splits, M, N, Cre, Cim, ldc, 0, 1, alpha, beta);
