@@ -74,6 +74,7 @@ struct rtcc_ctx {
   std::string err;
   Engine E;
   Engine EB[2];  // branch engines of E (own streams and scratch)
+  Memo memo[3];  // per-call memos of E and EB
   Arena arena;        // integrals and workspaces
   Arena arena32;      // FP32 integrals and workspace (allocated on demand)
   bool have32 = false;
@@ -628,6 +629,12 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     int64_t big = std::max<int64_t>({(int64_t)o * v * v * v, 2 * c->n2, (int64_t)o * o * o * o, c->n2 * 2});
     c->E.scratch.cap = (size_t)(8 * big + (1 << 22)) * sizeof(double) * 2;
     c->E.scratch.base = c->arena.alloc<char>(c->E.scratch.cap);
+    // per-call memo arenas (as large as the scratch) for the main and branch engines
+    for (int k = 0; k < 3; ++k) {
+      c->memo[k].cap = c->E.scratch.cap;
+      c->memo[k].base = c->arena.alloc<char>(c->memo[k].cap);
+    }
+    c->E.memo = &c->memo[0];
     if (branches) {
       RTCC_HIP(hipEventCreateWithFlags(&c->E.ev_fork, hipEventDisableTiming));
       for (int k = 0; k < 2; ++k) {
@@ -636,6 +643,7 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
         RTCC_HIP(hipEventCreateWithFlags(&c->E.ev_join[k], hipEventDisableTiming));
         b.scratch.cap = c->E.scratch.cap;
         b.scratch.base = c->arena.alloc<char>(b.scratch.cap);
+        b.memo = &c->memo[1 + k];
         c->E.br[k] = &b;
       }
     }

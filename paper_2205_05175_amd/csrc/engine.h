@@ -8,6 +8,7 @@
 // tensors are planar: separate real and imaginary planes.
 #pragma once
 #include <functional>
+#include <map>
 #include <string>
 #include <vector>
 #include "common.h"
@@ -79,9 +80,22 @@ size_t const_cache_bytes(const ConstCache* c);
 void* const_cache_get(ConstCache* c, const std::string& key, size_t bytes,
                       const std::function<void(void*, hipStream_t)>& fill);
 
+// Per-call memo of derived layouts (permuted copies, split-BF16 packs) of operands that stay fixed
+// during one right-hand side. memo_begin clears it and registers the fixed tensors' base pointers;
+// memo_end clears and disables it. Entries live in a device arena owned by the context. An engine
+// reads only its own memo, so every entry is written and read on that engine's stream.
+struct Memo {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool on = false;
+  std::vector<const void*> fixed;
+  std::map<std::string, void*> entries;
+};
+
 struct Engine {
   hipStream_t stream = nullptr;
   ConstCache* cache = nullptr;
+  Memo* memo = nullptr;  // nullptr: no memo (batched and adjoint workspaces)
   Scratch scratch;
   int64_t gemm_flops = 0;  // algorithmic real flops issued (accounting)
   // optional hook called before (phase 0) and after (phase 1) the ladder GEMM launch with the
@@ -105,6 +119,12 @@ struct Engine {
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[2] = {nullptr, nullptr};
 };
+
+void memo_begin(Engine& E, std::initializer_list<const void*> fixed);
+void memo_end(Engine& E);
+bool memo_fixed(const Engine& E, const void* p);
+// The memo buffer for `key` (*hit: it already holds the data), or nullptr when the arena is full.
+void* memo_get(Engine& E, const std::string& key, size_t bytes, bool* hit);
 
 // Branch engines take this engine's settings and wait for the work already on its stream.
 void fork_branches(Engine& E);

@@ -158,6 +158,39 @@ namespace {
 // A constant operand permuted into letter order `order`, made on first use and kept. The copy is
 // made on the cache's own stream and waited for, so it is complete before any later work (also when
 // the first use happens while the engine's stream is being captured into a graph).
+// A permuted copy of a tensor that is fixed for the current call, kept in the engine's memo so that
+// later contractions asking for the same layout reuse it; the copy counts as fixed itself.
+template <typename T>
+Ten<T> memo_permute(Engine& E, const Ten<T>& X, const std::string& sx, const std::string& order) {
+  char key[64 + 24 * 3 * kMaxDim];
+  int len = snprintf(key, 64, "p/%p/%p/%d", (const void*)X.re, (const void*)X.im, X.nd);
+  for (int i = 0; i < X.nd; ++i) len += snprintf(key + len, 40, "/%lld:%lld", (long long)X.d[i], (long long)X.s[i]);
+  for (char c : order) len += snprintf(key + len, 8, "/%d", (int)sx.find(c));
+  int64_t n = 1;
+  for (char c : order) n *= dim_of(X, sx, c);
+  bool hit = false;
+  void* buf = memo_get(E, key, (size_t)std::max<int64_t>(n, 1) * sizeof(T) * (X.im ? 2 : 1), &hit);
+  if (!buf) return permuted_copy(E, X, sx, order);
+  Ten<T> Y;
+  Y.nd = (int)order.size();
+  for (int i = 0; i < Y.nd; ++i) Y.d[i] = dim_of(X, sx, order[i]);
+  int64_t st = 1;
+  for (int i = Y.nd - 1; i >= 0; --i) {
+    Y.s[i] = st;
+    st *= Y.d[i];
+  }
+  Y.re = reinterpret_cast<T*>(buf);
+  Y.im = X.im ? Y.re + std::max<int64_t>(n, 1) : nullptr;
+  if (!hit) {
+    int64_t d[kMaxDim], is[kMaxDim];
+    strides_for(X, sx, order, d, is);
+    permute_axpby<T>(E.stream, Y.nd, d, X.re, X.im, is, Y.re, Y.im, Y.s, 1.0, 0.0);
+  }
+  if (E.trace) fprintf(stderr, "[rtcc] memo-permute %s src=%p %s->%s\n", hit ? "hit" : "new", (const void*)X.re, sx.c_str(), order.c_str());
+  E.memo->fixed.push_back(Y.re);
+  return Y;
+}
+
 template <typename T>
 Ten<T> cached_permute(Engine& E, const Ten<T>& X, const std::string& sx, const std::string& order) {
   ConstCache& cc = *E.cache;
@@ -285,6 +318,45 @@ Plan plan_for(const Ten<T>& A, const std::string& sa, const Ten<T>& B, const std
 
 }  // namespace
 
+void memo_begin(Engine& E, std::initializer_list<const void*> fixed) {
+  if (!E.memo) return;
+  E.memo->entries.clear();
+  E.memo->used = 0;
+  E.memo->fixed.assign(fixed.begin(), fixed.end());
+  E.memo->on = true;
+}
+
+void memo_end(Engine& E) {
+  if (!E.memo) return;
+  E.memo->on = false;
+  E.memo->entries.clear();
+  E.memo->fixed.clear();
+  E.memo->used = 0;
+}
+
+bool memo_fixed(const Engine& E, const void* p) {
+  if (!E.memo || !E.memo->on || !p) return false;
+  for (const void* q : E.memo->fixed)
+    if (q == p) return true;
+  return false;
+}
+
+void* memo_get(Engine& E, const std::string& key, size_t bytes, bool* hit) {
+  Memo& m = *E.memo;
+  auto it = m.entries.find(key);
+  if (it != m.entries.end()) {
+    *hit = true;
+    return it->second;
+  }
+  *hit = false;
+  const size_t b = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+  if (m.used + b > m.cap) return nullptr;
+  void* p = m.base + m.used;
+  m.used += b;
+  m.entries[key] = p;
+  return p;
+}
+
 void fork_branches(Engine& E) {
   RTCC_HIP(hipEventRecord(E.ev_fork, E.stream));
   for (Engine* b : E.br) {
@@ -377,12 +449,16 @@ void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const T
   Ten<T> Ap = A, Bp = B;
   const std::string ha = (hb && bA) ? "Z" : "", hbb = (hb && bB) ? "Z" : "";
   if (!view2d(A, sa, bm, bk, &oa)) {
-    Ap = (A.konst && !bA && E.cache) ? cached_permute(E, A, sa, bm + bk) : permuted_copy(E, A, sa, ha + bm + bk);
+    Ap = (A.konst && !bA && E.cache) ? cached_permute(E, A, sa, bm + bk)
+         : (!bA && memo_fixed(E, A.re)) ? memo_permute(E, A, sa, bm + bk)
+                                        : permuted_copy(E, A, sa, ha + bm + bk);
     sa = ha + bm + bk;
     view2d(Ap, sa, bm, bk, &oa);
   }
   if (!view2d(B, sb, bk, bn, &ob)) {
-    Bp = (B.konst && !bB && E.cache) ? cached_permute(E, B, sb, bk + bn) : permuted_copy(E, B, sb, hbb + bk + bn);
+    Bp = (B.konst && !bB && E.cache) ? cached_permute(E, B, sb, bk + bn)
+         : (!bB && memo_fixed(E, B.re)) ? memo_permute(E, B, sb, bk + bn)
+                                        : permuted_copy(E, B, sb, hbb + bk + bn);
     sb = hbb + bk + bn;
     view2d(Bp, sb, bk, bn, &ob);
   }

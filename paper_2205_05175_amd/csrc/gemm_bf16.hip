@@ -112,12 +112,25 @@ Packed pack_operand(Engine& E, const float* re, const float* im, int64_t ld, int
                        (__bf16*)dst);
     RTCC_HIP(hipGetLastError());
   };
+  char key[160];
+  snprintf(key, sizeof key, "bf16x3:%p/%p/%lld/%d/%lld/%lld/%d", (const void*)re, (const void*)im, (long long)ld,
+           trans, (long long)R, (long long)K, P.Rp);
   if (konst && E.cache) {
-    char key[160];
-    snprintf(key, sizeof key, "bf16x3:%p/%p/%lld/%d/%lld/%lld/%d", (const void*)re, (const void*)im, (long long)ld,
-             trans, (long long)R, (long long)K, P.Rp);
     P.p = (const __bf16*)const_cache_get(E.cache, key, bytes, fill);
-  } else {
+    return P;
+  }
+  if (memo_fixed(E, re)) {
+    // an operand fixed for the current call: packed once, reused by later products of this call
+    bool hit = false;
+    void* dst = memo_get(E, key, bytes, &hit);
+    if (dst) {
+      if (!hit) fill(dst, E.stream);
+      if (E.trace) fprintf(stderr, "[rtcc] memo-pack %s src=%p\n", hit ? "hit" : "new", (const void*)re);
+      P.p = (const __bf16*)dst;
+      return P;
+    }
+  }
+  {
     if (E.trace)
       fprintf(stderr, "[rtcc] pack-operand src=%p ld=%lld trans=%d R=%lld K=%lld\n", (const void*)re, (long long)ld, trans,
               (long long)R, (long long)K);

@@ -246,6 +246,17 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     const int64_t bs[6] = {t2.bs, l2.bs, tau.bs, w.taut.bs, w.t2s.bs, w.l2s.bs};
     amp_combo<T>(E.stream, o, v, E.nb, a1, t1.bs, a2, lambda ? b2 : nullptr, bs, o_tau, o_taut, o_t2s, o_l2s);
   }
+  // the amplitudes and their combinations are fixed from here on: derived layouts of them are kept
+  // (per engine) for the rest of this call
+  struct MemoScope {
+    Engine* e[3];
+    ~MemoScope() {
+      for (Engine* x : e)
+        if (x) memo_end(*x);
+    }
+  } memo_scope{{&E, par ? E.br[0] : nullptr, par ? E.br[1] : nullptr}};
+  for (Engine* x : memo_scope.e)
+    if (x) memo_begin(*x, {t1.re, t2.re, l1.re, l2.re, tau.re, w.taut.re, w.t2s.re, w.l2s.re});
 
   // Concurrent part 1 (with branch engines): the main engine builds the one-body intermediates,
   // the T1 residual, W, Hbar_mnie and the Hbar_mnie-free parts of the ring intermediates; branch 0
