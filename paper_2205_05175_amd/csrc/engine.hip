@@ -420,6 +420,7 @@ void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const T
   // the shared operand -- unless that needs more permuting than a batched GEMM with the shared
   // operand at batch stride 0. Z in the output only (both inputs shared): a batched GEMM.
   Plan pl;
+  char hl = 'Z';  // the batch letter
   if (bC && bA == bB) {
     pl = plan_for(A, sa, B, sb, C, sc, "Z");
   } else {
@@ -429,13 +430,37 @@ void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const T
       if (pz.cost < pl.cost) pl = pz;
     }
   }
+  if (!bC && pl.cost > 0) {
+    // Without a member batch, an output letter shared with one input (or both) may serve as the batch
+    // letter of a batched GEMM when that needs less permuting -- but not for products that would use
+    // the split-BF16 kernel (single GEMMs only) or the GEMV kernels (M or N of 1).
+    int64_t M0 = 1, N0 = 1, K0 = 1;
+    for (char c : pl.m) M0 *= dim_of(C, sc, c);
+    for (char c : pl.n) N0 *= dim_of(C, sc, c);
+    for (char c : pl.k) K0 *= dim_of(A, sa, c);
+    const bool split16 = sizeof(T) == 4 && E.bf16x3 && 2.0 * M0 * N0 * K0 >= E.bf16_min_flops;
+    if (!split16 && M0 > 1 && N0 > 1) {
+      for (char x : sc) {
+        if (sa.find(x) == std::string::npos && sb.find(x) == std::string::npos) continue;
+        if (dim_of(C, sc, x) < 2 || dim_of(C, sc, x) > 65535) continue;
+        Plan px = plan_for(A, sa, B, sb, C, sc, std::string(1, x));
+        if (px.cost < pl.cost) {
+          pl = px;
+          hl = x;
+        }
+      }
+    }
+  }
   const std::string &bm = pl.m, &bn = pl.n, &bk = pl.k;
   const bool hb = !pl.h.empty();
+  // the batch letter's presence in A and B (member batch: the operands' own batch flags)
+  const bool zA = hl == 'Z' ? bA : sa.find(hl) != std::string::npos;
+  const bool zB = hl == 'Z' ? bB : sb.find(hl) != std::string::npos;
   int64_t M = 1, N = 1, K = 1;
   for (char c : bm) M *= dim_of(C, sc, c);
   for (char c : bn) N *= dim_of(C, sc, c);
   for (char c : bk) K *= dim_of(A, sa, c);
-  const int nbt = hb ? E.nb : 1;
+  const int nbt = !hb ? 1 : hl == 'Z' ? E.nb : (int)dim_of(C, sc, hl);
 
   if (E.trace) {
     GemmOp<T> xa, xb, xc;
@@ -447,17 +472,17 @@ void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const T
   size_t mark = E.scratch.used;
   GemmOp<T> oa, ob, oc;
   Ten<T> Ap = A, Bp = B;
-  const std::string ha = (hb && bA) ? "Z" : "", hbb = (hb && bB) ? "Z" : "";
+  const std::string ha = (hb && zA) ? std::string(1, hl) : "", hbb = (hb && zB) ? std::string(1, hl) : "";
   if (!view2d(A, sa, bm, bk, &oa)) {
-    Ap = (A.konst && !bA && E.cache) ? cached_permute(E, A, sa, bm + bk)
-         : (!bA && memo_fixed(E, A.re)) ? memo_permute(E, A, sa, bm + bk)
+    Ap = (A.konst && !bA && E.cache) ? cached_permute(E, A, sa, ha + bm + bk)
+         : (!bA && memo_fixed(E, A.re)) ? memo_permute(E, A, sa, ha + bm + bk)
                                         : permuted_copy(E, A, sa, ha + bm + bk);
     sa = ha + bm + bk;
     view2d(Ap, sa, bm, bk, &oa);
   }
   if (!view2d(B, sb, bk, bn, &ob)) {
-    Bp = (B.konst && !bB && E.cache) ? cached_permute(E, B, sb, bk + bn)
-         : (!bB && memo_fixed(E, B.re)) ? memo_permute(E, B, sb, bk + bn)
+    Bp = (B.konst && !bB && E.cache) ? cached_permute(E, B, sb, hbb + bk + bn)
+         : (!bB && memo_fixed(E, B.re)) ? memo_permute(E, B, sb, hbb + bk + bn)
                                         : permuted_copy(E, B, sb, hbb + bk + bn);
     sb = hbb + bk + bn;
     view2d(Bp, sb, bk, bn, &ob);
@@ -465,9 +490,9 @@ void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const T
   GemmBatch gb;
   gb.n = nbt;
   if (hb) {
-    gb.a = bA ? str_of(Ap, sa, 'Z') : 0;
-    gb.b = bB ? str_of(Bp, sb, 'Z') : 0;
-    gb.c = str_of(C, sc, 'Z');
+    gb.a = zA ? str_of(Ap, sa, hl) : 0;
+    gb.b = zB ? str_of(Bp, sb, hl) : 0;
+    gb.c = str_of(C, sc, hl);
   }
   if (view2d(C, sc, bm, bn, &oc)) {
     if (oc.trans == 0) {
