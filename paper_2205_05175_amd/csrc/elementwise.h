@@ -66,8 +66,17 @@ void ring_combo(hipStream_t st, int64_t P, int64_t Q, int nb, const T* const x[8
                 int64_t wbs, T* hre, T* him, int64_t hbs);
 // tau = t2 + t1 t1, taut = t2 + t1 t1 / 2, t2s = 2 t2 - t2[ijba], l2s = 2 l2 - l2[ijba] (l2 may be null),
 // planar (re, im) pointer pairs; t1 at batch stride bs1, the doubles (t2, l2, tau, taut, t2s, l2s) at bs[k].
+// Optionally (non-null) also the stacked copies stk_t[i][a][s][j][b] = (t2s, t2)[s] and
+// stk_l[i][a][j][b][s] = (l2s, l2)[s] at batch strides sbs_t, sbs_l.
 template <typename T>
 void amp_combo(hipStream_t st, int o, int v, int nb, const T* const t1[2], int64_t bs1, const T* const t2[2],
                const T* const l2[2], const int64_t bs[6], T* const tau[2], T* const taut[2], T* const t2s[2],
-               T* const l2s[2]);
+               T* const l2s[2], T* const stk_t[2], int64_t sbs_t, T* const stk_l[2], int64_t sbs_l);
+// out[ijab] += base[ijab] + lad[ijab] + z[ijab] + zt[iajb] + z[jiba] + zt[jbia]: planar (re, im) pointer
+// pairs, base (shared by all members; either plane may be null) [o][o][v][v], lad and z [o][o][v][v], zt
+// [o][v][o][v], each at its own batch stride.
+template <typename T>
+void pair_combo(hipStream_t st, int o, int v, int nb, T* const out[2], int64_t obs, const T* const base[2],
+                const T* const lad[2], int64_t lbs, const T* const z[2], int64_t zbs, const T* const zt[2],
+                int64_t tbs);
 }  // namespace rtcc

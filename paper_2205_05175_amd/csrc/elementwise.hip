@@ -992,8 +992,9 @@ struct AmpArgs {
   T* taut[2];
   T* t2s[2];
   T* l2s[2];
+  T* stk[2][2];  // stacked (X-s, X) copies: [t2 / l2][re / im], or null
   int o, v, nt;
-  int64_t bs1, bs[6];
+  int64_t bs1, bs[6], sbs[2];
 };
 
 template <typename T>
@@ -1045,8 +1046,25 @@ __global__ __launch_bounds__(256) void amp_combo_kernel(AmpArgs<T> g) {
         const int64_t off = base + (int64_t)a * g.v + b;
         const T xr = s[h][0][r][tx], xi = s[h][1][r][tx];
         const T yr = s[ht][0][tx][r], yi = s[ht][1][tx][r];  // X[b][a]
-        XS[0][so + off] = T(2) * xr - yr;
-        XS[1][so + off] = T(2) * xi - yi;
+        const T sr = T(2) * xr - yr, si = T(2) * xi - yi;
+        XS[0][so + off] = sr;
+        XS[1][so + off] = si;
+        if (g.stk[which][0]) {
+          T* const* K = g.stk[which];
+          const int64_t ov = (int64_t)g.o * g.v, ia = (int64_t)i * g.v + a, ko = z * g.sbs[which];
+          if (which == 0) {  // [i][a][s][j][b]: s = 0 t2s, s = 1 t2
+            const int64_t q = ko + ia * 2 * ov + (int64_t)j * g.v + b;
+            K[0][q] = sr;
+            K[1][q] = si;
+            K[0][q + ov] = xr;
+            K[1][q + ov] = xi;
+          } else {  // [i][a][j][b][s]: s = 0 l2s, s = 1 l2, as one two-element store per plane
+            typedef T T2 __attribute__((ext_vector_type(2)));
+            const int64_t q = ko + ((ia * g.o + j) * g.v + b) * 2;
+            *reinterpret_cast<T2*>(K[0] + q) = T2{sr, xr};
+            *reinterpret_cast<T2*>(K[1] + q) = T2{si, xi};
+          }
+        }
         if (which == 0) {
           const T pr = t1r[a] * u1r[b] - t1i[a] * u1i[b];
           const T pi = t1r[a] * u1i[b] + t1i[a] * u1r[b];
@@ -1064,9 +1082,18 @@ __global__ __launch_bounds__(256) void amp_combo_kernel(AmpArgs<T> g) {
 template <typename T>
 void amp_combo(hipStream_t st, int o, int v, int nb, const T* const t1[2], int64_t bs1, const T* const t2[2],
                const T* const l2[2], const int64_t bs[6], T* const tau[2], T* const taut[2], T* const t2s[2],
-               T* const l2s[2]) {
+               T* const l2s[2], T* const stk_t[2], int64_t sbs_t, T* const stk_l[2], int64_t sbs_l) {
   RTCC_CHECK(o > 0 && v > 0 && nb >= 1 && nb <= 32767 && (int64_t)o * o <= 65535, kEInval, "amp_combo: bad extents");
+  RTCC_CHECK(!stk_l || ((uintptr_t)stk_l[0] % (2 * sizeof(T)) == 0 && (uintptr_t)stk_l[1] % (2 * sizeof(T)) == 0 &&
+                        sbs_l % 2 == 0),
+             kEInval, "amp_combo: misaligned stacked lambda copy");
   AmpArgs<T> g;
+  for (int c = 0; c < 2; ++c) {
+    g.stk[0][c] = stk_t ? stk_t[c] : nullptr;
+    g.stk[1][c] = (stk_l && l2) ? stk_l[c] : nullptr;
+  }
+  g.sbs[0] = sbs_t;
+  g.sbs[1] = sbs_l;
   for (int c = 0; c < 2; ++c) {
     g.t1[c] = t1[c];
     g.t2[c] = t2[c];
@@ -1087,9 +1114,95 @@ void amp_combo(hipStream_t st, int o, int v, int nb, const T* const t1[2], int64
 }
 template void amp_combo<double>(hipStream_t, int, int, int, const double* const[2], int64_t, const double* const[2],
                                 const double* const[2], const int64_t[6], double* const[2], double* const[2],
-                                double* const[2], double* const[2]);
+                                double* const[2], double* const[2], double* const[2], int64_t,
+                                double* const[2], int64_t);
 template void amp_combo<float>(hipStream_t, int, int, int, const float* const[2], int64_t, const float* const[2],
                                const float* const[2], const int64_t[6], float* const[2], float* const[2],
-                               float* const[2], float* const[2]);
+                               float* const[2], float* const[2], float* const[2], int64_t, float* const[2],
+                               int64_t);
+
+// ---- doubles residual assembly ------------------------------------------------------------------
+// out[ijab] += base[ijab] + lad[ijab] + z[ijab] + zt[iajb] + z[jiba] + zt[jbia]. A workgroup takes a
+// 32 x 32 (a, b) tile of one (i, j) block; the partners z[jiba] + zt[jbia] are read along a (the
+// contiguous index of both) into LDS and taken transposed.
+template <typename T>
+struct PairArgs {
+  T* out[2];
+  const T* base[2];
+  const T* lad[2];
+  const T* z[2];
+  const T* zt[2];
+  int o, v, nt;
+  int64_t obs, lbs, zbs, tbs;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void pair_combo_kernel(PairArgs<T> g) {
+  __shared__ T s[2][32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int ta = blockIdx.x / g.nt, tb = blockIdx.x - ta * g.nt;
+  const int ij = blockIdx.y, i = ij / g.o, j = ij - i * g.o;
+  const int64_t m = blockIdx.z, v = g.v, vv = v * v, ov = (int64_t)g.o * v;
+  const int a0 = ta * 32, b0 = tb * 32;
+  // partners: row r <-> b = b0 + r, column tx <-> a = a0 + tx
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = ty + 8 * k, a = a0 + tx, b = b0 + r;
+    if (a >= g.v || b >= g.v) continue;
+    const int64_t zo = m * g.zbs + ((int64_t)j * g.o + i) * vv + (int64_t)b * v + a;
+    const int64_t to = m * g.tbs + (int64_t)j * v * ov + (int64_t)b * ov + (int64_t)i * v + a;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) s[c][r][tx] = g.z[c][zo] + g.zt[c][to];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = ty + 8 * k, a = a0 + r, b = b0 + tx;
+    if (a >= g.v || b >= g.v) continue;
+    const int64_t off = (int64_t)ij * vv + (int64_t)a * v + b;
+    const int64_t to = m * g.tbs + (int64_t)i * v * ov + (int64_t)a * ov + (int64_t)j * v + b;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      T x = g.out[c][m * g.obs + off];
+      if (g.base[c]) x += g.base[c][off];
+      x += g.lad[c][m * g.lbs + off];
+      x += g.z[c][m * g.zbs + off];
+      x += g.zt[c][to];
+      x += s[c][tx][r];
+      g.out[c][m * g.obs + off] = x;
+    }
+  }
+}
+
+template <typename T>
+void pair_combo(hipStream_t st, int o, int v, int nb, T* const out[2], int64_t obs, const T* const base[2],
+                const T* const lad[2], int64_t lbs, const T* const z[2], int64_t zbs, const T* const zt[2],
+                int64_t tbs) {
+  RTCC_CHECK(o > 0 && v > 0 && nb >= 1 && nb <= 65535 && (int64_t)o * o <= 65535, kEInval, "pair_combo: bad extents");
+  PairArgs<T> g;
+  for (int c = 0; c < 2; ++c) {
+    g.out[c] = out[c];
+    g.base[c] = base[c];
+    g.lad[c] = lad[c];
+    g.z[c] = z[c];
+    g.zt[c] = zt[c];
+  }
+  g.o = o;
+  g.v = v;
+  g.nt = (int)cdiv(v, 32);
+  g.obs = obs;
+  g.lbs = lbs;
+  g.zbs = zbs;
+  g.tbs = tbs;
+  hipLaunchKernelGGL(pair_combo_kernel<T>, dim3((unsigned)(g.nt * g.nt), (unsigned)(o * o), (unsigned)nb), dim3(256),
+                     0, st, g);
+  RTCC_HIP(hipGetLastError());
+}
+template void pair_combo<double>(hipStream_t, int, int, int, double* const[2], int64_t, const double* const[2],
+                                 const double* const[2], int64_t, const double* const[2], int64_t,
+                                 const double* const[2], int64_t);
+template void pair_combo<float>(hipStream_t, int, int, int, float* const[2], int64_t, const float* const[2],
+                                const float* const[2], int64_t, const float* const[2], int64_t, const float* const[2],
+                                int64_t);
 
 }  // namespace rtcc

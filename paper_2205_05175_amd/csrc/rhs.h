@@ -58,7 +58,7 @@ struct Work {
   Ten<T> Fae, Fmi, Fme, Hvv, Hoo, Gvv, Goo, Q, Gx;  // one-body
   Ten<T> W, M, Mp, Hooov, Hvovv, Z1, Y, U, U2, Y3, Y6, B4, B5, B7, D, Nn;
   Ten<T> Lad, LadT, LadL;
-  Ten<T> Pd, Px, Bd, Bx, WW, Wd, Wx, HH, HHd, HHx, HH5, T2R, T2R0, T2R1, L2R, L2R0, L2R1, Zt, ZLt, B2, B3, Wr;
+  Ten<T> Pd, Px, Bd, Bx, WW, Wd, Wx, HH, HHd, HHx, HH5, T2R, L2R, Zt, ZLt, B2, B3, Wr;
   Ten<T> Z, ZL, S1t;                               // (1+P) brackets; t1-t1 ring piece
   Ten<T> R1, R2, S1, S2;                           // residuals: R_T (T1,T2), R_L (L1,L2)
   Ten<T> S1b, S1c, Wr2;                            // partial Lambda1 sums of the concurrent groups

@@ -187,11 +187,7 @@ void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
   w.HHx = view(w.HH, 1, {o, v, o, v}, {2 * ov * v, 2 * ov, 2 * v, 2});
   // stacked left operands of the ring GEMMs: (i,a,s,m,e) for T and (i,a,m,e,s) for Lambda
   w.T2R = A.cplx<T>({o, v, 2, o, v});
-  w.T2R0 = view(w.T2R, 0, {o, o, v, v}, {2 * ov * v, v, 2 * ov, 1});
-  w.T2R1 = view(w.T2R, ov, {o, o, v, v}, {2 * ov * v, v, 2 * ov, 1});
   w.L2R = A.cplx<T>({o, v, o, v, 2});
-  w.L2R0 = view(w.L2R, 0, {o, o, v, v}, {2 * ov * v, 2 * v, 2 * ov, 2});
-  w.L2R1 = view(w.L2R, 1, {o, o, v, v}, {2 * ov * v, 2 * v, 2 * ov, 2});
   w.Zt = A.cplx<T>({o, v, o, v});
   w.ZLt = A.cplx<T>({o, v, o, v});
   w.B2 = A.cplx<T>({o, v, o, v});
@@ -211,6 +207,26 @@ void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
   w.Dvv = A.cplx<T>({v, v});
   w.Doo = A.cplx<T>({o, o});
   w.P1 = A.cplx<T>({o, o});
+}
+
+// out += base + lad + z + zt[iajb] + (z + zt[iajb])[jiba] over [o][o][v][v] (zt stored [o][v][o][v])
+template <typename T>
+void pair_add(Engine& E, const Ten<T>& base, const Ten<T>& lad, const Ten<T>& z, const Ten<T>& zt, const Ten<T>& out) {
+  const int o = (int)out.d[0], v = (int)out.d[2];
+  auto dense = [&](const Ten<T>& x, int64_t d0, int64_t d1, int64_t d2, int64_t d3) {
+    return x.nd == 4 && x.d[0] == d0 && x.d[1] == d1 && x.d[2] == d2 && x.d[3] == d3 && x.s[3] == 1 &&
+           x.s[2] == d3 && x.s[1] == d2 * d3 && x.s[0] == d1 * d2 * d3;
+  };
+  RTCC_CHECK(dense(out, o, o, v, v) && dense(base, o, o, v, v) && dense(lad, o, o, v, v) && dense(z, o, o, v, v) &&
+                 dense(zt, o, v, o, v) && out.im && lad.im && z.im && zt.im && base.bs == 0 && (E.nb == 1 || out.bs != 0),
+             kEInval, "pair_add: unexpected layout");
+  if (E.trace) fprintf(stderr, "[rtcc] pair_add\n");
+  T* const op[2] = {out.re, out.im};
+  const T* const bp[2] = {base.re, base.im};
+  const T* const lp[2] = {lad.re, lad.im};
+  const T* const zp[2] = {z.re, z.im};
+  const T* const tp[2] = {zt.re, zt.im};
+  pair_combo<T>(E.stream, o, v, E.nb, op, out.bs, bp, lp, lad.bs, zp, z.bs, tp, zt.bs);
 }
 
 template <typename T>
@@ -244,7 +260,11 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     T* o_t2s[2] = {w.t2s.re, w.t2s.im};
     T* o_l2s[2] = {w.l2s.re, w.l2s.im};
     const int64_t bs[6] = {t2.bs, l2.bs, tau.bs, w.taut.bs, w.t2s.bs, w.l2s.bs};
-    amp_combo<T>(E.stream, o, v, E.nb, a1, t1.bs, a2, lambda ? b2 : nullptr, bs, o_tau, o_taut, o_t2s, o_l2s);
+    // with the t1 terms, also the stacked left operands of the ring products
+    T* o_tr[2] = {w.T2R.re, w.T2R.im};
+    T* o_lr[2] = {w.L2R.re, w.L2R.im};
+    amp_combo<T>(E.stream, o, v, E.nb, a1, t1.bs, a2, lambda ? b2 : nullptr, bs, o_tau, o_taut, o_t2s, o_l2s,
+                 tb ? o_tr : nullptr, w.T2R.bs, (tb && lambda) ? o_lr : nullptr, w.L2R.bs);
   }
   // the amplitudes and their combinations are fixed from here on: derived layouts of them are kept
   // (per engine) for the rest of this call
@@ -362,8 +382,6 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   C(1, "ijae,be->ijab", t2, w.Hvv, w.Z, 0);
   C(-1, "imab,mj->ijab", t2, w.Hoo, w.Z, 1);
   if (tb) {
-    P(1, "imae->imae", w.t2s, w.T2R0, 0);
-    P(1, "imae->imae", t2, w.T2R1, 0);
     C(1, "iasme,jbsme->iajb", w.T2R, w.WW, w.Zt, 0);
     C(1, "mjae,meib->iajb", t2, w.Wx, w.Zt, 1);
     C(-1, "mb,ijam->ijab", t1, w.Z1, w.Z, 1);
@@ -376,15 +394,13 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     }
     C(1, "ie,jeba->ijab", t1, I.ovvv, w.Z, 1);
     C(-1, "ma,ijmb->ijab", t1, I.ooov, w.Z, 1);
-    P(1, "iajb->ijab", w.Zt, w.Z, 1);
-    P(1, "ijab->ijab", I.oovv, w.R2, 0);
-    C(1, "mnab,mnij->ijab", tau, w.W, w.R2, 1);
-    P(1, "ijab->ijab", w.LadT, w.R2, 1);
-    P(1, "ijab->ijab", w.Z, w.R2, 1);
+    C(1, "mnab,mnij->ijab", tau, w.W, w.R2, 0);
+    // R2 += <ij|ab> + ladder + Z + Zt[iajb] + (the same two)[jiba], one pass
+    pair_add(*cur, I.oovv, w.LadT, w.Z, w.Zt, w.R2);
   } else {
     P(1, "ijab->ijab", w.Z, w.R2, 0);
+    P(1, "ijab->jiba", w.Z, w.R2, 1);
   }
-  P(1, "ijab->jiba", w.Z, w.R2, 1);
   if (!lambda) return;
 
   // ---- Lambda2 residual
@@ -397,23 +413,18 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     C(1, "ijef,mnef->ijmn", l2, tau, w.M, 0);
     C(1, "ie,ejab->ijab", l1, w.Hvovv, w.ZL, 1);
     C(-1, "ma,ijmb->ijab", l1, w.Hooov, w.ZL, 1);
-    P(1, "imae->imae", w.l2s, w.L2R0, 0);
-    P(1, "imae->imae", l2, w.L2R1, 0);
     C(1, "iames,jbmes->iajb", w.L2R, w.HH5, w.ZLt, 0);
     C(1, "mjae,ibme->iajb", l2, w.HHx, w.ZLt, 1);
-    P(1, "iajb->ijab", w.ZLt, w.ZL, 1);
     C(1, "ijae,be->ijab", I.oovv, w.Gvv, w.ZL, 1);
     C(-1, "imab,mj->ijab", I.oovv, w.Goo, w.ZL, 1);
     C(-1, "ijem,meba->ijab", w.Y, I.ovvv, w.ZL, 1);
-    P(1, "ijab->ijab", I.oovv, w.S2, 0);
-    C(1, "mnab,ijmn->ijab", l2, w.W, w.S2, 1);
-    P(1, "ijab->ijab", w.LadL, w.S2, 1);
+    C(1, "mnab,ijmn->ijab", l2, w.W, w.S2, 0);
     C(1, "ijmn,mnab->ijab", w.M, I.oovv, w.S2, 1);
-    P(1, "ijab->ijab", w.ZL, w.S2, 1);
+    pair_add(*cur, I.oovv, w.LadL, w.ZL, w.ZLt, w.S2);
   } else {
     P(1, "ijab->ijab", w.ZL, w.S2, 0);
+    P(1, "ijab->jiba", w.ZL, w.S2, 1);
   }
-  P(1, "ijab->jiba", w.ZL, w.S2, 1);
 
   // ---- Lambda1 residual: S1 = Fme + l1.Hvv - l1.Hoo + ... + A1 - A2, in three groups with their
   // own partial sums (S1, S1b, S1c), balanced over the three streams: group B (the Wr part of A1)
