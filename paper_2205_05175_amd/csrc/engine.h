@@ -165,6 +165,14 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
 bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<float> A, GemmOp<float> B,
                  float* Cre, float* Cim, int64_t ldc, double beta);
 
+// y(n) = alpha * sum_k x(k) W(k, n) + beta * y(n) for n < N, k < K, with x(k) at k * incx, y(n) at n * incy
+// and W(k, n) at (k / K2) sk1 + (k % K2) sk2 + (n / N2) sn1 + (n % N2) sn2 (two-level indices: a
+// matrix operand that no single row and column stride describes). Planar complex or real.
+template <typename T>
+void gemv_strided(Engine& E, int64_t N, int64_t K, double alpha, const T* xre, const T* xim, int64_t incx,
+                  const T* wre, const T* wim, int64_t N2, int64_t sn1, int64_t sn2, int64_t K2, int64_t sk1,
+                  int64_t sk2, T* yre, T* yim, int64_t incy, double beta);
+
 // Sum `splits` partial planes P[s][m][n] (plane stride M * N) into C = alpha * sum + beta * C, in a
 // fixed order; nbatch members (member z's planes start at z * splits * M * N, its C at Cre + z * sc).
 template <typename T>

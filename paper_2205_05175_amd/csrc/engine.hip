@@ -316,6 +316,49 @@ Plan plan_for(const Ten<T>& A, const std::string& sa, const Ten<T>& B, const std
   return best;
 }
 
+// y(n) = alpha sum_k x(k) W(k, n) + beta y(n) with W read in place through two-level indices (see
+// gemv_strided): x and y must each be one strided index (letters kl and nl), each letter group of W at
+// most two strided runs, and the lanes' direction (W's unit- or smallest-stride group) dense. Not taken
+// when W's permuted layout is kept anyway (a cached constant, an operand fixed for this call). Returns
+// false (nothing launched) when the form does not apply.
+template <typename T>
+bool gemv_two_level(Engine& E, double alpha, const Ten<T>& X, const std::string& sx, const Ten<T>& W,
+                    const std::string& sw, const Ten<T>& C, const std::string& sc, const std::string& nl,
+                    const std::string& kl, double beta, const char* specstr) {
+  if ((W.konst && E.cache) || memo_fixed(E, W.re)) return false;
+  auto by_stride = [&](std::string g) {
+    std::stable_sort(g.begin(), g.end(), [&](char a, char b) { return str_of(W, sw, a) > str_of(W, sw, b); });
+    return g;
+  };
+  // the letters g (outer to inner) as an outer and an inner run of W: extent of the inner run, strides
+  auto split2 = [&](const std::string& g, int64_t* n2, int64_t* s1, int64_t* s2) {
+    for (size_t q = 0; q < g.size(); ++q) {  // q = 0: one run
+      int64_t i1 = 0, e1 = 1, i2 = 0, e2 = 1;
+      if (!mergeable(W, sw, g.substr(q), &i2, &e2)) continue;
+      if (q > 0 && !mergeable(W, sw, g.substr(0, q), &i1, &e1)) continue;
+      *n2 = e2;
+      *s1 = i1;
+      *s2 = i2;
+      return true;
+    }
+    return false;
+  };
+  const std::string kord[2] = {kl, by_stride(kl)}, nord[2] = {nl, by_stride(nl)};
+  for (const std::string& ko : kord)
+    for (const std::string& no : nord) {
+      int64_t incx, ex, incy, ey, N2, sn1, sn2, K2, sk1, sk2;
+      if (!mergeable(X, sx, ko, &incx, &ex) || !mergeable(C, sc, no, &incy, &ey)) continue;
+      if (!split2(no, &N2, &sn1, &sn2) || !split2(ko, &K2, &sk1, &sk2)) continue;
+      const bool row = sn2 == 1 || (sk2 != 1 && sn2 < sk2);
+      if (row ? !(sn2 >= 1 && sn2 <= 2 && N2 >= 16) : !(sk2 >= 1 && sk2 <= 2 && K2 >= 16)) continue;
+      if (E.trace) fprintf(stderr, "[rtcc] ein %-22s two-level gemv (no permute)\n", specstr);
+      gemv_strided<T>(E, ey, ex, alpha, X.re, X.im, incx, W.re, W.im, N2, sn1, sn2, K2, sk1, sk2, C.re, C.im, incy,
+                      beta);
+      return true;
+    }
+  return false;
+}
+
 }  // namespace
 
 void memo_begin(Engine& E, std::initializer_list<const void*> fixed) {
@@ -461,6 +504,17 @@ void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const T
   for (char c : bn) N *= dim_of(C, sc, c);
   for (char c : bk) K *= dim_of(A, sa, c);
   const int nbt = !hb ? 1 : hl == 'Z' ? E.nb : (int)dim_of(C, sc, hl);
+
+  if (!hb && !bA && !bB && !bC && (M == 1) != (N == 1) && K > 1) {
+    // a GEMV whose matrix operand would need a permute
+    GemmOp<T> t;
+    const bool wb = M == 1;  // W = B(k, n) (else W = A(m, k))
+    if (wb ? !view2d(B, sb, bk, bn, &t) : !view2d(A, sa, bm, bk, &t)) {
+      if (gemv_two_level<T>(E, alpha, wb ? A : B, wb ? sa : sb, wb ? B : A, wb ? sb : sa, C, sc, wb ? bn : bm, bk,
+                            beta, specstr))
+        return;
+    }
+  }
 
   if (E.trace) {
     GemmOp<T> xa, xb, xc;

@@ -443,16 +443,33 @@ struct GemvParams {
   int N, K, kchunk;
   int64_t split_stride;
   T alpha, beta;
+  // two-level indices (GEN kernels): W(k, n) = W[(k / K2) sk1 + (k % K2) sk2 + (n / N2) sn1 + (n % N2) sn2];
+  // q64, r64 = 64 / K2, 64 % K2
+  int N2, K2, q64, r64;
+  int64_t sn1, sn2, sk1, sk2;
 };
 
-// Row layout W(k, n) = W[k * ldw + n]: consecutive lanes take consecutive n (coalesced rows of W);
-// each thread walks its k-range with eight rows of loads in flight and sums in k order.
-template <typename T, int XC, int WC>
+// Row layout W(k, n) = W[k * ldw + n] (GEN: the two-level form, lanes along n): consecutive lanes take
+// consecutive n (coalesced rows of W); each thread walks its k-range with eight rows of loads in
+// flight and sums in k order.
+template <typename T, int XC, int WC, int GEN>
 __global__ __launch_bounds__(256) void gemv_row_kernel(GemvParams<T> p) {
   const int n = blockIdx.x * 256 + threadIdx.x;
   if (n >= p.N) return;  // no barriers below
   const int s = blockIdx.y;
   const int kb = s * p.kchunk, ke = min(p.K, kb + p.kchunk);
+  const int64_t nn = GEN ? (int64_t)(n / p.N2) * p.sn1 + (int64_t)(n % p.N2) * p.sn2 : n;
+  int k1 = GEN ? kb / p.K2 : 0, k2 = GEN ? kb % p.K2 : 0;
+  // offset of row k of W; called once per k, in increasing k
+  auto kofs = [&](int k) -> int64_t {
+    if (!GEN) return (int64_t)k * p.ldw + nn;
+    const int64_t o = (int64_t)k1 * p.sk1 + (int64_t)k2 * p.sk2 + nn;
+    if (++k2 == p.K2) {
+      k2 = 0;
+      ++k1;
+    }
+    return o;
+  };
   T ar = 0, ai = 0;
   auto madd = [&](T xr, T xi, T wr, T wi) {
     ar = fma(xr, wr, ar);
@@ -465,7 +482,7 @@ __global__ __launch_bounds__(256) void gemv_row_kernel(GemvParams<T> p) {
     T wr[8], wi[8], xr[8], xi[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int64_t o = (int64_t)(k + u) * p.ldw + n;
+      const int64_t o = kofs(k + u);
       wr[u] = p.wre[o];
       wi[u] = WC ? p.wim[o] : T(0);
       xr[u] = p.xre[(int64_t)(k + u) * p.incx];
@@ -475,7 +492,7 @@ __global__ __launch_bounds__(256) void gemv_row_kernel(GemvParams<T> p) {
     for (int u = 0; u < 8; ++u) madd(xr[u], xi[u], wr[u], wi[u]);
   }
   for (; k < ke; ++k) {
-    const int64_t o = (int64_t)k * p.ldw + n;
+    const int64_t o = kofs(k);
     madd(p.xre[(int64_t)k * p.incx], XC ? p.xim[(int64_t)k * p.incx] : T(0), p.wre[o], WC ? p.wim[o] : T(0));
   }
   constexpr bool CC = XC || WC;
@@ -495,17 +512,32 @@ __global__ __launch_bounds__(256) void gemv_row_kernel(GemvParams<T> p) {
   }
 }
 
-// Column layout W(k, n) = W[n * ldw + k]: one wave per n, lanes stride over k (coalesced), four
-// loads in flight per lane; the 64 lane sums are combined in a fixed butterfly order.
-template <typename T, int XC, int WC>
+// Column layout W(k, n) = W[n * ldw + k] (GEN: the two-level form, lanes along k): one wave per n,
+// lanes stride over k (coalesced), four loads in flight per lane; the 64 lane sums are combined in a
+// fixed butterfly order.
+template <typename T, int XC, int WC, int GEN>
 __global__ __launch_bounds__(256) void gemv_col_kernel(GemvParams<T> p) {
   const int lane = threadIdx.x & 63;
   const int n = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (n >= p.N) return;  // whole waves leave together; no barriers below
   const int s = blockIdx.y;
   const int kb = s * p.kchunk, ke = min(p.K, kb + p.kchunk);
-  const T* wr = p.wre + (int64_t)n * p.ldw;
-  const T* wi = WC ? p.wim + (int64_t)n * p.ldw : nullptr;
+  const int64_t nn = GEN ? (int64_t)(n / p.N2) * p.sn1 + (int64_t)(n % p.N2) * p.sn2 : (int64_t)n * p.ldw;
+  const T* wr = p.wre + nn;
+  const T* wi = WC ? p.wim + nn : nullptr;
+  int k1 = GEN ? (kb + lane) / p.K2 : 0, k2 = GEN ? (kb + lane) % p.K2 : 0;
+  // offset of element k (this lane's k, k + 64, ...) in the row of n; called once per k, in order
+  auto kofs = [&](int k) -> int64_t {
+    if (!GEN) return k;
+    const int64_t o = (int64_t)k1 * p.sk1 + (int64_t)k2 * p.sk2;
+    k2 += p.r64;
+    k1 += p.q64;
+    if (k2 >= p.K2) {
+      k2 -= p.K2;
+      ++k1;
+    }
+    return o;
+  };
   T ar = 0, ai = 0;
   auto madd = [&](T xr, T xi, T vr, T vi) {
     ar = fma(xr, vr, ar);
@@ -519,16 +551,19 @@ __global__ __launch_bounds__(256) void gemv_col_kernel(GemvParams<T> p) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int kk = k + 64 * u;
-      vr[u] = wr[kk];
-      vi[u] = WC ? wi[kk] : T(0);
+      const int64_t o = kofs(kk);
+      vr[u] = wr[o];
+      vi[u] = WC ? wi[o] : T(0);
       xr[u] = p.xre[(int64_t)kk * p.incx];
       xi[u] = XC ? p.xim[(int64_t)kk * p.incx] : T(0);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) madd(xr[u], xi[u], vr[u], vi[u]);
   }
-  for (; k < ke; k += 64)
-    madd(p.xre[(int64_t)k * p.incx], XC ? p.xim[(int64_t)k * p.incx] : T(0), wr[k], WC ? wi[k] : T(0));
+  for (; k < ke; k += 64) {
+    const int64_t o = kofs(k);
+    madd(p.xre[(int64_t)k * p.incx], XC ? p.xim[(int64_t)k * p.incx] : T(0), wr[o], WC ? wi[o] : T(0));
+  }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     ar += __shfl_xor(ar, off);
@@ -552,11 +587,26 @@ __global__ __launch_bounds__(256) void gemv_col_kernel(GemvParams<T> p) {
   }
 }
 
-// x(k), W(k, n) as described above; y complex when x or W is. Returns the number of splits used.
+// Two-level index form of W for the GEN kernels (see GemvParams).
+struct GemvLayout {
+  int64_t N2, sn1, sn2, K2, sk1, sk2;
+};
+
+// x(k), W(k, n) as described above (or in the two-level form L when non-null); y complex when x or W
+// is. Returns the number of splits used.
 template <typename T>
 static int gemv(Engine& E, bool col, int64_t N, int64_t K, double alpha, const T* xre, const T* xim, int64_t incx,
-                const T* wre, const T* wim, int64_t ldw, T* yre, T* yim, int64_t incy, double beta) {
+                const T* wre, const T* wim, int64_t ldw, T* yre, T* yim, int64_t incy, double beta,
+                const GemvLayout* L = nullptr) {
   GemvParams<T> p;
+  p.N2 = L ? (int)L->N2 : 1;
+  p.K2 = L ? (int)L->K2 : 1;
+  p.sn1 = L ? L->sn1 : 0;
+  p.sn2 = L ? L->sn2 : 0;
+  p.sk1 = L ? L->sk1 : 0;
+  p.sk2 = L ? L->sk2 : 0;
+  p.q64 = 64 / p.K2;
+  p.r64 = 64 % p.K2;
   p.xre = xre;
   p.xim = xim;
   p.incx = incx;
@@ -599,9 +649,11 @@ static int gemv(Engine& E, bool col, int64_t N, int64_t K, double alpha, const T
   }
   const dim3 grid(gx, (unsigned)splits);
   const int sel = (xim ? 2 : 0) + (wim ? 1 : 0);
-#define RTCC_GEMV(XC, WC)                                                                             \
-  if (col) hipLaunchKernelGGL((gemv_col_kernel<T, XC, WC>), grid, dim3(256), 0, E.stream, p);          \
-  else hipLaunchKernelGGL((gemv_row_kernel<T, XC, WC>), grid, dim3(256), 0, E.stream, p);
+#define RTCC_GEMV(XC, WC)                                                                              \
+  if (L && col) hipLaunchKernelGGL((gemv_col_kernel<T, XC, WC, 1>), grid, dim3(256), 0, E.stream, p);   \
+  else if (L) hipLaunchKernelGGL((gemv_row_kernel<T, XC, WC, 1>), grid, dim3(256), 0, E.stream, p);     \
+  else if (col) hipLaunchKernelGGL((gemv_col_kernel<T, XC, WC, 0>), grid, dim3(256), 0, E.stream, p);   \
+  else hipLaunchKernelGGL((gemv_row_kernel<T, XC, WC, 0>), grid, dim3(256), 0, E.stream, p);
   switch (sel) {
     case 0: RTCC_GEMV(0, 0) break;
     case 1: RTCC_GEMV(0, 1) break;
@@ -826,6 +878,45 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
             (long long)M, (long long)N, (long long)K, nbt, AC ? "c" : "r", BC ? "c" : "r", A.trans, B.trans, BM,
             BN, BK, splits, (int)vec);
 }
+
+template <typename T>
+void gemv_strided(Engine& E, int64_t N, int64_t K, double alpha, const T* xre, const T* xim, int64_t incx,
+                  const T* wre, const T* wim, int64_t N2, int64_t sn1, int64_t sn2, int64_t K2, int64_t sk1,
+                  int64_t sk2, T* yre, T* yim, int64_t incy, double beta) {
+  if (N <= 0) return;
+  RTCC_CHECK(N < (1LL << 31) && K < (1LL << 31) && N2 >= 1 && K2 >= 1 && N % N2 == 0 && (K == 0 || K % K2 == 0),
+             kEInval, "gemv_strided: bad extents");
+  const bool XC = xim != nullptr, WC = wim != nullptr;
+  RTCC_CHECK(yim || (!XC && !WC), kEInval, "gemv_strided: complex product into a real output");
+  if (K <= 0) {
+    int64_t d[1] = {N}, st[1] = {incy};
+    permute_axpby<T>(E.stream, 1, d, yre, yim, st, yre, yim, st, 0.0, beta);
+    return;
+  }
+  if (!XC && !WC && yim) {  // real product into a complex output: the imaginary plane is only scaled
+    int64_t d[1] = {N}, st[1] = {incy};
+    permute_axpby<T>(E.stream, 1, d, yim, (T*)nullptr, st, yim, (T*)nullptr, st, 0.0, beta);
+    yim = nullptr;
+  }
+  // lanes along the index with unit (or the smaller) innermost stride
+  const bool col = !(sn2 == 1 || (sk2 != 1 && sn2 < sk2));
+  const GemvLayout L{N2, sn1, sn2, K2, sk1, sk2};
+  const int splits = gemv<T>(E, col, N, K, alpha, xre, xim, incx, wre, wim, 0, yre, yim, incy, beta, &L);
+  E.gemm_flops += 2 * N * K * ((XC && WC) ? 4 : (XC || WC) ? 2 : 1);
+  if (E.trace)
+    fprintf(stderr,
+            "[rtcc] gemv-strided N=%lld (%lld x %lld: %lld %lld) K=%lld (%lld x %lld: %lld %lld) %s%s %s splits=%d\n",
+            (long long)N, (long long)(N / N2), (long long)N2, (long long)sn1, (long long)sn2, (long long)K,
+            (long long)(K / K2), (long long)K2, (long long)sk1, (long long)sk2, XC ? "c" : "r", WC ? "c" : "r",
+            col ? "col" : "row", splits);
+}
+
+template void gemv_strided<double>(Engine&, int64_t, int64_t, double, const double*, const double*, int64_t,
+                                   const double*, const double*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                   double*, double*, int64_t, double);
+template void gemv_strided<float>(Engine&, int64_t, int64_t, double, const float*, const float*, int64_t,
+                                  const float*, const float*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                  float*, float*, int64_t, double);
 
 template void gemm<double>(Engine&, int64_t, int64_t, int64_t, double, GemmOp<double>, GemmOp<double>, double*,
                            double*, int64_t, double, GemmBatch);
