@@ -156,7 +156,8 @@ void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
   w.M = A.cplx<T>({o, o, o, o});
   w.Mp = A.cplx<T>({o, o, o, o});
   w.Hooov = A.cplx<T>({o, o, o, v});
-  w.Hvovv = A.cplx<T>({v, o, v, v});
+  w.Xin = A.cplx<T>({o, o});
+  w.Qnf = A.cplx<T>({o, v});
   w.Z1 = A.cplx<T>({o, o, v, o});
   w.Y = A.cplx<T>({o, o, v, o});
   w.U = A.cplx<T>({o, o, v, o});
@@ -192,7 +193,7 @@ void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
   w.ZLt = A.cplx<T>({o, v, o, v});
   w.B2 = A.cplx<T>({o, v, o, v});
   w.B3 = A.cplx<T>({o, v, o, v});
-  w.Wr = A.cplx<T>({o, o, v, v});
+  w.Wr = A.cplx<T>({o, v, o, v});
   w.Z = A.cplx<T>({o, o, v, v});
   w.S1t = A.cplx<T>({o, v, o, o});
   w.ZL = A.cplx<T>({o, o, v, v});
@@ -201,7 +202,7 @@ void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
   w.S1 = A.cplx<T>({o, v});
   w.S1b = A.cplx<T>({o, v});
   w.S1c = A.cplx<T>({o, v});
-  w.Wr2 = A.cplx<T>({o, o, v, v});
+  w.Wr2 = A.cplx<T>({v, o, o, v});
   w.S2 = A.cplx<T>({o, o, v, v});
   w.rho = A.cplx<T>({n, n});
   w.Dvv = A.cplx<T>({v, v});
@@ -243,9 +244,9 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   };
   const bool par = tb && lambda && E.br[0] && E.br[1];
   if (E.trace)
-    fprintf(stderr, "[rtcc] tensors t1=%p t2=%p l1=%p l2=%p tau=%p taut=%p t2s=%p l2s=%p W=%p Hooov=%p Hvovv=%p\n",
+    fprintf(stderr, "[rtcc] tensors t1=%p t2=%p l1=%p l2=%p tau=%p taut=%p t2s=%p l2s=%p W=%p Hooov=%p\n",
             (void*)w.t1.re, (void*)w.t2.re, (void*)w.l1.re, (void*)w.l2.re, (void*)w.tau.re, (void*)w.taut.re,
-            (void*)w.t2s.re, (void*)w.l2s.re, (void*)w.W.re, (void*)w.Hooov.re, (void*)w.Hvovv.re);
+            (void*)w.t2s.re, (void*)w.l2s.re, (void*)w.W.re, (void*)w.Hooov.re);
   const int o = w.o, v = w.v;
   const Ten<T>&t1 = w.t1, &t2 = w.t2, &l1 = w.l1, &l2 = w.l2, &tau = w.tau;
 
@@ -280,9 +281,10 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
 
   // Concurrent part 1 (with branch engines): the main engine builds the one-body intermediates,
   // the T1 residual, W, Hbar_mnie and the Hbar_mnie-free parts of the ring intermediates; branch 0
-  // the ladder, Z1 and Hbar_amef; branch 1 the t2-integral ring pieces and the Lambda
-  // intermediates G, U. Then the main engine completes the ring intermediates (the Hbar_mnie
-  // terms and the combinations) and part 2 forks the residuals.
+  // the ladder and Z1; branch 1 the t2-integral ring pieces and the Lambda intermediates G, U. Then
+  // the main engine completes the ring intermediates (the Hbar_mnie terms and the combinations) and
+  // part 2 forks the residuals. Hbar_amef is never formed: its uses take <ma|fe> and the t1 term
+  // separately.
   if (par) fork_branches(E);
 
   // ---- one-body intermediates
@@ -329,10 +331,6 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     C(-1, "jf,mbfe->mejb", t1, I.ovvv, w.Bx, 1);
 
     if (par) cur = E.br[0];
-    if (lambda) {
-      P(1, "mafe->amef", I.ovvv, w.Hvovv, 0);
-      C(-1, "na,nmef->amef", t1, I.oovv, w.Hvovv, 1);
-    }
     // particle-particle ladder: one GEMM over the stacked [tau; lambda2] rows
     {
       // batched: the members' [tau; lambda2] blocks are consecutive rows of one operand
@@ -411,7 +409,11 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   if (tb) {
     C(1, "ijef,mf->ijem", l2, t1, w.Y, 0);
     C(1, "ijef,mnef->ijmn", l2, tau, w.M, 0);
-    C(1, "ie,ejab->ijab", l1, w.Hvovv, w.ZL, 1);
+    // l1 . Hbar_ejab with Hbar_amef = <ma|fe> - t_na <nm|ef>: the integral part, then the t1 part
+    // through X_in = sum_e l_ie t_ne
+    C(1, "ie,jeba->ijab", l1, I.ovvv, w.ZL, 1);
+    C(1, "ie,ne->in", l1, t1, w.Xin, 0);
+    C(-1, "in,njab->ijab", w.Xin, I.oovv, w.ZL, 1);
     C(-1, "ma,ijmb->ijab", l1, w.Hooov, w.ZL, 1);
     C(1, "iames,jbmes->iajb", w.L2R, w.HH5, w.ZLt, 0);
     C(1, "mjae,ibme->iajb", l2, w.HHx, w.ZLt, 1);
@@ -432,12 +434,14 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   // engine, group C (the Y3 part of A1 and A2) on the second branch; summed after the join.
   if (tb) {
     // group B (the Wr part of A1)
-    C(1, "imef,nmeg->infg", w.l2s, t2, w.Wr, 0);
-    C(-1, "infg,nfag->ia", w.Wr, I.ovvv, w.S1b, 0);
-    C(1, "imef,nmgf->ineg", w.l2s, t2, w.Wr, 0);
-    C(1, "ineg,nega->ia", w.Wr, I.Lovvv, w.S1b, 1);
-    C(1, "imef,nmfg->ineg", w.l2s, t2, w.Wr, 0);
-    C(-1, "ineg,nega->ia", w.Wr, I.ovvv, w.S1b, 1);
+    // Wr in the product's own row-major layout (i f | n g), which the next contraction reads as
+    // rows i over one contiguous run of its summed letters
+    C(1, "imef,nmeg->ifng", w.l2s, t2, w.Wr, 0);
+    C(-1, "ifng,nfag->ia", w.Wr, I.ovvv, w.S1b, 0);
+    C(1, "imef,nmgf->ieng", w.l2s, t2, w.Wr, 0);
+    C(1, "ieng,nega->ia", w.Wr, I.Lovvv, w.S1b, 1);
+    C(1, "imef,nmfg->ieng", w.l2s, t2, w.Wr, 0);
+    C(-1, "ieng,nega->ia", w.Wr, I.ovvv, w.S1b, 1);
   }
   if (par) cur = &E;
   P(1, "ia->ia", w.Fme, w.S1, 0);
@@ -452,8 +456,10 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   // group A
   C(2, "me,iame->ia", l1, w.HHd, w.S1, 1);
   C(1, "me,iame->ia", l1, w.HHx, w.S1, 1);
-  C(-2, "ef,eifa->ia", w.Gvv, w.Hvovv, w.S1, 1);
-  C(1, "ef,eiaf->ia", w.Gvv, w.Hvovv, w.S1, 1);
+  // G_ef (-2 Hbar_eifa + Hbar_eiaf) = -G_ef L_ieaf + Q_nf L_nifa with Q_nf = sum_e t_ne G_ef
+  C(-1, "ef,ieaf->ia", w.Gvv, I.Lovvv, w.S1, 1);
+  C(1, "ne,ef->nf", t1, w.Gvv, w.Qnf, 0);
+  C(1, "nf,nifa->ia", w.Qnf, I.Loovv, w.S1, 1);
   C(-2, "mn,mina->ia", w.Goo, w.Hooov, w.S1, 1);
   C(1, "mn,imna->ia", w.Goo, w.Hooov, w.S1, 1);
   // A1 = sum_mef l2s_im^ef Hbar_efam
@@ -482,12 +488,14 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   C(1, "mnae,ke->mnak", w.l2s, t1, w.Y6, 0);
   C(1, "mnak,ikmn->ia", w.Y6, w.W, w.S1c, 1);
   C(-1, "mnae,nmei->ia", w.l2s, w.Z1, w.S1c, 1);
-  C(1, "mnae,nkef->mkaf", w.l2s, t2, w.Wr2, 0);
-  C(-1, "mkaf,ikmf->ia", w.Wr2, I.Looov, w.S1c, 1);
-  C(1, "mnae,nkfe->mkaf", w.l2s, t2, w.Wr2, 0);
-  C(1, "mkaf,ikmf->ia", w.Wr2, I.ooov, w.S1c, 1);
-  C(1, "mnae,mkfe->nkaf", w.l2s, t2, w.Wr2, 0);
-  C(1, "nkaf,kinf->ia", w.Wr2, I.ooov, w.S1c, 1);
+  // Wr2 as (a m | k f): the product's output rows (a m) and columns (k f), and for the next
+  // contraction rows a over the contiguous run of its summed letters
+  C(1, "mnae,nkef->amkf", w.l2s, t2, w.Wr2, 0);
+  C(-1, "amkf,ikmf->ia", w.Wr2, I.Looov, w.S1c, 1);
+  C(1, "mnae,nkfe->amkf", w.l2s, t2, w.Wr2, 0);
+  C(1, "amkf,ikmf->ia", w.Wr2, I.ooov, w.S1c, 1);
+  C(1, "mnae,mkfe->ankf", w.l2s, t2, w.Wr2, 0);
+  C(1, "ankf,kinf->ia", w.Wr2, I.ooov, w.S1c, 1);
   C(1, "mf,iefn->mien", t1, I.ovvo, w.B4, 0);
   C(-1, "mnae,mien->ia", w.l2s, w.B4, w.S1c, 1);
   C(1, "mf,ikfg->mikg", t1, I.oovv, w.B5, 0);
