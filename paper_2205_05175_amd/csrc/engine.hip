@@ -475,14 +475,16 @@ void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const T
   }
   if (!bC && pl.cost > 0) {
     // Without a member batch, an output letter shared with one input (or both) may serve as the batch
-    // letter of a batched GEMM when that needs less permuting -- but not for products that would use
-    // the split-BF16 kernel (single GEMMs only) or the GEMV kernels (M or N of 1).
+    // letter of a batched GEMM when that needs less permuting -- but only for small products (below
+    // the split-BF16 threshold, in every precision: a large product kept as one GEMM keeps its tiles
+    // full, where a batch of thin slices pads every slice to whole tiles; in FP32 the split-BF16 kernel
+    // takes single GEMMs only), and not for the GEMV kernels (M or N of 1).
     int64_t M0 = 1, N0 = 1, K0 = 1;
     for (char c : pl.m) M0 *= dim_of(C, sc, c);
     for (char c : pl.n) N0 *= dim_of(C, sc, c);
     for (char c : pl.k) K0 *= dim_of(A, sa, c);
-    const bool split16 = sizeof(T) == 4 && E.bf16x3 && 2.0 * M0 * N0 * K0 >= E.bf16_min_flops;
-    if (!split16 && M0 > 1 && N0 > 1) {
+    const bool large = 2.0 * M0 * N0 * K0 >= E.bf16_min_flops;
+    if (!large && M0 > 1 && N0 > 1) {
       for (char x : sc) {
         if (sa.find(x) == std::string::npos && sb.find(x) == std::string::npos) continue;
         if (dim_of(C, sc, x) < 2 || dim_of(C, sc, x) > 65535) continue;
