@@ -210,34 +210,52 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
     __syncthreads();
   }
 
-  // ---- epilogue: each lane holds four rows of one column of every 16x16 block
+  // ---- epilogue: each lane holds four rows of one column of every 16x16 block. With beta != 0 the
+  // old C values of a row block are all loaded before any of its stores (a store may alias a later
+  // load, so loads interleaved with stores would each wait a full memory latency).
   constexpr bool CC = AC || BC;
   const int cc = lane & 15;
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < FM; ++i) {
+    T oldr[FN][4], oldi[FN][4];
+    const bool acc = !p.split_stride && p.beta != T(0);
+    if (acc) {
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * WM + i * 16 + Mfma<T>::row(lane, r);
+          const int col = n0 + wn * WN + j * 16 + cc;
+          const bool ok = row < p.M && col < p.N;
+          const int64_t off = (int64_t)zb * p.sc + (int64_t)row * p.ldc + col;
+          oldr[j][r] = ok ? p.Cre[off] : T(0);
+          oldi[j][r] = (CC && ok) ? p.Cim[off] : T(0);
+        }
+    }
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int row = m0 + wm * WM + i * 16 + Mfma<T>::row(lane, r);
-        int col = n0 + wn * WN + j * 16 + cc;
+        const int row = m0 + wm * WM + i * 16 + Mfma<T>::row(lane, r);
+        const int col = n0 + wn * WN + j * 16 + cc;
         if (row >= p.M || col >= p.N) continue;
-        T vr = accr[i][j][r], vi = acci[i][j][r];
+        const T vr = accr[i][j][r], vi = acci[i][j][r];
         if (p.split_stride) {
-          int64_t off = (int64_t)blockIdx.z * p.split_stride + (int64_t)row * p.N + col;
+          const int64_t off = (int64_t)blockIdx.z * p.split_stride + (int64_t)row * p.N + col;
           p.Cre[off] = vr;
           if (CC) p.Cim[off] = vi;
         } else {
-          int64_t off = (int64_t)zb * p.sc + (int64_t)row * p.ldc + col;
+          const int64_t off = (int64_t)zb * p.sc + (int64_t)row * p.ldc + col;
           T outr = p.alpha * vr, outi = p.alpha * vi;
-          if (p.beta != T(0)) {
-            outr += p.beta * p.Cre[off];
-            if (CC) outi += p.beta * p.Cim[off];
+          if (acc) {
+            outr += p.beta * oldr[j][r];
+            outi += p.beta * oldi[j][r];
           }
           p.Cre[off] = outr;
           if (CC) p.Cim[off] = outi;
         }
       }
+  }
 }
 
 // Sum the split-K partial planes and apply alpha/beta. A block handles 16 outputs with 16
