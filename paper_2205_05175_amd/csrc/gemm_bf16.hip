@@ -359,13 +359,14 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   // a reduction that streams s partial planes and C (cache-resident: ~12 TB/s measured). A split
   // grid stays within kSplitWG workgroups: the right-hand side issues its large products from
   // three concurrent streams, and a split product that claims every CU holds the others back
-  // longer than its split gains (measured: ~160-192 of 256 is best for the o=20, v=76 step).
+  // longer than its split gains (measured for the o=20, v=76 step: 144-176 of 256 best, 192 0.5% and
+  // 256 3% slower; below 144 the 1520 x 1520 products lose their split and the step is 4% slower).
   const int stages = p.Kp / kBK;
   const double tile_time = 2.0 * kBM * kBN * (double)p.Kp * ((AC && BC) ? 4 : 2) / (0.35 * 2516.6e12 / 3 / 256);
   const double plane_bytes = (double)M * N * 4.0 * 2.0;
   int splits = 1;
   double best = 1e300;
-  constexpr int kSplitWG = 192;
+  constexpr int kSplitWG = 160;
   for (int sp = 1; sp <= 16 && (sp == 1 || stages / sp >= 4); ++sp) {
     if (sp > 1 && p.ntiles * sp > kSplitWG) break;
     const double rounds = (double)cdiv((int64_t)p.ntiles * sp, 256);
