@@ -248,8 +248,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); a single propagation does not "
-              f"shard across GPUs in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library evaluates each "
+              f"propagation on a single GPU; independent propagations are batched on that GPU instead",
+              file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         if args.steps is None:
