@@ -294,11 +294,26 @@ __global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p) {
     __syncthreads();
   }
 
+  // With beta != 0 the old C values of each 32 x 32 block are all loaded before its stores (a store
+  // may alias a later load, so loads interleaved with stores would each wait a full memory latency).
   constexpr bool CC = AC || BC;
+  const bool acc = !p.split_stride && p.beta != 0.f;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) {
+      float oldr[16], oldi[16];
+      if (acc) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int col = n0 + wn * 64 + j * 32 + l32;
+          const bool ok = row < p.M && col < p.N;
+          const int64_t off = (int64_t)row * p.ldc + col;
+          oldr[r] = ok ? p.Cre[off] : 0.f;
+          oldi[r] = (CC && ok) ? p.Cim[off] : 0.f;
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -312,14 +327,15 @@ __global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p) {
         } else {
           const int64_t off = (int64_t)row * p.ldc + col;
           float outr = p.alpha * vr, outi = p.alpha * vi;
-          if (p.beta != 0.f) {
-            outr += p.beta * p.Cre[off];
-            if (CC) outi += p.beta * p.Cim[off];
+          if (acc) {
+            outr += p.beta * oldr[r];
+            outi += p.beta * oldi[r];
           }
           p.Cre[off] = outr;
           if (CC) p.Cim[off] = outi;
         }
       }
+    }
 }
 
 }  // namespace
