@@ -32,7 +32,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6}
 # same counter on a plain device copy of the same run (the 72,247.5 KiB state clone: FETCH_SIZE
 # 36,139.2 KiB, x2.0; WRITE_SIZE 72,247.5 KiB, x1.0). Commands and raw figures:
 # profiles/ladder_traffic_o20v76.md. To be re-measured whenever that kernel changes.
-LADDER_TRAFFIC_BF16X3 = {"fetch_bytes": 246296.7 * 1024 * 2.0, "write_bytes": 38132.8 * 1024 * 1.0,
+LADDER_TRAFFIC_BF16X3 = {"fetch_bytes": 246305.8 * 1024 * 2.0, "write_bytes": 38464.0 * 1024 * 1.0,
                          "kernel": "gemm_bf16x3_nt<1, 0, 1, 4>"}
 
 
