@@ -16,12 +16,16 @@ arithmetic:
   -- module ``ccsd``;
 * the Gaussian pulse (Eq. field) and the Dirac-delta kick -- module ``field``;
 * the explicit Runge-Kutta family (Eqs. rk_y, rk_k; RK4, Eq. rk4truncation;
-  Cash-Karp, Eqs. ck-k, ck-y, ck-h, ck-h-final) -- module ``integrators``;
+  Cash-Karp, Eqs. ck-k, ck-y, ck-h, ck-h-final, trial and adaptive
+  propagation) -- module ``integrators``;
 * the ground state used as the initial condition (Theory, "Propagation of
   the RT-CC equations") -- module ``ground``;
 * a brute-force determinant-space evaluation of the same definitions, used
-  only to pin the factorised equations -- module ``bruteforce``;
-* the FFT spectrum readout -- module ``spectrum``.
+  only to pin the factorised equations -- module ``bruteforce``.
+
+The absorption-spectrum readout of a dipole trajectory is host-side analysis of
+the library's output, not part of the propagation, and lives in the package
+(``paper_2205_05175_amd.spectrum``); it is pinned on analytic signals.
 
 Closed-shell variables (used at the boundary) map to spin orbitals as
 ``t_i^a = t_{i alpha}^{a alpha}`` and ``t_ij^ab = t_{i alpha j beta}^{a alpha b beta}``;

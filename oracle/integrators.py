@@ -106,6 +106,34 @@ def cashkarp_step(f, t, y, h, eps, t_end=None, max_tries=50):
     raise RuntimeError("Cash-Karp step not accepted")
 
 
+def cashkarp_propagate(f, t0, y0, h0, eps, t_end, on_accept=None, max_trials=1000000):
+    """Adaptive Cash-Karp propagation from t0 to t_end (Eqs. ck-h, ck-h-final).
+
+    Each trial uses hh = min(h, t_end - t), so the last step lands on t_end. An accepted trial
+    advances y with the fifth-order solution and calls on_accept(t, y); after every trial
+    h = hh * factor. Returns (y, t, n_accepted, n_rejected, h_next).
+    """
+    y, t, h = y0.copy(), t0, h0
+    nacc = nrej = 0
+    for _ in range(max_trials):
+        if t >= t_end:
+            return y, t, nacc, nrej, h
+        hh = min(h, t_end - t)
+        y5, _, delta = cashkarp_trial(f, t, y, hh)
+        if not np.isfinite(delta):
+            raise FloatingPointError("non-finite Cash-Karp error estimate")
+        fac = ck_factor(eps, delta)
+        if delta <= eps:
+            y, t = y5, t + hh
+            nacc += 1
+            if on_accept is not None:
+                on_accept(t, y)
+        else:
+            nrej += 1
+        h = hh * fac
+    raise RuntimeError("Cash-Karp propagation: too many trials")
+
+
 def butcher_row_sums(c, A):
     """sum_j a_ij - c_i for each row (zero for a consistent tableau)."""
     return [sum(A[i], Fr(0)) - c[i] for i in range(len(c))]

@@ -149,6 +149,63 @@ def test_cash_karp_controller():
     assert abs(y[0] - np.exp(lam * 3.0)) < 1e-5
 
 
+# One Cash-Karp trial on y' = lam y multiplies y by these polynomials of z = h lam (from the
+# corrected tableau: the fifth-order solution adds z^6 / 800 to the degree-5 Taylor polynomial).
+def _R5(z):
+    return sum(z ** k / math.factorial(k) for k in range(6)) + z ** 6 / 800
+
+
+def _R4(z):
+    return (1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24 + Fr(10517, 1228800) * z ** 5
+            + Fr(1771, 1638400) * z ** 6)
+
+
+def test_cash_karp_amplification_polynomials():
+    """Exact rational amplification of one trial (Fraction arithmetic through the tableau)."""
+    for z in (Fr(1, 3), Fr(-7, 5), Fr(2)):
+        k = []
+        for i in range(6):
+            yi = 1 + sum(I.CK_A[i][j] * z * k[j] for j in range(len(I.CK_A[i])))
+            k.append(yi)  # f(y) = lam y, so h k_i = z y_i
+        y5 = 1 + z * sum(b * x for b, x in zip(I.CK_B5, k))
+        y4 = 1 + z * sum(b * x for b, x in zip(I.CK_B4, k))
+        assert y5 == _R5(z) and y4 == _R4(z)
+
+
+def test_cash_karp_propagation_sequence_closed_form():
+    """On y' = lam y every Delta = |R5(z) - R4(z)| |y| is known in closed form, so the whole
+    accept / reject / step-size sequence of the propagation, clipped to land on t_end, is predicted
+    exactly and must be reproduced."""
+    lam = -0.05 + 6.0j
+    eps, t_end, h0 = 1e-7, 4.0, 0.3
+    R5 = lambda z: complex(sum(z ** k / math.factorial(k) for k in range(6)) + z ** 6 / 800)
+    c4 = [1, 1, 1 / 2, 1 / 6, 1 / 24, 10517 / 1228800, 1771 / 1638400]
+    R4 = lambda z: sum(c * z ** k for k, c in enumerate(c4))
+    # predicted sequence
+    pred, y, t, h, nrej = [], 1.0 + 0j, 0.0, h0, 0
+    while t < t_end:
+        hh = min(h, t_end - t)
+        z = hh * lam
+        d = abs(R5(z) - R4(z)) * abs(y)
+        fac = min(max(0.84 * (eps / d) ** (0.2 if d <= eps else 0.25), 0.1), 5.0)
+        if d <= eps:
+            y, t = y * R5(z), t + hh
+            pred.append((t, y))
+        else:
+            nrej += 1
+        h = hh * fac
+    got = []
+    yf, tf, nacc, nrj, _ = I.cashkarp_propagate(lambda tt, yy: lam * yy, 0.0, np.array([1.0 + 0j]), h0, eps,
+                                                 t_end, on_accept=lambda tt, yy: got.append((tt, yy[0])))
+    assert nacc == len(pred) and nrj == nrej and nrej >= 1
+    assert tf == t_end
+    # Delta is a difference of two O(1) numbers: its rounding (~1e-16 / 1e-7 relative) moves each h
+    # by ~1e-10 relative, so the times and values agree to that level, the decisions exactly
+    for (ta, ya), (tb, yb) in zip(got, pred):
+        assert abs(ta - tb) < 1e-9 and abs(ya - yb) < 1e-8
+    assert abs(yf[0] - np.exp(lam * t_end)) < 1e-5
+
+
 def test_field_envelope_matches_paper_values():
     g = json.load(open(os.path.join(GOLDEN, "field_envelope.json")))
     for p in g["points"]:
