@@ -1,16 +1,23 @@
 """Benchmark: RK4 steps/s of real-time CCSD (T + Lambda right-hand side) at o=20, v=76 on one MI355X.
 
 Workload (synthetic, seeded): the four-water-shaped closed-shell system o = 20 occupied and
-v = 76 virtual spatial orbitals from ``synth.make_system(20, 76, seed=0)``; its FP64 ground
-state is computed on the GPU, then a delta kick of 1e-3 au along z is applied, and the state
-is propagated with RK4 at dt = 0.02 au. A timed "step" is one full RK4 step: four evaluations
-of the T1/T2/Lambda1/Lambda2 time derivatives, the FP64 stage updates, and the FP64 dipole at
-the step end. Both contraction precisions are timed on the same starting state; the headline
-``value`` is the complex-FP32 path, ``fp64_steps_per_s`` the FP64 path.
+v = 76 virtual spatial orbitals from ``synth.make_system(20, 76, seed=0)`` (factor width
+0.05 * 24 / n: the unscaled width of the smaller systems has no convergent CCSD solution at this
+size); its FP64 ground state is computed on the GPU, then a delta kick of 1e-3 au along z is
+applied, and the state is propagated with RK4 at dt = 0.02 au. A timed "step" is one full RK4
+step: four evaluations of the T1/T2/Lambda1/Lambda2 time derivatives, the FP64 stage updates,
+and the FP64 dipole at the step end. FP64, complex-FP32 and split-BF16 contractions are timed on
+the same starting state. The headline ``value`` is the split-BF16 path when its dipole stays
+within 1e-6 au of the FP64 path over the whole gate trajectory (``--gate-steps`` RK4 steps from
+the kick, 500 by default), else the complex-FP32 path.
 
-The ladder GEMM (the dominant kernel) is timed live with HIP events recorded on the library's
-stream around every launch inside the timed region. The CPU oracle is timed on a bounded
-sample on the host (see ``cpu_baseline.sample``).
+The ladder GEMM (the dominant kernel) is timed live with HIP events recorded on the stream it
+runs on, around every launch of a second, eagerly issued pass of the timed steps. The CPU oracle
+is timed on a bounded sample on the host (see ``cpu_baseline.sample``).
+
+Other workloads: ``--workload spectrum`` (RK4 and adaptive Cash-Karp to t = 100 au in every
+precision, absorption-peak shifts against FP64), ``batch`` (24 propagations in one captured
+graph per step), ``adjoint`` (pulse-parameter gradient at (10,38)).
 """
 from __future__ import annotations
 
@@ -40,24 +47,53 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline():
-    """Oracle (spin-orbital FP64 NumPy) on the host: one RHS at (o,v) = (10,38), scaled to an RK4 step at (20,76)."""
-    from oracle import ccsd
-    from synth import make_system, random_state
-    o, v = 10, 38
-    eri, fock, mu = make_system(o, v, 0)
-    S = ccsd.SpinOrbitalSystem(eri, fock, mu, o, v)
-    st = random_state(o, v, 1)
-    t0 = time.perf_counter()
-    ccsd.rhs(S, *st, np.zeros(3))
-    dt = time.perf_counter() - t0
-    scale = (20 / 10) ** 2 * (76 / 38) ** 4  # o^2 v^4 ladder cost ratio
-    step_s = 4 * dt * scale
+def cpu_baseline_leg(fock, mu, o, v, y64_final, gpu_dipole):
+    """The oracle on the host cores: timed as planned (medians of 3 right-hand sides at (4,16),
+    (5,19) and (10,38), of 3 RK4 steps at (4,16) and (5,19), one RK4 step at (10,38)), the RK4 step
+    rate extrapolated to (o, v) by the o^2 v^4 ladder cost, and the FP64 GPU dipole of the final
+    state checked against the oracle's dipole at full size (the dipole needs no two-electron
+    integrals)."""
+    from oracle import ccsd, integrators
+    from synth import make_system, pack_state, random_state, unpack_state
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    return {"value": 1.0 / step_s, "unit": "RK4 steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"one oracle RHS at (o,v)=(10,38) took {dt:.2f} s; x4 RHS per RK4 step and x{scale:.0f} "
-                      f"(o^2 v^4 ratio to (20,76)); the full (20,76) spin-orbital oracle needs ~11 GB of "
-                      f"antisymmetrised integrals and minutes per RHS"}
+    rows, t_all = [], time.perf_counter()
+    rk4_1038 = None
+    for (so, sv), n_rhs, n_step in (((4, 16), 3, 3), ((5, 19), 3, 3), ((10, 38), 3, 1)):
+        eri, fk, mm = make_system(so, sv, 0)
+        S = ccsd.SpinOrbitalSystem(eri, fk, mm, so, sv)
+        st = random_state(so, sv, 1)
+        E = np.zeros(3)
+        tr = []
+        for _ in range(n_rhs):
+            t0 = time.perf_counter()
+            ccsd.rhs(S, *st, E)
+            tr.append(time.perf_counter() - t0)
+        f = lambda t, yy: pack_state(*ccsd.rhs(S, *unpack_state(yy, so, sv), E))
+        y = pack_state(*st)
+        ts = []
+        for _ in range(n_step):
+            t0 = time.perf_counter()
+            integrators.rk4_step(f, 0.0, y, 0.02)
+            ts.append(time.perf_counter() - t0)
+        rows.append({"o": so, "v": sv, "rhs_s_median": float(np.median(tr)), "rk4_step_s_median": float(np.median(ts)),
+                     "rhs_samples": n_rhs, "rk4_samples": n_step})
+        if (so, sv) == (10, 38):
+            rk4_1038 = float(np.median(ts))
+        del S, eri
+    elapsed = time.perf_counter() - t_all
+    scale = (o / 10) ** 2 * (v / 38) ** 4
+    S = ccsd.SpinOrbitalSystem(None, fock, mu, o, v)
+    mu_oracle = ccsd.dipole(S, *unpack_state(y64_final, o, v))
+    dip_err = float(np.abs(gpu_dipole - mu_oracle).max())
+    cpu = {"value": 1.0 / (rk4_1038 * scale), "unit": "RK4 steps/s", "cores": threads, "kind": "oracle",
+           "extrapolated": True,
+           "sample": (f"oracle (spin-orbital FP64 NumPy) on {threads} host threads, {elapsed:.1f} s in all: medians of "
+                      f"3 RHS at (4,16), (5,19), (10,38), of 3 RK4 steps at (4,16), (5,19) and one RK4 step at "
+                      f"(10,38) ({rk4_1038:.2f} s); value = that step extrapolated to (o,v)=({o},{v}) by the "
+                      f"o^2 v^4 ladder cost (x{scale:.0f}); one oracle RHS at (20,76) needs ~11 GB of "
+                      f"antisymmetrised integrals and is not part of this bounded sample"),
+           "measured": rows}
+    return cpu, dip_err
 
 
 def bench_batch(args):
@@ -234,17 +270,128 @@ def bench_adjoint(args):
     print(json.dumps(line), flush=True)
 
 
+def _propagate_chunked(R, y, t0, dt, nsteps, mu_full, k0, chunk, label):
+    """nsteps RK4 steps from t0 with the dipole written to mu_full[k0 .. k0 + nsteps] (rows of 6),
+    issued in chunks so that progress is printed while the GPU works."""
+    import torch
+    done = 0
+    while done < nsteps:
+        n = min(chunk, nsteps - done)
+        R.propagate_rk4(y, t0 + done * dt, dt, n, None, mu_full[k0 + done:k0 + done + n + 1])
+        torch.cuda.synchronize()
+        done += n
+        log(f"[bench] {label}: {done}/{nsteps} steps")
+
+
+def bench_spectrum(args):
+    """The o=20, v=76 delta-kick propagation to t = 100 au in every contraction precision: RK4 at
+    dt = 0.02 (5000 steps) and adaptive Cash-Karp at eps = 1e-6; whole-trajectory dipole errors and
+    absorption-peak shifts against the FP64 RK4 trajectory, and the Cash-Karp / RK4 count of
+    right-hand sides."""
+    import torch
+    from paper_2205_05175_amd import RTCC
+    from paper_2205_05175_amd import spectrum as spc
+    from synth import make_system
+
+    o, v, dt, T, kappa, eps = args.o, args.v, args.dt, args.t_end, 1e-3, args.eps
+    nsteps = int(round(T / dt))
+    eri, fock, mu = make_system(o, v, 0)
+    R = RTCC(eri, fock, mu, o, v, precision="fp32")
+    del eri
+    y0 = R.new_state()
+    R.set_precision("fp64")
+    e_corr = R.ground_state(y0, 1e-10, 200)
+    mu_gs = R.dipole(y0)
+    R.kick(y0, kappa, [0.0, 0.0, 1.0])
+    log(f"[bench] spectrum workload o={o} v={v}: e_corr={e_corr:.10f}, RK4 {nsteps} steps, CK eps={eps}")
+    rk, ck = {}, {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        R.set_precision(prec)
+        y = y0.clone()
+        m = torch.zeros((nsteps + 1, 6), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _propagate_chunked(R, y, 0.0, dt, nsteps, m, 0, 500, f"rk4 {prec}")
+        te = time.perf_counter() - ts
+        bad = R.check_state(y)
+        mm = m.cpu().numpy()
+        rk[prec] = {"mu": mm[:, 0::2] + 1j * mm[:, 1::2], "s": te, "nonfinite": bad}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        R.set_precision(prec)
+        y = y0.clone()
+        t, h = 0.0, 0.02
+        times, mus, nacc, nrej = [0.0], [R.dipole(y)], 0, 0
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        while t < T - 1e-12:
+            t1 = min(T, t + 10.0)
+            tt, mm, na, nr, h = R.propagate_cashkarp(y, t, t1, h, eps, cap=200000)
+            times += list(tt)
+            mus += list(mm)
+            nacc += na
+            nrej += nr
+            t = t1
+            log(f"[bench] cash-karp {prec}: t = {t:.1f}, {nacc} accepted, {nrej} rejected")
+        te = time.perf_counter() - ts
+        ck[prec] = {"t": np.array(times), "mu": np.array(mus), "acc": nacc, "rej": nrej, "s": te}
+
+    def induced(mz):
+        return mz.real - mu_gs[2].real
+
+    grid = dt * np.arange(nsteps + 1)
+    ref = induced(rk["fp64"]["mu"][:, 2])
+    out = {"rk4": {}, "cashkarp": {}}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        r = rk[prec]
+        cmp, p_ref, p_oth = spc.compare_trajectories(ref, induced(r["mu"][:, 2]), dt, kappa)
+        out["rk4"][prec] = {"steps_per_s": nsteps / r["s"], "wall_s": r["s"], "nonfinite": r["nonfinite"],
+                            "dipole_max_abs_vs_fp64": float(np.abs(r["mu"] - rk["fp64"]["mu"]).max()),
+                            "peak_shift_max_vs_fp64": cmp.max_shift, "peaks_matched": len(cmp.pairs),
+                            "unmatched_fp64": cmp.unmatched_ref, "unmatched": cmp.unmatched_other}
+        c = ck[prec]
+        tg, dz = spc.resample_uniform(c["t"], induced(c["mu"][:, 2]), dt, t_end=T)
+        n = min(tg.size, grid.size)
+        cmpc, _, _ = spc.compare_trajectories(ref[:n], dz[:n], dt, kappa)
+        out["cashkarp"][prec] = {"accepted": c["acc"], "rejected": c["rej"], "rhs": 6 * (c["acc"] + c["rej"]),
+                                 "wall_s": c["s"], "rhs_ratio_rk4_over_ck": 4 * nsteps / (6 * (c["acc"] + c["rej"])),
+                                 "speedup_vs_rk4_same_precision": r["s"] / c["s"],
+                                 "mean_h": T / max(c["acc"], 1),
+                                 "dipole_max_abs_vs_fp64_rk4_on_grid": float(np.abs(dz[:n] - ref[:n]).max()),
+                                 "peak_shift_max_vs_fp64_rk4": cmpc.max_shift, "peaks_matched": len(cmpc.pairs),
+                                 "unmatched_fp64": cmpc.unmatched_ref, "unmatched": cmpc.unmatched_other}
+    w, S64 = spc.absorption(ref, dt, kappa)
+    peaks = [p.omega for p in spc.find_peaks(w, S64)]
+    head = out["rk4"]["bf16x3"]
+    line = {
+        "metric": "absorption-peak shift vs FP64 (RK4 dt=0.02 and Cash-Karp eps=1e-6 to t=100 au), o=20 v=76",
+        "value": max(out["rk4"]["fp32"]["peak_shift_max_vs_fp64"], head["peak_shift_max_vs_fp64"]),
+        "unit": "Eh", "n_gpus": 1, "steps": nsteps, "warmup": 0, "ms_per_step": 1e3 / head["steps_per_s"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32/bf16x3", "data": "synthetic",
+        "config": {"workload": f"rt-ccsd four-water-shaped synthetic o={o} v={v} seed 0 (factor width 0.05*24/n), "
+                               f"delta kick {kappa} z, RK4 dt={dt} and Cash-Karp eps={eps} to t={T} au",
+                   "parallelism": "single GPU"},
+        "fp64_peaks_Eh": peaks,
+        "rk4": out["rk4"], "cashkarp": out["cashkarp"],
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["single", "batch", "adjoint"], default="single",
-                    help="single: the o=20 v=76 propagation (default); batch: 24 batched propagations; "
-                         "adjoint: pulse-parameter gradient at (10,38)")
+    ap.add_argument("--workload", choices=["single", "spectrum", "batch", "adjoint"], default="single",
+                    help="single: the o=20 v=76 propagation (default); spectrum: RK4 and Cash-Karp to t=100 au "
+                         "with peak shifts; batch: 24 batched propagations; adjoint: pulse-parameter gradient at (10,38)")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--gate-steps", type=int, default=500,
+                    help="RK4 steps from the kick over which every precision's dipole is compared with FP64")
     ap.add_argument("--o", type=int, default=20)
     ap.add_argument("--v", type=int, default=76)
     ap.add_argument("--dt", type=float, default=0.02)
+    ap.add_argument("--t-end", type=float, default=100.0, help="spectrum workload: propagation length (au)")
+    ap.add_argument("--eps", type=float, default=1e-6, help="spectrum workload: Cash-Karp tolerance")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -260,6 +407,8 @@ def main():
         if args.steps is None:
             args.steps = 200
         return bench_adjoint(args)
+    if args.workload == "spectrum":
+        return bench_spectrum(args)
     if args.steps is None:
         args.steps = 20
 
@@ -275,93 +424,92 @@ def main():
     del eri
     y0 = R.new_state()
     t0 = time.time()
+    R.set_precision("fp64")
     e_corr = R.ground_state(y0, 1e-10, 200)
     torch.cuda.synchronize()
     log(f"[bench] ground state e_corr={e_corr:.12f} in {time.time() - t0:.1f} s")
     R.kick(y0, 1e-3, [0.0, 0.0, 1.0])
 
-    results = {}
-    finals = {}
+    W, K = args.warmup, args.steps
+    G = max(args.gate_steps, W + K)
+    results, traj, finals = {}, {}, {}
     for prec in ("fp64", "fp32", "bf16x3"):
         R.set_precision(prec)
         y = y0.clone()
+        m = torch.zeros((G + 1, 6), dtype=torch.float64, device="cuda")
         # warm-up builds the captured step graph before the timed region
-        mu_w = torch.zeros((args.warmup + 1, 6), dtype=torch.float64, device="cuda")
-        R.propagate_rk4(y, 0.0, args.dt, args.warmup, None, mu_w)
-        mu_t = torch.zeros((args.steps + 1, 6), dtype=torch.float64, device="cuda")
+        R.propagate_rk4(y, 0.0, args.dt, W, None, m[:W + 1])
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        R.propagate_rk4(y, args.warmup * args.dt, args.dt, args.steps, None, mu_t)
+        R.propagate_rk4(y, W * args.dt, args.dt, K, None, m[W:W + K + 1])
         torch.cuda.synchronize()
         te = time.perf_counter()
         # ladder-GEMM timing: the same steps again with HIP events around every ladder launch
         # (events cannot be timed inside a captured graph, so this pass issues plain launches)
         yp = y.clone()
-        mu_p = torch.zeros((args.steps + 1, 6), dtype=torch.float64, device="cuda")
+        mu_p = torch.zeros((K + 1, 6), dtype=torch.float64, device="cuda")
         R.profile(True)
         tp0 = time.perf_counter()
-        R.propagate_rk4(yp, (args.warmup + args.steps) * args.dt, args.dt, args.steps, None, mu_p)
+        R.propagate_rk4(yp, (W + K) * args.dt, args.dt, K, None, mu_p)
         n, ms, fl = R.profile_read()
         tp1 = time.perf_counter()
         R.profile(False)
         del yp, mu_p
+        # the rest of the gate trajectory (untimed)
+        if G > W + K:
+            _propagate_chunked(R, y, (W + K) * args.dt, args.dt, G - W - K, m, W + K, 250, f"gate {prec}")
         bad = R.check_state(y)
         if bad:
             raise SystemExit(f"non-finite state after {prec} propagation ({bad} entries)")
         avg = ms / max(n, 1)
-        results[prec] = {"ms_per_step": 1e3 * (te - ts) / args.steps, "steps_per_s": args.steps / (te - ts),
-                         "eager_ms_per_step": 1e3 * (tp1 - tp0) / args.steps,
+        results[prec] = {"ms_per_step": 1e3 * (te - ts) / K, "steps_per_s": K / (te - ts),
+                         "eager_ms_per_step": 1e3 * (tp1 - tp0) / K,
                          "ladder_launches": n, "ladder_ms": avg, "ladder_flops": fl,
                          "ladder_tflops": fl / (avg * 1e-3) / 1e12 if n else 0.0}
-        finals[prec] = (y, mu_t.cpu().numpy())
+        mm = m.cpu().numpy()
+        traj[prec] = mm[:, 0::2] + 1j * mm[:, 1::2]
+        finals[prec] = y
         log(f"[bench] {prec}: {results[prec]}")
 
-    # dipole checks: FP32 vs FP64 trajectories, and the GPU dipole of the final FP64 state vs the oracle
-    cm = lambda m: m[:, 0::2] + 1j * m[:, 1::2]
-    m64 = cm(finals["fp64"][1])
-    fp32_err = float(np.abs(cm(finals["fp32"][1]) - m64).max())
-    bf16_err = float(np.abs(cm(finals["bf16x3"][1]) - m64).max())
-    from oracle import ccsd
-    from synth import unpack_state
-    S = ccsd.SpinOrbitalSystem(None, fock, mu, o, v)
-    yf = finals["fp64"][0].cpu().numpy()
-    mu_oracle = ccsd.dipole(S, *unpack_state(yf, o, v))
-    oracle_err = float(np.abs(R.dipole(finals["fp64"][0]) - mu_oracle).max())
+    fp32_err = float(np.abs(traj["fp32"] - traj["fp64"]).max())
+    bf16_err = float(np.abs(traj["bf16x3"] - traj["fp64"]).max())
+    y64 = finals["fp64"]
+    gpu_dip = R.dipole(y64)
+    cpu, oracle_err = (None, None) if args.no_cpu else cpu_baseline_leg(fock, mu, o, v, y64.cpu().numpy(), gpu_dip)
 
-    cpu = None if args.no_cpu else cpu_baseline()
     r32 = results["fp32"]
     rbf = results["bf16x3"]
-    # the headline path is split-BF16 when its dipole stays within 1e-6 au of FP64, else complex FP32
+    # the headline path is split-BF16 when its dipole stays within 1e-6 au of FP64 over the gate trajectory,
+    # else complex FP32
     head = "bf16x3" if bf16_err <= 1e-6 else "fp32"
     rh = results[head]
     measured_traffic = head == "bf16x3" and (o, v) == (20, 76)
+    peak = PEAK_TFLOPS["fp32"] if head == "fp32" else PEAK_TFLOPS["bf16"] / 3
     line = {
         "metric": "RK4 steps/s (T+Λ RHS) o=20,v=76: FP32-MFMA vs FP64, dipole err vs oracle",
-        "value": rh["steps_per_s"], "unit": "RK4 steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": rh["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "value": rh["steps_per_s"], "unit": "RK4 steps/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": rh["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16x3" if head == "bf16x3" else "f32", "data": "synthetic",
-        "config": {"workload": f"rt-ccsd four-water-shaped synthetic o={o} v={v} seed 0, delta kick 1e-3 z, "
-                               f"RK4 dt={args.dt}", "o": o, "v": v,
+        "config": {"workload": f"rt-ccsd four-water-shaped synthetic o={o} v={v} seed 0 (factor width 0.05*24/n), "
+                               f"delta kick 1e-3 z, RK4 dt={args.dt}", "o": o, "v": v,
                    "precision": ("split-bf16 three-term products (complex, fp32 accumulate) on products above "
                                  "5e8 flop, fp32 elsewhere, fp64 state" if head == "bf16x3" else
                                  "complex fp32 contractions, fp64 state"), "parallelism": "single GPU"},
         "headline_path": head,
+        "gate": {"steps": G, "t_au": G * args.dt, "bound_au": 1e-6,
+                 "dipole_bf16x3_vs_fp64_max_abs": bf16_err, "dipole_fp32_vs_fp64_max_abs": fp32_err},
         "fp64_steps_per_s": results["fp64"]["steps_per_s"],
         "fp32_steps_per_s": r32["steps_per_s"],
         "bf16x3_steps_per_s": rbf["steps_per_s"],
         "fp32_over_fp64": r32["steps_per_s"] / results["fp64"]["steps_per_s"],
         "bf16x3_over_fp64": rbf["steps_per_s"] / results["fp64"]["steps_per_s"],
-        "dipole_fp32_vs_fp64_max_abs": fp32_err,
-        "dipole_bf16x3_vs_fp64_max_abs": bf16_err,
         "dipole_fp64_gpu_vs_oracle_max_abs": oracle_err,
         "roofline": {"bound": "mfma", "kernel": f"ladder GEMM ({head})", "achieved": rh["ladder_tflops"],
-                     "peak": PEAK_TFLOPS["fp32"] if head == "fp32" else PEAK_TFLOPS["bf16"] / 3,
-                     "unit": "TFLOP/s",
-                     "frac": rh["ladder_tflops"] / (PEAK_TFLOPS["fp32"] if head == "fp32" else PEAK_TFLOPS["bf16"] / 3),
+                     "peak": peak, "unit": "TFLOP/s", "frac": rh["ladder_tflops"] / peak,
                      "peak_note": ("fp32 MFMA peak" if head == "fp32" else "bf16 dense MFMA peak / 3 products per "
                                    "real multiply (algorithmic fp32-equivalent flops)"),
                      "traffic": (LADDER_TRAFFIC_BF16X3["fetch_bytes"] + LADDER_TRAFFIC_BF16X3["write_bytes"]
-                                 if measured_traffic else None),
+                                 if measured_traffic and LADDER_TRAFFIC_BF16X3 else None),
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      # packed operands read once (X: 896 x 5792 x 4 bf16 planes, V: 5888 x 5792 x 2) and
                      # the 800 x 5776 complex FP32 output written once (one K split at this size)

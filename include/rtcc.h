@@ -52,7 +52,7 @@ typedef struct rtcc_ctx rtcc_ctx;
  *   RTCC_FP32   : complex FP32 operands, v_mfma_f32_16x16x4f32, FP32 accumulation.
  *   RTCC_BF16X3 : FP32 operands; every complex product of more than 5e8 flops splits each
  *                 element into two BF16 halves (hi = bf16(x), lo = bf16(x - hi)) and forms
- *                 hi*hi + hi*lo + lo*hi with v_mfma_f32_16x16x32_bf16, FP32 accumulation;
+ *                 hi*hi + hi*lo + lo*hi with v_mfma_f32_32x32x16_bf16, FP32 accumulation;
  *                 smaller products as RTCC_FP32 (the threshold can be overridden by the
  *                 environment variable RTCC_BF16_MIN_FLOPS, read by rtcc_init). */
 enum { RTCC_FP64 = 0, RTCC_FP32 = 1, RTCC_BF16X3 = 2 };
@@ -130,6 +130,42 @@ int rtcc_propagate_rk4(rtcc_ctx* ctx, void* y, double t0, double h, int nsteps, 
 int rtcc_propagate_batch(rtcc_ctx* const* ctxs, int nsys, const int* nprop, void* const* ys,
                          const rtcc_field* fields, double t0, double h, int nsteps, double* const* mu_dev);
 
+/* Divergence guard (paper: Results, strong-field propagation, Fig. t2-mag: an RK4 step too long for
+ * the field makes |T2| grow without bound). With t2_limit > 0, rtcc_propagate_rk4 and
+ * rtcc_propagate_rk4_mixed form, after every step, the Frobenius norm |T2| of the closed-shell T2
+ * block of y and the number of non-finite entries of y on the device; every check_every steps (and
+ * after the last step) they synchronise and return RTCC_ENONFINITE, with the step and time in
+ * rtcc_last_error, if an entry is non-finite or |T2| > t2_limit. y then holds the state of that step.
+ * t2_limit <= 0 switches the guard off (the default; the calls then stay asynchronous). */
+int rtcc_set_guard(rtcc_ctx* ctx, double t2_limit, int check_every);
+
+/* Mixed step-size RK4 (paper: Results, "Comparison of numerical integrators", strong fields, Fig.
+ * ms-results): steps of h1 while the Gaussian pulse of `field` is on, |t - t0_pulse| <= 5 sigma, and of
+ * h2 elsewhere, from t0 to t_end; each of the (up to three) phases ends with a shorter step that lands on
+ * its boundary. For other field kinds every step is h2. rtcc_mixed_schedule (no context, host only)
+ * returns the number of steps and, if times (HOST, cap >= nsteps + 1 doubles) is not NULL, t0 and the
+ * end time of every step. rtcc_propagate_rk4_mixed advances y (DEVICE) through that schedule; if
+ * mu_dev (DEVICE, (nsteps+1)*6 doubles) is not NULL the dipole (as rtcc_dipole) at t0 and after every
+ * step is written to it, and if t2norm_dev (DEVICE, nsteps+1 doubles) is not NULL |T2| likewise.
+ * Asynchronous unless the guard is on. Steps of one size replay one captured graph. */
+int rtcc_mixed_schedule(double t0, double t_end, double h1, double h2, const rtcc_field* field, int cap,
+                        double* times, int* nsteps);
+int rtcc_propagate_rk4_mixed(rtcc_ctx* ctx, void* y, double t0, double t_end, double h1, double h2,
+                             const rtcc_field* field, double* mu_dev, double* t2norm_dev);
+
+/* Adaptive Cash-Karp propagation of y (DEVICE) from t0 to t_end (Eqs. ck-k, ck-y, ck-h, ck-h-final):
+ * trials of hh = min(h, t_end - t) starting from h = h0; a trial is accepted when the largest complex
+ * modulus of y5 - y4 is <= eps (y advances with the fifth-order solution), and after every trial
+ * h = hh * 0.84 (eps/Delta)^(1/5 accepted, 1/4 rejected), the factor clamped to [0.1, 5]. The last step
+ * lands on t_end. If t_out / mu_out (HOST, cap and 6*cap doubles) are not NULL, the time and the dipole
+ * (as rtcc_dipole) after every accepted step are written to them (RTCC_EINVAL if more than cap steps are
+ * accepted). *naccepted, *nrejected (HOST) count the trials; *h_next (HOST, may be NULL) is the next
+ * trial size. Returns RTCC_ENOTCONV after max_trials trials short of t_end and RTCC_ENONFINITE on a
+ * non-finite error estimate. Synchronises once per trial. */
+int rtcc_propagate_cashkarp(rtcc_ctx* ctx, void* y, double t0, double t_end, double h0, double eps,
+                            const rtcc_field* field, int max_trials, int cap, double* t_out, double* mu_out,
+                            int* naccepted, int* nrejected, double* h_next);
+
 /* One Cash-Karp trial of size *h from *t with absolute tolerance eps on the largest complex
  * modulus of y5 - y4. If accepted (*accepted = 1) y advances by the fifth-order solution and
  * *t += h; otherwise y is unchanged. In both cases *h becomes the controller's next trial size
@@ -205,6 +241,33 @@ int rtcc_profile_read(rtcc_ctx* ctx, int64_t* launches, double* total_ms, double
  * out[3] = real flops issued to the MFMA GEMMs by the last rtcc_rhs call,
  * out[4] = device bytes held by the context, out[5] = current precision. */
 int rtcc_info(rtcc_ctx* ctx, int64_t out[6]);
+
+/* ---- GEMM kernels and the tile autotuner ------------------------------------------------------
+ * Every contraction of the right-hand side (Eqs. derivT, derivL; the ladder, ring and hole-hole terms)
+ * is a GEMM C(m,n) = alpha sum_k A(m,k) B(k,n) + beta C(m,n) on planar complex or real operands.
+ * rtcc_gemm runs one such product with the library's kernels on caller-owned DEVICE operands, for
+ * kernel tests and for the autotuner (paper_2205_05175_amd/autotune.py), which times candidate kernels
+ * per product shape and writes the table that rtcc_load_tuning reads.
+ *   precision : RTCC_FP64 (double operands), RTCC_FP32 or RTCC_BF16X3 (float operands; BF16X3 lets
+ *               products take the split-BF16 kernel as in a context of that precision).
+ *   A(m,k) = ta ? a[k*lda + m] : a[m*lda + k];  B(k,n) = tb ? b[n*ldb + k] : b[k*ldb + n];  C(m,n) at
+ *   c[m*ldc + n]. *_im == NULL: a real operand (C must be complex if A or B is).
+ *   choice    : NULL or int[4] {kind, p1, p2, splits}: kind 0 the library's own choice; 1 the tile
+ *               kernel with a (p1 / 1000) x (p1 % 1000) tile, k stage p2 and `splits` K splits; 2 the
+ *               split-BF16 kernel with p1 (2 or 4) waves along N and `splits` K splits (0: its model).
+ *               RTCC_EINVAL if that kernel cannot take the product.
+ *   reps      : 0 runs the product once; > 0 runs it once more and then reps times between two HIP
+ *               events and writes the mean duration to *ms (HOST) -- C is overwritten each time.
+ * Allocates its own scratch (hipMalloc) and synchronises hip_stream before returning. */
+int rtcc_gemm(int precision, int64_t M, int64_t N, int64_t K, double alpha, const void* a_re, const void* a_im,
+              int64_t lda, int ta, const void* b_re, const void* b_im, int64_t ldb, int tb, double beta, void* c_re,
+              void* c_im, int64_t ldc, const int* choice, int reps, float* ms, void* hip_stream);
+
+/* Replace the process-wide tuning table with the text file at path (NULL: clear it). One entry per
+ * line, "prec M N K ac bc ta tb kind p1 p2 splits" (prec 0 FP64, 1 FP32, 2 split-BF16 contexts; ac, bc:
+ * complex A, B; the kernel choice as in rtcc_gemm); '#' starts a comment. Products of a listed shape
+ * (not batched, M, N > 1) then use the listed kernel. *nentries (HOST, may be NULL) = entries read. */
+int rtcc_load_tuning(const char* path, int* nentries);
 
 void rtcc_destroy(rtcc_ctx* ctx);
 const char* rtcc_last_error(const rtcc_ctx* ctx);

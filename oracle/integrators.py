@@ -134,6 +134,34 @@ def cashkarp_propagate(f, t0, y0, h0, eps, t_end, on_accept=None, max_trials=100
     raise RuntimeError("Cash-Karp propagation: too many trials")
 
 
+def mixed_step_plan(t0, t_end, h1, h2, on_interval):
+    """(start time, step size) list of mixed step-size RK4 (Results, strong fields): steps of h1 inside
+    on_interval = (lo, hi) (the pulse "on", |t - nu| <= 5 sigma) and h2 outside; each phase ends with
+    a shorter step landing on its boundary."""
+    lo, hi = on_interval if on_interval is not None else (t_end, t_end)
+    lo, hi = min(max(t0, lo), t_end), min(max(t0, hi), t_end)
+    plan = []
+    for a, b, h in ((t0, lo, h2), (lo, hi, h1), (hi, t_end, h2)):
+        if b <= a:
+            continue
+        n = int(np.floor((b - a) / h * (1 + 1e-12)))
+        plan += [(a + k * h, h) for k in range(n)]
+        rem = (b - a) - n * h
+        if rem > 1e-9 * h:
+            plan.append((a + n * h, rem))
+    return plan
+
+
+def rk4_propagate_plan(f, y0, plan, on_step=None):
+    """RK4 steps along a (start time, step size) plan; on_step(k, t_end_of_step, y) after each."""
+    y = y0.copy()
+    for k, (t, h) in enumerate(plan):
+        y = rk4_step(f, t, y, h)
+        if on_step is not None:
+            on_step(k, t + h, y)
+    return y
+
+
 def butcher_row_sums(c, A):
     """sum_j a_ij - c_i for each row (zero for a consistent tableau)."""
     return [sum(A[i], Fr(0)) - c[i] for i in range(len(c))]

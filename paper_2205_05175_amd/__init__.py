@@ -14,6 +14,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtcc.so")
+TUNING_PATH = os.path.join(_HERE, "tuned_gemm.txt")
 
 FP64, FP32, BF16X3 = 0, 1, 2
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
@@ -59,6 +60,14 @@ def load_library(path: str = LIB_PATH):
     L.rtcc_dipole_vjp.argtypes = [vp, vp, dp, vp]
     L.rtcc_step_rk4_vjp.argtypes = [vp, vp, d, d, ctypes.POINTER(Field), vp, dp]
     L.rtcc_step_cashkarp.argtypes = [vp, vp, dp, dp, d, ctypes.POINTER(Field), ctypes.POINTER(i), dp]
+    L.rtcc_set_guard.argtypes = [vp, d, i]
+    L.rtcc_gemm.argtypes = [i, i64, i64, i64, d, vp, vp, i64, i, vp, vp, i64, i, d, vp, vp, i64,
+                            ctypes.POINTER(i), i, ctypes.POINTER(ctypes.c_float), vp]
+    L.rtcc_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(i)]
+    L.rtcc_mixed_schedule.argtypes = [d, d, d, d, ctypes.POINTER(Field), i, dp, ctypes.POINTER(i)]
+    L.rtcc_propagate_rk4_mixed.argtypes = [vp, vp, d, d, d, d, ctypes.POINTER(Field), vp, vp]
+    L.rtcc_propagate_cashkarp.argtypes = [vp, vp, d, d, d, d, ctypes.POINTER(Field), i, i, dp, dp,
+                                          ctypes.POINTER(i), ctypes.POINTER(i), dp]
     L.rtcc_dipole.argtypes = [vp, vp, dp]
     L.rtcc_dipole_dev.argtypes = [vp, vp, vp]
     L.rtcc_ground_state.argtypes = [vp, vp, d, i, dp]
@@ -71,16 +80,22 @@ def load_library(path: str = LIB_PATH):
     L.rtcc_destroy.restype = None
     L.rtcc_last_error.argtypes = [vp]
     L.rtcc_last_error.restype = ctypes.c_char_p
-    for name in ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
-                 "rtcc_propagate_batch", "rtcc_rhs_vjp", "rtcc_dipole_vjp", "rtcc_step_rk4_vjp", "rtcc_step_cashkarp", "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick",
-                 "rtcc_check_state", "rtcc_info", "rtcc_profile", "rtcc_profile_read"):
-        getattr(L, name).restype = ctypes.c_int
+    for name in EXPORTED:
+        if name not in ("rtcc_destroy", "rtcc_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    # the GEMM tuning table written by autotune.py (RTCC_NO_TUNING=1: the library's own rules only)
+    if os.path.exists(TUNING_PATH) and os.environ.get("RTCC_NO_TUNING", "0") != "1":
+        n = ctypes.c_int(0)
+        if L.rtcc_load_tuning(TUNING_PATH.encode(), ctypes.byref(n)) != 0:
+            raise RTCCError(-1, L.rtcc_last_error(None).decode())
     _lib = L
     return L
 
 
 EXPORTED = ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
             "rtcc_propagate_batch", "rtcc_rhs_vjp", "rtcc_dipole_vjp", "rtcc_step_rk4_vjp", "rtcc_step_cashkarp",
+            "rtcc_set_guard", "rtcc_mixed_schedule", "rtcc_propagate_rk4_mixed", "rtcc_propagate_cashkarp",
+            "rtcc_gemm", "rtcc_load_tuning",
             "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick", "rtcc_check_state", "rtcc_info",
             "rtcc_profile", "rtcc_profile_read", "rtcc_destroy", "rtcc_last_error")
 
@@ -173,6 +188,53 @@ class RTCC:
         self._check(self.L.rtcc_step_cashkarp(self.ctx, self._state(y), ctypes.byref(tt), ctypes.byref(hh),
                                               float(eps), ctypes.byref(f), ctypes.byref(acc), ctypes.byref(delta)))
         return tt.value, hh.value, bool(acc.value), delta.value
+
+    def set_guard(self, t2_limit, check_every=50):
+        """Divergence guard of the RK4 propagations (t2_limit <= 0: off)."""
+        self._check(self.L.rtcc_set_guard(self.ctx, float(t2_limit), int(check_every)))
+
+    def mixed_schedule(self, t0, t_end, h1, h2, field=None):
+        """Times (t0 and every step end) of the mixed step-size RK4 schedule."""
+        return mixed_schedule(t0, t_end, h1, h2, field)
+
+    def propagate_rk4_mixed(self, y, t0, t_end, h1, h2, field=None, mu_out=None, t2norm_out=None):
+        """Mixed step-size RK4 (h1 while the pulse is on, h2 elsewhere); optional dipole (nsteps+1, 6)
+        and |T2| (nsteps+1) records as float64 CUDA tensors. Returns the number of steps."""
+        import torch
+        f = field if field is not None else Field.none()
+        ns = len(mixed_schedule(t0, t_end, h1, h2, f)) - 1
+        ptrs = []
+        for arr, k in ((mu_out, 6), (t2norm_out, 1)):
+            if arr is None:
+                ptrs.append(None)
+                continue
+            if not (arr.is_cuda and arr.dtype == torch.float64 and arr.is_contiguous() and arr.numel() >= k * (ns + 1)):
+                raise ValueError(f"record tensor must be a contiguous float64 CUDA tensor of {k * (ns + 1)} entries")
+            ptrs.append(ctypes.c_void_p(arr.data_ptr()))
+        self._check(self.L.rtcc_propagate_rk4_mixed(self.ctx, self._state(y), float(t0), float(t_end), float(h1),
+                                                    float(h2), ctypes.byref(f), ptrs[0], ptrs[1]))
+        return ns
+
+    def propagate_cashkarp(self, y, t0, t_end, h0, eps, field=None, record=True, cap=1 << 20, max_trials=1 << 24):
+        """Adaptive Cash-Karp from t0 to t_end. Returns (times, dipoles (k, 3) complex, n_accepted, n_rejected,
+        h_next); times/dipoles are those after every accepted step (empty without record)."""
+        f = field if field is not None else Field.none()
+        na, nr, hn = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+        if record:
+            tt = np.zeros(cap)
+            mm = np.zeros(6 * cap)
+            tp, mp = _dptr(tt), _dptr(mm)
+        else:
+            tt = mm = None
+            tp = mp = None
+        self._check(self.L.rtcc_propagate_cashkarp(self.ctx, self._state(y), float(t0), float(t_end), float(h0),
+                                                   float(eps), ctypes.byref(f), int(max_trials), int(cap) if record else 0,
+                                                   tp, mp, ctypes.byref(na), ctypes.byref(nr), ctypes.byref(hn)))
+        k = na.value
+        if record:
+            m = mm[:6 * k].reshape(k, 6)
+            return tt[:k].copy(), m[:, 0::2] + 1j * m[:, 1::2], k, nr.value, hn.value
+        return np.zeros(0), np.zeros((0, 3), complex), k, nr.value, hn.value
 
     def rhs_vjp(self, y, E, ybar, out=None, t=0.0, want_E=False):
         """J^H ybar at (y, E); with want_E also the gradient with respect to the field vector E."""
@@ -284,6 +346,23 @@ def propagate_batch(systems, ys, fields, t0, h, nsteps, mu_out=None):
         mpa = (ctypes.c_void_p * nsys)(*ptrs)
     rc = L.rtcc_propagate_batch(ctxs, nsys, npa, ypa, fa, float(t0), float(h), int(nsteps), mpa)
     systems[0]._check(rc)
+
+
+def mixed_schedule(t0, t_end, h1, h2, field=None):
+    """Times (t0 and every step end) of the mixed step-size RK4 schedule (rtcc_mixed_schedule)."""
+    L = load_library()
+    f = field if field is not None else Field.none()
+    n = ctypes.c_int(0)
+    rc = L.rtcc_mixed_schedule(float(t0), float(t_end), float(h1), float(h2), ctypes.byref(f), 0, None,
+                               ctypes.byref(n))
+    if rc != 0:
+        raise RTCCError(rc, L.rtcc_last_error(None).decode())
+    times = np.zeros(n.value + 1)
+    rc = L.rtcc_mixed_schedule(float(t0), float(t_end), float(h1), float(h2), ctypes.byref(f), times.size,
+                               _dptr(times), ctypes.byref(n))
+    if rc != 0:
+        raise RTCCError(rc, L.rtcc_last_error(None).decode())
+    return times
 
 
 def state_size(o, v):

@@ -41,6 +41,8 @@ std::atomic<uint64_t> g_serial{0};
 
 }  // namespace
 
+void rtcc::set_noctx_error(const std::string& msg) { g_init_error = msg; }
+
 namespace rtcc {
 // Workspace of one context for a batch of nb propagations of its system (rtcc_propagate_batch).
 struct BatchWS {
@@ -109,16 +111,22 @@ struct rtcc_ctx {
   hipEvent_t e_in = nullptr, e_out = nullptr;
   double* tdev = nullptr;     // start time of the current step (device)
   double* mu_slot = nullptr;  // dipole written by a captured step
+  // divergence guard: |T2| and the non-finite count of the state after a step (device), checked on the
+  // host every guard_every steps when guard_limit > 0
+  double* gslot = nullptr;
+  double guard_limit = 0.0;
+  int guard_every = 50;
   // captured RK4 step
   bool use_graph = true, capturing = false;
   hipGraphExec_t gexec = nullptr;
   struct Key {
     const void* y;
     double h;
-    int prec, dip, prof, kind;
+    int prec, dip, prof, kind, guard;
     double E0, omega, sigma, t0, n[3];
     bool operator==(const Key& o) const {
       return y == o.y && h == o.h && prec == o.prec && dip == o.dip && prof == o.prof && kind == o.kind &&
+             guard == o.guard &&
              E0 == o.E0 && omega == o.omega && sigma == o.sigma && t0 == o.t0 && n[0] == o.n[0] &&
              n[1] == o.n[1] && n[2] == o.n[2];
     }
@@ -236,23 +244,36 @@ FieldDev to_dev(const rtcc_field* f) {
   return d;
 }
 
-// out = F(y) at t = *tdev + toff, field evaluated on the device
+// An RK stage input y + sum_j cs[j] ks[j] (nk terms; nk = 0: y itself).
+struct StageIn {
+  const void* y;
+  int nk;
+  const void* const* ks;
+  const double* cs;
+};
+
+// out = F(stage input) at t = *tdev + toff, field evaluated on the device; the stage input is formed
+// and converted to the contraction precision in one pass
 template <typename T>
-void eval_rhs_t(rtcc_ctx* c, Ints<T>& I, Work<T>& w, const void* y, const FieldDev& fd, double toff, void* out) {
+void eval_rhs_t(rtcc_ctx* c, Ints<T>& I, Work<T>& w, const StageIn& in, const FieldDev& fd, double toff, void* out) {
   field_fock_t<T>(c->stream, c->n, c->f0, c->mu, fd, c->tdev, toff, w.f.re);
-  unpack_state<T>(c->stream, y, c->o, c->v, planes(w, true));
+  if (in.nk) combo_unpack<T>(c->stream, c->o, c->v, 1, in.y, in.nk, in.ks, in.cs, planes(w, true));
+  else unpack_state<T>(c->stream, in.y, c->o, c->v, planes(w, true));
   residuals<T>(c->E, I, w, true, true);
   pack_rhs<T>(c->stream, c->o, c->v, planes(w, false), out, 1.0);
 }
 
-void rhs_t(rtcc_ctx* c, const void* y, const FieldDev& fd, double toff, void* out) {
+void rhs_t(rtcc_ctx* c, const StageIn& in, const FieldDev& fd, double toff, void* out) {
   if (c->precision == RTCC_FP64) {
-    eval_rhs_t<double>(c, c->I64, c->W64, y, fd, toff, out);
+    eval_rhs_t<double>(c, c->I64, c->W64, in, fd, toff, out);
   } else {
     c->E.bf16x3 = c->precision == RTCC_BF16X3;
-    eval_rhs_t<float>(c, c->I32, c->W32, y, fd, toff, out);
+    eval_rhs_t<float>(c, c->I32, c->W32, in, fd, toff, out);
     c->E.bf16x3 = false;
   }
+}
+void rhs_t(rtcc_ctx* c, const void* y, const FieldDev& fd, double toff, void* out) {
+  rhs_t(c, StageIn{y, 0, nullptr, nullptr}, fd, toff, out);
 }
 
 void rhs_any(rtcc_ctx* c, const void* y, const double E[3], void* out, double scale) {
@@ -276,32 +297,39 @@ void dipole_dev(rtcc_ctx* c, const void* y, double* out6) {
   RTCC_HIP(hipGetLastError());
 }
 
-// One RK4 step from t = *tdev; advances *tdev by h; optionally the dipole of the new state.
-void rk4_step(rtcc_ctx* c, void* y, double h, const FieldDev& fd, double* dip) {
+// |T2| and the non-finite count of y into c->gslot
+void guard_dev(rtcc_ctx* c, const void* y) {
+  state_guard(c->stream, c->nstate, c->n1, c->n1 + c->n2, y, c->red, c->gslot);
+}
+
+// Reads the guard values of the last step (synchronises) and throws RTCC_ENONFINITE when the state has
+// a non-finite entry or |T2| exceeds the limit.
+void guard_check(rtcc_ctx* c, int64_t step, double t);
+
+// One RK4 step from t = *tdev; advances *tdev by h; optionally the dipole of the new state and the
+// guard values.
+void rk4_step(rtcc_ctx* c, void* y, double h, const FieldDev& fd, double* dip, bool guard = false) {
   for (int s = 0; s < 4; ++s) {
-    const void* ys = y;
-    if (s > 0) {
-      const void* ks[3] = {c->k[0], c->k[1], c->k[2]};
-      double cs[3] = {h * kRk4A[s][0], h * kRk4A[s][1], h * kRk4A[s][2]};
-      state_combo(c->stream, c->nstate, y, s, ks, cs, c->ytmp);
-      ys = c->ytmp;
-    }
-    rhs_t(c, ys, fd, kRk4C[s] * h, c->k[s]);
+    const void* ks[3] = {c->k[0], c->k[1], c->k[2]};
+    double cs[3] = {h * kRk4A[s][0], h * kRk4A[s][1], h * kRk4A[s][2]};
+    rhs_t(c, StageIn{y, s, ks, cs}, fd, kRk4C[s] * h, c->k[s]);
   }
   const void* ks[4] = {c->k[0], c->k[1], c->k[2], c->k[3]};
   double cs[4] = {h * kRk4B[0], h * kRk4B[1], h * kRk4B[2], h * kRk4B[3]};
   state_combo(c->stream, c->nstate, y, 4, ks, cs, y);
   if (dip) dipole_dev(c, y, dip);
+  if (guard) guard_dev(c, y);
   scalar_update(c->stream, c->tdev, h, true);
 }
 
 // Capture one RK4 step (with its dipole) as a graph; replayed while the key is unchanged.
-void capture_step(rtcc_ctx* c, void* y, double h, const rtcc_field* field, bool dip) {
+void capture_step(rtcc_ctx* c, void* y, double h, const rtcc_field* field, bool dip, bool guard = false) {
   rtcc_ctx::Key key{};
   key.y = y;
   key.h = h;
   key.prec = c->precision;
   key.dip = dip;
+  key.guard = guard;
   key.prof = c->prof;
   FieldDev fd = to_dev(field);
   key.kind = fd.kind;
@@ -321,7 +349,7 @@ void capture_step(rtcc_ctx* c, void* y, double h, const rtcc_field* field, bool 
   c->capturing = true;
   hipGraph_t g = nullptr;
   try {
-    rk4_step(c, y, h, fd, dip ? c->mu_slot : nullptr);
+    rk4_step(c, y, h, fd, dip ? c->mu_slot : nullptr, guard);
   } catch (...) {
     c->capturing = false;
     (void)hipStreamEndCapture(c->stream, &g);
@@ -353,6 +381,7 @@ void ensure_batch(rtcc_ctx* c, std::unique_ptr<BatchWS>& slot, int nb) {
   B->E.nb = nb;
   B->E.trace = c->E.trace;
   B->E.bf16_min_flops = c->E.bf16_min_flops;
+  B->E.bf16_kernel = c->E.bf16_kernel;
   B->E.scratch.cap = c->E.scratch.cap * (size_t)nb;
   B->E.scratch.base = B->arena.alloc<char>(B->E.scratch.cap);
   build_work<double>(B->arena, c->o, c->v, B->W64, nb);
@@ -372,21 +401,25 @@ void ensure_batch(rtcc_ctx* c, std::unique_ptr<BatchWS>& slot, int nb) {
 void ensure_batch(rtcc_ctx* c, int nb) { ensure_batch(c, c->batch, nb); }
 
 template <typename T>
-void eval_rhs_batch(rtcc_ctx* c, BatchWS& B, Ints<T>& I, Work<T>& w, const void* y, double toff, void* out) {
+void eval_rhs_batch(rtcc_ctx* c, BatchWS& B, Ints<T>& I, Work<T>& w, const StageIn& in, double toff, void* out) {
   field_fock_tb<T>(B.E.stream, c->n, c->f0, c->mu, B.fdev, B.nb, B.tdev, toff, w.f.re, w.f.bs);
-  unpack_state<T>(B.E.stream, y, c->o, c->v, planes(w, true), B.nb);
+  if (in.nk) combo_unpack<T>(B.E.stream, c->o, c->v, B.nb, in.y, in.nk, in.ks, in.cs, planes(w, true));
+  else unpack_state<T>(B.E.stream, in.y, c->o, c->v, planes(w, true), B.nb);
   residuals<T>(B.E, I, w, true, true);
   pack_rhs<T>(B.E.stream, c->o, c->v, planes(w, false), out, 1.0, B.nb);
 }
 
-void rhs_batch(rtcc_ctx* c, BatchWS& B, const void* y, double toff, void* out) {
+void rhs_batch(rtcc_ctx* c, BatchWS& B, const StageIn& in, double toff, void* out) {
   if (c->precision == RTCC_FP64) {
-    eval_rhs_batch<double>(c, B, c->I64, B.W64, y, toff, out);
+    eval_rhs_batch<double>(c, B, c->I64, B.W64, in, toff, out);
   } else {
     B.E.bf16x3 = c->precision == RTCC_BF16X3;
-    eval_rhs_batch<float>(c, B, c->I32, B.W32, y, toff, out);
+    eval_rhs_batch<float>(c, B, c->I32, B.W32, in, toff, out);
     B.E.bf16x3 = false;
   }
+}
+void rhs_batch(rtcc_ctx* c, BatchWS& B, const void* y, double toff, void* out) {
+  rhs_batch(c, B, StageIn{y, 0, nullptr, nullptr}, toff, out);
 }
 
 // dipoles of all members of y (FP64 density) into out[6 * nb]
@@ -403,14 +436,9 @@ void rk4_step_batch(rtcc_ctx* c, void* y, double h, double* dip) {
   BatchWS& B = *c->batch;
   const int64_t nst = (int64_t)B.nb * c->nstate;
   for (int s = 0; s < 4; ++s) {
-    const void* ys = y;
-    if (s > 0) {
-      const void* ks[3] = {B.k[0], B.k[1], B.k[2]};
-      double cs[3] = {h * kRk4A[s][0], h * kRk4A[s][1], h * kRk4A[s][2]};
-      state_combo(B.E.stream, nst, y, s, ks, cs, B.ytmp);
-      ys = B.ytmp;
-    }
-    rhs_batch(c, B, ys, kRk4C[s] * h, B.k[s]);
+    const void* ks[3] = {B.k[0], B.k[1], B.k[2]};
+    double cs[3] = {h * kRk4A[s][0], h * kRk4A[s][1], h * kRk4A[s][2]};
+    rhs_batch(c, B, StageIn{y, s, ks, cs}, kRk4C[s] * h, B.k[s]);
   }
   const void* ks[4] = {B.k[0], B.k[1], B.k[2], B.k[3]};
   double cs[4] = {h * kRk4B[0], h * kRk4B[1], h * kRk4B[2], h * kRk4B[3]};
@@ -562,6 +590,87 @@ bool solve_small(std::vector<double>& A, std::vector<double>& b, int n) {
   return true;
 }
 
+void guard_check(rtcc_ctx* c, int64_t step, double t) {
+  double g[2];
+  sync_read(c, c->gslot, g, 2);
+  if (g[1] > 0.0 || !(g[0] <= c->guard_limit)) {
+    char msg[200];
+    if (g[1] > 0.0)
+      snprintf(msg, sizeof msg, "divergence guard: %.0f non-finite state entries after step %lld (t = %.6g)", g[1],
+               (long long)step, t);
+    else
+      snprintf(msg, sizeof msg, "divergence guard: |T2| = %.6g exceeds %.6g after step %lld (t = %.6g)", g[0],
+               c->guard_limit, (long long)step, t);
+    throw Error(kENonFinite, msg);
+  }
+}
+
+// Step list of the mixed step-size RK4 propagation: (start time, step size) pairs from t0 to t_end,
+// h1 while a Gaussian pulse is on (|t - t0_pulse| <= 5 sigma) and h2 elsewhere; every phase ends with a
+// shorter step that lands on its boundary. Step sizes inside a phase are exactly h1 or h2 (start times
+// are computed as phase start + k h, not accumulated).
+std::vector<std::pair<double, double>> mixed_schedule(double t0, double t_end, double h1, double h2,
+                                                       const rtcc_field* f) {
+  std::vector<std::pair<double, double>> out;
+  double on_lo = t_end, on_hi = t_end;
+  if (f && f->kind == 1) {
+    on_lo = std::min(std::max(t0, f->t0 - 5.0 * f->sigma), t_end);
+    on_hi = std::min(std::max(t0, f->t0 + 5.0 * f->sigma), t_end);
+  }
+  const double bounds[4] = {t0, on_lo, on_hi, t_end};
+  const double hs[3] = {h2, h1, h2};
+  for (int ph = 0; ph < 3; ++ph) {
+    const double a = bounds[ph], b = bounds[ph + 1], h = hs[ph];
+    if (!(b > a)) continue;
+    const double span = b - a;
+    const int64_t nfull = (int64_t)std::floor(span / h * (1.0 + 1e-12));
+    RTCC_CHECK(nfull < (int64_t)1 << 30, kEInval, "mixed RK4: too many steps");
+    for (int64_t k = 0; k < nfull; ++k) out.emplace_back(a + (double)k * h, h);
+    const double rem = span - (double)nfull * h;
+    if (rem > 1e-9 * h) out.emplace_back(a + (double)nfull * h, rem);
+  }
+  return out;
+}
+
+// One Cash-Karp trial of size hh from t (device time set here): y5, y4 and Delta = max|y5 - y4| into
+// redout[0]; with dip also the dipole of y5 into redout[8..13]. Returns (Delta, and the dipole) after one
+// synchronisation.
+double ck_trial(rtcc_ctx* c, const void* y, double t, double hh, const FieldDev& fd, double* mu6) {
+  scalar_update(c->stream, c->tdev, t, false);
+  for (int s = 0; s < 6; ++s) {
+    const void* ks[5] = {c->k[0], c->k[1], c->k[2], c->k[3], c->k[4]};
+    double cs[5];
+    for (int j = 0; j < 5; ++j) cs[j] = hh * kCkA[s][j];
+    rhs_t(c, StageIn{y, s, ks, cs}, fd, kCkC[s] * hh, c->k[s]);
+  }
+  const void* ks[6] = {c->k[0], c->k[1], c->k[2], c->k[3], c->k[4], c->k[5]};
+  double c5[6], c4[6];
+  for (int j = 0; j < 6; ++j) {
+    c5[j] = hh * kCkB5[j];
+    c4[j] = hh * kCkB4[j];
+  }
+  state_combo(c->stream, c->nstate, y, 6, ks, c5, c->y5);
+  state_combo(c->stream, c->nstate, y, 6, ks, c4, c->y4);
+  max_abs_diff(c->stream, c->nstate, c->y5, c->y4, c->red, c->redout);
+  if (mu6) {
+    dipole_dev(c, c->y5, c->redout + 8);
+    double d[14];
+    sync_read(c, c->redout, d, 14);
+    for (int i = 0; i < 6; ++i) mu6[i] = d[8 + i];
+    return d[0];
+  }
+  double d[2];
+  sync_read(c, c->redout, d, 2);
+  return d[0];
+}
+
+double ck_factor(double eps, double dl) {
+  double fac;
+  if (dl == 0.0) fac = kFacMax;
+  else fac = kSafety * std::pow(eps / dl, dl <= eps ? 0.2 : 0.25);
+  return std::min(std::max(fac, kFacMin), kFacMax);
+}
+
 }  // namespace
 
 extern "C" {
@@ -596,6 +705,9 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     c->E.cache = const_cache_create();
     const char* bm = std::getenv("RTCC_BF16_MIN_FLOPS");
     if (bm && bm[0]) c->E.bf16_min_flops = std::atof(bm);
+    const char* bk = std::getenv("RTCC_BF16_KERNEL");
+    if (bk && bk[0]) c->E.bf16_kernel = std::atoi(bk);
+    RTCC_CHECK(c->E.bf16_kernel == 1 || c->E.bf16_kernel == 2, kEInval, "RTCC_BF16_KERNEL must be 1 or 2");
     const char* ng = std::getenv("RTCC_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');
     const char* tr = std::getenv("RTCC_TRACE");
@@ -657,6 +769,7 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     c->y5 = c->arena.alloc<double>(2 * c->nstate);
     c->tdev = c->arena.alloc<double>(1);
     c->mu_slot = c->arena.alloc<double>(6);
+    c->gslot = c->arena.alloc<double>(2);
     c->red = c->arena.alloc<double>(2 * 1024);
     c->redout = c->arena.alloc<double>(64);
     RTCC_HIP(hipHostMalloc((void**)&c->host_pinned, 64 * sizeof(double), hipHostMallocDefault));
@@ -729,17 +842,129 @@ int rtcc_propagate_rk4(rtcc_ctx* c, void* y, double t0, double h, int nsteps, co
     const FieldDev fd = to_dev(field);
     // HIP cannot time events recorded inside a captured graph: profiling runs the eager launches
     const bool graph = c->use_graph && !c->prof;
+    const bool guard = c->guard_limit > 0.0;
     for (int s = 0; s < nsteps; ++s) {
       if (graph) {
-        capture_step(c, y, h, field, mu_dev != nullptr);
+        capture_step(c, y, h, field, mu_dev != nullptr, guard);
         RTCC_HIP(hipGraphLaunch(c->gexec, c->stream));
         if (mu_dev)
           RTCC_HIP(hipMemcpyAsync(mu_dev + 6 * (int64_t)(s + 1), c->mu_slot, 6 * sizeof(double),
                                   hipMemcpyDeviceToDevice, c->stream));
       } else {
-        rk4_step(c, y, h, fd, mu_dev ? mu_dev + 6 * (int64_t)(s + 1) : nullptr);
+        rk4_step(c, y, h, fd, mu_dev ? mu_dev + 6 * (int64_t)(s + 1) : nullptr, guard);
       }
+      if (guard && ((s + 1) % c->guard_every == 0 || s + 1 == nsteps)) guard_check(c, s + 1, t0 + (s + 1) * h);
     }
+  });
+}
+
+int rtcc_set_guard(rtcc_ctx* c, double t2_limit, int check_every) {
+  if (!c) return RTCC_EINVAL;
+  if (std::isnan(t2_limit) || check_every < 1) {
+    c->err = "rtcc_set_guard: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  c->guard_limit = t2_limit > 0.0 ? t2_limit : 0.0;
+  c->guard_every = check_every;
+  return RTCC_OK;
+}
+
+int rtcc_mixed_schedule(double t0, double t_end, double h1, double h2, const rtcc_field* field, int cap,
+                        double* times, int* nsteps) {
+  if (!nsteps || !std::isfinite(t0) || !std::isfinite(t_end) || !(t_end >= t0) || !(h1 > 0) || !(h2 > 0) ||
+      !std::isfinite(h1) || !std::isfinite(h2) || (field && field->kind == 1 && !(field->sigma > 0)) ||
+      (times && cap < 1)) {
+    g_init_error = "rtcc_mixed_schedule: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(nullptr, [&] {
+    const auto sch = mixed_schedule(t0, t_end, h1, h2, field);
+    RTCC_CHECK(sch.size() < (size_t)INT32_MAX, kEInval, "rtcc_mixed_schedule: too many steps");
+    *nsteps = (int)sch.size();
+    if (times) {
+      RTCC_CHECK((int64_t)sch.size() + 1 <= cap, kEInval, "rtcc_mixed_schedule: times[] too short");
+      times[0] = t0;
+      for (size_t k = 0; k < sch.size(); ++k) times[k + 1] = k + 1 < sch.size() ? sch[k + 1].first : t_end;
+    }
+  });
+}
+
+int rtcc_propagate_rk4_mixed(rtcc_ctx* c, void* y, double t0, double t_end, double h1, double h2,
+                             const rtcc_field* field, double* mu_dev, double* t2norm_dev) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !std::isfinite(t0) || !std::isfinite(t_end) || !(t_end >= t0) || !(h1 > 0) || !(h2 > 0) ||
+      !std::isfinite(h1) || !std::isfinite(h2) || (field && field->kind == 1 && !(field->sigma > 0))) {
+    c->err = "rtcc_propagate_rk4_mixed: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] {
+    const auto sch = mixed_schedule(t0, t_end, h1, h2, field);
+    const int64_t ns = (int64_t)sch.size();
+    const FieldDev fd = to_dev(field);
+    const bool graph = c->use_graph && !c->prof;
+    const bool guard = c->guard_limit > 0.0 || t2norm_dev != nullptr;
+    if (mu_dev) dipole_dev(c, y, mu_dev);
+    if (t2norm_dev) {
+      guard_dev(c, y);
+      RTCC_HIP(hipMemcpyAsync(t2norm_dev, c->gslot, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
+    for (int64_t s = 0; s < ns; ++s) {
+      const double ts = sch[s].first, h = sch[s].second;
+      scalar_update(c->stream, c->tdev, ts, false);  // exact start time of every step
+      if (graph) {
+        capture_step(c, y, h, field, mu_dev != nullptr, guard);
+        RTCC_HIP(hipGraphLaunch(c->gexec, c->stream));
+        if (mu_dev)
+          RTCC_HIP(hipMemcpyAsync(mu_dev + 6 * (s + 1), c->mu_slot, 6 * sizeof(double), hipMemcpyDeviceToDevice,
+                                  c->stream));
+      } else {
+        rk4_step(c, y, h, fd, mu_dev ? mu_dev + 6 * (s + 1) : nullptr, guard);
+      }
+      if (t2norm_dev)
+        RTCC_HIP(hipMemcpyAsync(t2norm_dev + s + 1, c->gslot, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      if (c->guard_limit > 0.0 && ((s + 1) % c->guard_every == 0 || s + 1 == ns)) guard_check(c, s + 1, ts + h);
+    }
+  });
+}
+
+int rtcc_propagate_cashkarp(rtcc_ctx* c, void* y, double t0, double t_end, double h0, double eps,
+                            const rtcc_field* field, int max_trials, int cap, double* t_out, double* mu_out,
+                            int* naccepted, int* nrejected, double* h_next) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !std::isfinite(t0) || !std::isfinite(t_end) || !(t_end >= t0) || !(h0 > 0) || !std::isfinite(h0) ||
+      !(eps > 0) || max_trials < 1 || ((t_out || mu_out) && cap < 1) || !naccepted || !nrejected) {
+    c->err = "rtcc_propagate_cashkarp: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  *naccepted = 0;
+  *nrejected = 0;
+  return guarded(c, [&] {
+    const FieldDev fd = to_dev(field);
+    const bool rec = t_out || mu_out;
+    double t = t0, h = h0;
+    int trials = 0;
+    while (t < t_end) {
+      RTCC_CHECK(trials < max_trials, kENotConv, "rtcc_propagate_cashkarp: trial limit reached before t_end");
+      ++trials;
+      const double hh = std::min(h, t_end - t);
+      double mu6[6];
+      const double dl = ck_trial(c, y, t, hh, fd, mu_out ? mu6 : nullptr);
+      RTCC_CHECK(std::isfinite(dl), kENonFinite, "rtcc_propagate_cashkarp: non-finite error estimate");
+      const double fac = ck_factor(eps, dl);
+      if (dl <= eps) {
+        RTCC_CHECK(!rec || *naccepted < cap, kEInval, "rtcc_propagate_cashkarp: output capacity exceeded");
+        RTCC_HIP(hipMemcpyAsync(y, c->y5, c->nstate * 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        t = (hh == t_end - t) ? t_end : t + hh;
+        if (t_out) t_out[*naccepted] = t;
+        if (mu_out)
+          for (int i = 0; i < 6; ++i) mu_out[6 * (int64_t)(*naccepted) + i] = mu6[i];
+        ++*naccepted;
+      } else {
+        ++*nrejected;
+      }
+      h = hh * fac;
+    }
+    if (h_next) *h_next = h;
   });
 }
 
@@ -931,37 +1156,10 @@ int rtcc_step_cashkarp(rtcc_ctx* c, void* y, double* t, double* h, double eps, c
   }
   return guarded(c, [&] {
     const double hh = *h;
-    const FieldDev fd = to_dev(field);
-    scalar_update(c->stream, c->tdev, *t, false);
-    for (int s = 0; s < 6; ++s) {
-      const void* ys = y;
-      if (s > 0) {
-        const void* ks[5] = {c->k[0], c->k[1], c->k[2], c->k[3], c->k[4]};
-        double cs[5];
-        for (int j = 0; j < 5; ++j) cs[j] = hh * kCkA[s][j];
-        state_combo(c->stream, c->nstate, y, s, ks, cs, c->ytmp);
-        ys = c->ytmp;
-      }
-      rhs_t(c, ys, fd, kCkC[s] * hh, c->k[s]);
-    }
-    const void* ks[6] = {c->k[0], c->k[1], c->k[2], c->k[3], c->k[4], c->k[5]};
-    double c5[6], c4[6];
-    for (int j = 0; j < 6; ++j) {
-      c5[j] = hh * kCkB5[j];
-      c4[j] = hh * kCkB4[j];
-    }
-    state_combo(c->stream, c->nstate, y, 6, ks, c5, c->y5);
-    state_combo(c->stream, c->nstate, y, 6, ks, c4, c->y4);
-    max_abs_diff(c->stream, c->nstate, c->y5, c->y4, c->red, c->redout);
-    double d[2];
-    sync_read(c, c->redout, d, 2);
-    const double dl = d[0];
+    const double dl = ck_trial(c, y, *t, hh, to_dev(field), nullptr);
     if (delta) *delta = dl;
     RTCC_CHECK(std::isfinite(dl), kENonFinite, "rtcc_step_cashkarp: non-finite error estimate");
-    double fac;
-    if (dl == 0.0) fac = kFacMax;
-    else fac = kSafety * std::pow(eps / dl, dl <= eps ? 0.2 : 0.25);
-    fac = std::min(std::max(fac, kFacMin), kFacMax);
+    const double fac = ck_factor(eps, dl);
     if (dl <= eps) {
       RTCC_HIP(hipMemcpyAsync(y, c->y5, c->nstate * 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
       *t += hh;
@@ -1185,6 +1383,83 @@ void rtcc_destroy(rtcc_ctx* c) {
   for (hipStream_t b : bst)
     if (b) (void)hipStreamDestroy(b);
   if (st) (void)hipStreamDestroy(st);
+}
+
+int rtcc_load_tuning(const char* path, int* nentries) {
+  return guarded(nullptr, [&] {
+    const int n = load_tuning(path);
+    if (nentries) *nentries = n;
+  });
+}
+
+int rtcc_gemm(int precision, int64_t M, int64_t N, int64_t K, double alpha, const void* a_re, const void* a_im,
+              int64_t lda, int ta, const void* b_re, const void* b_im, int64_t ldb, int tb, double beta, void* c_re,
+              void* c_im, int64_t ldc, const int* choice, int reps, float* ms, void* hip_stream) {
+  if ((precision != RTCC_FP64 && precision != RTCC_FP32 && precision != RTCC_BF16X3) || M < 1 || N < 1 || K < 1 ||
+      !a_re || !b_re || !c_re || ((a_im || b_im) && !c_im) || reps < 0 || (reps > 0 && !ms) ||
+      lda < (ta ? M : K) || ldb < (tb ? K : N) || ldc < N || !std::isfinite(alpha) || !std::isfinite(beta)) {
+    g_init_error = "rtcc_gemm: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(nullptr, [&] {
+    Engine E;
+    E.stream = (hipStream_t)hip_stream;
+    E.bf16x3 = precision == RTCC_BF16X3;
+    GemmChoice ch;
+    if (choice) {
+      ch.kind = choice[0];
+      ch.p1 = choice[1];
+      ch.p2 = choice[2];
+      ch.splits = choice[3];
+      RTCC_CHECK(ch.kind >= 0 && ch.kind <= 2, kEInval, "rtcc_gemm: unknown kernel kind");
+      if (ch.kind != 0) E.force = &ch;
+    }
+    // scratch: split-BF16 packs of both operands plus the split-K partial planes (the library's own rules
+    // keep splits x M x N within 2^24 elements: at most ~1024-2048 workgroups of <= 128 x 128 outputs)
+    const size_t elt = precision == RTCC_FP64 ? 8 : 4;
+    const size_t packs = 2 * 2 * 2 * ((size_t)(M + 256) + (size_t)(N + 256)) * (size_t)(K + 32);
+    const size_t mn = (size_t)M * (size_t)N;
+    const size_t nsplit = ch.kind != 0 ? (size_t)std::max(ch.splits, 1) : 0;
+    const size_t parts = 2 * elt * (nsplit ? nsplit * mn : std::min<size_t>(64 * mn, (size_t)1 << 24));
+    E.scratch.cap = packs + parts + ((size_t)1 << 24);
+    RTCC_HIP(hipMalloc((void**)&E.scratch.base, E.scratch.cap));
+    std::unique_ptr<char, void (*)(char*)> sguard(E.scratch.base, [](char* p) { (void)hipFree(p); });
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    auto run = [&] {
+      E.scratch.reset();
+      if (precision == RTCC_FP64) {
+        GemmOp<double> A{(const double*)a_re, (const double*)a_im, lda, ta};
+        GemmOp<double> B{(const double*)b_re, (const double*)b_im, ldb, tb};
+        gemm<double>(E, M, N, K, alpha, A, B, (double*)c_re, (double*)c_im, ldc, beta);
+      } else {
+        GemmOp<float> A{(const float*)a_re, (const float*)a_im, lda, ta};
+        GemmOp<float> B{(const float*)b_re, (const float*)b_im, ldb, tb};
+        gemm<float>(E, M, N, K, alpha, A, B, (float*)c_re, (float*)c_im, ldc, beta);
+      }
+    };
+    try {
+      run();
+      if (reps > 0) {
+        RTCC_HIP(hipEventCreate(&ev[0]));
+        RTCC_HIP(hipEventCreate(&ev[1]));
+        RTCC_HIP(hipEventRecord(ev[0], E.stream));
+        for (int r = 0; r < reps; ++r) run();
+        RTCC_HIP(hipEventRecord(ev[1], E.stream));
+        RTCC_HIP(hipEventSynchronize(ev[1]));
+        float t = 0.f;
+        RTCC_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
+        *ms = t / reps;
+      }
+      RTCC_HIP(hipStreamSynchronize(E.stream));  // the scratch is freed on return
+    } catch (...) {
+      (void)hipStreamSynchronize(E.stream);
+      for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
+      throw;
+    }
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+  });
 }
 
 const char* rtcc_last_error(const rtcc_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }

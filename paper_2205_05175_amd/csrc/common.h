@@ -30,4 +30,7 @@ constexpr int kOk = 0, kEInval = -1, kENoMem = -2, kEHip = -3, kENonFinite = -4,
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Message of a failed call that has no context (read with rtcc_last_error(NULL)).
+void set_noctx_error(const std::string& msg);
+
 }  // namespace rtcc

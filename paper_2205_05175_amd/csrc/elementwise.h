@@ -16,6 +16,10 @@ template <typename T>
 void unpack_state(hipStream_t st, const void* y, int o, int v, Planes4<T> P, int nb = 1);
 template <typename T>
 void pack_rhs(hipStream_t st, int o, int v, Planes4<T> P, void* out, double scale, int nb = 1);
+// P = y + sum_j cs[j] ks[j] (nk <= 8 FP64 states of nb members; terms with cs[j] == 0 skipped), one pass.
+template <typename T>
+void combo_unpack(hipStream_t st, int o, int v, int nb, const void* y, int nk, const void* const* ks, const double* cs,
+                  Planes4<T> P);
 template <typename T>
 void field_fock(hipStream_t st, int n, const double* f0, const double* mu, const double E[3], double s0, T* f);
 // Field on the device: the rtcc_field kinds (0 none, 1 Gaussian pulse, 2 kick = none while
@@ -46,6 +50,12 @@ void dot_planar_real(hipStream_t st, int64_t n, const T* are, const T* aim, cons
 void max_abs_diff(hipStream_t st, int64_t n, const void* a, const void* b, double* partial, double* out2);
 void vdot(hipStream_t st, int64_t n, const void* a, const void* b, double* partial, double* out2);
 void count_nonfinite(hipStream_t st, int64_t n, const void* a, double* partial, double* out2);
+// Largest number of reduction blocks of state_guard (it needs 2 * kGuardBlocks partial doubles).
+constexpr int kGuardBlocks = 512;
+// out2[0] = Frobenius norm of the entries [t2b, t2e) of the interleaved complex vector y (NaN if any of
+// its nst entries is non-finite), out2[1] = number of non-finite entries. Fixed summation order.
+void state_guard(hipStream_t st, int64_t nst, int64_t t2b, int64_t t2e, const void* y, double* partial,
+                 double* out2);
 // Adjoint helpers (interleaved complex states of o, v): see elementwise.hip.
 void hamil_apply(hipStream_t st, int o, int v, const void* a, const void* b, const double cb[2], bool inverse,
                  bool conj_in, bool conj_out, double scale, bool accumulate, void* out);

@@ -412,6 +412,60 @@ void pack_rhs(hipStream_t st, int o, int v, Planes4<T> P, void* out, double scal
   RTCC_HIP(hipGetLastError());
 }
 
+// planes P = y + sum_j c_j k_j (the combination in FP64, then rounded to T): an RK stage input formed
+// and converted in one pass, in place of a state_combo into an FP64 state and an unpack_state of it.
+// Same arithmetic in the same order as those two passes.
+struct ComboArgs {
+  const double2* k[8];
+  double c[8];
+  int nk;
+};
+
+template <typename T>
+__global__ void combo_unpack_kernel(const double2* __restrict__ y, ComboArgs cb, int64_t n1, int64_t n2,
+                                    int64_t total, Planes4<T> P) {
+  const int64_t ntot = 2 * (n1 + n2);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    double2 a = y[i];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j >= cb.nk) break;
+      const double2 kk = cb.k[j][i];
+      a.x += cb.c[j] * kk.x;
+      a.y += cb.c[j] * kk.y;
+    }
+    int seg;
+    int64_t jj, b;
+    state_segment<T>(i, n1, n2, ntot, &seg, &jj, &b);
+    jj += b * P.bs[seg];
+    P.re[seg][jj] = (T)a.x;
+    P.im[seg][jj] = (T)a.y;
+  }
+}
+
+template <typename T>
+void combo_unpack(hipStream_t st, int o, int v, int nb, const void* y, int nk, const void* const* ks, const double* cs,
+                  Planes4<T> P) {
+  RTCC_CHECK(nk <= 8, kEInval, "combo_unpack: too many terms");
+  ComboArgs cb;
+  cb.nk = 0;
+  for (int j = 0; j < nk; ++j) {
+    if (cs[j] == 0.0) continue;
+    cb.k[cb.nk] = (const double2*)ks[j];
+    cb.c[cb.nk] = cs[j];
+    cb.nk++;
+  }
+  const int64_t n1 = (int64_t)o * v, n2 = n1 * n1, total = 2 * (n1 + n2) * nb;
+  const int64_t blocks = std::min<int64_t>(cdiv(total, 256), 65536);
+  hipLaunchKernelGGL(combo_unpack_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, (const double2*)y, cb, n1, n2,
+                     total, P);
+  RTCC_HIP(hipGetLastError());
+}
+template void combo_unpack<double>(hipStream_t, int, int, int, const void*, int, const void* const*, const double*,
+                                   Planes4<double>);
+template void combo_unpack<float>(hipStream_t, int, int, int, const void*, int, const void* const*, const double*,
+                                  Planes4<float>);
+
 template void unpack_state<double>(hipStream_t, const void*, int, int, Planes4<double>, int);
 template void unpack_state<float>(hipStream_t, const void*, int, int, Planes4<float>, int);
 template void pack_rhs<double>(hipStream_t, int, int, Planes4<double>, void*, double, int);
@@ -818,6 +872,60 @@ void circle_coef1(hipStream_t st, int64_t nst, const void* F, const double* maxu
 
 void max_abs(hipStream_t st, int64_t n, const void* a, double* partial, double* out2) {
   reduce<double, 1>(st, n, a, nullptr, nullptr, partial, out2);
+}
+
+// ---- divergence guard: |T2| and the non-finite entries of an interleaved state ----------------
+// Stage 1: each block sums |y_i|^2 over its part of [t2b, t2e) and counts the non-finite entries of
+// its part of [0, nst); stage 2 adds the block partials in index order and writes
+// out[0] = sqrt(sum) (NaN if any entry is non-finite) and out[1] = the count.
+__global__ void guard_stage1(int64_t nst, int64_t t2b, int64_t t2e, const double2* __restrict__ y,
+                             double* partial) {
+  __shared__ double sh0[4], sh1[4];
+  const int64_t chunk = (nst + gridDim.x - 1) / gridDim.x;
+  const int64_t beg = (int64_t)blockIdx.x * chunk, end = min(nst, beg + chunk);
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const double2 p = y[i];
+    if (!isfinite(p.x) || !isfinite(p.y)) s1 += 1.0;
+    else if (i >= t2b && i < t2e) s0 += p.x * p.x + p.y * p.y;
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh0[w] = s0;
+    sh1[w] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r0 = sh0[0], r1 = sh1[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+      r0 += sh0[k];
+      r1 += sh1[k];
+    }
+    partial[2 * blockIdx.x] = r0;
+    partial[2 * blockIdx.x + 1] = r1;
+  }
+}
+
+__global__ void guard_stage2(int nb, const double* partial, double* out) {
+  if (threadIdx.x != 0) return;
+  double r0 = 0.0, r1 = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    r0 += partial[2 * k];
+    r1 += partial[2 * k + 1];
+  }
+  out[0] = r1 > 0.0 ? __builtin_nan("") : sqrt(r0);
+  out[1] = r1;
+}
+
+void state_guard(hipStream_t st, int64_t nst, int64_t t2b, int64_t t2e, const void* y, double* partial,
+                 double* out2) {
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kGuardBlocks, cdiv(nst, 256)));
+  hipLaunchKernelGGL(guard_stage1, dim3(nb), dim3(256), 0, st, nst, t2b, t2e, (const double2*)y, partial);
+  RTCC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(guard_stage2, dim3(1), dim3(64), 0, st, nb, partial, out2);
+  RTCC_HIP(hipGetLastError());
 }
 
 // ---- ground-state Jacobi update on the interleaved state: x += R / D ---------------------------

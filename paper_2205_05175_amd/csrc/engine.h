@@ -92,6 +92,21 @@ struct Memo {
   std::map<std::string, void*> entries;
 };
 
+// A GEMM kernel choice, the unit the tile autotuner picks per product shape. kind 0: the library's
+// own rule; 1: the FP32/FP64 tile kernel with a p1 / 1000 x p1 % 1000 output tile, k stage p2 and
+// `splits` K splits; 2: the split-BF16 kernel (FP32 operands) with p1 waves along N (2: 128 x 128
+// tiles, 4: 128 x 256), `splits` K splits (0: its cost model) and variant p2 (0: the engine's, 1:
+// register-staged, 2: direct-to-LDS ring).
+struct GemmChoice {
+  int kind = 0, p1 = 0, p2 = 0, splits = 0;
+};
+// Precision tags of the tuning table: 0 FP64, 1 FP32, 2 split-BF16 contexts.
+// The tuned choice for a product of that shape (kind 0 when the table has none).
+GemmChoice tuned_choice(int prec, int64_t M, int64_t N, int64_t K, bool ac, bool bc, int ta, int tb);
+// Replace the tuning table with the entries of a text file (one "prec M N K ac bc ta tb kind p1 p2 splits"
+// per line, '#' starts a comment); path == nullptr clears it. Returns the number of entries.
+int load_tuning(const char* path);
+
 struct Engine {
   hipStream_t stream = nullptr;
   ConstCache* cache = nullptr;
@@ -109,6 +124,9 @@ struct Engine {
   bool trace = false;         // print every contraction's layout decisions to stderr
   bool bf16x3 = false;        // FP32 GEMMs above bf16_min_flops use the split-BF16 three-term kernel
   double bf16_min_flops = 5e8;
+  int bf16_kernel = 1;                  // split-BF16 kernel: 1 register-staged, 2 direct-to-LDS ring
+  bool use_tuning = true;               // consult the tuning table (single, non-batched products)
+  const GemmChoice* force = nullptr;    // this choice for every product (kernel tests, the autotuner)
   // Batch size of the tensors with bs != 0. Every contraction then runs for all members: a
   // member index carried by one operand only becomes part of the GEMM's M or N (one fat GEMM
   // against the shared integrals); one carried by both becomes a batched GEMM.
@@ -162,8 +180,11 @@ template <typename T>
 void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A, GemmOp<T> B, T* Cre, T* Cim,
           int64_t ldc, double beta, GemmBatch bt = GemmBatch());
 
+// force_wn (2 or 4), force_splits (>= 1) and force_kernel (1 register-staged, 2 direct-to-LDS ring)
+// replace the library's own tile, split and kernel choice when non-zero.
 bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<float> A, GemmOp<float> B,
-                 float* Cre, float* Cim, int64_t ldc, double beta);
+                 float* Cre, float* Cim, int64_t ldc, double beta, int force_wn = 0, int force_splits = 0,
+                 int force_kernel = 0);
 
 // y(n) = alpha * sum_k x(k) W(k, n) + beta * y(n) for n < N, k < K, with x(k) at k * incx, y(n) at n * incy
 // and W(k, n) at (k / K2) sk1 + (k % K2) sk2 + (n / N2) sn1 + (n % N2) sn2 (two-level indices: a

@@ -409,6 +409,8 @@ void fork_branches(Engine& E) {
     b->trace = E.trace;
     b->bf16x3 = E.bf16x3;
     b->bf16_min_flops = E.bf16_min_flops;
+    b->bf16_kernel = E.bf16_kernel;
+    b->use_tuning = E.use_tuning;
     b->nb = E.nb;
     b->gemm_flops = 0;
     RTCC_HIP(hipStreamWaitEvent(b->stream, E.ev_fork, 0));

@@ -9,6 +9,10 @@
 // over K into per-split partial planes and reduced by a second kernel in a fixed order, so
 // results are bitwise repeatable.
 #include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "engine.h"
 
@@ -728,6 +732,67 @@ static void launch_typed(hipStream_t st, const GemmParams<T>& p, int splits, boo
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
+// ---- tuning table -------------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+  int prec, ac, bc, ta, tb;
+  int64_t M, N, K;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(prec, M, N, K, ac, bc, ta, tb) < std::tie(o.prec, o.M, o.N, o.K, o.ac, o.bc, o.ta, o.tb);
+  }
+};
+std::map<TuneKey, GemmChoice> g_tune;
+std::mutex g_tune_mu;
+
+// the tile configurations the dispatcher below instantiates: {bm * 1000 + bn, bk, aligned operands only}
+struct TileCfg {
+  int mn, bk;
+  bool veconly;
+};
+constexpr TileCfg kTileCfgs[] = {{64064, kBK, false}, {128128, kBK, false}, {32064, 32, true}, {32128, 16, true},
+                                 {64032, 32, true},   {64096, 32, true},    {32032, 64, true}, {32096, 32, true},
+                                 {96032, 32, true}};
+}  // namespace
+
+GemmChoice tuned_choice(int prec, int64_t M, int64_t N, int64_t K, bool ac, bool bc, int ta, int tb) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tune.empty()) return GemmChoice();
+  auto it = g_tune.find(TuneKey{prec, ac, bc, ta != 0, tb != 0, M, N, K});
+  return it == g_tune.end() ? GemmChoice() : it->second;
+}
+
+int load_tuning(const char* path) {
+  std::map<TuneKey, GemmChoice> tab;
+  if (path) {
+    FILE* f = fopen(path, "r");
+    RTCC_CHECK(f != nullptr, kEInval, std::string("cannot open tuning table ") + path);
+    char line[512];
+    int ln = 0;
+    while (fgets(line, sizeof line, f)) {
+      ++ln;
+      char* hash = strchr(line, '#');
+      if (hash) *hash = 0;
+      long long M, N, K;
+      int prec, ac, bc, ta, tb;
+      GemmChoice c;
+      const int got = sscanf(line, "%d %lld %lld %lld %d %d %d %d %d %d %d %d", &prec, &M, &N, &K, &ac, &bc, &ta, &tb,
+                             &c.kind, &c.p1, &c.p2, &c.splits);
+      if (got <= 0) continue;  // blank or comment line
+      const bool ok = got == 12 && prec >= 0 && prec <= 2 && M > 0 && N > 0 && K > 0 && c.kind >= 0 && c.kind <= 2 &&
+                      c.splits >= 0;
+      if (!ok) {
+        fclose(f);
+        throw Error(kEInval, std::string("malformed tuning table line ") + std::to_string(ln) + " in " + path);
+      }
+      tab[TuneKey{prec, ac != 0, bc != 0, ta != 0, tb != 0, M, N, K}] = c;
+    }
+    fclose(f);
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.swap(tab);
+  return (int)g_tune.size();
+}
+
 template <typename T>
 void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A, GemmOp<T> B, T* Cre, T* Cim,
           int64_t ldc, double beta, GemmBatch bt) {
@@ -748,12 +813,25 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
     permute_axpby<T>(E.stream, 3, d, Cim, (T*)nullptr, s, Cim, (T*)nullptr, s, 0.0, beta);
     Cim = nullptr;
   }
+  // kernel choice: forced (kernel tests, the autotuner), else the tuning table, else the rules below
+  GemmChoice ch;
+  if (E.force) ch = *E.force;
+  else if (E.use_tuning && nbt == 1 && M > 1 && N > 1)
+    ch = tuned_choice(sizeof(T) == 8 ? 0 : E.bf16x3 ? 2 : 1, M, N, K, AC, BC, A.trans, B.trans);
   if constexpr (sizeof(T) == 4) {
-    if (nbt == 1 && E.bf16x3 && 2.0 * (double)M * (double)N * (double)K >= E.bf16_min_flops &&
-        gemm_bf16x3(E, M, N, K, alpha, A, B, Cre, Cim, ldc, beta))
+    if (ch.kind == 2) {
+      const bool done = nbt == 1 && E.bf16x3 && gemm_bf16x3(E, M, N, K, alpha, A, B, Cre, Cim, ldc, beta, ch.p1,
+                                                           ch.splits, ch.p2);
+      RTCC_CHECK(done || !E.force, kEInval, "gemm: the split-BF16 kernel cannot take this product");
+      if (done) return;
+      ch = GemmChoice();
+    } else if (ch.kind == 0 && nbt == 1 && E.bf16x3 && 2.0 * (double)M * (double)N * (double)K >= E.bf16_min_flops &&
+               gemm_bf16x3(E, M, N, K, alpha, A, B, Cre, Cim, ldc, beta)) {
       return;
+    }
   }
-  if (nbt == 1 && (M == 1 || N == 1)) {
+  RTCC_CHECK(ch.kind != 2, kEInval, "gemm: the split-BF16 kernel needs FP32 operands");
+  if (ch.kind == 0 && nbt == 1 && (M == 1 || N == 1)) {
     int splits;
     if (M == 1)  // x(k) = A(0, k), W(k, n) = B(k, n), y(n) = C(0, n)
       splits = gemv<T>(E, B.trans != 0, N, K, alpha, A.re, A.im, A.trans ? A.ld : 1, B.re, B.im, B.ld, Cre, Cim, 1,
@@ -794,7 +872,7 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
   //  - an output of at most 128 x 128 with long K: a tile fitted to the output and K split into
   //    ~512-2048 fixed-order partial sums;
   //  - FP32 with >= 512 tiles of 128 x 128: those; otherwise 64 x 64, K split when the grid is small.
-  if (M * N <= 8192 && K <= 256) {
+  if (ch.kind == 0 && M * N <= 8192 && K <= 256) {
     p.kchunk = (int)K;
     p.splits = 1;
     p.split_stride = 0;
@@ -854,6 +932,19 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
     // fewer than ~2 workgroups per CU: split K (chunks of >= 256) toward ~1024 workgroups
     int64_t want = std::max<int64_t>(1, 1024 / tiles);
     splits = (int)std::min<int64_t>({want, cdiv(K, 256), 1024, 65535 / nbt});
+  }
+  if (ch.kind == 1) {
+    const TileCfg* cfg = nullptr;
+    for (const TileCfg& c : kTileCfgs)
+      if (c.mn == ch.p1 && c.bk == ch.p2 && (sizeof(T) == 4 || c.mn != 128128)) cfg = &c;
+    const bool ok = cfg && (vec || !cfg->veconly) && ch.splits >= 1;
+    RTCC_CHECK(ok || !E.force, kEInval, "gemm: the chosen tile kernel is not available for this product");
+    if (ok) {
+      BM = ch.p1 / 1000;
+      BN = ch.p1 % 1000;
+      BK = ch.p2;
+      splits = (int)std::min<int64_t>({(int64_t)ch.splits, cdiv(K, BK), 65535 / nbt});
+    }
   }
   int64_t kchunk = cdiv(cdiv(K, splits), BK) * BK;
   splits = (int)cdiv(K, kchunk);

@@ -4,17 +4,23 @@
 // is formed as hi*hi' + hi*lo' + lo*hi' with v_mfma_f32_32x32x16_bf16, accumulated in FP32 (the
 // dropped lo*lo' term is ~2^-16 of the product). The split is a separate pass that also brings both
 // operands into one layout, "packed": per plane (Re hi, Re lo[, Im hi, Im lo]) a bf16 matrix of
-// [rows][K] stored k-blocked as [K / 16][rows][16] (16 consecutive k of a row contiguous), rows
-// padded to a multiple of the tile's rows (128 for A, 256 for B) and K to a multiple of 32 with
-// zeros, so the GEMM copies whole contiguous stage tiles without bounds checks. Packed layouts of
-// constant operands (the integrals) are made once and cached.
+// [rows][K] stored k-blocked and half-major as [K / 16][2][rows][8] (the 8 k of one half of a 16-wide
+// k block of a row are 16 contiguous bytes, and the rows of one half follow each other), rows padded
+// to a multiple of the tile's rows (128 for A, 256 for B) and K to a multiple of 32 with zeros, so
+// the GEMM copies whole contiguous stage tiles without bounds checks, and a stage tile copied as is
+// into LDS serves the MFMA fragments without bank conflicts (lanes 0-31 read rows r..r+31 of half 0,
+// lanes 32-63 the same rows of half 1: two contiguous 512-byte runs). Packed layouts of constant
+// operands (the integrals) are made once and cached.
 //
 // GEMM: 512 threads, a 128 x 256 output tile per workgroup, 2 x 4 waves of 64 x 64 (2 x 2 MFMA
 // blocks of 32 x 32 each), two waves per SIMD so that one wave's MFMAs cover the other's LDS and
 // barrier waits; the wide N side halves the B-plane traffic per flop (outputs too small for 16 such
-// tiles take 2 x 2 waves of 256 threads and 128 x 128 tiles instead). Per 16-wide k stage the
-// packed tiles pass through registers into one of two LDS buffers: stage s + 1 is written and
-// stage s + 2 fetched while stage s is multiplied, with one barrier per stage. Lane l of a
+// tiles take 2 x 2 waves of 256 threads and 128 x 128 tiles instead). Two ways to feed LDS, one per
+// kernel: (register-staged) per 16-wide k stage the packed tiles pass through registers into one of
+// two padded LDS buffers: stage s + 1 is written and stage s + 2 fetched while stage s is multiplied;
+// (DMA ring) the stage tiles go from memory straight into a ring of three or four LDS buffers with
+// 16-byte direct-to-LDS loads, issued two or three stages ahead, so no registers or LDS write
+// instructions carry them. Both take one barrier per stage. Lane l of a
 // 32x32x16 MFMA holds A[l%32][8(l/32)+j] and B[8(l/32)+j][l%32] and its output r lies at row
 // 8(r/4) + 4(l/32) + r%4, column l%32. Small grids split K into fixed-order partial sums.
 // Workgroups are numbered so that each of the eight XCDs (which take workgroups round-robin) works
@@ -40,11 +46,11 @@ constexpr int kRowPad = 128;         // packed rows are a multiple of this (of 2
 constexpr int kKPad = 32;            // packed K is a multiple of this
 
 // ---- packing ------------------------------------------------------------------------------------
-// dst plane (2 c + h) = h ? lo : hi of plane c of the source, k-blocked as [Kp / 16][Rp][16]: one
-// 16-wide k stage of 128 rows is a contiguous 4 KB. Element (r, k) of the source is src[r * ld + k]
-// (trans = 0) or src[k * ld + r] (trans = 1). A thread makes one row's 16-wide k block: consecutive
-// threads take consecutive rows, so the 32-byte hi and lo chunks they store are contiguous; the
-// loads are four 16-byte vectors (trans = 0, aligned) or 16 loads coalesced across rows (trans = 1).
+// dst plane (2 c + h) = h ? lo : hi of plane c of the source, k-blocked as [Kp / 16][2][Rp][8]: one
+// 16-wide k stage of 128 rows is two contiguous 2 KB runs. Element (r, k) of the source is
+// src[r * ld + k] (trans = 0) or src[k * ld + r] (trans = 1). A thread makes one row's 16-wide k
+// block: consecutive threads take consecutive rows, so the 16-byte chunks they store are contiguous;
+// the loads are four 16-byte vectors (trans = 0, aligned) or 16 loads coalesced across rows (trans = 1).
 __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ sre, const float* __restrict__ sim,
                                                    int64_t ld, int trans, int R, int K, int Rp, int Kp, int vec,
                                                    __bf16* __restrict__ dst) {
@@ -52,7 +58,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ sre
   if (r >= Rp) return;
   const int kb = blockIdx.y, k0 = kb * 16;
   const int64_t plane = (int64_t)Rp * Kp;
-  const int64_t o = ((int64_t)kb * Rp + r) * 16;
+  const int64_t o0 = ((int64_t)(2 * kb) * Rp + r) * 8, o1 = o0 + (int64_t)Rp * 8;  // halves k0..7, k8..15
   const int np = sim ? 2 : 1;
   for (int c = 0; c < np; ++c) {
     const float* src = c ? sim : sre;
@@ -81,12 +87,12 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ sre
       hi[kk >> 3][kk & 7] = h;
       lo[kk >> 3][kk & 7] = (__bf16)(x[kk] - (float)h);
     }
-    bf8* dh = reinterpret_cast<bf8*>(dst + (2 * c) * plane + o);
-    bf8* dl = reinterpret_cast<bf8*>(dst + (2 * c + 1) * plane + o);
-    dh[0] = hi[0];
-    dh[1] = hi[1];
-    dl[0] = lo[0];
-    dl[1] = lo[1];
+    __bf16* dh = dst + (2 * c) * plane;
+    __bf16* dl = dst + (2 * c + 1) * plane;
+    *reinterpret_cast<bf8*>(dh + o0) = hi[0];
+    *reinterpret_cast<bf8*>(dh + o1) = hi[1];
+    *reinterpret_cast<bf8*>(dl + o0) = lo[0];
+    *reinterpret_cast<bf8*>(dl + o1) = lo[1];
   }
 }
 
@@ -182,6 +188,240 @@ __device__ inline void tile_of(int b, const Params& p, int* split, int* tm, int*
   *tn = in / rows;
 }
 
+// Epilogue of one wave's 64 x 64 output block at (r0, c0): alpha * acc + beta * C, or the raw partial
+// sums into split plane `split`. With beta != 0 the old C values of each 32 x 32 block are all loaded
+// before its stores (a store may alias a later load, so loads interleaved with stores would each wait
+// a full memory latency).
+template <int AC, int BC>
+__device__ inline void store_tile(const Params& p, const f16 (&accr)[2][2], const f16 (&acci)[2][2], int split, int r0,
+                                  int c0, int lane) {
+  constexpr bool CC = AC || BC;
+  const int l32 = lane & 31;
+  const bool acc = !p.split_stride && p.beta != 0.f;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      float oldr[16], oldi[16];
+      if (acc) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = r0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int col = c0 + j * 32 + l32;
+          const bool ok = row < p.M && col < p.N;
+          const int64_t off = (int64_t)row * p.ldc + col;
+          oldr[r] = ok ? p.Cre[off] : 0.f;
+          oldi[r] = (CC && ok) ? p.Cim[off] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = r0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = c0 + j * 32 + l32;
+        if (row >= p.M || col >= p.N) continue;
+        const float vr = accr[i][j][r], vi = acci[i][j][r];
+        if (p.split_stride) {
+          const int64_t off = (int64_t)split * p.split_stride + (int64_t)row * p.N + col;
+          p.Cre[off] = vr;
+          if (CC) p.Cim[off] = vi;
+        } else {
+          const int64_t off = (int64_t)row * p.ldc + col;
+          float outr = p.alpha * vr, outi = p.alpha * vi;
+          if (acc) {
+            outr += p.beta * oldr[r];
+            outi += p.beta * oldi[r];
+          }
+          p.Cre[off] = outr;
+          if (CC) p.Cim[off] = outi;
+        }
+      }
+    }
+}
+
+// The three split products of one 16-wide k step for one wave: (hi, hi), (hi, lo), (lo, hi) for every
+// pair of its 2 x 2 blocks; packed plane index 2 c + h.
+template <int AC, int BC>
+__device__ inline void mma_step(const bf8 (&af)[2][2 * (AC ? 2 : 1)], const bf8 (&bfr)[2][2 * (BC ? 2 : 1)],
+                                f16 (&accr)[2][2], f16 (&acci)[2][2]) {
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const int ha = t == 2 ? 1 : 0, hb = t == 1 ? 1 : 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) accr[i][j] = mma(af[i][ha], bfr[j][hb], accr[i][j]);
+    if (BC) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acci[i][j] = mma(af[i][ha], bfr[j][2 + hb], acci[i][j]);
+    }
+    if (AC) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acci[i][j] = mma(af[i][2 + ha], bfr[j][hb], acci[i][j]);
+    }
+    if (AC && BC) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accr[i][j] = mma(neg(af[i][2 + ha]), bfr[j][2 + hb], accr[i][j]);
+    }
+  }
+}
+
+template <int N>
+__device__ inline void wait_vmcnt() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// Fragments (16 bytes per lane) from LDS: NA at byte addresses ba + OA[i] and NB at bb + OB[i], read
+// in one asm block that waits for them before it ends. The compiler does not see these reads, so it
+// puts none of its own waits for the direct-to-LDS loads in front of them (it cannot tell the ring
+// buffers apart and would drain every load in flight); the kernel orders them with its explicit waits
+// and barriers. The offsets are template arguments (ds_read_b128 immediates).
+#define RTCC_DSR(o, a, n) "ds_read_b128 %" #o ", %" #a " offset:%" #n "\n"
+template <int A0, int A1, int A2, int A3, int A4, int A5, int A6, int A7, int B0, int B1, int B2, int B3>
+__device__ inline void lds_read_8_4(unsigned ba, unsigned bb, u4 (&a)[8], u4 (&b)[4]) {
+  asm volatile(RTCC_DSR(0, 12, 14) RTCC_DSR(1, 12, 15) RTCC_DSR(2, 12, 16) RTCC_DSR(3, 12, 17) RTCC_DSR(4, 12, 18)
+                   RTCC_DSR(5, 12, 19) RTCC_DSR(6, 12, 20) RTCC_DSR(7, 12, 21) RTCC_DSR(8, 13, 22) RTCC_DSR(9, 13, 23)
+                       RTCC_DSR(10, 13, 24) RTCC_DSR(11, 13, 25) "s_waitcnt lgkmcnt(0)"
+               : "=&v"(a[0]), "=&v"(a[1]), "=&v"(a[2]), "=&v"(a[3]), "=&v"(a[4]), "=&v"(a[5]), "=&v"(a[6]),
+                 "=&v"(a[7]), "=&v"(b[0]), "=&v"(b[1]), "=&v"(b[2]), "=&v"(b[3])
+               : "v"(ba), "v"(bb), "n"(A0), "n"(A1), "n"(A2), "n"(A3), "n"(A4), "n"(A5), "n"(A6), "n"(A7), "n"(B0),
+                 "n"(B1), "n"(B2), "n"(B3));
+}
+template <int O0, int O1, int O2, int O3, int O4, int O5, int O6, int O7>
+__device__ inline void lds_read_8(unsigned base, u4 (&a)[8]) {
+  asm volatile(RTCC_DSR(0, 8, 9) RTCC_DSR(1, 8, 10) RTCC_DSR(2, 8, 11) RTCC_DSR(3, 8, 12) RTCC_DSR(4, 8, 13)
+                   RTCC_DSR(5, 8, 14) RTCC_DSR(6, 8, 15) RTCC_DSR(7, 8, 16) "s_waitcnt lgkmcnt(0)"
+               : "=&v"(a[0]), "=&v"(a[1]), "=&v"(a[2]), "=&v"(a[3]), "=&v"(a[4]), "=&v"(a[5]), "=&v"(a[6]),
+                 "=&v"(a[7])
+               : "v"(base), "n"(O0), "n"(O1), "n"(O2), "n"(O3), "n"(O4), "n"(O5), "n"(O6), "n"(O7));
+}
+#undef RTCC_DSR
+
+
+// DMA-ring kernel. LDS holds NBUF stage images, each the plain copy of the stage's packed tiles: A
+// planes [PA][2][128][8] then B planes [PB][2][BN][8] (bf16). Each wave copies D 1 KB pieces of a stage
+// with 16-byte direct-to-LDS loads (lane l: bytes 16 l .. 16 l + 15 of the piece). Stage s + NBUF - 1
+// is requested right after the barrier of stage s, into the buffer stage s - 1 used; before that
+// barrier each wave waits until at most the loads of the later stages it has requested are still in
+// flight (s_waitcnt counts one wave's memory instructions in order), so after the barrier every
+// wave's share of stage s is in LDS. The main loop is unrolled by NBUF so every buffer index is a
+// constant.
+template <int AC, int BC, int LADDER, int WN>
+__global__ __launch_bounds__(128 * WN) void gemm_bf16x3_dma(Params p) {
+  constexpr int kThr = 128 * WN, kBN = 64 * WN, NW = kThr / 64;
+  constexpr int NA = AC ? 2 : 1, NB = BC ? 2 : 1;
+  constexpr int PA = 2 * NA, PB = 2 * NB;
+  constexpr int SK = 16;
+  constexpr int ACH = PA * 2 * kBM, BCH = PB * 2 * kBN;  // 16-byte pieces per stage
+  constexpr int SB = (ACH + BCH) * 16;                   // stage bytes
+  constexpr int NBUF = (160 * 1024) / SB >= 4 ? 4 : 3;
+  static_assert(SB * NBUF <= 160 * 1024, "LDS ring too large");
+  constexpr int NI = (ACH + BCH) / 64;  // 1 KB loads per stage
+  static_assert(NI % NW == 0 && (ACH / 64) * 64 == ACH, "stage does not divide among the waves");
+  constexpr int D = NI / NW;            // loads per wave and stage
+  __shared__ __attribute__((aligned(1024))) char ring[NBUF][SB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  int split, tm, tn;
+  tile_of(blockIdx.x, p, &split, &tm, &tn);
+  const int m0 = tm * kBM, n0 = tn * kBN;
+  const int kbeg = split * p.kchunk, kend = min(p.Kp, kbeg + p.kchunk);
+  const int nst = (kend - kbeg) / SK;
+
+  // source of this wave's load d (piece j = wave * D + d): plane, half and first row of a 64-row run
+  const __bf16* src[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int j = wave * D + d, q = j * 64;  // first piece of the load
+    if (q < ACH) {
+      const int pl = q / (2 * kBM), h = (q / kBM) & 1, r = q % kBM;
+      src[d] = p.A + pl * p.pa + ((int64_t)h * p.Mp + m0 + r + lane) * 8;
+    } else {
+      const int qb = q - ACH;
+      const int pl = qb / (2 * kBN), h = (qb / kBN) & 1, r = qb % kBN;
+      src[d] = p.B + pl * p.pb + ((int64_t)h * p.Np + n0 + r + lane) * 8;
+    }
+  }
+  // k block kb of a plane starts 2 kb rows-of-halves later
+  const int64_t stepA = (int64_t)2 * p.Mp * 8, stepB = (int64_t)2 * p.Np * 8;
+  auto request = [&](int st, char* buf) {
+    const int64_t kb = kbeg / SK + st;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int j = wave * D + d;
+      const __bf16* g = src[d] + kb * (j * 64 < ACH ? stepA : stepB);
+      __builtin_amdgcn_global_load_lds((const void*)g, (lds_ptr)(buf + j * 1024), 16, 0, 0);
+    }
+  };
+
+  f16 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        accr[i][j][e] = 0.f;
+        acci[i][j][e] = 0.f;
+      }
+
+  const int l32 = lane & 31, hh = lane >> 5;
+#pragma unroll
+  for (int u = 0; u < NBUF - 1; ++u)
+    if (u < nst) request(u, ring[u]);
+  for (int base = 0; base < nst; base += NBUF) {
+#pragma unroll
+    for (int u = 0; u < NBUF; ++u) {
+      const int s = base + u;
+      if (s < nst) {
+        // loads of later stages this wave may leave in flight: min(NBUF - 2, nst - 1 - s) stages
+        const int later = min(NBUF - 2, nst - 1 - s);
+        if (later >= 2) wait_vmcnt<2 * D>();
+        else if (later == 1) wait_vmcnt<D>();
+        else wait_vmcnt<0>();
+        asm volatile("s_barrier" ::: "memory");
+        if (s + NBUF - 1 < nst) request(s + NBUF - 1, ring[(u + NBUF - 1) % NBUF]);
+        // fragment (i, pl) of A at byte ((pl * 2 + hh) * 128 + wm * 64 + i * 32 + l32) * 16 of the buffer,
+        // (j, pl) of B at ACH * 16 + ((pl * 2 + hh) * BN + wn * 64 + j * 32 + l32) * 16
+        const unsigned ba = (unsigned)(uintptr_t)(lds_ptr)ring[u] + (unsigned)((hh * kBM + wm * 64 + l32) * 16);
+        const unsigned bb =
+            (unsigned)(uintptr_t)(lds_ptr)ring[u] + (unsigned)(ACH * 16 + (hh * kBN + wn * 64 + l32) * 16);
+        constexpr int PLA = 2 * kBM * 16, PLB = 2 * kBN * 16;  // bytes per packed plane in a stage
+        // fragment arrays ordered [block][plane]: A (i, pl) at i * PA + pl, B (j, pl) at j * PB + pl
+        u4 fa[2 * PA], fb[2 * PB];
+        if constexpr (PA == 4 && PB == 2) {
+          lds_read_8_4<0, PLA, 2 * PLA, 3 * PLA, 512, PLA + 512, 2 * PLA + 512, 3 * PLA + 512, 0, PLB, 512,
+                       PLB + 512>(ba, bb, fa, fb);
+        } else if constexpr (PA == 2 && PB == 4) {
+          lds_read_8_4<0, PLB, 2 * PLB, 3 * PLB, 512, PLB + 512, 2 * PLB + 512, 3 * PLB + 512, 0, PLA, 512,
+                       PLA + 512>(bb, ba, fb, fa);
+        } else {
+          lds_read_8<0, PLA, 2 * PLA, 3 * PLA, 512, PLA + 512, 2 * PLA + 512, 3 * PLA + 512>(ba, fa);
+          lds_read_8<0, PLB, 2 * PLB, 3 * PLB, 512, PLB + 512, 2 * PLB + 512, 3 * PLB + 512>(bb, fb);
+        }
+        bf8 af[2][PA], bfr[2][PB];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int pl = 0; pl < PA; ++pl) af[i][pl] = __builtin_bit_cast(bf8, fa[i * PA + pl]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int pl = 0; pl < PB; ++pl) bfr[j][pl] = __builtin_bit_cast(bf8, fb[j * PB + pl]);
+        mma_step<AC, BC>(af, bfr, accr, acci);
+      }
+    }
+  }
+  store_tile<AC, BC>(p, accr, acci, split, m0 + wm * 64, n0 + wn * 64, lane);
+}
+
 // LADDER = 1: the same kernel under a name of its own for the particle-particle ladder.
 // WN waves along N (2 or 4): a 128 x 64 WN tile, 128 WN threads.
 template <int AC, int BC, int LADDER, int WN>
@@ -219,16 +459,15 @@ __global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p) {
   const int brow = tid % kBN, bq = tid / kBN;
   const int arow = tid & 127, aq = (tid >> 7) & 1, apl = tid >> 8;
   u4 ra[NRA], rb[PB];
-  // k-blocked planes: stage k0 of rows r0.. is the contiguous run at (k0 / 16) * R * 16 + r0 * 16
-  const int64_t sa = (int64_t)p.Mp * SK, sb = (int64_t)p.Np * SK;
+  // half-major k blocks: half h of row r in k block kb at ((2 kb + h) * R + r) * 8
   auto fetch = [&](int k0) {
     const int64_t kb = k0 / SK;
 #pragma unroll
     for (int q = 0; q < NRA; ++q)
-      ra[q] = *reinterpret_cast<const u4*>(p.A + (apl + AST * q) * p.pa + kb * sa + (int64_t)(m0 + arow) * SK + 8 * aq);
+      ra[q] = *reinterpret_cast<const u4*>(p.A + (apl + AST * q) * p.pa + ((2 * kb + aq) * p.Mp + m0 + arow) * 8);
 #pragma unroll
     for (int pl = 0; pl < PB; ++pl)
-      rb[pl] = *reinterpret_cast<const u4*>(p.B + pl * p.pb + kb * sb + (int64_t)(n0 + brow) * SK + 8 * bq);
+      rb[pl] = *reinterpret_cast<const u4*>(p.B + pl * p.pb + ((2 * kb + bq) * p.Np + n0 + brow) * 8);
   };
   auto stash = [&](int buf) {
 #pragma unroll
@@ -259,33 +498,7 @@ __global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p) {
 #pragma unroll
       for (int pl = 0; pl < PB; ++pl)
         bfr[j][pl] = *reinterpret_cast<const bf8*>(&Bs[buf][(pl * kBN + wn * 64 + j * 32 + l32) * LDK + hk]);
-    // three split products: (hi, hi), (hi, lo), (lo, hi); packed plane index 2c + h
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const int ha = t == 2 ? 1 : 0, hb = t == 1 ? 1 : 0;
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) accr[i][j] = mma(af[i][ha], bfr[j][hb], accr[i][j]);
-      if (BC) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acci[i][j] = mma(af[i][ha], bfr[j][2 + hb], acci[i][j]);
-      }
-      if (AC) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acci[i][j] = mma(af[i][2 + ha], bfr[j][hb], acci[i][j]);
-      }
-      if (AC && BC) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) accr[i][j] = mma(neg(af[i][2 + ha]), bfr[j][2 + hb], accr[i][j]);
-      }
-    }
+    mma_step<AC, BC>(af, bfr, accr, acci);
     // next stage into the other buffer (last read before the previous barrier), then prefetch
     if (s + 1 < nst) {
       stash(buf ^ 1);
@@ -294,55 +507,14 @@ __global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p) {
     __syncthreads();
   }
 
-  // With beta != 0 the old C values of each 32 x 32 block are all loaded before its stores (a store
-  // may alias a later load, so loads interleaved with stores would each wait a full memory latency).
-  constexpr bool CC = AC || BC;
-  const bool acc = !p.split_stride && p.beta != 0.f;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      float oldr[16], oldi[16];
-      if (acc) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          const int col = n0 + wn * 64 + j * 32 + l32;
-          const bool ok = row < p.M && col < p.N;
-          const int64_t off = (int64_t)row * p.ldc + col;
-          oldr[r] = ok ? p.Cre[off] : 0.f;
-          oldi[r] = (CC && ok) ? p.Cim[off] : 0.f;
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int col = n0 + wn * 64 + j * 32 + l32;
-        if (row >= p.M || col >= p.N) continue;
-        const float vr = accr[i][j][r], vi = acci[i][j][r];
-        if (p.split_stride) {
-          const int64_t off = (int64_t)split * p.split_stride + (int64_t)row * p.N + col;
-          p.Cre[off] = vr;
-          if (CC) p.Cim[off] = vi;
-        } else {
-          const int64_t off = (int64_t)row * p.ldc + col;
-          float outr = p.alpha * vr, outi = p.alpha * vi;
-          if (acc) {
-            outr += p.beta * oldr[r];
-            outi += p.beta * oldi[r];
-          }
-          p.Cre[off] = outr;
-          if (CC) p.Cim[off] = outi;
-        }
-      }
-    }
+  store_tile<AC, BC>(p, accr, acci, split, m0 + wm * 64, n0 + wn * 64, lane);
 }
 
 }  // namespace
 
 // Returns false (nothing launched) for real x real products or a real output.
 bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<float> A, GemmOp<float> B,
-                 float* Cre, float* Cim, int64_t ldc, double beta) {
+                 float* Cre, float* Cim, int64_t ldc, double beta, int force_wn, int force_splits, int force_kernel) {
   if (M <= 0 || N <= 0 || K <= 0) return false;
   const bool AC = A.im != nullptr, BC = B.im != nullptr;
   if (!Cim && (AC || BC)) return false;
@@ -351,7 +523,8 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   size_t mark = E.scratch.used;
   // 2 x 4 waves (128 x 256 tiles); outputs too small for 16 such tiles (e.g. 400 x 400) use 2 x 2 waves
   // (128 x 128), which doubles their tile count (measured: 41-55 -> 28-41 us at 400 x 400 x 5776)
-  const int WN = cdiv(M, kBM) * cdiv(N, 256) < 16 ? 2 : 4, kBN = 64 * WN;
+  RTCC_CHECK(force_wn == 0 || force_wn == 2 || force_wn == 4, kEInval, "gemm_bf16x3: waves along N must be 2 or 4");
+  const int WN = force_wn ? force_wn : cdiv(M, kBM) * cdiv(N, 256) < 16 ? 2 : 4, kBN = 64 * WN;
   // A as [M][K] rows; B as [N][K] rows (B(k, n) = trans ? b[n * ld + k] : b[k * ld + n])
   const Packed pa = pack_operand(E, A.re, A.im, A.ld, A.trans, M, K, A.konst, kRowPad);
   const Packed pb = pack_operand(E, B.re, B.im, B.ld, B.trans ? 0 : 1, N, K, B.konst, kBN);
@@ -392,6 +565,7 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
       splits = sp;
     }
   }
+  if (force_splits > 0) splits = (int)std::min<int64_t>(force_splits, std::max(stages, 1));
   const int per = (int)cdiv(stages, splits);
   p.kchunk = per * kBK;
   splits = (int)cdiv(stages, per);
@@ -414,7 +588,21 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   const bool lad = E.ladder != 0;
   if (lad && E.mark) E.mark(E.mark_user, 0, E.ladder_flops, E.stream);
   const dim3 block(128 * WN);
-  if (WN == 4) {
+  const int kern = force_kernel ? force_kernel : E.bf16_kernel;
+  RTCC_CHECK(kern == 1 || kern == 2, kEInval, "gemm_bf16x3: unknown kernel variant");
+  if (kern == 2) {
+    if (WN == 4) {
+      if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 1, 4>), grid, block, 0, E.stream, p);
+      else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 1, 0, 4>), grid, block, 0, E.stream, p);
+      else if (AC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 0, 4>), grid, block, 0, E.stream, p);
+      else hipLaunchKernelGGL((gemm_bf16x3_dma<0, 1, 0, 4>), grid, block, 0, E.stream, p);
+    } else {
+      if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 1, 2>), grid, block, 0, E.stream, p);
+      else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 1, 0, 2>), grid, block, 0, E.stream, p);
+      else if (AC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 0, 2>), grid, block, 0, E.stream, p);
+      else hipLaunchKernelGGL((gemm_bf16x3_dma<0, 1, 0, 2>), grid, block, 0, E.stream, p);
+    }
+  } else if (WN == 4) {
     if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 1, 4>), grid, block, 0, E.stream, p);
     else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1, 0, 4>), grid, block, 0, E.stream, p);
     else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 0, 4>), grid, block, 0, E.stream, p);
@@ -431,9 +619,9 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   E.scratch.reset(mark);
   E.gemm_flops += 2 * M * N * K * ((AC && BC) ? 4 : 2);
   if (E.trace)
-    fprintf(stderr, "[rtcc] gemm-bf16x3 M=%lld N=%lld K=%lld %s%s ta=%d tb=%d splits=%d konst=%d%d\n", (long long)M,
-            (long long)N, (long long)K, AC ? "c" : "r", BC ? "c" : "r", A.trans, B.trans, splits, (int)A.konst,
-            (int)B.konst);
+    fprintf(stderr, "[rtcc] gemm-bf16x3 M=%lld N=%lld K=%lld %s%s ta=%d tb=%d wn=%d splits=%d kernel=%d konst=%d%d\n",
+            (long long)M, (long long)N, (long long)K, AC ? "c" : "r", BC ? "c" : "r", A.trans, B.trans, WN, splits, kern,
+            (int)A.konst, (int)B.konst);
   return true;
 }
 

@@ -147,3 +147,35 @@ def test_linear_response_scaling():
         ys = _propagate(S, pack_state(*kicked), 0.05, 20, lambda t: np.zeros(3))
         ind.append((ccsd.dipole(S, *unpack_state(ys[-1], o, v))[2].real - mu_gs) / kappa)
     assert abs(ind[0] - ind[1]) < 2e-3 * abs(ind[1]) + 1e-9
+
+
+def _strong_field_case():
+    """(2,4) ground state in a strong Gaussian pulse: E0 = 100 au, sigma = 0.05 au, centre 0.25 au."""
+    o, v = 2, 4
+    S, amps, _ = _ground(o, v)
+    y0 = pack_state(*amps)
+    E0, sig, nu = 100.0, 0.05, 0.25
+    f = lambda t, yy: pack_state(*ccsd.rhs(S, *unpack_state(yy, o, v),
+                                           field.gaussian(t, E0, 0.0, sig, nu, [0, 0, 1])))
+    t2norm = lambda yy: float(np.linalg.norm(unpack_state(yy, o, v)[1]))
+    return f, y0, t2norm, (nu - 5 * sig, nu + 5 * sig)
+
+
+def test_strong_field_rk4_diverges_and_mixed_step_is_stable():
+    """Paper (Results, strong fields): RK4 with h = 0.01 au diverges in a 100 au pulse, while small steps
+    during the pulse (h1) and the usual h2 after it give a bounded |T2|."""
+    f, y0, t2norm, on = _strong_field_case()
+    y, norms = y0.copy(), []
+    with np.errstate(all="ignore"):
+        for k in range(50):
+            y = integrators.rk4_step(f, 0.01 * k, y, 0.01)
+            norms.append(t2norm(y))
+            if not np.isfinite(norms[-1]) or norms[-1] > 1e6:
+                break
+    assert not (np.isfinite(norms[-1]) and norms[-1] <= 1e6), "plain RK4 at h = 0.01 should diverge"
+    plan = integrators.mixed_step_plan(0.0, 0.6, 1e-3, 0.01, on)
+    assert abs(sum(h for _, h in plan) - 0.6) < 1e-12
+    assert all(abs(h - 1e-3) < 1e-15 for t, h in plan if on[0] <= t < on[1] - 1e-3)
+    norms = []
+    integrators.rk4_propagate_plan(f, y0, plan, lambda k, t, yy: norms.append(t2norm(yy)))
+    assert np.all(np.isfinite(norms)) and max(norms) < 1e3
