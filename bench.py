@@ -393,6 +393,8 @@ def main():
     ap.add_argument("--t-end", type=float, default=100.0, help="spectrum workload: propagation length (au)")
     ap.add_argument("--eps", type=float, default=1e-6, help="spectrum workload: Cash-Karp tolerance")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3",
+                    help="single workload: the precisions to run (profiling one at a time); the JSON line needs all three")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library evaluates each "
@@ -433,7 +435,8 @@ def main():
     W, K = args.warmup, args.steps
     G = max(args.gate_steps, W + K)
     results, traj, finals = {}, {}, {}
-    for prec in ("fp64", "fp32", "bf16x3"):
+    precs = args.precisions.split(",")
+    for prec in precs:
         R.set_precision(prec)
         y = y0.clone()
         m = torch.zeros((G + 1, 6), dtype=torch.float64, device="cuda")
@@ -471,6 +474,9 @@ def main():
         finals[prec] = y
         log(f"[bench] {prec}: {results[prec]}")
 
+    if set(precs) != {"fp64", "fp32", "bf16x3"}:
+        log("[bench] not all precisions ran: no JSON line")
+        return
     fp32_err = float(np.abs(traj["fp32"] - traj["fp64"]).max())
     bf16_err = float(np.abs(traj["bf16x3"] - traj["fp64"]).max())
     y64 = finals["fp64"]

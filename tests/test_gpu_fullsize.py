@@ -2,7 +2,10 @@
 the launch configuration the benchmark times: captured RK4 steps, the right-hand side on three streams.
 
 The spin-orbital oracle cannot evaluate a right-hand side at this size inside a test (its
-antisymmetrised integrals alone take ~11 GB), so these tests check what holds at any size:
+antisymmetrised integrals alone take ~11 GB and one evaluation minutes of host time), so one
+oracle right-hand side was evaluated by tests/golden/make_fullsize.py and a seeded sample of its
+entries (all singles, 4096 doubles) is compared with the library's, element by element. The other
+tests check what holds at any size:
 
 * the FP64 path (pinned to the oracle element by element at the smaller sizes) against the same
   right-hand side in FP32 and split-BF16, to the rounding bounds the parity tests use (3e-5 and 3e-4
@@ -41,6 +44,34 @@ def _rel(a, b):
 def _pair_asym(d, scale):
     t2, l2 = d[1], d[3]
     return max(np.abs(t2 - t2.transpose(1, 0, 3, 2)).max(), np.abs(l2 - l2.transpose(1, 0, 3, 2)).max()) / scale
+
+
+def test_fullsize_rhs_matches_oracle_samples(system):
+    """FP64 1e-11, FP32 3e-5 and split-BF16 (default settings: the production kernels) 3e-4, relative to
+    the largest entry of the oracle's right-hand side."""
+    import json
+    import os
+    import torch
+    from paper_2205_05175_amd import RTCC
+    path = os.path.join(os.path.dirname(__file__), "golden", "rhs_o20v76_samples.json")
+    g = json.load(open(path))
+    c = g["case"]
+    assert (c["o"], c["v"], c["seed"]) == (O, V, 0)
+    idx = np.array(g["index"])
+    ref = np.array(g["value"])
+    ref = ref[:, 0] + 1j * ref[:, 1]
+    scale = g["max_abs_all"]
+    print(f"full-size rhs vs {idx.size} oracle samples", flush=True)
+    eri, fock, mu = system
+    R = RTCC(eri, fock, mu, O, V, "fp32")
+    y = torch.tensor(pack_state(*random_state(O, V, c["state_seed"], c["scale1"], c["scale2"])), device="cuda")
+    for prec, tol in (("fp64", 1e-11), ("fp32", 3e-5), ("bf16x3", 3e-4)):
+        R.set_precision(prec)
+        out = R.rhs(y, c["E"]).cpu().numpy()
+        err = np.abs(out[idx] - ref).max() / scale
+        print(f"  {prec}: max rel error over the samples {err:.3e}")
+        assert err < tol
+    R.close()
 
 
 def test_fullsize_rhs_precisions_and_pair_symmetry(system):
