@@ -269,6 +269,17 @@ int rtcc_gemm(int precision, int64_t M, int64_t N, int64_t K, double alpha, cons
  * (not batched, M, N > 1) then use the listed kernel. *nentries (HOST, may be NULL) = entries read. */
 int rtcc_load_tuning(const char* path, int* nentries);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the check of rtcc_check_state without a context and without
+ * synchronising. For a state y (DEVICE, the layout above for o, v) it writes out_dev[0] = |T2| (the
+ * Frobenius norm of the T2 block; NaN if y has a non-finite entry) and out_dev[1] = the number of
+ * non-finite complex entries of y (out_dev: DEVICE, 2 doubles), enqueued on hip_stream. Nothing is
+ * allocated: the only scratch, 8 KB of reduction partials, is a static device array of the library,
+ * one copy per GPU, held until the process ends; its contents need no clearing (every call overwrites
+ * the partials it reads), and calls that overlap on one GPU race on it. Returns RTCC_EINVAL for o or
+ * v < 1, null pointers or o v > 2^20 (the message is rtcc_last_error(NULL)). */
+int rtcc_check_state_noalloc(int o, int v, const void* y, double* out_dev, void* hip_stream);
+
 void rtcc_destroy(rtcc_ctx* ctx);
 const char* rtcc_last_error(const rtcc_ctx* ctx);
 

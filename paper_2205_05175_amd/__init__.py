@@ -64,6 +64,7 @@ def load_library(path: str = LIB_PATH):
     L.rtcc_gemm.argtypes = [i, i64, i64, i64, d, vp, vp, i64, i, vp, vp, i64, i, d, vp, vp, i64,
                             ctypes.POINTER(i), i, ctypes.POINTER(ctypes.c_float), vp]
     L.rtcc_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(i)]
+    L.rtcc_check_state_noalloc.argtypes = [i, i, vp, vp, vp]
     L.rtcc_mixed_schedule.argtypes = [d, d, d, d, ctypes.POINTER(Field), i, dp, ctypes.POINTER(i)]
     L.rtcc_propagate_rk4_mixed.argtypes = [vp, vp, d, d, d, d, ctypes.POINTER(Field), vp, vp]
     L.rtcc_propagate_cashkarp.argtypes = [vp, vp, d, d, d, d, ctypes.POINTER(Field), i, i, dp, dp,
@@ -95,7 +96,7 @@ def load_library(path: str = LIB_PATH):
 EXPORTED = ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
             "rtcc_propagate_batch", "rtcc_rhs_vjp", "rtcc_dipole_vjp", "rtcc_step_rk4_vjp", "rtcc_step_cashkarp",
             "rtcc_set_guard", "rtcc_mixed_schedule", "rtcc_propagate_rk4_mixed", "rtcc_propagate_cashkarp",
-            "rtcc_gemm", "rtcc_load_tuning",
+            "rtcc_gemm", "rtcc_load_tuning", "rtcc_check_state_noalloc",
             "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick", "rtcc_check_state", "rtcc_info",
             "rtcc_profile", "rtcc_profile_read", "rtcc_destroy", "rtcc_last_error")
 
@@ -363,6 +364,21 @@ def mixed_schedule(t0, t_end, h1, h2, field=None):
     if rc != 0:
         raise RTCCError(rc, L.rtcc_last_error(None).decode())
     return times
+
+
+def check_state_noalloc(o, v, y, out, stream=None):
+    """rtcc_check_state_noalloc: out (float64 CUDA tensor, 2 entries) = (|T2|, non-finite count) of the
+    state y, enqueued on the stream without any allocation or synchronisation."""
+    import torch
+    L = load_library()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    if not (out.is_cuda and out.dtype == torch.float64 and out.numel() >= 2 and y.is_cuda and
+            y.dtype == torch.complex128 and y.numel() == state_size(o, v)):
+        raise ValueError("y must be a complex128 CUDA state of (o, v) and out a float64 CUDA tensor of 2 entries")
+    rc = L.rtcc_check_state_noalloc(int(o), int(v), ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise RTCCError(rc, L.rtcc_last_error(None).decode())
 
 
 def state_size(o, v):
