@@ -9,7 +9,8 @@ times of the winner and of the library's own rule as comments, into the tuning t
 kept only when it beats the library's own rule by more than ``--min-gain``.
 
 Candidates: the tile kernel in each of its tile / k-stage shapes with 1 to 64 K splits; for
-split-BF16 contexts also the split-BF16 kernel with 128 x 128 or 128 x 256 tiles and 1 to 16 splits.
+split-BF16 contexts also both split-BF16 kernels (register-staged, direct-to-LDS ring) with 128 x 128
+or 128 x 256 tiles and 1 to 16 splits.
 
 Usage: python -m paper_2205_05175_amd.autotune --o 20 --v 76 [--out FILE] [--precisions fp64,fp32,bf16x3]
 """
@@ -38,22 +39,28 @@ _LINE = re.compile(r"\[rtcc\] gemm(-bf16x3)? M=(\d+) N=(\d+) K=(\d+)(?: batch=(\
 _CHILD = r"""
 import sys, numpy as np, torch
 sys.path.insert(0, sys.argv[1])
-from paper_2205_05175_amd import RTCC
+from paper_2205_05175_amd import RTCC, Field, propagate_batch
 from synth import make_system, pack_state, random_state
-o, v, prec = int(sys.argv[2]), int(sys.argv[3]), sys.argv[4]
+o, v, prec, nb = int(sys.argv[2]), int(sys.argv[3]), sys.argv[4], int(sys.argv[5])
 R = RTCC(*make_system(o, v, 0), o, v, prec)
-y = torch.tensor(pack_state(*random_state(o, v, 3)), device="cuda")
-R.rhs(y, [0.001, 0.0, 0.002])
+if nb == 0:
+    y = torch.tensor(pack_state(*random_state(o, v, 3)), device="cuda")
+    R.rhs(y, [0.001, 0.0, 0.002])
+else:
+    # one batched RK4 step of nb members (eager launches: every product is traced)
+    ys = torch.tensor(np.stack([pack_state(*random_state(o, v, 3 + m)) for m in range(nb)]), device="cuda")
+    propagate_batch([R], [ys], [[Field.none() for _ in range(nb)]], 0.0, 0.02, 1, None)
 torch.cuda.synchronize()
 """
 
 
-def collect_shapes(o, v, prec):
-    """(M, N, K, ac, bc, ta, tb) of the non-batched GEMMs of one right-hand side in precision prec."""
-    env = dict(os.environ, RTCC_TRACE="1", RTCC_NO_TUNING="1")
+def collect_shapes(o, v, prec, batch=0):
+    """(M, N, K, ac, bc, ta, tb) of the non-batched GEMMs of one right-hand side in precision prec (with
+    batch > 0: of one batched RK4 step of that many members, whose member-folded products are single GEMMs)."""
+    env = dict(os.environ, RTCC_TRACE="1", RTCC_NO_TUNING="1", RTCC_NO_GRAPH="1")
     root = os.path.dirname(HERE)
-    r = subprocess.run([sys.executable, "-c", _CHILD, root, str(o), str(v), prec], env=env, capture_output=True,
-                       text=True, timeout=900)
+    r = subprocess.run([sys.executable, "-c", _CHILD, root, str(o), str(v), prec, str(batch)], env=env,
+                       capture_output=True, text=True, timeout=900)
     if r.returncode != 0:
         raise RuntimeError(f"shape collection failed:\n{r.stderr[-2000:]}")
     shapes = {}
@@ -118,11 +125,12 @@ def candidates(prec, shape):
                 continue
             out.append((1, mn, bk, s))
     if prec == "bf16x3" and (ac or bc) and 2.0 * M * N * K >= 1e8:
-        for wn in (2, 4):
-            for s in range(1, 17):
-                if s > 1 and K // s < 64:
-                    continue
-                out.append((2, wn, 0, s))
+        for kern in (1, 2):  # register-staged, direct-to-LDS ring
+            for wn in (2, 4):
+                for s in range(1, 17):
+                    if s > 1 and K // s < 64:
+                        continue
+                    out.append((2, wn, kern, s))
     return out
 
 
@@ -146,6 +154,7 @@ def main():
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3")
     ap.add_argument("--out", default=DEFAULT_TABLE)
     ap.add_argument("--min-gain", type=float, default=0.03)
+    ap.add_argument("--batch", type=int, default=0, help="tune the products of a batched step of this many members")
     args = ap.parse_args()
     import torch
     from paper_2205_05175_amd import load_library
@@ -159,8 +168,8 @@ def main():
                 keep[tuple(int(x) for x in body[:8])] = line.rstrip("\n")
     total_gain = 0.0
     for prec in args.precisions.split(","):
-        shapes = collect_shapes(args.o, args.v, prec)
-        print(f"[autotune] ({args.o},{args.v}) {prec}: {len(shapes)} GEMM shapes", flush=True)
+        shapes = collect_shapes(args.o, args.v, prec, args.batch)
+        print(f"[autotune] ({args.o},{args.v}) x{max(args.batch, 1)} {prec}: {len(shapes)} GEMM shapes", flush=True)
         for shape, count in sorted(shapes.items()):
             t1 = time.time()
             base, (best_t, c) = tune_shape(L, prec, shape)
@@ -171,8 +180,9 @@ def main():
                    f"x{count}: rule {1e3 * base:.1f} us, best {1e3 * best_t:.1f} us {c} ({time.time() - t1:.1f} s)")
             print(msg, flush=True)
             if c[0] != 0 and gain > args.min_gain:
+                tag = f"({args.o},{args.v})" + (f" x{args.batch} members" if args.batch else "")
                 keep[key] = (" ".join(str(x) for x in key) + " " + " ".join(str(x) for x in c) +
-                             f"  # ({args.o},{args.v}) x{count}: {1e3 * best_t:.1f} us vs rule {1e3 * base:.1f} us")
+                             f"  # {tag}, {count} per call: {1e3 * best_t:.1f} us vs rule {1e3 * base:.1f} us")
                 total_gain += count * (base - best_t)
             else:
                 keep.pop(key, None)

@@ -401,6 +401,7 @@ void* memo_get(Engine& E, const std::string& key, size_t bytes, bool* hit) {
 }
 
 void fork_branches(Engine& E) {
+  RTCC_CHECK(E.br[0] && E.br[1] && E.ev_fork, kEInval, "fork_branches: engine has no branch engines");
   RTCC_HIP(hipEventRecord(E.ev_fork, E.stream));
   for (Engine* b : E.br) {
     b->cache = E.cache;
@@ -418,6 +419,7 @@ void fork_branches(Engine& E) {
 }
 
 void join_branches(Engine& E) {
+  RTCC_CHECK(E.br[0] && E.br[1], kEInval, "join_branches: engine has no branch engines");
   for (int k = 0; k < 2; ++k) {
     RTCC_HIP(hipEventRecord(E.ev_join[k], E.br[k]->stream));
     RTCC_HIP(hipStreamWaitEvent(E.stream, E.ev_join[k], 0));
