@@ -377,10 +377,33 @@ def bench_spectrum(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_profile(args):
+    """Only the RK4 steps of one precision at (o, v), from a random non-stationary state (no ground state,
+    no kick, no oracle): the command to run under rocprofv3 so that its kernel summary holds the step's
+    kernels alone."""
+    import torch
+    from paper_2205_05175_amd import RTCC
+    from synth import make_system, pack_state, random_state
+    o, v = args.o, args.v
+    prec = args.precisions.split(",")[0]
+    R = RTCC(*make_system(o, v, 0), o, v, precision="fp32" if prec == "fp64" else prec)
+    R.set_precision(prec)
+    y = torch.tensor(pack_state(*random_state(o, v, 3, 0.01, 0.002)), device="cuda")
+    m = torch.zeros((args.warmup + args.steps + 2, 6), dtype=torch.float64, device="cuda")
+    R.propagate_rk4(y, 0.0, args.dt, args.warmup, None, m[:args.warmup + 1])
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    R.propagate_rk4(y, args.warmup * args.dt, args.dt, args.steps, None, m[args.warmup:args.warmup + args.steps + 1])
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    log(f"[bench] profile workload {prec} o={o} v={v}: {args.steps} RK4 steps in {te - ts:.3f} s "
+        f"({args.steps / (te - ts):.2f} steps/s), non-finite entries {R.check_state(y)}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["single", "spectrum", "batch", "adjoint"], default="single",
+    ap.add_argument("--workload", choices=["single", "spectrum", "batch", "adjoint", "profile"], default="single",
                     help="single: the o=20 v=76 propagation (default); spectrum: RK4 and Cash-Karp to t=100 au "
                          "with peak shifts; batch: 24 batched propagations; adjoint: pulse-parameter gradient at (10,38)")
     ap.add_argument("--steps", type=int, default=None)
@@ -411,6 +434,10 @@ def main():
         return bench_adjoint(args)
     if args.workload == "spectrum":
         return bench_spectrum(args)
+    if args.workload == "profile":
+        if args.steps is None:
+            args.steps = 3
+        return bench_profile(args)
     if args.steps is None:
         args.steps = 20
 

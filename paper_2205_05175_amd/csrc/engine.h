@@ -96,7 +96,7 @@ struct Memo {
 // own rule; 1: the FP32/FP64 tile kernel with a p1 / 1000 x p1 % 1000 output tile, k stage p2 and
 // `splits` K splits; 2: the split-BF16 kernel (FP32 operands) with p1 waves along N (2: 128 x 128
 // tiles, 4: 128 x 256), `splits` K splits (0: its cost model) and variant p2 (0: the engine's, 1:
-// register-staged, 2: direct-to-LDS ring).
+// register-staged, 2: direct-to-LDS ring, 3: the ring with 128 x 128 tiles, two workgroups per CU).
 struct GemmChoice {
   int kind = 0, p1 = 0, p2 = 0, splits = 0;
 };
@@ -124,7 +124,7 @@ struct Engine {
   bool trace = false;         // print every contraction's layout decisions to stderr
   bool bf16x3 = false;        // FP32 GEMMs above bf16_min_flops use the split-BF16 three-term kernel
   double bf16_min_flops = 5e8;
-  int bf16_kernel = 1;                  // split-BF16 kernel: 1 register-staged, 2 direct-to-LDS ring
+  int bf16_kernel = 1;  // split-BF16 kernel: 1 register-staged, 2 direct-to-LDS ring, 3 the ring at 2 per CU
   bool use_tuning = true;               // consult the tuning table (single, non-batched products)
   const GemmChoice* force = nullptr;    // this choice for every product (kernel tests, the autotuner)
   // Batch size of the tensors with bs != 0. Every contraction then runs for all members: a
@@ -180,8 +180,8 @@ template <typename T>
 void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A, GemmOp<T> B, T* Cre, T* Cim,
           int64_t ldc, double beta, GemmBatch bt = GemmBatch());
 
-// force_wn (2 or 4), force_splits (>= 1) and force_kernel (1 register-staged, 2 direct-to-LDS ring)
-// replace the library's own tile, split and kernel choice when non-zero.
+// force_wn (2 or 4), force_splits (>= 1) and force_kernel (1 register-staged, 2 direct-to-LDS ring, 3 the
+// ring with 128 x 128 tiles and two workgroups per CU) replace the library's own choices when non-zero.
 bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<float> A, GemmOp<float> B,
                  float* Cre, float* Cim, int64_t ldc, double beta, int force_wn = 0, int force_splits = 0,
                  int force_kernel = 0);

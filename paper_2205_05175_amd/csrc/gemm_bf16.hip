@@ -313,16 +313,19 @@ __device__ inline void lds_read_8(unsigned base, u4 (&a)[8]) {
 // flight (s_waitcnt counts one wave's memory instructions in order), so after the barrier every
 // wave's share of stage s is in LDS. The main loop is unrolled by NBUF so every buffer index is a
 // constant.
-template <int AC, int BC, int LADDER, int WN>
-__global__ __launch_bounds__(128 * WN) void gemm_bf16x3_dma(Params p) {
+// TWO = 1: at most half the LDS and 256 registers per lane, so that two workgroups share a CU (their
+// barriers are independent, so one's MFMAs run while the other waits at a stage boundary).
+template <int AC, int BC, int LADDER, int WN, int TWO>
+__global__ __launch_bounds__(128 * WN, 2) void gemm_bf16x3_dma(Params p) {
   constexpr int kThr = 128 * WN, kBN = 64 * WN, NW = kThr / 64;
   constexpr int NA = AC ? 2 : 1, NB = BC ? 2 : 1;
   constexpr int PA = 2 * NA, PB = 2 * NB;
   constexpr int SK = 16;
   constexpr int ACH = PA * 2 * kBM, BCH = PB * 2 * kBN;  // 16-byte pieces per stage
   constexpr int SB = (ACH + BCH) * 16;                   // stage bytes
-  constexpr int NBUF = (160 * 1024) / SB >= 4 ? 4 : 3;
-  static_assert(SB * NBUF <= 160 * 1024, "LDS ring too large");
+  constexpr int LDSB = TWO ? 80 * 1024 : 160 * 1024;
+  constexpr int NBUF = LDSB / SB >= 4 ? 4 : LDSB / SB >= 3 ? 3 : 2;
+  static_assert(SB * NBUF <= LDSB, "LDS ring too large");
   constexpr int NI = (ACH + BCH) / 64;  // 1 KB loads per stage
   static_assert(NI % NW == 0 && (ACH / 64) * 64 == ACH, "stage does not divide among the waves");
   constexpr int D = NI / NW;            // loads per wave and stage
@@ -524,7 +527,9 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   // 2 x 4 waves (128 x 256 tiles); outputs too small for 16 such tiles (e.g. 400 x 400) use 2 x 2 waves
   // (128 x 128), which doubles their tile count (measured: 41-55 -> 28-41 us at 400 x 400 x 5776)
   RTCC_CHECK(force_wn == 0 || force_wn == 2 || force_wn == 4, kEInval, "gemm_bf16x3: waves along N must be 2 or 4");
-  const int WN = force_wn ? force_wn : cdiv(M, kBM) * cdiv(N, 256) < 16 ? 2 : 4, kBN = 64 * WN;
+  const int kern = force_kernel ? force_kernel : E.bf16_kernel;
+  RTCC_CHECK(kern >= 1 && kern <= 3, kEInval, "gemm_bf16x3: unknown kernel variant");
+  const int WN = force_wn ? force_wn : kern == 3 || cdiv(M, kBM) * cdiv(N, 256) < 16 ? 2 : 4, kBN = 64 * WN;
   // A as [M][K] rows; B as [N][K] rows (B(k, n) = trans ? b[n * ld + k] : b[k * ld + n])
   const Packed pa = pack_operand(E, A.re, A.im, A.ld, A.trans, M, K, A.konst, kRowPad);
   const Packed pb = pack_operand(E, B.re, B.im, B.ld, B.trans ? 0 : 1, N, K, B.konst, kBN);
@@ -588,19 +593,23 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   const bool lad = E.ladder != 0;
   if (lad && E.mark) E.mark(E.mark_user, 0, E.ladder_flops, E.stream);
   const dim3 block(128 * WN);
-  const int kern = force_kernel ? force_kernel : E.bf16_kernel;
-  RTCC_CHECK(kern == 1 || kern == 2, kEInval, "gemm_bf16x3: unknown kernel variant");
-  if (kern == 2) {
+  RTCC_CHECK(kern != 3 || WN == 2, kEInval, "gemm_bf16x3: the two-per-CU kernel takes 128 x 128 tiles");
+  if (kern == 3) {  // 128 x 128 tiles, two workgroups per CU
+    if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 1, 2, 1>), grid, block, 0, E.stream, p);
+    else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 1, 0, 2, 1>), grid, block, 0, E.stream, p);
+    else if (AC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 0, 2, 1>), grid, block, 0, E.stream, p);
+    else hipLaunchKernelGGL((gemm_bf16x3_dma<0, 1, 0, 2, 1>), grid, block, 0, E.stream, p);
+  } else if (kern == 2) {
     if (WN == 4) {
-      if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 1, 4>), grid, block, 0, E.stream, p);
-      else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 1, 0, 4>), grid, block, 0, E.stream, p);
-      else if (AC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 0, 4>), grid, block, 0, E.stream, p);
-      else hipLaunchKernelGGL((gemm_bf16x3_dma<0, 1, 0, 4>), grid, block, 0, E.stream, p);
+      if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 1, 4, 0>), grid, block, 0, E.stream, p);
+      else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 1, 0, 4, 0>), grid, block, 0, E.stream, p);
+      else if (AC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 0, 4, 0>), grid, block, 0, E.stream, p);
+      else hipLaunchKernelGGL((gemm_bf16x3_dma<0, 1, 0, 4, 0>), grid, block, 0, E.stream, p);
     } else {
-      if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 1, 2>), grid, block, 0, E.stream, p);
-      else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 1, 0, 2>), grid, block, 0, E.stream, p);
-      else if (AC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 0, 2>), grid, block, 0, E.stream, p);
-      else hipLaunchKernelGGL((gemm_bf16x3_dma<0, 1, 0, 2>), grid, block, 0, E.stream, p);
+      if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 1, 2, 0>), grid, block, 0, E.stream, p);
+      else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 1, 0, 2, 0>), grid, block, 0, E.stream, p);
+      else if (AC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 0, 2, 0>), grid, block, 0, E.stream, p);
+      else hipLaunchKernelGGL((gemm_bf16x3_dma<0, 1, 0, 2, 0>), grid, block, 0, E.stream, p);
     }
   } else if (WN == 4) {
     if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 1, 4>), grid, block, 0, E.stream, p);
