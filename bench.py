@@ -316,6 +316,21 @@ def bench_spectrum(args):
         bad = R.check_state(y)
         mm = m.cpu().numpy()
         rk[prec] = {"mu": mm[:, 0::2] + 1j * mm[:, 1::2], "s": te, "nonfinite": bad}
+    sweep = {}
+    for eps_k in [float(x) for x in args.eps_sweep.split(",") if x]:
+        R.set_precision("bf16x3")
+        y = y0.clone()
+        t, h, nacc, nrej, times, mus = 0.0, 0.02, 0, 0, [0.0], [R.dipole(y)]
+        ts = time.perf_counter()
+        while t < T - 1e-12:
+            t1 = min(T, t + 10.0)
+            tt, mm, na, nr, h = R.propagate_cashkarp(y, t, t1, h, eps_k, cap=200000)
+            times += list(tt)
+            mus += list(mm)
+            nacc, nrej, t = nacc + na, nrej + nr, t1
+        log(f"[bench] cash-karp sweep eps={eps_k}: {nacc} accepted, {nrej} rejected")
+        sweep[eps_k] = {"t": np.array(times), "mu": np.array(mus), "acc": nacc, "rej": nrej,
+                        "s": time.perf_counter() - ts}
     for prec in ("fp64", "fp32", "bf16x3"):
         R.set_precision(prec)
         y = y0.clone()
@@ -352,13 +367,32 @@ def bench_spectrum(args):
         tg, dz = spc.resample_uniform(c["t"], induced(c["mu"][:, 2]), dt, t_end=T)
         n = min(tg.size, grid.size)
         cmpc, _, _ = spc.compare_trajectories(ref[:n], dz[:n], dt, kappa)
+        c64 = ck["fp64"]
+        _, dz64 = spc.resample_uniform(c64["t"], induced(c64["mu"][:, 2]), dt, t_end=T)
+        cmpp, _, _ = spc.compare_trajectories(dz64[:n], dz[:n], dt, kappa)
+        same_steps = c["t"].size == c64["t"].size and bool(np.abs(c["t"] - c64["t"]).max() < 1e-9)
         out["cashkarp"][prec] = {"accepted": c["acc"], "rejected": c["rej"], "rhs": 6 * (c["acc"] + c["rej"]),
                                  "wall_s": c["s"], "rhs_ratio_rk4_over_ck": 4 * nsteps / (6 * (c["acc"] + c["rej"])),
                                  "speedup_vs_rk4_same_precision": r["s"] / c["s"],
                                  "mean_h": T / max(c["acc"], 1),
+                                 "same_steps_as_fp64_ck": same_steps,
+                                 "dipole_max_abs_vs_fp64_ck": (float(np.abs(c["mu"] - c64["mu"]).max())
+                                                               if same_steps else None),
+                                 "peak_shift_max_vs_fp64_ck": cmpp.max_shift, "unmatched_vs_fp64_ck":
+                                     cmpp.unmatched_ref + cmpp.unmatched_other,
                                  "dipole_max_abs_vs_fp64_rk4_on_grid": float(np.abs(dz[:n] - ref[:n]).max()),
                                  "peak_shift_max_vs_fp64_rk4": cmpc.max_shift, "peaks_matched": len(cmpc.pairs),
                                  "unmatched_fp64": cmpc.unmatched_ref, "unmatched": cmpc.unmatched_other}
+    out["cashkarp_eps_sweep_bf16x3"] = {}
+    for eps_k, c in sweep.items():
+        tg, dz = spc.resample_uniform(c["t"], induced(c["mu"][:, 2]), dt, t_end=T)
+        n = min(tg.size, grid.size)
+        cm, _, _ = spc.compare_trajectories(ref[:n], dz[:n], dt, kappa)
+        out["cashkarp_eps_sweep_bf16x3"][str(eps_k)] = {
+            "accepted": c["acc"], "rejected": c["rej"], "rhs": 6 * (c["acc"] + c["rej"]), "wall_s": c["s"],
+            "rhs_ratio_rk4_over_ck": 4 * nsteps / (6 * (c["acc"] + c["rej"])),
+            "dipole_max_abs_vs_fp64_rk4_on_grid": float(np.abs(dz[:n] - ref[:n]).max()),
+            "peak_shift_max_vs_fp64_rk4": cm.max_shift, "unmatched": cm.unmatched_ref + cm.unmatched_other}
     w, S64 = spc.absorption(ref, dt, kappa)
     peaks = [p.omega for p in spc.find_peaks(w, S64)]
     head = out["rk4"]["bf16x3"]
@@ -371,7 +405,7 @@ def bench_spectrum(args):
                                f"delta kick {kappa} z, RK4 dt={dt} and Cash-Karp eps={eps} to t={T} au",
                    "parallelism": "single GPU"},
         "fp64_peaks_Eh": peaks,
-        "rk4": out["rk4"], "cashkarp": out["cashkarp"],
+        "rk4": out["rk4"], "cashkarp": out["cashkarp"], "cashkarp_eps_sweep_bf16x3": out["cashkarp_eps_sweep_bf16x3"],
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
@@ -396,6 +430,10 @@ def bench_profile(args):
     R.propagate_rk4(y, args.warmup * args.dt, args.dt, args.steps, None, m[args.warmup:args.warmup + args.steps + 1])
     torch.cuda.synchronize()
     te = time.perf_counter()
+    # one plain device copy of the state (2 * 16 * state entries bytes moved): the reference that scales
+    # the HBM traffic counters of the step's kernels
+    y.clone()
+    torch.cuda.synchronize()
     log(f"[bench] profile workload {prec} o={o} v={v}: {args.steps} RK4 steps in {te - ts:.3f} s "
         f"({args.steps / (te - ts):.2f} steps/s), non-finite entries {R.check_state(y)}")
 
@@ -415,6 +453,8 @@ def main():
     ap.add_argument("--dt", type=float, default=0.02)
     ap.add_argument("--t-end", type=float, default=100.0, help="spectrum workload: propagation length (au)")
     ap.add_argument("--eps", type=float, default=1e-6, help="spectrum workload: Cash-Karp tolerance")
+    ap.add_argument("--eps-sweep", default="", help="spectrum workload: further Cash-Karp tolerances, split-BF16 only "
+                                                    "(comma-separated)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3",
                     help="single workload: the precisions to run (profiling one at a time); the JSON line needs all three")

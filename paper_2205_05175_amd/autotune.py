@@ -9,8 +9,9 @@ times of the winner and of the library's own rule as comments, into the tuning t
 kept only when it beats the library's own rule by more than ``--min-gain``.
 
 Candidates: the tile kernel in each of its tile / k-stage shapes with 1 to 64 K splits; for
-split-BF16 contexts also both split-BF16 kernels (register-staged, direct-to-LDS ring) with 128 x 128
-or 128 x 256 tiles and 1 to 16 splits.
+split-BF16 contexts also the split-BF16 kernels (register-staged, direct-to-LDS ring, the ring at two
+workgroups per CU) with 128 x 128 or 128 x 256 tiles and 1 to 16 splits, within the workgroup cap the
+library applies to split grids.
 
 Usage: python -m paper_2205_05175_amd.autotune --o 20 --v 76 [--out FILE] [--precisions fp64,fp32,bf16x3]
 """
@@ -125,10 +126,14 @@ def candidates(prec, shape):
                 continue
             out.append((1, mn, bk, s))
     if prec == "bf16x3" and (ac or bc) and 2.0 * M * N * K >= 1e8:
-        for kern in (1, 2):  # register-staged, direct-to-LDS ring
-            for wn in (2, 4):
+        # the right-hand side runs its large products on three streams at once: a split grid is kept
+        # within the library's own workgroup cap (160; 320 for the two-per-CU kernel) so that a product
+        # timed alone does not win by taking CUs the other streams need
+        for kern in (1, 2, 3):  # register-staged, direct-to-LDS ring, the ring at two per CU
+            for wn in ((2,) if kern == 3 else (2, 4)):
+                tiles = -(-M // 128) * -(-N // (64 * wn))
                 for s in range(1, 17):
-                    if s > 1 and K // s < 64:
+                    if s > 1 and (K // s < 64 or tiles * s > (320 if kern == 3 else 160)):
                         continue
                     out.append((2, wn, kern, s))
     return out
