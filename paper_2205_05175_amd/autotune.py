@@ -129,8 +129,8 @@ def candidates(prec, shape):
         # the right-hand side runs its large products on three streams at once: a split grid is kept
         # within the library's own workgroup cap (160; 320 for the two-per-CU kernel) so that a product
         # timed alone does not win by taking CUs the other streams need
-        for kern in (1, 2, 3):  # register-staged, direct-to-LDS ring, the ring at two per CU
-            for wn in ((2,) if kern == 3 else (2, 4)):
+        for kern in (1, 2, 3, 4):  # register-staged, direct-to-LDS ring, the ring at two per CU, wide waves
+            for wn in ((2,) if kern == 3 else (4,) if kern == 4 else (2, 4)):
                 tiles = -(-M // 128) * -(-N // (64 * wn))
                 for s in range(1, 17):
                     if s > 1 and (K // s < 64 or tiles * s > (320 if kern == 3 else 160)):

@@ -707,7 +707,7 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     if (bm && bm[0]) c->E.bf16_min_flops = std::atof(bm);
     const char* bk = std::getenv("RTCC_BF16_KERNEL");
     if (bk && bk[0]) c->E.bf16_kernel = std::atoi(bk);
-    RTCC_CHECK(c->E.bf16_kernel >= 1 && c->E.bf16_kernel <= 3, kEInval, "RTCC_BF16_KERNEL must be 1, 2 or 3");
+    RTCC_CHECK(c->E.bf16_kernel >= 1 && c->E.bf16_kernel <= 4, kEInval, "RTCC_BF16_KERNEL must be 1 to 4");
     const char* ng = std::getenv("RTCC_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');
     const char* tr = std::getenv("RTCC_TRACE");

@@ -192,16 +192,16 @@ __device__ inline void tile_of(int b, const Params& p, int* split, int* tm, int*
 // sums into split plane `split`. With beta != 0 the old C values of each 32 x 32 block are all loaded
 // before its stores (a store may alias a later load, so loads interleaved with stores would each wait
 // a full memory latency).
-template <int AC, int BC>
-__device__ inline void store_tile(const Params& p, const f16 (&accr)[2][2], const f16 (&acci)[2][2], int split, int r0,
-                                  int c0, int lane) {
+template <int AC, int BC, int NJ>
+__device__ inline void store_tile(const Params& p, const f16 (&accr)[2][NJ], const f16 (&acci)[2][NJ], int split,
+                                  int r0, int c0, int lane) {
   constexpr bool CC = AC || BC;
   const int l32 = lane & 31;
   const bool acc = !p.split_stride && p.beta != 0.f;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       float oldr[16], oldi[16];
       if (acc) {
 #pragma unroll
@@ -235,6 +235,8 @@ __device__ inline void store_tile(const Params& p, const f16 (&accr)[2][2], cons
           if (CC) p.Cim[off] = outi;
         }
       }
+      // one 32 x 32 block at a time: keeps the scheduler from holding every block's values in registers
+      __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -422,7 +424,7 @@ __global__ __launch_bounds__(128 * WN, 2) void gemm_bf16x3_dma(Params p) {
       }
     }
   }
-  store_tile<AC, BC>(p, accr, acci, split, m0 + wm * 64, n0 + wn * 64, lane);
+  store_tile<AC, BC, 2>(p, accr, acci, split, m0 + wm * 64, n0 + wn * 64, lane);
 }
 
 // LADDER = 1: the same kernel under a name of its own for the particle-particle ladder.
@@ -510,7 +512,120 @@ __global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p) {
     __syncthreads();
   }
 
-  store_tile<AC, BC>(p, accr, acci, split, m0 + wm * 64, n0 + wn * 64, lane);
+  store_tile<AC, BC, 2>(p, accr, acci, split, m0 + wm * 64, n0 + wn * 64, lane);
+}
+
+// Wide-wave kernel: 256 threads, a 128 x 256 output tile, 2 x 2 waves of 64 x 128 (2 x 4 MFMA blocks of
+// 32 x 32), one wave per SIMD. Per 16-wide k stage a wave reads 2 PA A fragments and 4 PB B fragments for
+// 12 PA PB / 2 MFMAs (c x r: 16 fragments for 48 MFMAs, a third fewer LDS reads per MFMA than 64 x 64 wave
+// tiles); the B fragments are used block by block, so the MFMAs of block j run while the reads of block
+// j + 1 are still in flight. Register-staged double-buffered LDS as in gemm_bf16x3_nt.
+template <int AC, int BC, int LADDER>
+__global__ __launch_bounds__(256) void gemm_bf16x3_w4(Params p) {
+  constexpr int kBN = 256;
+  constexpr int NA = AC ? 2 : 1, NB = BC ? 2 : 1;
+  constexpr int PA = 2 * NA, PB = 2 * NB;
+  constexpr int SK = 16, LDK = 24;
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][PA * kBM * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][PB * kBN * LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int split, tm, tn;
+  tile_of(blockIdx.x, p, &split, &tm, &tn);
+  const int m0 = tm * kBM, n0 = tn * kBN;
+  const int kbeg = split * p.kchunk, kend = min(p.Kp, kbeg + p.kchunk);
+
+  f16 accr[2][4], acci[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        accr[i][j][e] = 0.f;
+        acci[i][j][e] = 0.f;
+      }
+
+  // stage tiles: A [PA][128 rows][2 halves], thread t: row t % 128, half t / 128, every plane;
+  // B [PB][256 rows][2 halves], thread t: row t, both halves, every plane
+  const int arow = tid & 127, aq = tid >> 7;
+  u4 ra[PA], rb[PB][2];
+  auto fetch = [&](int k0) {
+    const int64_t kb = k0 / SK;
+#pragma unroll
+    for (int pl = 0; pl < PA; ++pl)
+      ra[pl] = *reinterpret_cast<const u4*>(p.A + pl * p.pa + ((2 * kb + aq) * p.Mp + m0 + arow) * 8);
+#pragma unroll
+    for (int pl = 0; pl < PB; ++pl)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        rb[pl][h] = *reinterpret_cast<const u4*>(p.B + pl * p.pb + ((2 * kb + h) * p.Np + n0 + tid) * 8);
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int pl = 0; pl < PA; ++pl) *reinterpret_cast<u4*>(&As[buf][(pl * kBM + arow) * LDK + 8 * aq]) = ra[pl];
+#pragma unroll
+    for (int pl = 0; pl < PB; ++pl)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) *reinterpret_cast<u4*>(&Bs[buf][(pl * kBN + tid) * LDK + 8 * h]) = rb[pl][h];
+  };
+
+  const int l32 = lane & 31, hk = 8 * (lane >> 5);
+  const int nst = (kend - kbeg) / SK;
+  if (nst > 0) {
+    fetch(kbeg);
+    stash(0);
+    if (nst > 1) fetch(kbeg + SK);
+    __syncthreads();
+  }
+  for (int s = 0; s < nst; ++s) {
+    const int buf = s & 1;
+    bf8 af[2][PA], an[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int pl = 0; pl < PA; ++pl)
+        af[i][pl] = *reinterpret_cast<const bf8*>(&As[buf][(pl * kBM + wm * 64 + i * 32 + l32) * LDK + hk]);
+    if (AC && BC) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) an[i][h] = neg(af[i][2 + h]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bf8 bfr[PB];
+#pragma unroll
+      for (int pl = 0; pl < PB; ++pl)
+        bfr[pl] = *reinterpret_cast<const bf8*>(&Bs[buf][(pl * kBN + wn * 128 + j * 32 + l32) * LDK + hk]);
+      // three split products; within each, the two row blocks' updates alternate so that an
+      // accumulator's consecutive MFMAs are several instructions apart
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int ha = t == 2 ? 1 : 0, hb = t == 1 ? 1 : 0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) accr[i][j] = mma(af[i][ha], bfr[hb], accr[i][j]);
+        if (BC) {
+#pragma unroll
+          for (int i = 0; i < 2; ++i) acci[i][j] = mma(af[i][ha], bfr[2 + hb], acci[i][j]);
+        }
+        if (AC) {
+#pragma unroll
+          for (int i = 0; i < 2; ++i) acci[i][j] = mma(af[i][2 + ha], bfr[hb], acci[i][j]);
+        }
+        if (AC && BC) {
+#pragma unroll
+          for (int i = 0; i < 2; ++i) accr[i][j] = mma(an[i][ha], bfr[2 + hb], accr[i][j]);
+        }
+      }
+    }
+    if (s + 1 < nst) {
+      stash(buf ^ 1);
+      if (s + 2 < nst) fetch(kbeg + (s + 2) * SK);
+    }
+    __syncthreads();
+  }
+  store_tile<AC, BC, 4>(p, accr, acci, split, m0 + wm * 64, n0 + wn * 128, lane);
 }
 
 }  // namespace
@@ -528,8 +643,9 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   // (128 x 128), which doubles their tile count (measured: 41-55 -> 28-41 us at 400 x 400 x 5776)
   RTCC_CHECK(force_wn == 0 || force_wn == 2 || force_wn == 4, kEInval, "gemm_bf16x3: waves along N must be 2 or 4");
   const int kern = force_kernel ? force_kernel : E.bf16_kernel;
-  RTCC_CHECK(kern >= 1 && kern <= 3, kEInval, "gemm_bf16x3: unknown kernel variant");
-  const int WN = force_wn ? force_wn : kern == 3 || cdiv(M, kBM) * cdiv(N, 256) < 16 ? 2 : 4, kBN = 64 * WN;
+  RTCC_CHECK(kern >= 1 && kern <= 4, kEInval, "gemm_bf16x3: unknown kernel variant");
+  const int WN = force_wn ? force_wn : kern == 3 ? 2 : kern == 4 ? 4 : cdiv(M, kBM) * cdiv(N, 256) < 16 ? 2 : 4,
+            kBN = 64 * WN;
   // A as [M][K] rows; B as [N][K] rows (B(k, n) = trans ? b[n * ld + k] : b[k * ld + n])
   const Packed pa = pack_operand(E, A.re, A.im, A.ld, A.trans, M, K, A.konst, kRowPad);
   const Packed pb = pack_operand(E, B.re, B.im, B.ld, B.trans ? 0 : 1, N, K, B.konst, kBN);
@@ -592,9 +708,15 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   const dim3 grid((unsigned)(p.ntiles * splits));
   const bool lad = E.ladder != 0;
   if (lad && E.mark) E.mark(E.mark_user, 0, E.ladder_flops, E.stream);
-  const dim3 block(128 * WN);
+  const dim3 block(kern == 4 ? 256 : 128 * WN);
   RTCC_CHECK(kern != 3 || WN == 2, kEInval, "gemm_bf16x3: the two-per-CU kernel takes 128 x 128 tiles");
-  if (kern == 3) {  // 128 x 128 tiles, two workgroups per CU
+  RTCC_CHECK(kern != 4 || WN == 4, kEInval, "gemm_bf16x3: the wide-wave kernel takes 128 x 256 tiles");
+  if (kern == 4) {  // 128 x 256 tiles, four waves of 64 x 128
+    if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_w4<1, 0, 1>), grid, block, 0, E.stream, p);
+    else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_w4<1, 1, 0>), grid, block, 0, E.stream, p);
+    else if (AC) hipLaunchKernelGGL((gemm_bf16x3_w4<1, 0, 0>), grid, block, 0, E.stream, p);
+    else hipLaunchKernelGGL((gemm_bf16x3_w4<0, 1, 0>), grid, block, 0, E.stream, p);
+  } else if (kern == 3) {  // 128 x 128 tiles, two workgroups per CU
     if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 1, 2, 1>), grid, block, 0, E.stream, p);
     else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 1, 0, 2, 1>), grid, block, 0, E.stream, p);
     else if (AC) hipLaunchKernelGGL((gemm_bf16x3_dma<1, 0, 0, 2, 1>), grid, block, 0, E.stream, p);

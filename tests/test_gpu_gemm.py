@@ -106,8 +106,9 @@ def test_every_kernel_choice_matches_host(shape):
                 # thin tiles need 16-byte aligned operands: refused otherwise, never wrong
                 _check(prec, case, (1, mn, bk, s), must_run=mn in (64064, 128128))
         if prec == "bf16x3":
-            for kern in (1, 2):  # register-staged, direct-to-LDS ring
-                for wn in (2, 4):
+            # register-staged, direct-to-LDS ring, the ring at two per CU, wide waves
+            for kern, wns in ((1, (2, 4)), (2, (2, 4)), (3, (2,)), (4, (4,))):
+                for wn in wns:
                     for s in (1, 2, 5):
                         _check(prec, case, (2, wn, kern, s))
     # accumulation into C
@@ -115,6 +116,8 @@ def test_every_kernel_choice_matches_host(shape):
     _check("bf16x3", case, (2, 4, 1, 1), alpha=0.5, beta=1.0)
     _check("bf16x3", case, (2, 2, 2, 3), alpha=-1.0, beta=1.0)
     _check("bf16x3", case, (2, 4, 2, 1), alpha=0.5, beta=1.0)
+    _check("bf16x3", case, (2, 2, 3, 2), alpha=0.5, beta=1.0)
+    _check("bf16x3", case, (2, 4, 4, 1), alpha=-0.5, beta=1.0)
     _check("fp64", case, (1, 64064, 16, 4), alpha=2.0, beta=1.0)
 
 
