@@ -16,7 +16,17 @@ equations" subsection and "Comparison of numerical integrators":
   h_new = 0.84 h (eps/Delta)^(1/5); otherwise reject and retry with
   h_new = 0.84 h (eps/Delta)^(1/4). The error Delta is the largest complex
   modulus of y5 - y4 over the state. The factor is clamped to [0.1, 5]
-  (not stated in the paper).
+  (not stated in the paper);
+* Fehlberg's embedded 4(5) pair (Comparison of numerical integrators: six
+  evaluations give a fifth- and a fourth-order solution, and the step advances
+  with the fourth-order one), driven by the same controller;
+* implicit Runge-Kutta with a full Butcher matrix (Introduction and Table
+  tab:butcher: implicit methods couple the stages of one step and need an
+  iterative solution), here Gauss-Legendre collocation. The paper gives no
+  iteration: the stage equations k_i = f(t_n + c_i h, y_n + h sum_j a_ij k_j)
+  are solved by fixed-point (Jacobi) sweeps from k_i = f(t_n, y_n), every
+  sweep evaluating all s stages from the previous sweep's k, until
+  h max_i max|k_i(new) - k_i(old)| <= tol.
 """
 from __future__ import annotations
 
@@ -160,6 +170,106 @@ def rk4_propagate_plan(f, y0, plan, on_step=None):
         if on_step is not None:
             on_step(k, t + h, y)
     return y
+
+
+# Fehlberg's 4(5) pair (Fehlberg 1969; the published coefficients).
+RKF45_C = [Fr(0), Fr(1, 4), Fr(3, 8), Fr(12, 13), Fr(1), Fr(1, 2)]
+RKF45_A = [
+    [],
+    [Fr(1, 4)],
+    [Fr(3, 32), Fr(9, 32)],
+    [Fr(1932, 2197), Fr(-7200, 2197), Fr(7296, 2197)],
+    [Fr(439, 216), Fr(-8), Fr(3680, 513), Fr(-845, 4104)],
+    [Fr(-8, 27), Fr(2), Fr(-3544, 2565), Fr(1859, 4104), Fr(-11, 40)],
+]
+RKF45_B4 = [Fr(25, 216), Fr(0), Fr(1408, 2565), Fr(2197, 4104), Fr(-1, 5), Fr(0)]
+RKF45_B5 = [Fr(16, 135), Fr(0), Fr(6656, 12825), Fr(28561, 56430), Fr(-9, 50), Fr(2, 55)]
+
+
+def controller_factor(eps, delta, p):
+    """Step factor of Eq. ck-h-final for a pair whose lower order is p: 0.84 (eps/Delta)^(1/(p+1))
+    after an accepted trial, 0.84 (eps/Delta)^(1/p) after a rejected one, clamped to [0.1, 5]
+    (p = 4 gives the paper's exponents 1/5 and 1/4)."""
+    if delta == 0.0:
+        return FACTOR_MAX
+    e = 1.0 / (p + 1) if delta <= eps else 1.0 / p
+    return min(max(SAFETY * (eps / delta) ** e, FACTOR_MIN), FACTOR_MAX)
+
+
+def embedded_trial(f, t, y, h, c, A, b_adv, b_emb):
+    """One trial of an embedded explicit pair: (advancing solution, Delta = max|y_adv - y_emb|)."""
+    ks = rk_stages(f, t, y, h, c, A)
+    y_adv = rk_combine(y, h, b_adv, ks)
+    y_emb = rk_combine(y, h, b_emb, ks)
+    delta = float(np.max(np.abs(y_adv - y_emb))) if y_adv.size else 0.0
+    return y_adv, delta
+
+
+def embedded_propagate(f, t0, y0, h0, eps, t_end, c, A, b_adv, b_emb, p, on_accept=None, max_trials=1000000):
+    """Adaptive propagation with an embedded pair and the controller of Eq. ck-h-final; trial sizes
+    are clipped to land on t_end as in cashkarp_propagate. Returns (y, t, n_accepted, n_rejected,
+    h_next)."""
+    y, t, h = y0.copy(), t0, h0
+    nacc = nrej = 0
+    for _ in range(max_trials):
+        if t >= t_end:
+            return y, t, nacc, nrej, h
+        hh = min(h, t_end - t)
+        y_adv, delta = embedded_trial(f, t, y, hh, c, A, b_adv, b_emb)
+        if not np.isfinite(delta):
+            raise FloatingPointError("non-finite error estimate")
+        fac = controller_factor(eps, delta, p)
+        if delta <= eps:
+            y, t = y_adv, t + hh
+            nacc += 1
+            if on_accept is not None:
+                on_accept(t, y)
+        else:
+            nrej += 1
+        h = hh * fac
+    raise RuntimeError("embedded propagation: too many trials")
+
+
+def gauss_legendre_tableau(s):
+    """s-stage Gauss-Legendre collocation: nodes c_i at the zeros of the shifted Legendre polynomial
+    P_s(2c - 1), a_ij = integral over [0, c_i] and b_j = integral over [0, 1] of the j-th Lagrange
+    basis polynomial on those nodes (order 2s). Returns (c, A, b) as float arrays."""
+    x, w = np.polynomial.legendre.leggauss(s)
+    c = (x + 1.0) / 2.0
+    A = np.zeros((s, s))
+    b = np.zeros(s)
+    for j in range(s):
+        lj = np.polynomial.Polynomial([1.0])
+        for m in range(s):
+            if m != j:
+                lj = lj * np.polynomial.Polynomial([-c[m], 1.0]) / (c[j] - c[m])
+        Lj = lj.integ()
+        b[j] = Lj(1.0) - Lj(0.0)
+        for i in range(s):
+            A[i, j] = Lj(c[i]) - Lj(0.0)
+    return c, A, b
+
+
+def implicit_rk_step(f, t, y, h, c, A, b, tol, max_iter):
+    """One step of an implicit Runge-Kutta method (full Butcher matrix A): the stage equations are
+    solved by Jacobi fixed-point sweeps starting from k_i = f(t, y) until the largest change of
+    h k_i in a sweep is <= tol. Returns (y_new, sweeps)."""
+    s = len(c)
+    k0 = f(t, y)
+    ks = [k0] * s
+    for it in range(1, max_iter + 1):
+        new = []
+        for i in range(s):
+            yi = y.copy()
+            for j in range(s):
+                if A[i][j] != 0:
+                    yi = yi + h * float(A[i][j]) * ks[j]
+            new.append(f(t + float(c[i]) * h, yi))
+        d = h * max(float(np.max(np.abs(new[i] - ks[i]))) if y.size else 0.0 for i in range(s))
+        ks = new
+        if d <= tol:
+            return rk_combine(y, h, b, ks), it
+    raise RuntimeError("implicit Runge-Kutta: stage iteration did not converge")
 
 
 def butcher_row_sums(c, A):

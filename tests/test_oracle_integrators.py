@@ -223,3 +223,145 @@ def test_gaussian_field_shape():
     iso = np.ones(3) / math.sqrt(3)
     E = field.gaussian(12.0, 0.01, 0.5, 5.0, 15.0, iso)
     assert np.allclose(E, -0.01 * math.exp(-0.5 * 9 / 25) * math.cos(-1.5) * iso)
+
+
+# ---- Fehlberg 4(5), the generic embedded driver, Gauss-Legendre ---------------------------------
+
+def test_rkf45_orders():
+    """Fehlberg's pair: consistent rows; the advancing weights are exactly fourth order (and not
+    fifth), the embedded weights exactly fifth order."""
+    assert all(x == 0 for x in I.butcher_row_sums(I.RKF45_C, I.RKF45_A))
+    r4 = _order_conditions(I.RKF45_B4, I.RKF45_C, I.RKF45_A)
+    r5 = _order_conditions(I.RKF45_B5, I.RKF45_C, I.RKF45_A)
+    assert all(x == 0 for k in (1, 2, 3, 4) for x in r4[k])
+    assert any(x != 0 for x in r4[5])
+    assert all(x == 0 for k in (1, 2, 3, 4, 5) for x in r5[k])
+
+
+def test_controller_factor_matches_paper_exponents():
+    for d in (1e-9, 1e-7, 1e-6, 3e-6, 1e-3, 0.0, 1e30):
+        assert I.controller_factor(1e-6, d, 4) == I.ck_factor(1e-6, d)
+    assert I.controller_factor(1e-6, 1e-8, 2) == pytest.approx(0.84 * 100 ** (1 / 3))
+
+
+@pytest.mark.parametrize("which,order", [("rkf4", 4), ("rkf5", 5)])
+def test_rkf45_global_order(which, order):
+    f = lambda t, y: y * np.cos(t)
+    exact = math.exp(math.sin(2.0))
+    b = I.RKF45_B4 if which == "rkf4" else I.RKF45_B5
+    step = lambda f, t, y, h: I.rk_combine(y, h, b, I.rk_stages(f, t, y, h, I.RKF45_C, I.RKF45_A))
+    # the fourth-order solution's leading error constant is small: asymptotic only from h = 0.1
+    errs = [abs(_integrate(step, f, np.array([1.0]), 2.0, n)[0] - exact) for n in (20, 40, 80)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert abs(math.log2(r2) - order) < 0.35 and abs(math.log2(r1) - order) < 0.5
+
+
+def test_embedded_driver_with_cash_karp_is_the_cash_karp_driver():
+    f = lambda t, y: np.array([y[1], -np.sin(y[0]) + 0.3 * np.cos(1.7 * t)], dtype=complex)
+    y0 = np.array([1.0 + 0j, 0.0 + 0j])
+    a, b = [], []
+    ra = I.cashkarp_propagate(f, 0.0, y0, 0.4, 1e-8, 6.0, on_accept=lambda t, y: a.append((t, y.copy())))
+    rb = I.embedded_propagate(f, 0.0, y0, 0.4, 1e-8, 6.0, I.CK_C, I.CK_A, I.CK_B5, I.CK_B4, 4,
+                              on_accept=lambda t, y: b.append((t, y.copy())))
+    assert ra[2:] == rb[2:] and len(a) == len(b)
+    assert all(ta == tb and np.array_equal(ya, yb) for (ta, ya), (tb, yb) in zip(a, b))
+
+
+def test_rkf45_adaptive_propagation_accuracy():
+    """The fourth-order advancing solution under the controller: y' = lam y to t = 4 with eps = 1e-8
+    stays within a few eps per accepted step of the exact solution, and a larger first step is rejected."""
+    lam = -0.05 + 6.0j
+    y, t, nacc, nrej, _ = I.embedded_propagate(lambda t, y: lam * y, 0.0, np.array([1.0 + 0j]), 0.5, 1e-8, 4.0,
+                                               I.RKF45_C, I.RKF45_A, I.RKF45_B4, I.RKF45_B5, 4)
+    assert t == 4.0 and nrej >= 1
+    assert abs(y[0] - np.exp(lam * 4.0)) < 10 * nacc * 1e-8
+
+
+SQ3, SQ15 = math.sqrt(3.0), math.sqrt(15.0)
+GL_CLOSED = {
+    2: ([0.5 - SQ3 / 6, 0.5 + SQ3 / 6], [[0.25, 0.25 - SQ3 / 6], [0.25 + SQ3 / 6, 0.25]], [0.5, 0.5]),
+    3: ([0.5 - SQ15 / 10, 0.5, 0.5 + SQ15 / 10],
+        [[5 / 36, 2 / 9 - SQ15 / 15, 5 / 36 - SQ15 / 30], [5 / 36 + SQ15 / 24, 2 / 9, 5 / 36 - SQ15 / 24],
+         [5 / 36 + SQ15 / 30, 2 / 9 + SQ15 / 15, 5 / 36]], [5 / 18, 4 / 9, 5 / 18]),
+}
+
+
+@pytest.mark.parametrize("s", [2, 3])
+def test_gauss_legendre_closed_form(s):
+    """The collocation construction gives the textbook two- and three-stage Gauss tableaux."""
+    c, A, b = I.gauss_legendre_tableau(s)
+    cc, AA, bb = GL_CLOSED[s]
+    # (the construction integrates products of s - 1 linear factors: a few ulps of rounding)
+    assert np.allclose(c, cc, atol=1e-15, rtol=0) and np.allclose(b, bb, atol=4e-15, rtol=0)
+    assert np.allclose(A, AA, atol=4e-15, rtol=0)
+
+
+@pytest.mark.parametrize("s", [1, 2, 3, 4])
+def test_gauss_legendre_simplifying_assumptions(s):
+    """B(2s) (quadrature exact to degree 2s-1) and C(s) (stage order s): together order 2s."""
+    c, A, b = I.gauss_legendre_tableau(s)
+    for k in range(1, 2 * s + 1):
+        assert abs(np.dot(b, c ** (k - 1)) - 1.0 / k) < 1e-14
+    for k in range(1, s + 1):
+        assert np.allclose(A @ c ** (k - 1), c ** k / k, atol=1e-14, rtol=0)
+
+
+def _pade(s, z):
+    # diagonal Pade approximant of exp(z) of degree s (the stability function of s-stage Gauss)
+    num = sum(math.factorial(2 * s - j) * math.factorial(s) / (math.factorial(2 * s) * math.factorial(j)
+                                                               * math.factorial(s - j)) * z ** j for j in range(s + 1))
+    return num / sum(math.factorial(2 * s - j) * math.factorial(s) / (math.factorial(2 * s) * math.factorial(j)
+                                                                   * math.factorial(s - j)) * (-z) ** j
+                     for j in range(s + 1))
+
+
+@pytest.mark.parametrize("s", [2, 3])
+def test_gauss_legendre_step_is_pade(s):
+    """On y' = lam y the converged step multiplies y by the (s,s) Pade approximant of exp(h lam)."""
+    c, A, b = I.gauss_legendre_tableau(s)
+    lam = -0.4 + 3.0j
+    for h in (0.02, 0.1):
+        y1, it = I.implicit_rk_step(lambda t, y: lam * y, 0.0, np.array([1.0 + 0j]), h, c, A, b, 1e-15, 200)
+        assert abs(y1[0] - _pade(s, h * lam)) < 1e-13 and it >= 2
+
+
+@pytest.mark.parametrize("s", [2, 3])
+def test_gauss_legendre_linear_system_and_unitarity(s):
+    """y' = -i H y with a random Hermitian H: the fixed-point stages equal the direct solve of the
+    linear stage equations, and 200 steps keep the norm (the Pade map of an imaginary-axis spectrum
+    is unitary)."""
+    rng = np.random.default_rng(5)
+    n = 6
+    M = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    H = (M + M.conj().T) / 8
+    J = -1j * H
+    f = lambda t, y: J @ y
+    c, A, b = I.gauss_legendre_tableau(s)
+    y = rng.normal(size=n) + 1j * rng.normal(size=n)
+    h = 0.05
+    y1, _ = I.implicit_rk_step(f, 0.0, y, h, c, A, b, 1e-15, 200)
+    big = np.eye(s * n, dtype=complex) - h * np.kron(A, J)
+    K = np.linalg.solve(big, np.kron(np.ones(s), J @ y)).reshape(s, n)
+    assert np.abs(y1 - (y + h * (b @ K))).max() < 1e-13
+    nrm = np.linalg.norm(y)
+    for _ in range(200):
+        y, _ = I.implicit_rk_step(f, 0.0, y, h, c, A, b, 1e-15, 200)
+    assert abs(np.linalg.norm(y) - nrm) < 1e-11 * nrm
+
+
+@pytest.mark.parametrize("s,order", [(2, 4), (3, 6)])
+def test_gauss_legendre_global_order(s, order):
+    f = lambda t, y: y * np.cos(t)
+    exact = math.exp(math.sin(2.0))
+    c, A, b = I.gauss_legendre_tableau(s)
+    step = lambda f, t, y, h: I.implicit_rk_step(f, t, y, h, c, A, b, 1e-16, 400)[0]
+    ns = (4, 8, 16) if s == 3 else (8, 16, 32)
+    errs = [abs(_integrate(step, f, np.array([1.0]), 2.0, n)[0] - exact) for n in ns]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert abs(math.log2(r2) - order) < 0.5 and abs(math.log2(r1) - order) < 0.6
+
+
+def test_implicit_iteration_limit():
+    c, A, b = I.gauss_legendre_tableau(2)
+    with pytest.raises(RuntimeError):
+        I.implicit_rk_step(lambda t, y: -40.0 * y, 0.0, np.array([1.0]), 0.2, c, A, b, 1e-12, 50)

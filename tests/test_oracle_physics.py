@@ -117,6 +117,58 @@ def test_two_electron_delta_kick_dynamics_matches_fci():
     assert abs(mu0 - np.vdot(psi, M @ psi)) < 1e-11
 
 
+def _two_electron_kick_case():
+    o, v = 1, 3
+    S, amps, _ = _ground(o, v)
+    kappa, n = 2e-2, np.array([0.0, 0.0, 1.0])
+    kicked = field.kick(S, amps, kappa, n)
+    bf = bruteforce.BruteForce(S.f0, S.g, 2 * o)
+    dim = bf.space.dim
+    cols = lambda A1, A2: np.column_stack([bruteforce._apply_hamiltonian(bf.space, A1, A2, np.eye(dim)[:, k].astype(complex))
+                                           for k in range(dim)])
+    H = cols(bf.h, bf.g)
+    M = cols(S.mu[2], None)
+    w, U = np.linalg.eigh(H)
+    k0 = next(k for k in range(dim) if abs(U[bf.space.ref, k]) > 0.1)
+    psi = sla.expm(1j * kappa * M) @ U[:, k0]
+
+    def exact(T):
+        psit = sla.expm(-1j * H * T) @ psi
+        return (np.vdot(psit, M @ psit) / np.vdot(psit, psit)).real
+
+    f = lambda t, yy: pack_state(*ccsd.rhs(S, *unpack_state(yy, o, v), np.zeros(3)))
+    mu_z = lambda y: ccsd.dipole(S, *unpack_state(y, o, v))[2].real
+    return pack_state(*kicked), f, mu_z, exact
+
+
+def test_two_electron_gauss_legendre_matches_fci():
+    """Implicit two-stage Gauss-Legendre on the kicked two-electron system: TD-FCI <mu_z>(T) with
+    the fourth-order error ratio when h is halved."""
+    y0, f, mu_z, exact = _two_electron_kick_case()
+    c, A, b = integrators.gauss_legendre_tableau(2)
+    T = 2.0
+    errs = []
+    for nsteps in (10, 20):
+        h, y = T / nsteps, y0
+        for k in range(nsteps):
+            y, it = integrators.implicit_rk_step(f, k * h, y, h, c, A, b, 1e-14, 100)
+        errs.append(abs(mu_z(y) - exact(T)))
+    assert errs[1] < 1e-6
+    assert 8 < errs[0] / errs[1] < 24
+
+
+def test_two_electron_rkf45_matches_fci():
+    """Adaptive Fehlberg 4(5) on the same system: accepted samples follow TD-FCI to within the
+    accumulated tolerance."""
+    y0, f, mu_z, exact = _two_electron_kick_case()
+    samples = []
+    y, t, nacc, nrej, _ = integrators.embedded_propagate(
+        f, 0.0, y0, 0.05, 1e-9, 3.0, integrators.RKF45_C, integrators.RKF45_A, integrators.RKF45_B4,
+        integrators.RKF45_B5, 4, on_accept=lambda tt, yy: samples.append((tt, mu_z(yy))))
+    assert t == 3.0 and nacc >= 5
+    assert max(abs(m - exact(tt)) for tt, m in samples) < 20 * nacc * 1e-9
+
+
 def test_lagrangian_conserved_field_free():
     """Field-free propagation conserves L = <0|(1+Lambda)Hbar|0>; RK4 drift falls as h^4."""
     o, v = 2, 4
