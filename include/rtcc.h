@@ -173,6 +173,56 @@ int rtcc_propagate_cashkarp(rtcc_ctx* ctx, void* y, double t0, double t_end, dou
 int rtcc_step_cashkarp(rtcc_ctx* ctx, void* y, double* t, double* h, double eps, const rtcc_field* field,
                        int* accepted, double* delta);
 
+/* ---- General Runge-Kutta tableaux ---------------------------------------------------------------
+ * Any Runge-Kutta method given by its Butcher tableau (Eqs. rk_y, rk_k; Table tab:butcher): explicit
+ * (A strictly lower triangular), embedded (explicit with a second weight row, driven by the controller
+ * of Eq. ck-h-final) and implicit (a full A; the Introduction's third type of integrator, here
+ * Gauss-Legendre collocation), through the same stage machinery as RK4 and Cash-Karp: the stage input
+ * y + h sum_j a_ij k_j is formed and converted to the contraction precision in one pass, all
+ * combinations are FP64. The coefficients are a host struct owned by the caller. */
+#define RTCC_MAX_STAGES 6
+typedef struct {
+  int stages;    /* s, 1..RTCC_MAX_STAGES (implicit tableaux: 1..3) */
+  int err_order; /* p > 0: b_err is an embedded solution of order p, the controller takes exponents
+                    1/(p+1) after an accepted and 1/p after a rejected trial (p = 4: the paper's 1/5,
+                    1/4); 0: no embedded solution */
+  double a[RTCC_MAX_STAGES][RTCC_MAX_STAGES]; /* a[i][j], i, j < stages; the rest is ignored */
+  double b[RTCC_MAX_STAGES];                  /* weights of the solution the step advances with */
+  double b_err[RTCC_MAX_STAGES];              /* weights of the embedded solution (err_order > 0) */
+  double c[RTCC_MAX_STAGES];                  /* nodes: stage i is evaluated at t + c[i] h */
+} rtcc_tableau;
+
+/* Built-in tableaux. RK4: classical (Eq. rk4truncation). CASHKARP: the corrected Cash-Karp pair of
+ * Eqs. ck-k/ck-y, advancing with the fifth-order weights, err_order 4. RKF45: Fehlberg's 4(5) pair
+ * (Comparison of numerical integrators), advancing with the fourth-order weights, embedded fifth-order
+ * weights, err_order 4. GL2, GL3: two- and three-stage Gauss-Legendre collocation (orders 4 and 6,
+ * implicit). */
+enum { RTCC_TAB_RK4 = 1, RTCC_TAB_CASHKARP = 2, RTCC_TAB_RKF45 = 3, RTCC_TAB_GL2 = 4, RTCC_TAB_GL3 = 5 };
+
+/* Fill *out (HOST) with built-in tableau `id`. Needs no context or GPU; RTCC_EINVAL for an unknown id
+ * (message via rtcc_last_error(NULL)). */
+int rtcc_tableau_builtin(int id, rtcc_tableau* out);
+
+/* One step of size h from t with tableau *tab (HOST); y (DEVICE) advances in place with the b weights.
+ * Explicit tableau: s right-hand sides; if err_order > 0 and delta (HOST) is not NULL, *delta = the
+ * largest complex modulus of the difference between the b and b_err solutions (synchronises).
+ * Implicit tableau: the stage equations k_i = f(t + c_i h, y + h sum_j a_ij k_j) are solved by fixed-point
+ * sweeps that start from k_i = f(t, y) and evaluate every stage from the previous sweep's k, until
+ * h max_i max|k_i(new) - k_i(old)| <= tol (tol > 0); each sweep costs s right-hand sides and one
+ * synchronisation. *sweeps (HOST, may be NULL) receives the number of sweeps; RTCC_ENOTCONV after
+ * max_iter sweeps (y unchanged), RTCC_ENONFINITE on a non-finite change. tol and max_iter are ignored
+ * for explicit tableaux. */
+int rtcc_step_tableau(rtcc_ctx* ctx, void* y, double t, double h, const rtcc_tableau* tab,
+                      const rtcc_field* field, double tol, int max_iter, double* delta, int* sweeps);
+
+/* Adaptive propagation from t0 to t_end with an explicit embedded tableau (err_order > 0): the
+ * trial / accept / controller loop of rtcc_propagate_cashkarp (same arguments, same outputs) with the
+ * tableau's weights and exponents; with the built-in CASHKARP tableau it performs the same operations
+ * as rtcc_propagate_cashkarp. */
+int rtcc_propagate_embedded(rtcc_ctx* ctx, void* y, double t0, double t_end, double h0, double eps,
+                            const rtcc_tableau* tab, const rtcc_field* field, int max_trials, int cap,
+                            double* t_out, double* mu_out, int* naccepted, int* nrejected, double* h_next);
+
 /* ---- Adjoint (vector-Jacobian products) -------------------------------------------------------
  * Gradients follow the convention for a real loss L of complex variables z: zbar = dL/dRe z + i dL/dIm z
  * (PyTorch's), so a map z -> w(z) holomorphic in z sends wbar to J^H wbar.

@@ -35,6 +35,47 @@ class Field(ctypes.Structure):
         return cls(FIELD_NONE, 0.0, 0.0, 1.0, 0.0, (ctypes.c_double * 3)(0.0, 0.0, 0.0))
 
 
+MAX_STAGES = 6
+TAB_RK4, TAB_CASHKARP, TAB_RKF45, TAB_GL2, TAB_GL3 = 1, 2, 3, 4, 5
+_TAB = {"rk4": TAB_RK4, "cashkarp": TAB_CASHKARP, "rkf45": TAB_RKF45, "gl2": TAB_GL2, "gl3": TAB_GL3}
+
+
+class Tableau(ctypes.Structure):
+    """rtcc_tableau: stages, err_order, a[6][6], b[6], b_err[6], c[6]."""
+    _fields_ = [("stages", ctypes.c_int), ("err_order", ctypes.c_int),
+                ("a", (ctypes.c_double * MAX_STAGES) * MAX_STAGES), ("b", ctypes.c_double * MAX_STAGES),
+                ("b_err", ctypes.c_double * MAX_STAGES), ("c", ctypes.c_double * MAX_STAGES)]
+
+    @classmethod
+    def builtin(cls, name):
+        """One of the library's tableaux: "rk4", "cashkarp", "rkf45", "gl2", "gl3" (rtcc_tableau_builtin)."""
+        L = load_library()
+        t = cls()
+        rc = L.rtcc_tableau_builtin(_TAB[name] if isinstance(name, str) else int(name), ctypes.byref(t))
+        if rc != 0:
+            raise RTCCError(rc, L.rtcc_last_error(None).decode())
+        return t
+
+    @classmethod
+    def from_arrays(cls, a, b, c, b_err=None, err_order=0):
+        """A caller's tableau from nested sequences (a: s x s)."""
+        s = len(b)
+        t = cls()
+        t.stages, t.err_order = s, int(err_order)
+        for i in range(s):
+            t.b[i], t.c[i] = float(b[i]), float(c[i])
+            if b_err is not None:
+                t.b_err[i] = float(b_err[i])
+            for j in range(s):
+                t.a[i][j] = float(a[i][j]) if j < len(a[i]) else 0.0
+        return t
+
+    def arrays(self):
+        s = self.stages
+        A = np.array([[self.a[i][j] for j in range(s)] for i in range(s)])
+        return A, np.array(self.b[:s]), np.array(self.c[:s]), np.array(self.b_err[:s])
+
+
 _lib = None
 
 
@@ -69,6 +110,11 @@ def load_library(path: str = LIB_PATH):
     L.rtcc_propagate_rk4_mixed.argtypes = [vp, vp, d, d, d, d, ctypes.POINTER(Field), vp, vp]
     L.rtcc_propagate_cashkarp.argtypes = [vp, vp, d, d, d, d, ctypes.POINTER(Field), i, i, dp, dp,
                                           ctypes.POINTER(i), ctypes.POINTER(i), dp]
+    tp = ctypes.POINTER(Tableau)
+    L.rtcc_tableau_builtin.argtypes = [i, tp]
+    L.rtcc_step_tableau.argtypes = [vp, vp, d, d, tp, ctypes.POINTER(Field), d, i, dp, ctypes.POINTER(i)]
+    L.rtcc_propagate_embedded.argtypes = [vp, vp, d, d, d, d, tp, ctypes.POINTER(Field), i, i, dp, dp,
+                                          ctypes.POINTER(i), ctypes.POINTER(i), dp]
     L.rtcc_dipole.argtypes = [vp, vp, dp]
     L.rtcc_dipole_dev.argtypes = [vp, vp, vp]
     L.rtcc_ground_state.argtypes = [vp, vp, d, i, dp]
@@ -96,7 +142,8 @@ def load_library(path: str = LIB_PATH):
 EXPORTED = ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
             "rtcc_propagate_batch", "rtcc_rhs_vjp", "rtcc_dipole_vjp", "rtcc_step_rk4_vjp", "rtcc_step_cashkarp",
             "rtcc_set_guard", "rtcc_mixed_schedule", "rtcc_propagate_rk4_mixed", "rtcc_propagate_cashkarp",
-            "rtcc_gemm", "rtcc_load_tuning", "rtcc_check_state_noalloc",
+            "rtcc_gemm", "rtcc_load_tuning", "rtcc_check_state_noalloc", "rtcc_tableau_builtin",
+            "rtcc_step_tableau", "rtcc_propagate_embedded",
             "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick", "rtcc_check_state", "rtcc_info",
             "rtcc_profile", "rtcc_profile_read", "rtcc_destroy", "rtcc_last_error")
 
@@ -216,9 +263,33 @@ class RTCC:
                                                     float(h2), ctypes.byref(f), ptrs[0], ptrs[1]))
         return ns
 
+    def step_tableau(self, y, t, h, tab, field=None, tol=1e-10, max_iter=100):
+        """One step of any tableau (Tableau or a built-in name); y advances in place. Returns (delta, sweeps):
+        the embedded error estimate of an explicit pair (None otherwise) and the implicit stage sweeps (1 for
+        explicit tableaux)."""
+        T = Tableau.builtin(tab) if isinstance(tab, (str, int)) else tab
+        f = field if field is not None else Field.none()
+        dl, sw = ctypes.c_double(float("nan")), ctypes.c_int(0)
+        self._check(self.L.rtcc_step_tableau(self.ctx, self._state(y), float(t), float(h), ctypes.byref(T),
+                                             ctypes.byref(f), float(tol), int(max_iter), ctypes.byref(dl),
+                                             ctypes.byref(sw)))
+        return (dl.value if T.err_order > 0 else None), sw.value
+
+    def propagate_embedded(self, y, t0, t_end, h0, eps, tab, field=None, record=True, cap=1 << 20,
+                           max_trials=1 << 24):
+        """Adaptive propagation with an embedded explicit tableau (Tableau or "cashkarp" / "rkf45"); the
+        returns of propagate_cashkarp."""
+        T = Tableau.builtin(tab) if isinstance(tab, (str, int)) else tab
+        return self._adaptive(self.L.rtcc_propagate_embedded, (ctypes.byref(T),), y, t0, t_end, h0, eps, field,
+                              record, cap, max_trials)
+
     def propagate_cashkarp(self, y, t0, t_end, h0, eps, field=None, record=True, cap=1 << 20, max_trials=1 << 24):
         """Adaptive Cash-Karp from t0 to t_end. Returns (times, dipoles (k, 3) complex, n_accepted, n_rejected,
         h_next); times/dipoles are those after every accepted step (empty without record)."""
+        return self._adaptive(self.L.rtcc_propagate_cashkarp, (), y, t0, t_end, h0, eps, field, record, cap,
+                              max_trials)
+
+    def _adaptive(self, fn, extra, y, t0, t_end, h0, eps, field, record, cap, max_trials):
         f = field if field is not None else Field.none()
         na, nr, hn = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
         if record:
@@ -228,9 +299,9 @@ class RTCC:
         else:
             tt = mm = None
             tp = mp = None
-        self._check(self.L.rtcc_propagate_cashkarp(self.ctx, self._state(y), float(t0), float(t_end), float(h0),
-                                                   float(eps), ctypes.byref(f), int(max_trials), int(cap) if record else 0,
-                                                   tp, mp, ctypes.byref(na), ctypes.byref(nr), ctypes.byref(hn)))
+        self._check(fn(self.ctx, self._state(y), float(t0), float(t_end), float(h0), float(eps), *extra,
+                       ctypes.byref(f), int(max_trials), int(cap) if record else 0, tp, mp, ctypes.byref(na),
+                       ctypes.byref(nr), ctypes.byref(hn)))
         k = na.value
         if record:
             m = mm[:6 * k].reshape(k, 6)

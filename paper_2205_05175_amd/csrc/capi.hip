@@ -1,5 +1,5 @@
-// C ABI: context lifetime, right-hand side, RK4 / Cash-Karp stepping, delta kick, dipole and
-// ground state. See include/rtcc.h for the contract of every entry point.
+// C ABI: context lifetime, right-hand side, RK4 / Cash-Karp / general-tableau stepping, delta kick,
+// dipole and ground state. See include/rtcc.h for the contract of every entry point.
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -33,6 +33,17 @@ const double kCkA[6][5] = {
 // fifth-order weights (the step advances with these) and the embedded fourth-order ones
 const double kCkB5[6] = {37.0 / 378, 0.0, 250.0 / 621, 125.0 / 594, 0.0, 512.0 / 1771};
 const double kCkB4[6] = {2825.0 / 27648, 0.0, 18575.0 / 48384, 13525.0 / 55296, 277.0 / 14336, 1.0 / 4};
+// Fehlberg's 4(5) pair (the published coefficients); the step advances with the fourth-order weights.
+const double kRkfC[6] = {0.0, 1.0 / 4, 3.0 / 8, 12.0 / 13, 1.0, 1.0 / 2};
+const double kRkfA[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.0 / 4, 0, 0, 0, 0},
+    {3.0 / 32, 9.0 / 32, 0, 0, 0},
+    {1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197, 0, 0},
+    {439.0 / 216, -8.0, 3680.0 / 513, -845.0 / 4104, 0},
+    {-8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40}};
+const double kRkfB4[6] = {25.0 / 216, 0.0, 1408.0 / 2565, 2197.0 / 4104, -1.0 / 5, 0.0};
+const double kRkfB5[6] = {16.0 / 135, 0.0, 6656.0 / 12825, 28561.0 / 56430, -9.0 / 50, 2.0 / 55};
 const double kSafety = 0.84, kFacMin = 0.1, kFacMax = 5.0;
 const int kMaxBatchSystems = 64, kMaxBatchMembers = 4096;
 
@@ -632,25 +643,59 @@ std::vector<std::pair<double, double>> mixed_schedule(double t0, double t_end, d
   return out;
 }
 
-// One Cash-Karp trial of size hh from t (device time set here): y5, y4 and Delta = max|y5 - y4| into
-// redout[0]; with dip also the dipole of y5 into redout[8..13]. Returns (Delta, and the dipole) after one
-// synchronisation.
-double ck_trial(rtcc_ctx* c, const void* y, double t, double hh, const FieldDev& fd, double* mu6) {
+bool tab_explicit(const rtcc_tableau& T) {
+  for (int i = 0; i < T.stages; ++i)
+    for (int j = i; j < T.stages; ++j)
+      if (T.a[i][j] != 0.0) return false;
+  return true;
+}
+
+// Shape and finiteness of a caller's tableau; implicit tableaux are limited by the six stage buffers
+// (old and new derivatives of up to three stages).
+void check_tab(const rtcc_tableau* T, bool need_embedded, const char* who) {
+  RTCC_CHECK(T && T->stages >= 1 && T->stages <= RTCC_MAX_STAGES && T->err_order >= 0, kEInval,
+             std::string(who) + ": invalid tableau");
+  for (int i = 0; i < T->stages; ++i) {
+    RTCC_CHECK(std::isfinite(T->b[i]) && std::isfinite(T->c[i]) && std::isfinite(T->b_err[i]), kEInval,
+               std::string(who) + ": non-finite tableau entry");
+    for (int j = 0; j < T->stages; ++j)
+      RTCC_CHECK(std::isfinite(T->a[i][j]), kEInval, std::string(who) + ": non-finite tableau entry");
+  }
+  const bool ex = tab_explicit(*T);
+  RTCC_CHECK(ex || T->stages <= 3, kEInval, std::string(who) + ": implicit tableaux are limited to 3 stages");
+  RTCC_CHECK(!need_embedded || (ex && T->err_order > 0), kEInval,
+             std::string(who) + ": needs an explicit tableau with an embedded solution (err_order > 0)");
+}
+
+// All stage derivatives k[0..s-1] of an explicit tableau for a step of size hh from the device time.
+void explicit_stages(rtcc_ctx* c, const void* y, double hh, const rtcc_tableau& T, const FieldDev& fd) {
+  for (int s = 0; s < T.stages; ++s) {
+    const void* ks[RTCC_MAX_STAGES];
+    double cs[RTCC_MAX_STAGES];
+    for (int j = 0; j < s; ++j) {
+      ks[j] = c->k[j];
+      cs[j] = hh * T.a[s][j];
+    }
+    rhs_t(c, StageIn{y, s, ks, cs}, fd, T.c[s] * hh, c->k[s]);
+  }
+}
+
+// One trial of an embedded explicit tableau of size hh from t (device time set here): the advancing
+// solution into y5, the embedded one into y4, Delta = max|y5 - y4| into redout[0]; with mu6 also the
+// dipole of y5 (redout[8..13]). Returns Delta (and the dipole) after one synchronisation.
+double emb_trial(rtcc_ctx* c, const void* y, double t, double hh, const rtcc_tableau& T, const FieldDev& fd,
+                 double* mu6) {
   scalar_update(c->stream, c->tdev, t, false);
-  for (int s = 0; s < 6; ++s) {
-    const void* ks[5] = {c->k[0], c->k[1], c->k[2], c->k[3], c->k[4]};
-    double cs[5];
-    for (int j = 0; j < 5; ++j) cs[j] = hh * kCkA[s][j];
-    rhs_t(c, StageIn{y, s, ks, cs}, fd, kCkC[s] * hh, c->k[s]);
+  explicit_stages(c, y, hh, T, fd);
+  const void* ks[RTCC_MAX_STAGES];
+  double cb[RTCC_MAX_STAGES], ce[RTCC_MAX_STAGES];
+  for (int j = 0; j < T.stages; ++j) {
+    ks[j] = c->k[j];
+    cb[j] = hh * T.b[j];
+    ce[j] = hh * T.b_err[j];
   }
-  const void* ks[6] = {c->k[0], c->k[1], c->k[2], c->k[3], c->k[4], c->k[5]};
-  double c5[6], c4[6];
-  for (int j = 0; j < 6; ++j) {
-    c5[j] = hh * kCkB5[j];
-    c4[j] = hh * kCkB4[j];
-  }
-  state_combo(c->stream, c->nstate, y, 6, ks, c5, c->y5);
-  state_combo(c->stream, c->nstate, y, 6, ks, c4, c->y4);
+  state_combo(c->stream, c->nstate, y, T.stages, ks, cb, c->y5);
+  state_combo(c->stream, c->nstate, y, T.stages, ks, ce, c->y4);
   max_abs_diff(c->stream, c->nstate, c->y5, c->y4, c->red, c->redout);
   if (mu6) {
     dipole_dev(c, c->y5, c->redout + 8);
@@ -664,11 +709,129 @@ double ck_trial(rtcc_ctx* c, const void* y, double t, double hh, const FieldDev&
   return d[0];
 }
 
-double ck_factor(double eps, double dl) {
+// Controller of Eq. ck-h-final for a pair of lower order p (p = 4: exponents 1/5 and 1/4).
+double ctl_factor(double eps, double dl, int p) {
   double fac;
   if (dl == 0.0) fac = kFacMax;
-  else fac = kSafety * std::pow(eps / dl, dl <= eps ? 0.2 : 0.25);
+  else fac = kSafety * std::pow(eps / dl, dl <= eps ? 1.0 / (p + 1) : 1.0 / p);
   return std::min(std::max(fac, kFacMin), kFacMax);
+}
+
+void builtin_tableau(int id, rtcc_tableau& T) {
+  T = rtcc_tableau{};
+  if (id == RTCC_TAB_RK4) {
+    T.stages = 4;
+    for (int i = 0; i < 4; ++i) {
+      T.c[i] = kRk4C[i];
+      T.b[i] = kRk4B[i];
+      for (int j = 0; j < 3; ++j) T.a[i][j] = kRk4A[i][j];
+    }
+  } else if (id == RTCC_TAB_CASHKARP || id == RTCC_TAB_RKF45) {
+    const bool ck = id == RTCC_TAB_CASHKARP;
+    T.stages = 6;
+    T.err_order = 4;
+    for (int i = 0; i < 6; ++i) {
+      T.c[i] = ck ? kCkC[i] : kRkfC[i];
+      T.b[i] = ck ? kCkB5[i] : kRkfB4[i];
+      T.b_err[i] = ck ? kCkB4[i] : kRkfB5[i];
+      for (int j = 0; j < 5; ++j) T.a[i][j] = ck ? kCkA[i][j] : kRkfA[i][j];
+    }
+  } else if (id == RTCC_TAB_GL2) {
+    // Gauss-Legendre, two stages: nodes 1/2 -+ sqrt(3)/6 (order 4)
+    const double r = std::sqrt(3.0) / 6.0;
+    T.stages = 2;
+    T.c[0] = 0.5 - r;
+    T.c[1] = 0.5 + r;
+    T.a[0][0] = 0.25;
+    T.a[0][1] = 0.25 - r;
+    T.a[1][0] = 0.25 + r;
+    T.a[1][1] = 0.25;
+    T.b[0] = T.b[1] = 0.5;
+  } else if (id == RTCC_TAB_GL3) {
+    // Gauss-Legendre, three stages: nodes 1/2 - sqrt(15)/10, 1/2, 1/2 + sqrt(15)/10 (order 6)
+    const double q = std::sqrt(15.0);
+    T.stages = 3;
+    T.c[0] = 0.5 - q / 10;
+    T.c[1] = 0.5;
+    T.c[2] = 0.5 + q / 10;
+    const double a[3][3] = {{5.0 / 36, 2.0 / 9 - q / 15, 5.0 / 36 - q / 30},
+                            {5.0 / 36 + q / 24, 2.0 / 9, 5.0 / 36 - q / 24},
+                            {5.0 / 36 + q / 30, 2.0 / 9 + q / 15, 5.0 / 36}};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) T.a[i][j] = a[i][j];
+    T.b[0] = T.b[2] = 5.0 / 18;
+    T.b[1] = 4.0 / 9;
+  } else {
+    throw Error(kEInval, "rtcc_tableau_builtin: unknown tableau id");
+  }
+}
+
+// Adaptive propagation with an embedded explicit tableau (shared by rtcc_propagate_cashkarp).
+void propagate_embedded(rtcc_ctx* c, void* y, double t0, double t_end, double h0, double eps, const rtcc_tableau& T,
+                        const rtcc_field* field, int max_trials, int cap, double* t_out, double* mu_out,
+                        int* naccepted, int* nrejected, double* h_next, const char* who) {
+  const FieldDev fd = to_dev(field);
+  const bool rec = t_out || mu_out;
+  double t = t0, h = h0;
+  int trials = 0;
+  while (t < t_end) {
+    RTCC_CHECK(trials < max_trials, kENotConv, std::string(who) + ": trial limit reached before t_end");
+    ++trials;
+    const double hh = std::min(h, t_end - t);
+    double mu6[6];
+    const double dl = emb_trial(c, y, t, hh, T, fd, mu_out ? mu6 : nullptr);
+    RTCC_CHECK(std::isfinite(dl), kENonFinite, std::string(who) + ": non-finite error estimate");
+    const double fac = ctl_factor(eps, dl, T.err_order);
+    if (dl <= eps) {
+      RTCC_CHECK(!rec || *naccepted < cap, kEInval, std::string(who) + ": output capacity exceeded");
+      RTCC_HIP(hipMemcpyAsync(y, c->y5, c->nstate * 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      t = (hh == t_end - t) ? t_end : t + hh;
+      if (t_out) t_out[*naccepted] = t;
+      if (mu_out)
+        for (int i = 0; i < 6; ++i) mu_out[6 * (int64_t)(*naccepted) + i] = mu6[i];
+      ++*naccepted;
+    } else {
+      ++*nrejected;
+    }
+    h = hh * fac;
+  }
+  if (h_next) *h_next = h;
+}
+
+// One implicit step (full A, s <= 3): Jacobi fixed-point sweeps over the stage derivatives, alternating
+// between the buffer sets k[0..2] and k[3..5]; the first sweep reads k[0] = f(t, y) for every stage.
+int implicit_step(rtcc_ctx* c, void* y, double t, double h, const rtcc_tableau& T, const FieldDev& fd, double tol,
+                  int max_iter) {
+  const int S = T.stages;
+  scalar_update(c->stream, c->tdev, t, false);
+  rhs_t(c, y, fd, 0.0, c->k[0]);
+  const void* old[3] = {c->k[0], c->k[0], c->k[0]};
+  int set = 1;  // the set the next sweep writes
+  for (int it = 1; it <= max_iter; ++it) {
+    void* nw[3] = {c->k[3 * set], c->k[3 * set + 1], c->k[3 * set + 2]};
+    for (int i = 0; i < S; ++i) {
+      double cs[3];
+      for (int j = 0; j < S; ++j) cs[j] = h * T.a[i][j];
+      rhs_t(c, StageIn{y, S, old, cs}, fd, T.c[i] * h, nw[i]);
+    }
+    for (int i = 0; i < S; ++i) max_abs_diff(c->stream, c->nstate, nw[i], old[i], c->red, c->redout + 2 * i);
+    double d[6];
+    sync_read(c, c->redout, d, 2 * S);
+    double dmax = 0.0;
+    for (int i = 0; i < S; ++i) {
+      RTCC_CHECK(std::isfinite(d[2 * i]), kENonFinite, "rtcc_step_tableau: non-finite stage change");
+      dmax = std::max(dmax, d[2 * i]);
+    }
+    for (int i = 0; i < S; ++i) old[i] = nw[i];
+    set ^= 1;
+    if (h * dmax <= tol) {
+      double cb[3];
+      for (int j = 0; j < S; ++j) cb[j] = h * T.b[j];
+      state_combo(c->stream, c->nstate, y, S, old, cb, y);
+      return it;
+    }
+  }
+  throw Error(kENotConv, "rtcc_step_tableau: stage iteration did not converge within max_iter sweeps");
 }
 
 }  // namespace
@@ -939,32 +1102,76 @@ int rtcc_propagate_cashkarp(rtcc_ctx* c, void* y, double t0, double t_end, doubl
   *naccepted = 0;
   *nrejected = 0;
   return guarded(c, [&] {
+    rtcc_tableau T;
+    builtin_tableau(RTCC_TAB_CASHKARP, T);
+    propagate_embedded(c, y, t0, t_end, h0, eps, T, field, max_trials, cap, t_out, mu_out, naccepted, nrejected,
+                       h_next, "rtcc_propagate_cashkarp");
+  });
+}
+
+int rtcc_propagate_embedded(rtcc_ctx* c, void* y, double t0, double t_end, double h0, double eps,
+                            const rtcc_tableau* tab, const rtcc_field* field, int max_trials, int cap,
+                            double* t_out, double* mu_out, int* naccepted, int* nrejected, double* h_next) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !std::isfinite(t0) || !std::isfinite(t_end) || !(t_end >= t0) || !(h0 > 0) || !std::isfinite(h0) ||
+      !(eps > 0) || max_trials < 1 || ((t_out || mu_out) && cap < 1) || !naccepted || !nrejected || !tab) {
+    c->err = "rtcc_propagate_embedded: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  *naccepted = 0;
+  *nrejected = 0;
+  return guarded(c, [&] {
+    check_tab(tab, true, "rtcc_propagate_embedded");
+    propagate_embedded(c, y, t0, t_end, h0, eps, *tab, field, max_trials, cap, t_out, mu_out, naccepted,
+                       nrejected, h_next, "rtcc_propagate_embedded");
+  });
+}
+
+int rtcc_tableau_builtin(int id, rtcc_tableau* out) {
+  if (!out) {
+    g_init_error = "rtcc_tableau_builtin: out is NULL";
+    return RTCC_EINVAL;
+  }
+  return guarded(nullptr, [&] { builtin_tableau(id, *out); });
+}
+
+int rtcc_step_tableau(rtcc_ctx* c, void* y, double t, double h, const rtcc_tableau* tab, const rtcc_field* field,
+                      double tol, int max_iter, double* delta, int* sweeps) {
+  if (!c) return RTCC_EINVAL;
+  if (!y || !tab || !std::isfinite(t) || !std::isfinite(h)) {
+    c->err = "rtcc_step_tableau: invalid arguments";
+    return RTCC_EINVAL;
+  }
+  return guarded(c, [&] {
+    check_tab(tab, false, "rtcc_step_tableau");
     const FieldDev fd = to_dev(field);
-    const bool rec = t_out || mu_out;
-    double t = t0, h = h0;
-    int trials = 0;
-    while (t < t_end) {
-      RTCC_CHECK(trials < max_trials, kENotConv, "rtcc_propagate_cashkarp: trial limit reached before t_end");
-      ++trials;
-      const double hh = std::min(h, t_end - t);
-      double mu6[6];
-      const double dl = ck_trial(c, y, t, hh, fd, mu_out ? mu6 : nullptr);
-      RTCC_CHECK(std::isfinite(dl), kENonFinite, "rtcc_propagate_cashkarp: non-finite error estimate");
-      const double fac = ck_factor(eps, dl);
-      if (dl <= eps) {
-        RTCC_CHECK(!rec || *naccepted < cap, kEInval, "rtcc_propagate_cashkarp: output capacity exceeded");
-        RTCC_HIP(hipMemcpyAsync(y, c->y5, c->nstate * 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        t = (hh == t_end - t) ? t_end : t + hh;
-        if (t_out) t_out[*naccepted] = t;
-        if (mu_out)
-          for (int i = 0; i < 6; ++i) mu_out[6 * (int64_t)(*naccepted) + i] = mu6[i];
-        ++*naccepted;
-      } else {
-        ++*nrejected;
-      }
-      h = hh * fac;
+    const rtcc_tableau& T = *tab;
+    if (!tab_explicit(T)) {
+      RTCC_CHECK(tol > 0 && std::isfinite(tol) && max_iter >= 1, kEInval,
+                 "rtcc_step_tableau: implicit tableaux need tol > 0 and max_iter >= 1");
+      const int it = implicit_step(c, y, t, h, T, fd, tol, max_iter);
+      if (sweeps) *sweeps = it;
+      return;
     }
-    if (h_next) *h_next = h;
+    scalar_update(c->stream, c->tdev, t, false);
+    explicit_stages(c, y, h, T, fd);
+    const void* ks[RTCC_MAX_STAGES];
+    double cb[RTCC_MAX_STAGES], ce[RTCC_MAX_STAGES];
+    for (int j = 0; j < T.stages; ++j) {
+      ks[j] = c->k[j];
+      cb[j] = h * T.b[j];
+      ce[j] = h * T.b_err[j];
+    }
+    const bool est = T.err_order > 0 && delta;
+    if (est) state_combo(c->stream, c->nstate, y, T.stages, ks, ce, c->y4);
+    state_combo(c->stream, c->nstate, y, T.stages, ks, cb, y);
+    if (est) {
+      max_abs_diff(c->stream, c->nstate, y, c->y4, c->red, c->redout);
+      double d[2];
+      sync_read(c, c->redout, d, 2);
+      *delta = d[0];
+    }
+    if (sweeps) *sweeps = 1;
   });
 }
 
@@ -1156,10 +1363,12 @@ int rtcc_step_cashkarp(rtcc_ctx* c, void* y, double* t, double* h, double eps, c
   }
   return guarded(c, [&] {
     const double hh = *h;
-    const double dl = ck_trial(c, y, *t, hh, to_dev(field), nullptr);
+    rtcc_tableau T;
+    builtin_tableau(RTCC_TAB_CASHKARP, T);
+    const double dl = emb_trial(c, y, *t, hh, T, to_dev(field), nullptr);
     if (delta) *delta = dl;
     RTCC_CHECK(std::isfinite(dl), kENonFinite, "rtcc_step_cashkarp: non-finite error estimate");
-    const double fac = ck_factor(eps, dl);
+    const double fac = ctl_factor(eps, dl, T.err_order);
     if (dl <= eps) {
       RTCC_HIP(hipMemcpyAsync(y, c->y5, c->nstate * 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
       *t += hh;

@@ -64,3 +64,37 @@ def test_mixed_schedule_matches_oracle_plan():
     short = np.zeros(3)
     assert L.rtcc_mixed_schedule(0.0, 1.0, 0.1, 0.1, None, 3, short.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                  ctypes.byref(n)) == -1
+
+
+def test_builtin_tableaux_match_oracle():
+    """The library's tableaux (host-only call) against the oracle's: RK4 and the corrected Cash-Karp and
+    Fehlberg pairs exactly as published, Gauss-Legendre against the oracle's collocation construction."""
+    from oracle import integrators as I
+    P, L = _lib()
+
+    def dense(A, s):
+        return np.array([[float(A[i][j]) if j < len(A[i]) else 0.0 for j in range(s)] for i in range(s)])
+
+    cases = {
+        "rk4": (dense(I.RK4_A, 4), I.RK4_B, I.RK4_C, [0.0] * 4, 0),
+        "cashkarp": (dense(I.CK_A, 6), I.CK_B5, I.CK_C, I.CK_B4, 4),
+        "rkf45": (dense(I.RKF45_A, 6), I.RKF45_B4, I.RKF45_C, I.RKF45_B5, 4),
+    }
+    for name, (A, b, c, be, p) in cases.items():
+        T = P.Tableau.builtin(name)
+        TA, Tb, Tc, Tbe = T.arrays()
+        assert T.err_order == p
+        assert np.array_equal(TA, A), name
+        assert np.array_equal(Tb, np.array([float(x) for x in b]))
+        assert np.array_equal(Tc, np.array([float(x) for x in c]))
+        assert np.array_equal(Tbe, np.array([float(x) for x in be]))
+    for name, s in (("gl2", 2), ("gl3", 3)):
+        T = P.Tableau.builtin(name)
+        TA, Tb, Tc, _ = T.arrays()
+        c, A, b = I.gauss_legendre_tableau(s)
+        assert T.err_order == 0 and T.stages == s
+        assert np.allclose(TA, A, atol=4e-15, rtol=0) and np.allclose(Tb, b, atol=4e-15, rtol=0)
+        assert np.allclose(Tc, c, atol=1e-15, rtol=0)
+    with pytest.raises(P.RTCCError):
+        P.Tableau.builtin(99)
+    assert L.rtcc_tableau_builtin(1, None) == -1
