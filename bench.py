@@ -16,8 +16,10 @@ runs on, around every launch of a second, eagerly issued pass of the timed steps
 is timed on a bounded sample on the host (see ``cpu_baseline.sample``).
 
 Other workloads: ``--workload spectrum`` (RK4 and adaptive Cash-Karp to t = 100 au in every
-precision, absorption-peak shifts against FP64), ``batch`` (24 propagations in one captured
-graph per step), ``adjoint`` (pulse-parameter gradient at (10,38)).
+precision, absorption-peak shifts against FP64), ``sp-spectra`` (the paper's narrow-pulse double- vs
+single-precision spectra at (5,19) and (10,38) to t = 300 au, and the dipole noise-injection study),
+``batch`` (24 propagations in one captured graph per step), ``adjoint`` (pulse-parameter gradient at
+(10,38)).
 """
 from __future__ import annotations
 
@@ -411,6 +413,90 @@ def bench_spectrum(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_sp_spectra(args):
+    """Double- vs single-precision spectra with the paper's narrow pulse (Results, single precision):
+    E0 = 0.01 au, nu = 0.05 au, sigma = 0.01 au, no carrier, isotropic n, RK4 at h = 0.01 au to
+    t = 300 au, for each synthetic size in --sizes and every contraction precision; then the noise
+    study on the FP64 trajectory (uniform noise of magnitude 1e-9 ... 1e-3 au added to the dipole)."""
+    import torch
+    from paper_2205_05175_amd import RTCC, Field
+    from paper_2205_05175_amd import spectrum as spc
+    from synth import make_system
+
+    dt, T = args.dt, args.t_end
+    E0, nu, sigma = 0.01, 0.05, 0.01
+    n_iso = np.ones(3) / np.sqrt(3.0)
+    kappa = -E0 * sigma * np.sqrt(2.0 * np.pi)  # integral of the pulse: the equivalent kick
+    nsteps = int(round(T / dt))
+    mags = [10.0 ** k for k in range(-9, -2)]
+    sizes = [tuple(int(x) for x in s.split("x")) for s in args.sizes.split(",") if s]
+    out = {}
+    for o, v in sizes:
+        eri, fock, mu = make_system(o, v, 0)
+        R = RTCC(eri, fock, mu, o, v, precision="fp32")
+        del eri
+        y0 = R.new_state()
+        R.set_precision("fp64")
+        R.ground_state(y0, 1e-10, 200)
+        d_gs = float(np.dot(n_iso, R.dipole(y0).real))
+        fld = Field.gaussian(E0, 0.0, sigma, nu, n_iso)
+        traj = {}
+        for prec in ("fp64", "fp32", "bf16x3"):
+            R.set_precision(prec)
+            y = y0.clone()
+            m = torch.zeros((nsteps + 1, 6), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            done = 0
+            while done < nsteps:
+                n = min(2000, nsteps - done)
+                R.propagate_rk4(y, done * dt, dt, n, fld, m[done:done + n + 1])
+                torch.cuda.synchronize()
+                done += n
+                log(f"[bench] sp-spectra ({o},{v}) {prec}: {done}/{nsteps} steps")
+            te = time.perf_counter() - ts
+            mm = m.cpu().numpy()
+            traj[prec] = {"d": mm[:, 0::2] @ n_iso - d_gs, "s": te, "nonfinite": R.check_state(y)}
+        R.close()
+        # samples at t_k = k dt, the pulse centred at nu: time origin of the response at the pulse
+        d64 = traj["fp64"]["d"]
+        w, s64 = spc.absorption(d64, dt, kappa, t0=-nu)
+        p64 = spc.find_peaks(w, s64)
+        res = {"fp64_peaks_Eh": [p.omega for p in p64], "steps_per_s": {}, "vs_fp64": {}}
+        for prec, tr in traj.items():
+            res["steps_per_s"][prec] = nsteps / tr["s"]
+            if prec == "fp64":
+                continue
+            _, sp_ = spc.absorption(tr["d"], dt, kappa, t0=-nu)
+            c = spc.match_peaks(p64, spc.find_peaks(w, sp_))
+            res["vs_fp64"][prec] = {"dipole_max_abs": float(np.abs(tr["d"] - d64).max()),
+                                    "peak_shift_max": c.max_shift, "peaks_matched": len(c.pairs),
+                                    "unmatched": c.unmatched_ref + c.unmatched_other,
+                                    "nonfinite": tr["nonfinite"]}
+        study = spc.noise_study(d64, dt, kappa, mags, seed=0, t0=-nu)
+        res["noise_study_fp64"] = [{"magnitude": r.magnitude, "unchanged": r.unchanged,
+                                    "peak_shift_max": r.comparison.max_shift,
+                                    "unmatched": len(r.comparison.unmatched_ref) + len(r.comparison.unmatched_other),
+                                    "low_freq_peaks": r.low_freq_peaks, "max_rel_change": r.max_rel_change}
+                                   for r in study]
+        res["first_noise_magnitude_that_changes_spectrum"] = next((r.magnitude for r in study if not r.unchanged), None)
+        res["induced_dipole_max_abs"] = float(np.abs(d64).max())
+        out[f"{o}x{v}"] = res
+    worst = max(r["vs_fp64"][p]["peak_shift_max"] for r in out.values() for p in ("fp32", "bf16x3"))
+    line = {
+        "metric": "absorption-peak shift, single vs double precision (paper's narrow pulse, RK4 h=0.01 to t=300 au)",
+        "value": worst, "unit": "Eh", "n_gpus": 1, "steps": nsteps, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32/bf16x3", "data": "synthetic",
+        "config": {"workload": f"rt-ccsd water-cluster-shaped synthetic {args.sizes} seed 0, Gaussian pulse E0={E0} "
+                               f"nu={nu} sigma={sigma} au along (1,1,1)/sqrt3, RK4 h={dt} to t={T} au; noise study "
+                               f"on the FP64 dipole (uniform, magnitudes 1e-9..1e-3 au)",
+                   "parallelism": "single GPU"},
+        "sizes": out, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_profile(args):
     """Only the RK4 steps of one precision at (o, v), from a random non-stationary state (no ground state,
     no kick, no oracle): the command to run under rocprofv3 so that its kernel summary holds the step's
@@ -441,7 +527,8 @@ def bench_profile(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["single", "spectrum", "batch", "adjoint", "profile"], default="single",
+    ap.add_argument("--workload", choices=["single", "spectrum", "sp-spectra", "batch", "adjoint", "profile"],
+                    default="single",
                     help="single: the o=20 v=76 propagation (default); spectrum: RK4 and Cash-Karp to t=100 au "
                          "with peak shifts; batch: 24 batched propagations; adjoint: pulse-parameter gradient at (10,38)")
     ap.add_argument("--steps", type=int, default=None)
@@ -455,6 +542,7 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-6, help="spectrum workload: Cash-Karp tolerance")
     ap.add_argument("--eps-sweep", default="", help="spectrum workload: further Cash-Karp tolerances, split-BF16 only "
                                                     "(comma-separated)")
+    ap.add_argument("--sizes", default="5x19,10x38", help="sp-spectra workload: synthetic sizes oxv")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3",
                     help="single workload: the precisions to run (profiling one at a time); the JSON line needs all three")
@@ -472,6 +560,12 @@ def main():
         if args.steps is None:
             args.steps = 200
         return bench_adjoint(args)
+    if args.workload == "sp-spectra":
+        if "--dt" not in sys.argv:
+            args.dt = 0.01
+        if "--t-end" not in sys.argv:
+            args.t_end = 300.0
+        return bench_sp_spectra(args)
     if args.workload == "spectrum":
         return bench_spectrum(args)
     if args.workload == "profile":

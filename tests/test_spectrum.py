@@ -99,3 +99,38 @@ def test_spline_resampling_of_adaptive_samples():
     assert np.max(np.abs(x - f(grid))) < 1e-7
     with pytest.raises(ValueError):
         sp.resample_uniform([0.0, 0.1, 0.1], [0, 1, 2], DT)
+
+
+def test_noise_samples_are_bounded_and_seeded():
+    a = sp.uniform_noise(10000, 3e-5, 7)
+    assert np.abs(a).max() <= 3e-5 and np.abs(a).max() > 2.9e-5
+    assert np.array_equal(a, sp.uniform_noise(10000, 3e-5, 7))
+    assert abs(a.mean()) < 3e-5 * 0.05  # centred
+
+
+def test_noise_change_is_linear_and_bounded():
+    """The FFT is linear: the spectrum change is m times the spectrum of the unit noise pattern, and
+    |dS(w)| <= w m sum_k exp(-gamma t_k) dt / kappa (every sample moves by at most m)."""
+    n = int(round(T / DT)) + 1
+    _, d = _signal(COMPS, n)
+    w, s0 = sp.absorption(d, DT, KAPPA)
+    unit = sp.uniform_noise(n, 1.0, 3)
+    ds = {}
+    for m in (1e-7, 1e-5):
+        _, s1 = sp.absorption(d + m * unit, DT, KAPPA)
+        ds[m] = s1 - s0
+    assert np.allclose(ds[1e-5], 100.0 * ds[1e-7], rtol=1e-6, atol=1e-9 * np.abs(ds[1e-5]).max())
+    gamma = sp.WINDOW_DECAY / T
+    wsum = np.sum(np.exp(-gamma * DT * np.arange(n))) * DT
+    assert np.all(np.abs(ds[1e-5]) <= w * 1e-5 * wsum / KAPPA * (1 + 1e-12))
+
+
+def test_noise_study_threshold():
+    """Noise far below the signal leaves every peak in place; noise of the signal's size does not."""
+    n = int(round(T / DT)) + 1
+    _, d = _signal(COMPS, n)
+    res = sp.noise_study(d, DT, KAPPA, [1e-10, 1e-8, 1e-3], seed=1)
+    assert res[0].unchanged and res[0].comparison.max_shift < 1e-6 and res[0].max_rel_change < 1e-5
+    assert res[1].unchanged and res[1].max_rel_change < 1e-3
+    assert not res[2].unchanged and res[2].max_rel_change > 0.1
+    assert res[0].max_rel_change < res[1].max_rel_change < res[2].max_rel_change
