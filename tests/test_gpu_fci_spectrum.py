@@ -8,10 +8,11 @@ dt = 0.05 au to t = 300 au in FP64, complex FP32 and split-BF16 (forced onto eve
 Checked:
 * the FP64 GPU trajectory equals the exact TD-FCI dipole (eigen-decomposition of the determinant
   Hamiltonian of the oracle's brute-force module) to the RK4 error, and its spectrum peaks equal the
-  exact signal's peaks through the same pipeline;
+  exact signal's peaks through the same pipeline up to RK4's dispersion, w (h w)^4 / 120;
 * every FCI excitation with oscillator weight omega |<n|mu_z|0>|^2 above 5% of the largest has a
-  spectrum peak within 1e-3 Eh (the finite window moves a peak by ~1e-4 Eh), and every peak above 5%
-  has such an excitation;
+  spectrum peak, and every peak above 5% has such an excitation, within a fifth of the window's
+  Lorentzian half-width gamma = 4.6 / T = 0.015 Eh (an isolated peak lands ~1e-4 Eh from its
+  excitation; a weak one beside a strong one is pulled by the strong one's tail, here by 1.1e-3 Eh);
 * FP32 and split-BF16 spectra: the same peaks as FP64 within 1e-4 Eh.
 """
 import numpy as np
@@ -91,15 +92,20 @@ def test_two_electron_spectrum_matches_fci_sticks(monkeypatch):
     p64 = sp.find_peaks(w, s64)
     cmp = sp.match_peaks(p_exact, p64)
     print(f"  peaks {[round(p.omega, 5) for p in p64]}; vs exact signal max shift {cmp.max_shift:.2e}", flush=True)
-    assert cmp.ok and cmp.max_shift < 2e-5
+    # RK4 advances a mode of frequency w with phase error (h w)^5 / 120 per step, i.e. it oscillates at
+    # w (1 - (h w)^4 / 120): allow twice that dispersion (3.7e-5 Eh at the 3.72 Eh peak) plus rounding
+    assert cmp.ok
+    for a, b in cmp.pairs:
+        assert abs(a - b) <= 2 * a * (DT * a) ** 4 / 120 + 2e-6, (a, b)
 
+    tol = 0.2 * 4.6 / T_END
     allowed = exc > 1e-6
     strong = allowed & (weight >= 0.05 * weight.max())
     for e in exc[strong]:
-        assert min(abs(p.omega - e) for p in p64) < 1e-3, f"FCI excitation {e:.5f} Eh has no peak"
+        assert min(abs(p.omega - e) for p in p64) < tol, f"FCI excitation {e:.5f} Eh has no peak"
     visible = exc[allowed & (weight >= 1e-3 * weight.max())]
     for p in p64:
-        assert np.abs(visible - p.omega).min() < 1e-3, f"peak {p.omega:.5f} Eh is no FCI excitation"
+        assert np.abs(visible - p.omega).min() < tol, f"peak {p.omega:.5f} Eh is no FCI excitation"
 
     # the same spectrum from complex-FP32 and split-BF16 contractions (split forced onto every product)
     monkeypatch.setenv("RTCC_BF16_MIN_FLOPS", "0")
