@@ -40,7 +40,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6}
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by the
 # same counter on a plain device copy of the same run (the 72,247.5 KiB state clone: FETCH_SIZE
 # 36,139.2 KiB, x2.0; WRITE_SIZE 72,247.5 KiB, x1.0). Commands and raw figures:
-# profiles/ladder_traffic_o20v76.md. To be re-measured whenever that kernel changes.
+# profiles/ladder_traffic_o20v76.md. To be re-measured whenever that kernel changes. It applies to the
+# full ladder product (RTCC_LADDER=full); the default symmetric / antisymmetric form has no figure.
 LADDER_TRAFFIC_BF16X3 = {"fetch_bytes": 246305.8 * 1024 * 2.0, "write_bytes": 38464.0 * 1024 * 1.0,
                          "kernel": "gemm_bf16x3_nt<1, 0, 1, 4>"}
 
@@ -479,7 +480,9 @@ def bench_sp_spectra(args):
                                     "unmatched": len(r.comparison.unmatched_ref) + len(r.comparison.unmatched_other),
                                     "low_freq_peaks": r.low_freq_peaks, "max_rel_change": r.max_rel_change}
                                    for r in study]
-        res["first_noise_magnitude_that_changes_spectrum"] = next((r.magnitude for r in study if not r.unchanged), None)
+        res["first_noise_magnitude_that_loses_peaks"] = next((r.magnitude for r in study if not r.unchanged), None)
+        res["first_noise_magnitude_shifting_peaks_over_1e-4_Eh"] = next(
+            (r.magnitude for r in study if r.comparison.max_shift > 1e-4 or not r.unchanged), None)
         res["induced_dipole_max_abs"] = float(np.abs(d64).max())
         out[f"{o}x{v}"] = res
     worst = max(r["vs_fp64"][p]["peak_shift_max"] for r in out.values() for p in ("fp32", "bf16x3"))
@@ -650,7 +653,8 @@ def main():
     # else complex FP32
     head = "bf16x3" if bf16_err <= 1e-6 else "fp32"
     rh = results[head]
-    measured_traffic = head == "bf16x3" and (o, v) == (20, 76)
+    full_ladder = os.environ.get("RTCC_LADDER", "symmetric") == "full"
+    measured_traffic = head == "bf16x3" and (o, v) == (20, 76) and full_ladder
     peak = PEAK_TFLOPS["fp32"] if head == "fp32" else PEAK_TFLOPS["bf16"] / 3
     line = {
         "metric": "RK4 steps/s (T+Λ RHS) o=20,v=76: FP32-MFMA vs FP64, dipole err vs oracle",
@@ -661,7 +665,9 @@ def main():
                                f"delta kick 1e-3 z, RK4 dt={args.dt}", "o": o, "v": v,
                    "precision": ("split-bf16 three-term products (complex, fp32 accumulate) on products above "
                                  "5e8 flop, fp32 elsewhere, fp64 state" if head == "bf16x3" else
-                                 "complex fp32 contractions, fp64 state"), "parallelism": "single GPU"},
+                                 "complex fp32 contractions, fp64 state"), "parallelism": "single GPU",
+                   "ladder": "full o^2 v^4 product" if full_ladder else
+                             "symmetric/antisymmetric pair-triangle products (a quarter of the flops)"},
         "headline_path": head,
         "gate": {"steps": G, "t_au": G * args.dt, "bound_au": 1e-6,
                  "dipole_bf16x3_vs_fp64_max_abs": bf16_err, "dipole_fp32_vs_fp64_max_abs": fp32_err},
@@ -671,7 +677,9 @@ def main():
         "fp32_over_fp64": r32["steps_per_s"] / results["fp64"]["steps_per_s"],
         "bf16x3_over_fp64": rbf["steps_per_s"] / results["fp64"]["steps_per_s"],
         "dipole_fp64_gpu_vs_oracle_max_abs": oracle_err,
-        "roofline": {"bound": "mfma", "kernel": f"ladder GEMM ({head})", "achieved": rh["ladder_tflops"],
+        "roofline": {"bound": "mfma", "kernel": (f"ladder GEMM ({head})" if full_ladder else
+                                                 f"ladder GEMMs X+V+ and X-V- ({head})"),
+                     "achieved": rh["ladder_tflops"],
                      "peak": peak, "unit": "TFLOP/s", "frac": rh["ladder_tflops"] / peak,
                      "peak_note": ("fp32 MFMA peak" if head == "fp32" else "bf16 dense MFMA peak / 3 products per "
                                    "real multiply (algorithmic fp32-equivalent flops)"),

@@ -281,9 +281,13 @@ int rtcc_check_state(rtcc_ctx* ctx, const void* y, int64_t* nonfinite);
  * its kernels one by one instead of replaying the captured step graph (events recorded inside a
  * captured graph cannot be timed); rtcc_propagate_batch does the same when any of its contexts
  * is profiling, and times that context's batched ladder. rtcc_profile_read synchronises and returns
- * the number of timed launches, their summed duration in ms and the algorithmic real flops of the
- * last timed launch (4 * rows * v^2 * v^2 for rows = 2 o^2 complex rows per member times the real
- * <ab|ef> matrix). */
+ * the number of timed launches, their summed duration in ms and the algorithmic real flops per
+ * launch, averaged over the timed launches (real x complex products: 4 flops per row, column and k).
+ * The ladder is by default the two GEMMs of its symmetric / antisymmetric form, X+ V+ over the
+ * (i <= j) x (e <= f) and X- V- over the (i < j) x (e < f) pair triangles (rows o(o+1) and o(o-1) per
+ * member for tau and lambda2, K = N = v(v+1)/2 and v(v-1)/2), a quarter of the flops of the full
+ * product of 2 o^2 rows with the v^2 x v^2 matrix <ab|ef>; the environment variable RTCC_LADDER=full,
+ * read by rtcc_init, selects the full product (one launch, 4 * 2 o^2 * v^4 flops). */
 int rtcc_profile(rtcc_ctx* ctx, int enable);
 int rtcc_profile_read(rtcc_ctx* ctx, int64_t* launches, double* total_ms, double* flops_per_launch);
 

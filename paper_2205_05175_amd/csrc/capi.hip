@@ -236,10 +236,12 @@ void prof_flush(rtcc_ctx* c) {
 void prof_mark(void* user, int phase, double flops, hipStream_t st) {
   rtcc_ctx* c = (rtcc_ctx*)user;
   if (!c->prof) return;
-  c->prof_flops = flops;
   if (phase == 0 && c->ev_used + 2 > (int)c->ev.size()) prof_flush(c);
   RTCC_HIP(hipEventRecord(c->ev[c->ev_used++], st));
-  if (phase == 1) c->prof_launches++;
+  if (phase == 1) {
+    c->prof_launches++;
+    c->prof_flops += flops;  // the ladder may be one GEMM or two of different sizes
+  }
 }
 
 FieldDev to_dev(const rtcc_field* f) {
@@ -393,6 +395,7 @@ void ensure_batch(rtcc_ctx* c, std::unique_ptr<BatchWS>& slot, int nb) {
   B->E.trace = c->E.trace;
   B->E.bf16_min_flops = c->E.bf16_min_flops;
   B->E.bf16_kernel = c->E.bf16_kernel;
+  B->E.sym_ladder = c->E.sym_ladder;
   B->E.scratch.cap = c->E.scratch.cap * (size_t)nb;
   B->E.scratch.base = B->arena.alloc<char>(B->E.scratch.cap);
   build_work<double>(B->arena, c->o, c->v, B->W64, nb);
@@ -871,6 +874,12 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     const char* bk = std::getenv("RTCC_BF16_KERNEL");
     if (bk && bk[0]) c->E.bf16_kernel = std::atoi(bk);
     RTCC_CHECK(c->E.bf16_kernel >= 1 && c->E.bf16_kernel <= 4, kEInval, "RTCC_BF16_KERNEL must be 1 to 4");
+    const char* lm = std::getenv("RTCC_LADDER");
+    if (lm && lm[0]) {
+      RTCC_CHECK(!std::strcmp(lm, "full") || !std::strcmp(lm, "symmetric"), kEInval,
+                 "RTCC_LADDER must be full or symmetric");
+      c->E.sym_ladder = std::strcmp(lm, "full") != 0;
+    }
     const char* ng = std::getenv("RTCC_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');
     const char* tr = std::getenv("RTCC_TRACE");
@@ -1539,6 +1548,7 @@ int rtcc_profile(rtcc_ctx* c, int enable) {
       prof_flush(c);
       c->prof_launches = 0;
       c->prof_ms = 0.0;
+      c->prof_flops = 0.0;
     }
     c->prof = enable != 0;
     c->E.mark = enable ? prof_mark : nullptr;
@@ -1552,7 +1562,7 @@ int rtcc_profile_read(rtcc_ctx* c, int64_t* launches, double* total_ms, double* 
     prof_flush(c);
     *launches = c->prof_launches;
     *total_ms = c->prof_ms;
-    *flops_per_launch = c->prof_flops;
+    *flops_per_launch = c->prof_launches ? c->prof_flops / (double)c->prof_launches : 0.0;
   });
 }
 

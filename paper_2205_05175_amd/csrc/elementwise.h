@@ -50,6 +50,17 @@ void dot_planar_real(hipStream_t st, int64_t n, const T* are, const T* aim, cons
 void max_abs_diff(hipStream_t st, int64_t n, const void* a, const void* b, double* partial, double* out2);
 void vdot(hipStream_t st, int64_t n, const void* a, const void* b, double* partial, double* out2);
 void count_nonfinite(hipStream_t st, int64_t n, const void* a, double* partial, double* out2);
+// Symmetric / antisymmetric ladder (ladder.hip). nblk blocks of o*o*v*v consecutive entries X[blk][i][j][e][f]
+// (pair-symmetric: X_ji^fe = X_ij^ef) -> X+ rows (blk, i <= j) x (e <= f) and X- rows (blk, i < j) x (e < f);
+// back: Z[blk][i][j][a][b] = S+(pairs) +- S-(pairs) over the full square. Row-major upper-triangle pair order.
+template <typename T>
+void ladder_fold(hipStream_t st, int nblk, int o, int v, const T* xre, const T* xim, T* pre, T* pim, T* mre, T* mim);
+template <typename T>
+void ladder_unfold(hipStream_t st, int nblk, int o, int v, const T* sre, const T* sim, const T* are, const T* aim,
+                   T* zre, T* zim);
+// V+ (v(v+1)/2 square) and V- (v(v-1)/2 square) from <ab|ef> as the v^2 x v^2 matrix [(ab)][(ef)].
+void ladder_sym_build(hipStream_t st, int v, const double* vvvv, double* vp, double* vm);
+
 // Largest number of reduction blocks of state_guard (it needs 2 * kGuardBlocks partial doubles).
 constexpr int kGuardBlocks = 512;
 // out2[0] = Frobenius norm of the entries [t2b, t2e) of the interleaved complex vector y (NaN if any of

@@ -124,6 +124,9 @@ struct Engine {
   bool trace = false;         // print every contraction's layout decisions to stderr
   bool bf16x3 = false;        // FP32 GEMMs above bf16_min_flops use the split-BF16 three-term kernel
   double bf16_min_flops = 5e8;
+  // particle-particle ladder in its symmetric / antisymmetric form (two GEMMs over pair triangles);
+  // false: one GEMM over the full o^2 x v^2 x v^2 product
+  bool sym_ladder = true;
   int bf16_kernel = 1;  // split-BF16 kernel: 1 register-staged, 2 direct-to-LDS ring, 3 the ring at 2 per CU,
                         // 4 wide waves (64 x 128 per wave)
   bool use_tuning = true;               // consult the tuning table (single, non-batched products)

@@ -48,6 +48,7 @@ struct Arena {
 template <typename T>
 struct Ints {
   Ten<T> oooo, ooov, oovv, ovov, ovvo, ovvv, vvvv, Loovv, Looov, Lovvv, Lovvo;
+  Ten<T> vvp, vvm;  // symmetric / antisymmetric ladder integrals over the (e <= f) and (e < f) pairs
 };
 
 template <typename T>
@@ -58,6 +59,7 @@ struct Work {
   Ten<T> Fae, Fmi, Fme, Hvv, Hoo, Gvv, Goo, Q, Gx;  // one-body
   Ten<T> W, M, Mp, Hooov, Z1, Y, U, U2, Y3, Y6, B4, B5, B7, D, Nn, Xin, Qnf;
   Ten<T> Lad, LadT, LadL;
+  Ten<T> Xp, Xm, Sp, Sm;                           // symmetric / antisymmetric ladder operands and products
   Ten<T> Pd, Px, Bd, Bx, WW, Wd, Wx, HH, HHd, HHx, HH5, T2R, L2R, Zt, ZLt, B2, B3, Wr;
   Ten<T> Z, ZL, S1t;                               // (1+P) brackets; t1-t1 ring piece
   Ten<T> R1, R2, S1, S2;                           // residuals: R_T (T1,T2), R_L (L1,L2)

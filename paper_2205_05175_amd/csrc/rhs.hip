@@ -40,7 +40,7 @@ void extract(Engine& E, const double* eri, int n, int p0, int q0, int r0, int s0
 template <typename T>
 void mark_constant(Ints<T>& I) {
   for (Ten<T>* t : {&I.oooo, &I.ooov, &I.oovv, &I.ovov, &I.ovvo, &I.ovvv, &I.vvvv, &I.Loovv, &I.Looov, &I.Lovvv,
-                    &I.Lovvo})
+                    &I.Lovvo, &I.vvp, &I.vvm})
     t->konst = true;
 }
 
@@ -71,6 +71,10 @@ void build_ints<double>(Engine& E, Arena& A, int o, int v, const double* eri, In
   extract<double>(E, eri, n, 0, o, o, 0, I.ovvo);
   extract<double>(E, eri, n, 0, o, o, o, I.ovvv);
   extract<double>(E, eri, n, o, o, o, o, I.vvvv);
+  const int64_t pv = (int64_t)v * (v + 1) / 2, mv = (int64_t)v * (v - 1) / 2;
+  I.vvp = A.real<double>({pv, pv});
+  I.vvm = A.real<double>({mv, mv});
+  ladder_sym_build(E.stream, v, I.vvvv.re, I.vvp.re, I.vvm.re);
   I.Loovv = A.real<double>({o, o, v, v});
   I.Looov = A.real<double>({o, o, o, v});
   I.Lovvv = A.real<double>({o, v, v, v});
@@ -99,6 +103,7 @@ void build_ints<float>(Engine& E, Arena& A, int o, int v, const double* eri, Int
       t.s[i] = src.s[i];
     }
     int64_t nel = src.size();
+    if (nel == 0) return t;  // e.g. the antisymmetric ladder block at v = 1
     hipLaunchKernelGGL(convert_kernel, dim3((unsigned)std::min<int64_t>(cdiv(nel, 256), 65536)), dim3(256), 0,
                        E.stream, nel, src.re, t.re);
     RTCC_HIP(hipGetLastError());
@@ -111,6 +116,8 @@ void build_ints<float>(Engine& E, Arena& A, int o, int v, const double* eri, Int
   I.ovvo = cvt(D.ovvo);
   I.ovvv = cvt(D.ovvv);
   I.vvvv = cvt(D.vvvv);
+  I.vvp = cvt(D.vvp);
+  I.vvm = cvt(D.vvm);
   I.Loovv = cvt(D.Loovv);
   I.Looov = cvt(D.Looov);
   I.Lovvv = cvt(D.Lovvv);
@@ -172,6 +179,14 @@ void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
   w.Lad = A.cplx<T>({2, o, o, v, v});
   w.LadT = view(w.Lad, 0, {o, o, v, v}, {o * v * v, v * v, v, 1});
   w.LadL = view(w.Lad, oovv, {o, o, v, v}, {o * v * v, v * v, v, 1});
+  {
+    const int64_t po = (int64_t)o * (o + 1) / 2, pm = (int64_t)o * (o - 1) / 2;
+    const int64_t pv = (int64_t)v * (v + 1) / 2, mv = (int64_t)v * (v - 1) / 2;
+    w.Xp = A.cplx<T>({2, po, pv});
+    w.Sp = A.cplx<T>({2, po, pv});
+    w.Xm = A.cplx<T>({2, std::max<int64_t>(pm, 1), std::max<int64_t>(mv, 1)});
+    w.Sm = A.cplx<T>({2, std::max<int64_t>(pm, 1), std::max<int64_t>(mv, 1)});
+  }
   // ring intermediates, element X_mbej stored at (m,e,j,b)
   w.Pd = A.cplx<T>({o, v, o, v});
   w.Px = A.cplx<T>({o, v, o, v});
@@ -331,10 +346,37 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
     C(-1, "jf,mbfe->mejb", t1, I.ovvv, w.Bx, 1);
 
     if (par) cur = E.br[0];
-    // particle-particle ladder: one GEMM over the stacked [tau; lambda2] rows
-    {
+    // particle-particle ladder: one GEMM over the stacked [tau; lambda2] rows, or the two GEMMs of its
+    // symmetric / antisymmetric form over the pair triangles (a quarter of the flops)
+    const int nblk = E.nb * (lambda || E.nb > 1 ? 2 : 1);
+    if (E.sym_ladder) {
+      const int64_t vv = (int64_t)v * v;
+      RTCC_CHECK(E.nb == 1 || (w.X.bs == 2 * (int64_t)o * o * vv && w.Lad.bs == w.X.bs &&
+                               w.Xp.bs == 2 * w.Xp.d[1] * w.Xp.d[2] && w.Xm.bs == 2 * w.Xm.d[1] * w.Xm.d[2] &&
+                               w.Sp.bs == w.Xp.bs && w.Sm.bs == w.Xm.bs),
+                 kEInval, "ladder operands are not member-contiguous");
+      const int64_t po = (int64_t)o * (o + 1) / 2, pm = (int64_t)o * (o - 1) / 2;
+      const int64_t pv = (int64_t)v * (v + 1) / 2, mv = (int64_t)v * (v - 1) / 2;
+      ladder_fold<T>(cur->stream, nblk, o, v, w.X.re, w.X.im, w.Xp.re, w.Xp.im, w.Xm.re, w.Xm.im);
+      const bool split16 = sizeof(T) == 4 && cur->bf16x3;  // the split-BF16 path marks its kernel itself
+      const int64_t rows_[2] = {nblk * po, nblk * pm}, kn[2] = {pv, mv};
+      const Ten<T>* ops[2][3] = {{&w.Xp, &I.vvp, &w.Sp}, {&w.Xm, &I.vvm, &w.Sm}};
+      for (int h = 0; h < 2; ++h) {
+        if (rows_[h] == 0 || kn[h] == 0) continue;
+        GemmOp<T> a{ops[h][0]->re, ops[h][0]->im, kn[h], 0};
+        GemmOp<T> b{ops[h][1]->re, nullptr, kn[h], 1, true};  // V+- are symmetric matrices
+        E.ladder_flops = 4.0 * (double)rows_[h] * (double)kn[h] * (double)kn[h];
+        cur->ladder_flops = E.ladder_flops;
+        cur->ladder = 1;
+        if (E.mark && !split16) E.mark(E.mark_user, 0, E.ladder_flops, cur->stream);
+        gemm<T>(*cur, rows_[h], kn[h], kn[h], 1.0, a, b, ops[h][2]->re, ops[h][2]->im, kn[h], 0.0);
+        if (E.mark && !split16) E.mark(E.mark_user, 1, E.ladder_flops, cur->stream);
+        cur->ladder = 0;
+      }
+      ladder_unfold<T>(cur->stream, nblk, o, v, w.Sp.re, w.Sp.im, w.Sm.re, w.Sm.im, w.Lad.re, w.Lad.im);
+    } else {
       // batched: the members' [tau; lambda2] blocks are consecutive rows of one operand
-      const int64_t rows = E.nb * (lambda || E.nb > 1 ? 2 : 1) * (int64_t)o * o, vv = (int64_t)v * v;
+      const int64_t rows = nblk * (int64_t)o * o, vv = (int64_t)v * v;
       RTCC_CHECK(E.nb == 1 || w.X.bs == 2 * (int64_t)o * o * vv, kEInval, "ladder operand is not member-contiguous");
       GemmOp<T> a{w.X.re, w.X.im, vv, 0};
       GemmOp<T> b{I.vvvv.re, nullptr, vv, 1, true};  // B(ef, ab) = <ab|ef> = <ef|ab>: V is symmetric
