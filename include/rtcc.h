@@ -287,7 +287,9 @@ int rtcc_check_state(rtcc_ctx* ctx, const void* y, int64_t* nonfinite);
  * (i <= j) x (e <= f) and X- V- over the (i < j) x (e < f) pair triangles (rows o(o+1) and o(o-1) per
  * member for tau and lambda2, K = N = v(v+1)/2 and v(v-1)/2), a quarter of the flops of the full
  * product of 2 o^2 rows with the v^2 x v^2 matrix <ab|ef>; the environment variable RTCC_LADDER=full,
- * read by rtcc_init, selects the full product (one launch, 4 * 2 o^2 * v^4 flops). */
+ * read by rtcc_init, selects the full product (one launch, 4 * 2 o^2 * v^4 flops), and
+ * RTCC_LADDER=symmetric-nolds the symmetric form with its element fold / unfold kernels (the LDS-staged
+ * ones serve v <= 96). */
 int rtcc_profile(rtcc_ctx* ctx, int enable);
 int rtcc_profile_read(rtcc_ctx* ctx, int64_t* launches, double* total_ms, double* flops_per_launch);
 

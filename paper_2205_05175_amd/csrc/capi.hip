@@ -396,6 +396,7 @@ void ensure_batch(rtcc_ctx* c, std::unique_ptr<BatchWS>& slot, int nb) {
   B->E.bf16_min_flops = c->E.bf16_min_flops;
   B->E.bf16_kernel = c->E.bf16_kernel;
   B->E.sym_ladder = c->E.sym_ladder;
+  B->E.ladder_lds = c->E.ladder_lds;
   B->E.scratch.cap = c->E.scratch.cap * (size_t)nb;
   B->E.scratch.base = B->arena.alloc<char>(B->E.scratch.cap);
   build_work<double>(B->arena, c->o, c->v, B->W64, nb);
@@ -876,9 +877,10 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     RTCC_CHECK(c->E.bf16_kernel >= 1 && c->E.bf16_kernel <= 4, kEInval, "RTCC_BF16_KERNEL must be 1 to 4");
     const char* lm = std::getenv("RTCC_LADDER");
     if (lm && lm[0]) {
-      RTCC_CHECK(!std::strcmp(lm, "full") || !std::strcmp(lm, "symmetric"), kEInval,
-                 "RTCC_LADDER must be full or symmetric");
+      RTCC_CHECK(!std::strcmp(lm, "full") || !std::strcmp(lm, "symmetric") || !std::strcmp(lm, "symmetric-nolds"),
+                 kEInval, "RTCC_LADDER must be full, symmetric or symmetric-nolds");
       c->E.sym_ladder = std::strcmp(lm, "full") != 0;
+      c->E.ladder_lds = std::strcmp(lm, "symmetric-nolds") != 0;
     }
     const char* ng = std::getenv("RTCC_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');

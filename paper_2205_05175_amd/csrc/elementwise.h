@@ -53,11 +53,14 @@ void count_nonfinite(hipStream_t st, int64_t n, const void* a, double* partial, 
 // Symmetric / antisymmetric ladder (ladder.hip). nblk blocks of o*o*v*v consecutive entries X[blk][i][j][e][f]
 // (pair-symmetric: X_ji^fe = X_ij^ef) -> X+ rows (blk, i <= j) x (e <= f) and X- rows (blk, i < j) x (e < f);
 // back: Z[blk][i][j][a][b] = S+(pairs) +- S-(pairs) over the full square. Row-major upper-triangle pair order.
+// lds: stage one (i, j) plane per workgroup through LDS (v <= 96; otherwise, or with lds = false, element
+// kernels that read the transposed entries from global memory).
 template <typename T>
-void ladder_fold(hipStream_t st, int nblk, int o, int v, const T* xre, const T* xim, T* pre, T* pim, T* mre, T* mim);
+void ladder_fold(hipStream_t st, int nblk, int o, int v, const T* xre, const T* xim, T* pre, T* pim, T* mre, T* mim,
+                 bool lds = true);
 template <typename T>
 void ladder_unfold(hipStream_t st, int nblk, int o, int v, const T* sre, const T* sim, const T* are, const T* aim,
-                   T* zre, T* zim);
+                   T* zre, T* zim, bool lds = true);
 // V+ (v(v+1)/2 square) and V- (v(v-1)/2 square) from <ab|ef> as the v^2 x v^2 matrix [(ab)][(ef)].
 void ladder_sym_build(hipStream_t st, int v, const double* vvvv, double* vp, double* vm);
 

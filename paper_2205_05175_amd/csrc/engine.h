@@ -127,6 +127,7 @@ struct Engine {
   // particle-particle ladder in its symmetric / antisymmetric form (two GEMMs over pair triangles);
   // false: one GEMM over the full o^2 x v^2 x v^2 product
   bool sym_ladder = true;
+  bool ladder_lds = true;  // LDS-staged fold / unfold of the symmetric ladder (false: element kernels)
   int bf16_kernel = 1;  // split-BF16 kernel: 1 register-staged, 2 direct-to-LDS ring, 3 the ring at 2 per CU,
                         // 4 wide waves (64 x 128 per wave)
   bool use_tuning = true;               // consult the tuning table (single, non-batched products)

@@ -86,6 +86,100 @@ __global__ __launch_bounds__(256) void unfold_kernel(int o, int v, const T* __re
   zim[oz] = zi;
 }
 
+// (e, f) of the pair index q of the upper triangle of n (diag = 1: e <= f, diag = 0: e < f); the float
+// root gives the row to within one, the integer comparisons settle it.
+__device__ inline void tri_decode2(int64_t q, int n, int diag, int& e, int& f) {
+  const double m = 2.0 * n + (diag ? 1.0 : -1.0);
+  int r = (int)((m - sqrt(fmax(m * m - 8.0 * (double)q, 0.0))) * 0.5);
+  r = max(0, min(r, n - 1));
+  while (r > 0 && tri_index(r, r + 1 - diag, n, diag) > q) --r;
+  while (r + 1 < n && tri_index(r + 1, r + 2 - diag, n, diag) <= q) ++r;
+  e = r;
+  f = (int)(q - tri_index(r, r + 1 - diag, n, diag)) + r + 1 - diag;
+}
+
+constexpr int kLdsV = 96;  // largest v of the LDS-staged fold / unfold (one v x v plane per workgroup)
+
+// One workgroup per (block, i <= j): the v x v plane X[blk][i][j] is read once, coalesced, into LDS and the
+// X+ row (and for i < j the X- row) written contiguously; planes one after the other.
+template <typename T>
+__global__ __launch_bounds__(256) void fold_lds_kernel(int o, int v, const T* __restrict__ xre,
+                                                       const T* __restrict__ xim, T* __restrict__ pre,
+                                                       T* __restrict__ pim, T* __restrict__ mre, T* __restrict__ mim) {
+  __shared__ T sx[kLdsV * kLdsV];
+  const int po = o * (o + 1) / 2, pm = o * (o - 1) / 2;
+  const int64_t pv = (int64_t)v * (v + 1) / 2, mv = (int64_t)v * (v - 1) / 2;
+  const int blk = blockIdx.y / po, pidx = blockIdx.y - blk * po;
+  int i, j;
+  tri_decode(pidx, o, i, j);
+  const int vv = v * v;
+  const int64_t base = ((int64_t)blk * o * o + (int64_t)i * o + j) * vv;
+  const int64_t rp = ((int64_t)blk * po + pidx) * pv;
+  const int64_t rm = i < j ? ((int64_t)blk * pm + tri_index(i, j, o, 0)) * mv : 0;
+  for (int pl = 0; pl < 2; ++pl) {
+    const T* x = pl ? xim : xre;
+    T* outp = pl ? pim : pre;
+    T* outm = pl ? mim : mre;
+    for (int k = threadIdx.x; k < vv; k += blockDim.x) sx[k] = x[base + k];
+    __syncthreads();
+    for (int64_t q = threadIdx.x; q < pv; q += blockDim.x) {
+      int e, f;
+      tri_decode2(q, v, 1, e, f);
+      outp[rp + q] = e == f ? sx[e * v + e] : sx[e * v + f] + sx[f * v + e];
+    }
+    if (i < j)
+      for (int64_t q = threadIdx.x; q < mv; q += blockDim.x) {
+        int e, f;
+        tri_decode2(q, v, 0, e, f);
+        outm[rm + q] = sx[e * v + f] - sx[f * v + e];
+      }
+    __syncthreads();
+  }
+}
+
+// One workgroup per (block, i <= j): the S+ row (and for i < j the S- row) is read once into LDS and both
+// output planes Z[blk][i][j] and Z[blk][j][i] are written, coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void unfold_lds_kernel(int o, int v, const T* __restrict__ sre,
+                                                         const T* __restrict__ sim, const T* __restrict__ are,
+                                                         const T* __restrict__ aim, T* __restrict__ zre,
+                                                         T* __restrict__ zim) {
+  __shared__ T sp[kLdsV * (kLdsV + 1) / 2];
+  __shared__ T sm[kLdsV * (kLdsV - 1) / 2];
+  const int po = o * (o + 1) / 2, pm = o * (o - 1) / 2;
+  const int64_t pv = (int64_t)v * (v + 1) / 2, mv = (int64_t)v * (v - 1) / 2;
+  const int blk = blockIdx.y / po, pidx = blockIdx.y - blk * po;
+  int i, j;
+  tri_decode(pidx, o, i, j);
+  const int vv = v * v;
+  const int64_t rp = ((int64_t)blk * po + pidx) * pv;
+  const int64_t rm = i < j ? ((int64_t)blk * pm + tri_index(i, j, o, 0)) * mv : 0;
+  const int64_t oij = ((int64_t)blk * o * o + (int64_t)i * o + j) * vv;
+  const int64_t oji = ((int64_t)blk * o * o + (int64_t)j * o + i) * vv;
+  for (int pl = 0; pl < 2; ++pl) {
+    const T* s = pl ? sim : sre;
+    const T* a = pl ? aim : are;
+    T* z = pl ? zim : zre;
+    for (int64_t k = threadIdx.x; k < pv; k += blockDim.x) sp[k] = s[rp + k];
+    if (i < j)
+      for (int64_t k = threadIdx.x; k < mv; k += blockDim.x) sm[k] = a[rm + k];
+    __syncthreads();
+    for (int k = threadIdx.x; k < vv; k += blockDim.x) {
+      const int aa = k / v, bb = k - aa * v;
+      const int c = min(aa, bb), d = max(aa, bb);
+      const T sv = sp[tri_index(c, d, v, 1)];
+      if (i == j) {
+        z[oij + k] = sv;
+      } else {
+        const T av = aa == bb ? T(0) : (aa < bb ? sm[tri_index(c, d, v, 0)] : -sm[tri_index(c, d, v, 0)]);
+        z[oij + k] = sv + av;
+        z[oji + k] = sv - av;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // V+ [(e <= f)][(a <= b)] and V- [(e < f)][(a < b)] from the v^2 x v^2 matrix V[(ab)][(ef)] = <ab|ef>
 __global__ __launch_bounds__(256) void sym_build_kernel(int v, const double* __restrict__ V, double* __restrict__ vp,
                                                         double* __restrict__ vm) {
@@ -102,9 +196,16 @@ __global__ __launch_bounds__(256) void sym_build_kernel(int v, const double* __r
 }  // namespace
 
 template <typename T>
-void ladder_fold(hipStream_t st, int nblk, int o, int v, const T* xre, const T* xim, T* pre, T* pim, T* mre, T* mim) {
+void ladder_fold(hipStream_t st, int nblk, int o, int v, const T* xre, const T* xim, T* pre, T* pim, T* mre, T* mim,
+                 bool lds) {
   const int po = o * (o + 1) / 2;
   RTCC_CHECK((int64_t)nblk * po < 65536, kEInval, "ladder_fold: too many pair rows");
+  if (lds && v <= kLdsV) {
+    hipLaunchKernelGGL(fold_lds_kernel<T>, dim3(1, (unsigned)(nblk * po)), dim3(256), 0, st, o, v, xre, xim, pre, pim,
+                       mre, mim);
+    RTCC_HIP(hipGetLastError());
+    return;
+  }
   hipLaunchKernelGGL(fold_kernel<T>, dim3((unsigned)cdiv((int64_t)v * v, 256), (unsigned)(nblk * po)), dim3(256), 0, st,
                      o, v, xre, xim, pre, pim, mre, mim);
   RTCC_HIP(hipGetLastError());
@@ -112,8 +213,14 @@ void ladder_fold(hipStream_t st, int nblk, int o, int v, const T* xre, const T* 
 
 template <typename T>
 void ladder_unfold(hipStream_t st, int nblk, int o, int v, const T* sre, const T* sim, const T* are, const T* aim,
-                   T* zre, T* zim) {
+                   T* zre, T* zim, bool lds) {
   RTCC_CHECK((int64_t)nblk * o * o < 65536, kEInval, "ladder_unfold: too many pair rows");
+  if (lds && v <= kLdsV) {
+    hipLaunchKernelGGL(unfold_lds_kernel<T>, dim3(1, (unsigned)(nblk * (o * (o + 1) / 2))), dim3(256), 0, st, o, v,
+                       sre, sim, are, aim, zre, zim);
+    RTCC_HIP(hipGetLastError());
+    return;
+  }
   hipLaunchKernelGGL(unfold_kernel<T>, dim3((unsigned)cdiv((int64_t)v * v, 256), (unsigned)(nblk * o * o)), dim3(256),
                      0, st, o, v, sre, sim, are, aim, zre, zim);
   RTCC_HIP(hipGetLastError());
@@ -127,12 +234,12 @@ void ladder_sym_build(hipStream_t st, int v, const double* vvvv, double* vp, dou
 }
 
 template void ladder_fold<double>(hipStream_t, int, int, int, const double*, const double*, double*, double*, double*,
-                                  double*);
+                                  double*, bool);
 template void ladder_fold<float>(hipStream_t, int, int, int, const float*, const float*, float*, float*, float*,
-                                 float*);
+                                 float*, bool);
 template void ladder_unfold<double>(hipStream_t, int, int, int, const double*, const double*, const double*,
-                                    const double*, double*, double*);
+                                    const double*, double*, double*, bool);
 template void ladder_unfold<float>(hipStream_t, int, int, int, const float*, const float*, const float*, const float*,
-                                   float*, float*);
+                                   float*, float*, bool);
 
 }  // namespace rtcc

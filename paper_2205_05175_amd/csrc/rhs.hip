@@ -357,7 +357,7 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
                  kEInval, "ladder operands are not member-contiguous");
       const int64_t po = (int64_t)o * (o + 1) / 2, pm = (int64_t)o * (o - 1) / 2;
       const int64_t pv = (int64_t)v * (v + 1) / 2, mv = (int64_t)v * (v - 1) / 2;
-      ladder_fold<T>(cur->stream, nblk, o, v, w.X.re, w.X.im, w.Xp.re, w.Xp.im, w.Xm.re, w.Xm.im);
+      ladder_fold<T>(cur->stream, nblk, o, v, w.X.re, w.X.im, w.Xp.re, w.Xp.im, w.Xm.re, w.Xm.im, E.ladder_lds);
       const bool split16 = sizeof(T) == 4 && cur->bf16x3;  // the split-BF16 path marks its kernel itself
       const int64_t rows_[2] = {nblk * po, nblk * pm}, kn[2] = {pv, mv};
       const Ten<T>* ops[2][3] = {{&w.Xp, &I.vvp, &w.Sp}, {&w.Xm, &I.vvm, &w.Sm}};
@@ -373,7 +373,8 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
         if (E.mark && !split16) E.mark(E.mark_user, 1, E.ladder_flops, cur->stream);
         cur->ladder = 0;
       }
-      ladder_unfold<T>(cur->stream, nblk, o, v, w.Sp.re, w.Sp.im, w.Sm.re, w.Sm.im, w.Lad.re, w.Lad.im);
+      ladder_unfold<T>(cur->stream, nblk, o, v, w.Sp.re, w.Sp.im, w.Sm.re, w.Sm.im, w.Lad.re, w.Lad.im,
+                       E.ladder_lds);
     } else {
       // batched: the members' [tau; lambda2] blocks are consecutive rows of one operand
       const int64_t rows = nblk * (int64_t)o * o, vv = (int64_t)v * v;
