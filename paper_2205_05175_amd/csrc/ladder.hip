@@ -86,22 +86,16 @@ __global__ __launch_bounds__(256) void unfold_kernel(int o, int v, const T* __re
   zim[oz] = zi;
 }
 
-// (e, f) of the pair index q of the upper triangle of n (diag = 1: e <= f, diag = 0: e < f); the float
-// root gives the row to within one, the integer comparisons settle it.
-__device__ inline void tri_decode2(int64_t q, int n, int diag, int& e, int& f) {
-  const double m = 2.0 * n + (diag ? 1.0 : -1.0);
-  int r = (int)((m - sqrt(fmax(m * m - 8.0 * (double)q, 0.0))) * 0.5);
-  r = max(0, min(r, n - 1));
-  while (r > 0 && tri_index(r, r + 1 - diag, n, diag) > q) --r;
-  while (r + 1 < n && tri_index(r + 1, r + 2 - diag, n, diag) <= q) ++r;
-  e = r;
-  f = (int)(q - tri_index(r, r + 1 - diag, n, diag)) + r + 1 - diag;
+// 32-bit pair index (every triangle of the LDS-staged kernels has fewer than 2^31 entries)
+__device__ inline int tri32(int p, int q, int n, int diag) {
+  return p * (n - 1 + diag) - p * (p - 1) / 2 + (q - p - (1 - diag));
 }
 
 constexpr int kLdsV = 96;  // largest v of the LDS-staged fold / unfold (one v x v plane per workgroup)
 
-// One workgroup per (block, i <= j): the v x v plane X[blk][i][j] is read once, coalesced, into LDS and the
-// X+ row (and for i < j the X- row) written contiguously; planes one after the other.
+// One workgroup per (block, i <= j, plane): the v x v plane X[blk][i][j] is read once, coalesced, into LDS;
+// then each (e, f) with e <= f writes its X+ entry (and for i < j, e < f its X- entry): within a row e the
+// outputs are consecutive.
 template <typename T>
 __global__ __launch_bounds__(256) void fold_lds_kernel(int o, int v, const T* __restrict__ xre,
                                                        const T* __restrict__ xim, T* __restrict__ pre,
@@ -114,31 +108,22 @@ __global__ __launch_bounds__(256) void fold_lds_kernel(int o, int v, const T* __
   tri_decode(pidx, o, i, j);
   const int vv = v * v;
   const int64_t base = ((int64_t)blk * o * o + (int64_t)i * o + j) * vv;
-  const int64_t rp = ((int64_t)blk * po + pidx) * pv;
-  const int64_t rm = i < j ? ((int64_t)blk * pm + tri_index(i, j, o, 0)) * mv : 0;
-  for (int pl = 0; pl < 2; ++pl) {
-    const T* x = pl ? xim : xre;
-    T* outp = pl ? pim : pre;
-    T* outm = pl ? mim : mre;
-    for (int k = threadIdx.x; k < vv; k += blockDim.x) sx[k] = x[base + k];
-    __syncthreads();
-    for (int64_t q = threadIdx.x; q < pv; q += blockDim.x) {
-      int e, f;
-      tri_decode2(q, v, 1, e, f);
-      outp[rp + q] = e == f ? sx[e * v + e] : sx[e * v + f] + sx[f * v + e];
-    }
-    if (i < j)
-      for (int64_t q = threadIdx.x; q < mv; q += blockDim.x) {
-        int e, f;
-        tri_decode2(q, v, 0, e, f);
-        outm[rm + q] = sx[e * v + f] - sx[f * v + e];
-      }
-    __syncthreads();
+  const T* x = blockIdx.x ? xim : xre;
+  T* outp = (blockIdx.x ? pim : pre) + ((int64_t)blk * po + pidx) * pv;
+  T* outm = (blockIdx.x ? mim : mre) + (i < j ? ((int64_t)blk * pm + tri_index(i, j, o, 0)) * mv : 0);
+  for (int k = threadIdx.x; k < vv; k += blockDim.x) sx[k] = x[base + k];
+  __syncthreads();
+  for (int k = threadIdx.x; k < vv; k += blockDim.x) {
+    const int e = k / v, f = k - e * v;
+    if (f < e) continue;
+    const T a = sx[k], b = sx[f * v + e];
+    outp[tri32(e, f, v, 1)] = e == f ? a : a + b;
+    if (i < j && e < f) outm[tri32(e, f, v, 0)] = a - b;
   }
 }
 
-// One workgroup per (block, i <= j): the S+ row (and for i < j the S- row) is read once into LDS and both
-// output planes Z[blk][i][j] and Z[blk][j][i] are written, coalesced.
+// One workgroup per (block, i <= j, plane): the S+ row (and for i < j the S- row) is read once into LDS and
+// both output planes Z[blk][i][j] and Z[blk][j][i] are written, coalesced.
 template <typename T>
 __global__ __launch_bounds__(256) void unfold_lds_kernel(int o, int v, const T* __restrict__ sre,
                                                          const T* __restrict__ sim, const T* __restrict__ are,
@@ -147,36 +132,31 @@ __global__ __launch_bounds__(256) void unfold_lds_kernel(int o, int v, const T* 
   __shared__ T sp[kLdsV * (kLdsV + 1) / 2];
   __shared__ T sm[kLdsV * (kLdsV - 1) / 2];
   const int po = o * (o + 1) / 2, pm = o * (o - 1) / 2;
-  const int64_t pv = (int64_t)v * (v + 1) / 2, mv = (int64_t)v * (v - 1) / 2;
+  const int pv = v * (v + 1) / 2, mv = v * (v - 1) / 2;
   const int blk = blockIdx.y / po, pidx = blockIdx.y - blk * po;
   int i, j;
   tri_decode(pidx, o, i, j);
   const int vv = v * v;
-  const int64_t rp = ((int64_t)blk * po + pidx) * pv;
-  const int64_t rm = i < j ? ((int64_t)blk * pm + tri_index(i, j, o, 0)) * mv : 0;
+  const T* s = (blockIdx.x ? sim : sre) + ((int64_t)blk * po + pidx) * pv;
+  const T* a = (blockIdx.x ? aim : are) + (i < j ? ((int64_t)blk * pm + tri_index(i, j, o, 0)) * mv : 0);
+  T* z = blockIdx.x ? zim : zre;
   const int64_t oij = ((int64_t)blk * o * o + (int64_t)i * o + j) * vv;
   const int64_t oji = ((int64_t)blk * o * o + (int64_t)j * o + i) * vv;
-  for (int pl = 0; pl < 2; ++pl) {
-    const T* s = pl ? sim : sre;
-    const T* a = pl ? aim : are;
-    T* z = pl ? zim : zre;
-    for (int64_t k = threadIdx.x; k < pv; k += blockDim.x) sp[k] = s[rp + k];
-    if (i < j)
-      for (int64_t k = threadIdx.x; k < mv; k += blockDim.x) sm[k] = a[rm + k];
-    __syncthreads();
-    for (int k = threadIdx.x; k < vv; k += blockDim.x) {
-      const int aa = k / v, bb = k - aa * v;
-      const int c = min(aa, bb), d = max(aa, bb);
-      const T sv = sp[tri_index(c, d, v, 1)];
-      if (i == j) {
-        z[oij + k] = sv;
-      } else {
-        const T av = aa == bb ? T(0) : (aa < bb ? sm[tri_index(c, d, v, 0)] : -sm[tri_index(c, d, v, 0)]);
-        z[oij + k] = sv + av;
-        z[oji + k] = sv - av;
-      }
+  for (int k = threadIdx.x; k < pv; k += blockDim.x) sp[k] = s[k];
+  if (i < j)
+    for (int k = threadIdx.x; k < mv; k += blockDim.x) sm[k] = a[k];
+  __syncthreads();
+  for (int k = threadIdx.x; k < vv; k += blockDim.x) {
+    const int aa = k / v, bb = k - aa * v;
+    const int c = min(aa, bb), d = max(aa, bb);
+    const T sv = sp[tri32(c, d, v, 1)];
+    if (i == j) {
+      z[oij + k] = sv;
+    } else {
+      const T av = aa == bb ? T(0) : (aa < bb ? sm[tri32(c, d, v, 0)] : -sm[tri32(c, d, v, 0)]);
+      z[oij + k] = sv + av;
+      z[oji + k] = sv - av;
     }
-    __syncthreads();
   }
 }
 
@@ -201,7 +181,7 @@ void ladder_fold(hipStream_t st, int nblk, int o, int v, const T* xre, const T* 
   const int po = o * (o + 1) / 2;
   RTCC_CHECK((int64_t)nblk * po < 65536, kEInval, "ladder_fold: too many pair rows");
   if (lds && v <= kLdsV) {
-    hipLaunchKernelGGL(fold_lds_kernel<T>, dim3(1, (unsigned)(nblk * po)), dim3(256), 0, st, o, v, xre, xim, pre, pim,
+    hipLaunchKernelGGL(fold_lds_kernel<T>, dim3(2, (unsigned)(nblk * po)), dim3(256), 0, st, o, v, xre, xim, pre, pim,
                        mre, mim);
     RTCC_HIP(hipGetLastError());
     return;
@@ -216,7 +196,7 @@ void ladder_unfold(hipStream_t st, int nblk, int o, int v, const T* sre, const T
                    T* zre, T* zim, bool lds) {
   RTCC_CHECK((int64_t)nblk * o * o < 65536, kEInval, "ladder_unfold: too many pair rows");
   if (lds && v <= kLdsV) {
-    hipLaunchKernelGGL(unfold_lds_kernel<T>, dim3(1, (unsigned)(nblk * (o * (o + 1) / 2))), dim3(256), 0, st, o, v,
+    hipLaunchKernelGGL(unfold_lds_kernel<T>, dim3(2, (unsigned)(nblk * (o * (o + 1) / 2))), dim3(256), 0, st, o, v,
                        sre, sim, are, aim, zre, zim);
     RTCC_HIP(hipGetLastError());
     return;
