@@ -367,6 +367,8 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
         GemmOp<T> b{ops[h][1]->re, nullptr, kn[h], 1, true};  // V+- are symmetric matrices
         E.ladder_flops = 4.0 * (double)rows_[h] * (double)kn[h] * (double)kn[h];
         cur->ladder_flops = E.ladder_flops;
+        if (E.trace) fprintf(stderr, "[rtcc] ladder %s M=%lld N=K=%lld\n", h ? "X-V-" : "X+V+", (long long)rows_[h],
+                             (long long)kn[h]);
         cur->ladder = 1;
         if (E.mark && !split16) E.mark(E.mark_user, 0, E.ladder_flops, cur->stream);
         gemm<T>(*cur, rows_[h], kn[h], kn[h], 1.0, a, b, ops[h][2]->re, ops[h][2]->im, kn[h], 0.0);
@@ -383,6 +385,7 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
       GemmOp<T> b{I.vvvv.re, nullptr, vv, 1, true};  // B(ef, ab) = <ab|ef> = <ef|ab>: V is symmetric
       E.ladder_flops = 4.0 * (double)rows * (double)vv * (double)vv;  // real x complex: 2 MACs per entry
       cur->ladder_flops = E.ladder_flops;
+      if (E.trace) fprintf(stderr, "[rtcc] ladder full M=%lld N=K=%lld\n", (long long)rows, (long long)vv);
       cur->ladder = 1;
       const bool split16 = sizeof(T) == 4 && cur->bf16x3;  // the split-BF16 path marks its kernel itself
       if (E.mark && !split16) E.mark(E.mark_user, 0, E.ladder_flops, cur->stream);
