@@ -87,6 +87,13 @@ struct rtcc_ctx {
   std::string err;
   Engine E;
   Engine EB[2];  // branch engines of E (own streams and scratch)
+  // engine of the dipole that a captured FP32 / split-BF16 step computes for its start state beside the
+  // first right-hand side (own stream, scratch and reduction buffer; FP64 workspace W64, which those
+  // right-hand sides do not touch)
+  Engine ED;
+  hipEvent_t ev_dfork = nullptr, ev_djoin = nullptr;
+  double* red_d = nullptr;
+  bool dip_overlap = true;
   Memo memo[3];  // per-call memos of E and EB
   Arena arena;        // integrals and workspaces
   Arena arena32;      // FP32 integrals and workspace (allocated on demand)
@@ -133,7 +140,7 @@ struct rtcc_ctx {
   struct Key {
     const void* y;
     double h;
-    int prec, dip, prof, kind, guard;
+    int prec, dip, prof, kind, guard;  // dip: 0 none, 1 end state, 2 start state (overlapped)
     double E0, omega, sigma, t0, n[3];
     bool operator==(const Key& o) const {
       return y == o.y && h == o.h && prec == o.prec && dip == o.dip && prof == o.prof && kind == o.kind &&
@@ -310,6 +317,23 @@ void dipole_dev(rtcc_ctx* c, const void* y, double* out6) {
   RTCC_HIP(hipGetLastError());
 }
 
+// The dipole of y on the dipole engine's stream (the caller orders it with the main stream).
+void dipole_dev_overlap(rtcc_ctx* c, const void* y, double* out6) {
+  Engine& D = c->ED;
+  D.cache = c->E.cache;
+  D.trace = c->E.trace;
+  D.use_tuning = c->E.use_tuning;
+  D.nb = 1;
+  Work<double>& w = c->W64;
+  unpack_state<double>(D.stream, y, c->o, c->v, planes(w, true));
+  density<double>(D, w);
+  int64_t nn = (int64_t)c->n * c->n;
+  for (int a = 0; a < 3; ++a)
+    dot_planar_real<double>(D.stream, nn, w.rho.re, w.rho.im, c->mu + a * nn, c->red_d, out6 + 2 * a);
+  hipLaunchKernelGGL(add_mu_ref, dim3(1), dim3(64), 0, D.stream, out6, c->mu_ref_dev);
+  RTCC_HIP(hipGetLastError());
+}
+
 // |T2| and the non-finite count of y into c->gslot
 void guard_dev(rtcc_ctx* c, const void* y) {
   state_guard(c->stream, c->nstate, c->n1, c->n1 + c->n2, y, c->red, c->gslot);
@@ -319,29 +343,42 @@ void guard_dev(rtcc_ctx* c, const void* y) {
 // a non-finite entry or |T2| exceeds the limit.
 void guard_check(rtcc_ctx* c, int64_t step, double t);
 
-// One RK4 step from t = *tdev; advances *tdev by h; optionally the dipole of the new state and the
-// guard values.
-void rk4_step(rtcc_ctx* c, void* y, double h, const FieldDev& fd, double* dip, bool guard = false) {
+// One RK4 step from t = *tdev; advances *tdev by h; optionally the dipole of the new state (dip_start:
+// of the start state, on the dipole engine beside the right-hand sides; not in FP64, whose right-hand
+// sides use the same workspace) and the guard values.
+void rk4_step(rtcc_ctx* c, void* y, double h, const FieldDev& fd, double* dip, bool guard = false,
+              bool dip_start = false) {
+  RTCC_CHECK(!dip_start || (c->precision != RTCC_FP64 && c->ED.stream), kEInval,
+             "rk4_step: no overlapped dipole for this context");
+  if (dip && dip_start) {
+    RTCC_HIP(hipEventRecord(c->ev_dfork, c->stream));
+    RTCC_HIP(hipStreamWaitEvent(c->ED.stream, c->ev_dfork, 0));
+    dipole_dev_overlap(c, y, dip);
+    RTCC_HIP(hipEventRecord(c->ev_djoin, c->ED.stream));
+  }
   for (int s = 0; s < 4; ++s) {
     const void* ks[3] = {c->k[0], c->k[1], c->k[2]};
     double cs[3] = {h * kRk4A[s][0], h * kRk4A[s][1], h * kRk4A[s][2]};
     rhs_t(c, StageIn{y, s, ks, cs}, fd, kRk4C[s] * h, c->k[s]);
   }
+  // the dipole engine has finished reading y before y is overwritten
+  if (dip && dip_start) RTCC_HIP(hipStreamWaitEvent(c->stream, c->ev_djoin, 0));
   const void* ks[4] = {c->k[0], c->k[1], c->k[2], c->k[3]};
   double cs[4] = {h * kRk4B[0], h * kRk4B[1], h * kRk4B[2], h * kRk4B[3]};
   state_combo(c->stream, c->nstate, y, 4, ks, cs, y);
-  if (dip) dipole_dev(c, y, dip);
+  if (dip && !dip_start) dipole_dev(c, y, dip);
   if (guard) guard_dev(c, y);
   scalar_update(c->stream, c->tdev, h, true);
 }
 
 // Capture one RK4 step (with its dipole) as a graph; replayed while the key is unchanged.
-void capture_step(rtcc_ctx* c, void* y, double h, const rtcc_field* field, bool dip, bool guard = false) {
+void capture_step(rtcc_ctx* c, void* y, double h, const rtcc_field* field, bool dip, bool guard = false,
+                  bool dip_start = false) {
   rtcc_ctx::Key key{};
   key.y = y;
   key.h = h;
   key.prec = c->precision;
-  key.dip = dip;
+  key.dip = dip ? (dip_start ? 2 : 1) : 0;
   key.guard = guard;
   key.prof = c->prof;
   FieldDev fd = to_dev(field);
@@ -362,7 +399,7 @@ void capture_step(rtcc_ctx* c, void* y, double h, const rtcc_field* field, bool 
   c->capturing = true;
   hipGraph_t g = nullptr;
   try {
-    rk4_step(c, y, h, fd, dip ? c->mu_slot : nullptr, guard);
+    rk4_step(c, y, h, fd, dip ? c->mu_slot : nullptr, guard, dip_start);
   } catch (...) {
     c->capturing = false;
     (void)hipStreamEndCapture(c->stream, &g);
@@ -921,7 +958,15 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
       c->memo[k].base = c->arena.alloc<char>(c->memo[k].cap);
     }
     c->E.memo = &c->memo[0];
+    const char* dov = std::getenv("RTCC_DIPOLE_OVERLAP");
+    c->dip_overlap = !(dov && dov[0] == '0');
     if (branches) {
+      RTCC_HIP(hipStreamCreateWithFlags(&c->ED.stream, hipStreamNonBlocking));
+      RTCC_HIP(hipEventCreateWithFlags(&c->ev_dfork, hipEventDisableTiming));
+      RTCC_HIP(hipEventCreateWithFlags(&c->ev_djoin, hipEventDisableTiming));
+      c->ED.scratch.cap = c->E.scratch.cap;
+      c->ED.scratch.base = c->arena.alloc<char>(c->ED.scratch.cap);
+      c->red_d = c->arena.alloc<double>(2 * 1024);
       RTCC_HIP(hipEventCreateWithFlags(&c->E.ev_fork, hipEventDisableTiming));
       for (int k = 0; k < 2; ++k) {
         Engine& b = c->EB[k];
@@ -957,6 +1002,9 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
       if (c->E.ev_join[k]) (void)hipEventDestroy(c->E.ev_join[k]);
     }
     if (c->E.ev_fork) (void)hipEventDestroy(c->E.ev_fork);
+    if (c->ED.stream) (void)hipStreamDestroy(c->ED.stream);
+    if (c->ev_dfork) (void)hipEventDestroy(c->ev_dfork);
+    if (c->ev_djoin) (void)hipEventDestroy(c->ev_djoin);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     if (c->e_in) (void)hipEventDestroy(c->e_in);
     if (c->e_out) (void)hipEventDestroy(c->e_out);
@@ -1012,23 +1060,27 @@ int rtcc_propagate_rk4(rtcc_ctx* c, void* y, double t0, double h, int nsteps, co
   }
   return guarded(c, [&] {
     scalar_update(c->stream, c->tdev, t0, false);
-    if (mu_dev) dipole_dev(c, y, mu_dev);
     const FieldDev fd = to_dev(field);
     // HIP cannot time events recorded inside a captured graph: profiling runs the eager launches
     const bool graph = c->use_graph && !c->prof;
     const bool guard = c->guard_limit > 0.0;
+    // captured FP32 / split-BF16 steps compute the dipole of their start state beside the right-hand
+    // sides; the final state's dipole follows the last step
+    const bool overlap = graph && mu_dev && c->dip_overlap && c->precision != RTCC_FP64 && c->ED.stream;
+    if (mu_dev && !overlap) dipole_dev(c, y, mu_dev);
     for (int s = 0; s < nsteps; ++s) {
       if (graph) {
-        capture_step(c, y, h, field, mu_dev != nullptr, guard);
+        capture_step(c, y, h, field, mu_dev != nullptr, guard, overlap);
         RTCC_HIP(hipGraphLaunch(c->gexec, c->stream));
         if (mu_dev)
-          RTCC_HIP(hipMemcpyAsync(mu_dev + 6 * (int64_t)(s + 1), c->mu_slot, 6 * sizeof(double),
+          RTCC_HIP(hipMemcpyAsync(mu_dev + 6 * (int64_t)(overlap ? s : s + 1), c->mu_slot, 6 * sizeof(double),
                                   hipMemcpyDeviceToDevice, c->stream));
       } else {
         rk4_step(c, y, h, fd, mu_dev ? mu_dev + 6 * (int64_t)(s + 1) : nullptr, guard);
       }
       if (guard && ((s + 1) % c->guard_every == 0 || s + 1 == nsteps)) guard_check(c, s + 1, t0 + (s + 1) * h);
     }
+    if (overlap) dipole_dev(c, y, mu_dev + 6 * (int64_t)nsteps);
   });
 }
 
@@ -1593,12 +1645,14 @@ void rtcc_destroy(rtcc_ctx* c) {
   if (c->host_pinned) (void)hipHostFree(c->host_pinned);
   hipStream_t st = c->stream;
   ConstCache* cache = c->E.cache;
-  hipStream_t bst[2] = {c->EB[0].stream, c->EB[1].stream};
-  for (int k = 0; k < 2; ++k) {
+  hipStream_t bst[3] = {c->EB[0].stream, c->EB[1].stream, c->ED.stream};
+  for (int k = 0; k < 3; ++k)
     if (bst[k]) (void)hipStreamSynchronize(bst[k]);
+  for (int k = 0; k < 2; ++k)
     if (c->E.ev_join[k]) (void)hipEventDestroy(c->E.ev_join[k]);
-  }
   if (c->E.ev_fork) (void)hipEventDestroy(c->E.ev_fork);
+  if (c->ev_dfork) (void)hipEventDestroy(c->ev_dfork);
+  if (c->ev_djoin) (void)hipEventDestroy(c->ev_djoin);
   delete c;  // frees device memory first
   const_cache_destroy(cache);
   for (hipStream_t b : bst)

@@ -1,4 +1,8 @@
-"""The captured RK4 step (one hipGraph replayed every step) equals the eager launch sequence bitwise."""
+"""The captured RK4 step (one hipGraph replayed every step) equals the eager launch sequence bitwise.
+
+In FP32 and split-BF16 contexts the captured step computes the dipole of its start state on a fourth
+stream beside the right-hand sides (and the final state's dipole after the last step); the eager
+sequence computes each step's end-state dipole after the step: the recorded dipoles must agree bitwise."""
 import os
 
 import numpy as np
@@ -28,7 +32,7 @@ def _ctx(o, v, precision, graph):
             os.environ["RTCC_NO_GRAPH"] = old
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_graph_replays_match_eager(precision):
     import torch
     from paper_2205_05175_amd import Field
