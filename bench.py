@@ -18,6 +18,8 @@ is timed on a bounded sample on the host (see ``cpu_baseline.sample``).
 Other workloads: ``--workload spectrum`` (RK4 and adaptive Cash-Karp to t = 100 au in every
 precision, absorption-peak shifts against FP64), ``sp-spectra`` (the paper's narrow-pulse double- vs
 single-precision spectra at (5,19) and (10,38) to t = 300 au, and the dipole noise-injection study),
+``integrators`` (RK4, Cash-Karp, Fehlberg 4(5) and implicit Gauss-Legendre on the (20,76) propagation:
+right-hand sides and dipole error against a finer RK4),
 ``batch`` (24 propagations in one captured graph per step), ``adjoint`` (pulse-parameter gradient at
 (10,38)).
 """
@@ -500,6 +502,86 @@ def bench_sp_spectra(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_integrators(args):
+    """The integrators of the tableau engine on the o=20, v=76 delta-kick propagation (split-BF16
+    contractions): RK4 at h = dt, adaptive Cash-Karp and Fehlberg 4(5) at eps, implicit Gauss-Legendre
+    with two and three stages at larger steps; right-hand sides, wall time and the largest dipole
+    deviation from RK4 at h = dt / 2 (the reference, splined onto every integrator's sample times)."""
+    import torch
+    from scipy.interpolate import CubicSpline
+    from paper_2205_05175_amd import RTCC
+    from synth import make_system
+
+    o, v, dt, T, eps = args.o, args.v, args.dt, args.t_end, args.eps
+    eri, fock, mu = make_system(o, v, 0)
+    R = RTCC(eri, fock, mu, o, v, precision="bf16x3")
+    del eri
+    y0 = R.new_state()
+    R.set_precision("fp64")
+    R.ground_state(y0, 1e-10, 200)
+    R.kick(y0, 1e-3, [0.0, 0.0, 1.0])
+    R.set_precision("bf16x3")
+    log(f"[bench] integrators workload o={o} v={v}: t_end={T}, RK4 dt={dt}, eps={eps}")
+
+    def rk4(h):
+        n = int(round(T / h))
+        y = y0.clone()
+        m = torch.zeros((n + 1, 6), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _propagate_chunked(R, y, 0.0, h, n, m, 0, 500, f"rk4 h={h}")
+        te = time.perf_counter() - ts
+        return h * np.arange(n + 1), m.cpu().numpy()[:, 4], 4 * n, te
+
+    tref, mref, _, _ = rk4(dt / 2)
+    ref = CubicSpline(tref, mref)
+    res = {}
+    t_, m_, rhs, te = rk4(dt)
+    res[f"rk4 h={dt}"] = {"rhs": rhs, "wall_s": te, "accepted": len(t_) - 1, "rejected": 0,
+                         "dipole_max_abs_vs_ref": float(np.abs(m_ - ref(t_)).max())}
+    for e in (eps, eps / 100):
+        for name in ("cashkarp", "rkf45"):
+            y = y0.clone()
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            tt, mm, na, nr, _ = R.propagate_embedded(y, 0.0, T, dt, e, name)
+            te = time.perf_counter() - ts
+            res[f"{name} eps={e:g}"] = {"rhs": 6 * (na + nr), "wall_s": te, "accepted": na, "rejected": nr,
+                                        "dipole_max_abs_vs_ref": float(np.abs(mm[:, 2].real - ref(tt)).max())}
+    for name, h in (("gl2", 2.5 * dt), ("gl3", 5 * dt)):
+        n = int(round(T / h))
+        y = y0.clone()
+        sweeps, tt, mm = 0, [], []
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for k in range(n):
+            _, sw = R.step_tableau(y, k * h, h, name, tol=1e-8, max_iter=100)
+            sweeps += sw
+            tt.append((k + 1) * h)
+            mm.append(R.dipole(y)[2].real)
+        te = time.perf_counter() - ts
+        res[f"{name} h={h}"] = {"rhs": n * (1 + sweeps / n * (2 if name == "gl2" else 3)), "wall_s": te,
+                               "accepted": n, "rejected": 0, "mean_sweeps": sweeps / n,
+                               "dipole_max_abs_vs_ref": float(np.abs(np.array(mm) - ref(np.array(tt))).max())}
+        log(f"[bench] {name}: {res[f'{name} h={h}']}")
+    R.close()
+    base = res[f"rk4 h={dt}"]["rhs"]
+    for r in res.values():
+        r["rhs_ratio_rk4_over_this"] = base / r["rhs"]
+    line = {
+        "metric": f"right-hand sides per propagation to t={T} au by integrator (o={o} v={v}, split-BF16)",
+        "value": res[f"cashkarp eps={eps:g}"]["rhs_ratio_rk4_over_this"], "unit": "RK4 RHS / Cash-Karp RHS",
+        "n_gpus": 1, "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
+        "config": {"workload": f"rt-ccsd four-water-shaped synthetic o={o} v={v} seed 0, delta kick 1e-3 z, "
+                               f"RK4 h={dt}, Cash-Karp and Fehlberg eps={eps:g} and {eps / 100:g}, Gauss-Legendre 2 / 3 stages at "
+                               f"h={2.5 * dt} / {5 * dt} (stage sweeps to 1e-8), reference RK4 h={dt / 2}",
+                   "parallelism": "single GPU"},
+        "integrators": res, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_profile(args):
     """Only the RK4 steps of one precision at (o, v), from a random non-stationary state (no ground state,
     no kick, no oracle): the command to run under rocprofv3 so that its kernel summary holds the step's
@@ -530,7 +612,8 @@ def bench_profile(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["single", "spectrum", "sp-spectra", "batch", "adjoint", "profile"],
+    ap.add_argument("--workload", choices=["single", "spectrum", "sp-spectra", "integrators", "batch", "adjoint",
+                                           "profile"],
                     default="single",
                     help="single: the o=20 v=76 propagation (default); spectrum: RK4 and Cash-Karp to t=100 au "
                          "with peak shifts; batch: 24 batched propagations; adjoint: pulse-parameter gradient at (10,38)")
@@ -563,6 +646,10 @@ def main():
         if args.steps is None:
             args.steps = 200
         return bench_adjoint(args)
+    if args.workload == "integrators":
+        if "--t-end" not in sys.argv:
+            args.t_end = 20.0
+        return bench_integrators(args)
     if args.workload == "sp-spectra":
         if "--dt" not in sys.argv:
             args.dt = 0.01
