@@ -8,7 +8,7 @@ times of the winner and of the library's own rule as comments, into the tuning t
 ``rtcc_load_tuning`` reads (the package loads ``tuned_gemm.txt`` beside it at start-up). An entry is
 kept only when it beats the library's own rule by more than ``--min-gain``.
 
-Candidates: the tile kernel in each of its tile / k-stage shapes with 1 to 64 K splits; for
+Candidates: the tile kernel in each of its tile / k-stage shapes with 1 to 1024 K splits; for
 split-BF16 contexts also the split-BF16 kernels (register-staged, direct-to-LDS ring, the ring at two
 workgroups per CU) with 128 x 128 or 128 x 256 tiles and 1 to 16 splits, within the workgroup cap the
 library applies to split grids.
@@ -32,8 +32,9 @@ DEFAULT_TABLE = os.path.join(HERE, "tuned_gemm.txt")
 PREC_TAG = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # (bm * 1000 + bn, k stage, aligned operands only) as instantiated by the library's dispatcher
 TILES = [(64064, 16, False), (128128, 16, False), (32064, 32, True), (32128, 16, True), (64032, 32, True),
-         (64096, 32, True), (32032, 64, True), (32096, 32, True), (96032, 32, True)]
-SPLITS = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64]
+         (64096, 32, True), (32032, 64, True), (32096, 32, True), (96032, 32, True), (32096, 64, True),
+         (64032, 64, True), (32064, 64, True)]
+SPLITS = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 128, 256, 512, 1024]
 
 _LINE = re.compile(r"\[rtcc\] gemm(-bf16x3)? M=(\d+) N=(\d+) K=(\d+)(?: batch=(\d+))? ([cr])([cr]) ta=(\d) tb=(\d)")
 

@@ -751,7 +751,7 @@ struct TileCfg {
 };
 constexpr TileCfg kTileCfgs[] = {{64064, kBK, false}, {128128, kBK, false}, {32064, 32, true}, {32128, 16, true},
                                  {64032, 32, true},   {64096, 32, true},    {32032, 64, true}, {32096, 32, true},
-                                 {96032, 32, true}};
+                                 {96032, 32, true},   {32096, 64, true},    {64032, 64, true}, {32064, 64, true}};
 }  // namespace
 
 GemmChoice tuned_choice(int prec, int64_t M, int64_t N, int64_t K, bool ac, bool bc, int ta, int tb) {
@@ -971,12 +971,15 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
   if (BK == kBK && BM == 64 && BN == 64) launch_typed<T, 64, 64>(E.stream, p, z, vec);
   else if (cfg == 128128) {
     if constexpr (sizeof(T) == 4) launch_typed<T, 128, 128>(E.stream, p, z, vec);
-  } else if (cfg == 32064) launch_typed<T, 32, 64, 32, true>(E.stream, p, z, vec);
+  } else if (cfg == 32064 && BK == 32) launch_typed<T, 32, 64, 32, true>(E.stream, p, z, vec);
+  else if (cfg == 32064 && BK == 64) launch_typed<T, 32, 64, 64, true>(E.stream, p, z, vec);
   else if (cfg == 32128) launch_typed<T, 32, 128, 16, true>(E.stream, p, z, vec);
-  else if (cfg == 64032) launch_typed<T, 64, 32, 32, true>(E.stream, p, z, vec);
+  else if (cfg == 64032 && BK == 32) launch_typed<T, 64, 32, 32, true>(E.stream, p, z, vec);
+  else if (cfg == 64032 && BK == 64) launch_typed<T, 64, 32, 64, true>(E.stream, p, z, vec);
   else if (cfg == 64096) launch_typed<T, 64, 96, 32, true>(E.stream, p, z, vec);
   else if (cfg == 32032) launch_typed<T, 32, 32, 64, true>(E.stream, p, z, vec);
-  else if (cfg == 32096) launch_typed<T, 32, 96, 32, true>(E.stream, p, z, vec);
+  else if (cfg == 32096 && BK == 32) launch_typed<T, 32, 96, 32, true>(E.stream, p, z, vec);
+  else if (cfg == 32096 && BK == 64) launch_typed<T, 32, 96, 64, true>(E.stream, p, z, vec);
   else if (cfg == 96032) launch_typed<T, 96, 32, 32, true>(E.stream, p, z, vec);
   else RTCC_CHECK(false, kEInval, "gemm: no kernel for the chosen tile");
   if (splits > 1) splitk_reduce_launch<T>(E.stream, Pre, Pim, splits, M, N, Cre, Cim, ldc, bt.c, nbt, alpha, beta);

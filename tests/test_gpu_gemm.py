@@ -27,7 +27,7 @@ def _need_gpu(require_gpu):
 TOL = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 1e-4}
 TAG = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 TILES = [(64064, 16), (128128, 16), (32064, 32), (32128, 16), (64032, 32), (64096, 32), (32032, 64), (32096, 32),
-         (96032, 32)]
+         (96032, 32), (32096, 64), (64032, 64), (32064, 64)]
 
 
 class Case:
