@@ -46,6 +46,12 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6}
 # full ladder product (RTCC_LADDER=full); the default symmetric / antisymmetric form has no figure.
 LADDER_TRAFFIC_BF16X3 = {"fetch_bytes": 246305.8 * 1024 * 2.0, "write_bytes": 38464.0 * 1024 * 1.0,
                          "kernel": "gemm_bf16x3_nt<1, 0, 1, 4>"}
+# The same for the symmetric / antisymmetric ladder (the default): the mean over the launches of its two
+# GEMMs (X+V+: 420 x 2926 x 2926, 3 K splits; X-V-: 380 x 2850 x 2850, 4 K splits) in the RK4 step of
+# bench.py --workload profile (FETCH_SIZE 32,743.6 KiB, WRITE_SIZE 37,161.6 KiB per dispatch; the same
+# run's state clone: FETCH_SIZE x2.0, WRITE_SIZE x1.0). Commands: profiles/ladder_traffic_o20v76.md.
+LADDER_TRAFFIC_BF16X3_SYM = {"fetch_bytes": 32743.6 * 1024 * 2.0, "write_bytes": 37161.6 * 1024 * 1.0,
+                             "kernel": "gemm_bf16x3_nt<1, 0, 1, 4>"}
 
 
 def log(*a):
@@ -741,7 +747,18 @@ def main():
     head = "bf16x3" if bf16_err <= 1e-6 else "fp32"
     rh = results[head]
     full_ladder = os.environ.get("RTCC_LADDER", "symmetric") == "full"
-    measured_traffic = head == "bf16x3" and (o, v) == (20, 76) and full_ladder
+    measured_traffic = head == "bf16x3" and (o, v) == (20, 76) and os.environ.get("RTCC_LADDER", "symmetric") in (
+        "full", "symmetric")
+    lt = LADDER_TRAFFIC_BF16X3 if full_ladder else LADDER_TRAFFIC_BF16X3_SYM
+    # algorithmic minimum per launch: the packed operands read once and the complex FP32 output written
+    # once (rows padded to 128, K to 32, B rows to 256; hi and lo planes of bf16)
+    def packed(rows, cols, k, planes_a):
+        pad = lambda x, m: -(-x // m) * m
+        return (2 * pad(rows, 128) * pad(k, 32) * 2 * planes_a + 2 * pad(cols, 256) * pad(k, 32) * 2
+                + rows * cols * 8)
+    alg_min = (packed(2 * o * o, v * v, v * v, 2) if full_ladder else
+               0.5 * (packed(o * (o + 1), v * (v + 1) // 2, v * (v + 1) // 2, 2)
+                      + packed(o * (o - 1), v * (v - 1) // 2, v * (v - 1) // 2, 2)))
     peak = PEAK_TFLOPS["fp32"] if head == "fp32" else PEAK_TFLOPS["bf16"] / 3
     line = {
         "metric": "RK4 steps/s (T+Λ RHS) o=20,v=76: FP32-MFMA vs FP64, dipole err vs oracle",
@@ -770,13 +787,10 @@ def main():
                      "peak": peak, "unit": "TFLOP/s", "frac": rh["ladder_tflops"] / peak,
                      "peak_note": ("fp32 MFMA peak" if head == "fp32" else "bf16 dense MFMA peak / 3 products per "
                                    "real multiply (algorithmic fp32-equivalent flops)"),
-                     "traffic": (LADDER_TRAFFIC_BF16X3["fetch_bytes"] + LADDER_TRAFFIC_BF16X3["write_bytes"]
-                                 if measured_traffic and LADDER_TRAFFIC_BF16X3 else None),
-                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     # packed operands read once (X: 896 x 5792 x 4 bf16 planes, V: 5888 x 5792 x 2) and
-                     # the 800 x 5776 complex FP32 output written once (one K split at this size)
-                     "traffic_algorithmic_min": (2 * 896 * 5792 * 4 + 2 * 5888 * 5792 * 2 + 800 * 5776 * 8
-                                                 if measured_traffic else None),
+                     "traffic": (lt["fetch_bytes"] + lt["write_bytes"] if measured_traffic else None),
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
+                                     "symmetric form: mean of its two GEMMs)",
+                     "traffic_algorithmic_min": alg_min if measured_traffic else None,
                      "avg_ms": rh["ladder_ms"], "flops_per_launch": rh["ladder_flops"],
                      "fp32": {"achieved": r32["ladder_tflops"], "peak": PEAK_TFLOPS["fp32"],
                               "frac": r32["ladder_tflops"] / PEAK_TFLOPS["fp32"], "avg_ms": r32["ladder_ms"]},
