@@ -434,6 +434,7 @@ void ensure_batch(rtcc_ctx* c, std::unique_ptr<BatchWS>& slot, int nb) {
   B->E.bf16_kernel = c->E.bf16_kernel;
   B->E.sym_ladder = c->E.sym_ladder;
   B->E.ladder_lds = c->E.ladder_lds;
+  B->E.pair_splits = c->E.pair_splits;
   B->E.scratch.cap = c->E.scratch.cap * (size_t)nb;
   B->E.scratch.base = B->arena.alloc<char>(B->E.scratch.cap);
   build_work<double>(B->arena, c->o, c->v, B->W64, nb);
@@ -919,6 +920,10 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
       c->E.sym_ladder = std::strcmp(lm, "full") != 0;
       c->E.ladder_lds = std::strcmp(lm, "symmetric-nolds") != 0;
     }
+    const char* ps = std::getenv("RTCC_LADDER_PAIR_SPLITS");
+    if (ps && ps[0]) c->E.pair_splits = std::atoi(ps);
+    RTCC_CHECK(c->E.pair_splits >= -1 && c->E.pair_splits <= 16, kEInval,
+               "RTCC_LADDER_PAIR_SPLITS must be -1 (no pairing) to 16");
     const char* ng = std::getenv("RTCC_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');
     const char* tr = std::getenv("RTCC_TRACE");

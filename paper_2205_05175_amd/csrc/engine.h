@@ -127,7 +127,8 @@ struct Engine {
   // particle-particle ladder in its symmetric / antisymmetric form (two GEMMs over pair triangles);
   // false: one GEMM over the full o^2 x v^2 x v^2 product
   bool sym_ladder = true;
-  bool ladder_lds = true;  // LDS-staged fold / unfold of the symmetric ladder (false: element kernels)
+  bool ladder_lds = true;
+  int pair_splits = 0;  // K splits of the paired split-BF16 ladder launch (0: the cost model; -1: no pairing)  // LDS-staged fold / unfold of the symmetric ladder (false: element kernels)
   int bf16_kernel = 1;  // split-BF16 kernel: 1 register-staged, 2 direct-to-LDS ring, 3 the ring at 2 per CU,
                         // 4 wide waves (64 x 128 per wave)
   bool use_tuning = true;               // consult the tuning table (single, non-batched products)
@@ -190,6 +191,23 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
 bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<float> A, GemmOp<float> B,
                  float* Cre, float* Cim, int64_t ldc, double beta, int force_wn = 0, int force_splits = 0,
                  int force_kernel = 0);
+
+// One product of a pair issued together (gemm_bf16x3_pair).
+struct Bf16Job {
+  int64_t M, N, K;
+  double alpha;
+  GemmOp<float> A, B;
+  float* Cre;
+  float* Cim;
+  int64_t ldc;
+  double beta;
+};
+// The two products in one launch of the register-staged split-BF16 kernel (workgroups of the first, then
+// of the second; one K split for both from the cost model over their summed tiles), each then reduced on
+// its own. For complex x real pairs (the symmetric / antisymmetric ladder, issued while E.ladder is set and
+// marked as one ladder launch); returns false (nothing launched) for other operand kinds or when the
+// context selects another split-BF16 kernel.
+bool gemm_bf16x3_pair(Engine& E, const Bf16Job (&jobs)[2]);
 
 // y(n) = alpha * sum_k x(k) W(k, n) + beta * y(n) for n < N, k < K, with x(k) at k * incx, y(n) at n * incy
 // and W(k, n) at (k / K2) sk1 + (k % K2) sk2 + (n / N2) sn1 + (n % N2) sn2 (two-level indices: a

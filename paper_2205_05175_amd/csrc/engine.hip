@@ -411,6 +411,7 @@ void fork_branches(Engine& E) {
     b->bf16x3 = E.bf16x3;
     b->bf16_min_flops = E.bf16_min_flops;
     b->bf16_kernel = E.bf16_kernel;
+    b->pair_splits = E.pair_splits;
     b->use_tuning = E.use_tuning;
     b->nb = E.nb;
     b->gemm_flops = 0;

@@ -427,10 +427,9 @@ __global__ __launch_bounds__(128 * WN, 2) void gemm_bf16x3_dma(Params p) {
   store_tile<AC, BC, 2>(p, accr, acci, split, m0 + wm * 64, n0 + wn * 64, lane);
 }
 
-// LADDER = 1: the same kernel under a name of its own for the particle-particle ladder.
-// WN waves along N (2 or 4): a 128 x 64 WN tile, 128 WN threads.
-template <int AC, int BC, int LADDER, int WN>
-__global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p) {
+// WN waves along N (2 or 4): a 128 x 64 WN tile, 128 WN threads; workgroup `bid` of the product p.
+template <int AC, int BC, int WN>
+__device__ __forceinline__ void nt_body(const Params& p, int bid) {
   constexpr int kThr = 128 * WN, kBN = 64 * WN;
   constexpr int NA = AC ? 2 : 1, NB = BC ? 2 : 1;  // complex planes
   constexpr int PA = 2 * NA, PB = 2 * NB;            // packed planes (hi, lo per complex plane)
@@ -442,7 +441,7 @@ __global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   int split, tm, tn;
-  tile_of(blockIdx.x, p, &split, &tm, &tn);
+  tile_of(bid, p, &split, &tm, &tn);
   const int m0 = tm * kBM, n0 = tn * kBN;
   const int kbeg = split * p.kchunk, kend = min(p.Kp, kbeg + p.kchunk);
 
@@ -513,6 +512,20 @@ __global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p) {
   }
 
   store_tile<AC, BC, 2>(p, accr, acci, split, m0 + wm * 64, n0 + wn * 64, lane);
+}
+
+// LADDER = 1: the same kernel under a name of its own for the particle-particle ladder.
+template <int AC, int BC, int LADDER, int WN>
+__global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p) {
+  nt_body<AC, BC, WN>(p, blockIdx.x);
+}
+
+// Two products of the same kind in one launch: workgroups [0, wg0) take p0, the rest p1 (the two GEMMs
+// of the symmetric / antisymmetric ladder, which alone would each fill only part of the chip).
+template <int AC, int BC, int LADDER, int WN>
+__global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt2(Params p0, Params p1, int wg0) {
+  if ((int)blockIdx.x < wg0) nt_body<AC, BC, WN>(p0, blockIdx.x);
+  else nt_body<AC, BC, WN>(p1, blockIdx.x - wg0);
 }
 
 // Wide-wave kernel: 256 threads, a 128 x 256 output tile, 2 x 2 waves of 64 x 128 (2 x 4 MFMA blocks of
@@ -753,6 +766,103 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
     fprintf(stderr, "[rtcc] gemm-bf16x3 M=%lld N=%lld K=%lld %s%s ta=%d tb=%d wn=%d splits=%d kernel=%d konst=%d%d\n",
             (long long)M, (long long)N, (long long)K, AC ? "c" : "r", BC ? "c" : "r", A.trans, B.trans, WN, splits, kern,
             (int)A.konst, (int)B.konst);
+  return true;
+}
+
+bool gemm_bf16x3_pair(Engine& E, const Bf16Job (&jobs)[2]) {
+  for (const Bf16Job& j : jobs) {
+    if (j.M <= 0 || j.N <= 0 || j.K <= 0 || !j.A.im || j.B.im || !j.Cim) return false;
+    RTCC_CHECK(j.M < (1LL << 30) && j.N < (1LL << 30) && j.K < (1LL << 30), kEInval,
+               "gemm_bf16x3_pair: dimension too large");
+  }
+  if (E.bf16_kernel != 1) return false;
+  constexpr int WN = 4, kBN = 64 * WN;
+  size_t mark = E.scratch.used;
+  Params p[2];
+  int64_t tiles = 0;
+  int stages = 0;
+  for (int h = 0; h < 2; ++h) {
+    const Bf16Job& j = jobs[h];
+    const Packed pa = pack_operand(E, j.A.re, j.A.im, j.A.ld, j.A.trans, j.M, j.K, j.A.konst, kRowPad);
+    const Packed pb = pack_operand(E, j.B.re, j.B.im, j.B.ld, j.B.trans ? 0 : 1, j.N, j.K, j.B.konst, kBN);
+    Params& q = p[h];
+    q.A = pa.p;
+    q.B = pb.p;
+    q.pa = pa.plane;
+    q.pb = pb.plane;
+    q.Kp = pa.Kp;
+    q.Mp = pa.Rp;
+    q.Np = pb.Rp;
+    q.M = (int)j.M;
+    q.N = (int)j.N;
+    q.tiles_m = (int)cdiv(j.M, kBM);
+    q.tiles_n = (int)cdiv(j.N, kBN);
+    q.ntiles = q.tiles_m * q.tiles_n;
+    q.alpha = (float)j.alpha;
+    q.beta = (float)j.beta;
+    tiles += q.ntiles;
+    stages = std::max(stages, q.Kp / kBK);
+  }
+  // one K split for both, from the single-product cost model over the summed tiles (the longer K sets
+  // the per-tile time) within the same workgroup cap
+  const double tile_time = 2.0 * kBM * kBN * (double)stages * kBK * 2 / (0.35 * 2516.6e12 / 3 / 256);
+  double plane_bytes = 0.0;
+  for (const Bf16Job& j : jobs) plane_bytes += (double)j.M * j.N * 8.0;
+  int splits = 1;
+  double best = 1e300;
+  // the pair replaces two launches of up to 160 workgroups that ran one after the other: up to one
+  // workgroup per CU (measured in the (20,76) step: 3 splits, 252 workgroups, 114 us for both GEMMs
+  // against 2 x 79 us apart; 2 splits 133 us; 4 splits 146 us)
+  constexpr int kSplitWG = 256;
+  for (int sp = 1; sp <= 16 && (sp == 1 || stages / sp >= 4); ++sp) {
+    if (sp > 1 && tiles * sp > kSplitWG) break;
+    const double rounds = (double)cdiv(tiles * sp, 256);
+    const double t = rounds * tile_time / sp + (sp > 1 ? (2.0 * sp + 2.0) * plane_bytes / 12e12 : 0.0);
+    if (t < best * 0.97) {
+      best = t;
+      splits = sp;
+    }
+  }
+  if (E.pair_splits > 0) splits = std::min(E.pair_splits, std::max(stages, 1));
+  float* P[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  for (int h = 0; h < 2; ++h) {
+    const Bf16Job& j = jobs[h];
+    Params& q = p[h];
+    const int st = q.Kp / kBK, per = (int)cdiv(st, splits);
+    q.kchunk = per * kBK;
+    q.splits = (int)cdiv(st, per);
+    if (q.splits > 1) {
+      q.split_stride = j.M * j.N;
+      P[h][0] = E.scratch.get<float>(q.splits * j.M * j.N);
+      P[h][1] = E.scratch.get<float>(q.splits * j.M * j.N);
+      q.Cre = P[h][0];
+      q.Cim = P[h][1];
+      q.ldc = j.N;
+    } else {
+      q.split_stride = 0;
+      q.Cre = j.Cre;
+      q.Cim = j.Cim;
+      q.ldc = j.ldc;
+    }
+  }
+  const int wg0 = p[0].ntiles * p[0].splits, wg = wg0 + p[1].ntiles * p[1].splits;
+  const bool lad = E.ladder != 0;
+  if (lad && E.mark) E.mark(E.mark_user, 0, E.ladder_flops, E.stream);
+  if (lad) hipLaunchKernelGGL((gemm_bf16x3_nt2<1, 0, 1, WN>), dim3((unsigned)wg), dim3(128 * WN), 0, E.stream, p[0], p[1], wg0);
+  else hipLaunchKernelGGL((gemm_bf16x3_nt2<1, 0, 0, WN>), dim3((unsigned)wg), dim3(128 * WN), 0, E.stream, p[0], p[1], wg0);
+  RTCC_HIP(hipGetLastError());
+  if (lad && E.mark) E.mark(E.mark_user, 1, E.ladder_flops, E.stream);
+  for (int h = 0; h < 2; ++h) {
+    const Bf16Job& j = jobs[h];
+    if (p[h].splits > 1)
+      splitk_reduce_launch<float>(E.stream, P[h][0], P[h][1], p[h].splits, j.M, j.N, j.Cre, j.Cim, j.ldc, 0, 1,
+                                  j.alpha, j.beta);
+    E.gemm_flops += 2 * j.M * j.N * j.K * 2;
+    if (E.trace)
+      fprintf(stderr, "[rtcc] gemm-bf16x3 pair %d/2 M=%lld N=%lld K=%lld cr ta=%d tb=%d wn=%d splits=%d\n", h + 1,
+              (long long)j.M, (long long)j.N, (long long)j.K, j.A.trans, j.B.trans, WN, p[h].splits);
+  }
+  E.scratch.reset(mark);
   return true;
 }
 

@@ -361,7 +361,29 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
       const bool split16 = sizeof(T) == 4 && cur->bf16x3;  // the split-BF16 path marks its kernel itself
       const int64_t rows_[2] = {nblk * po, nblk * pm}, kn[2] = {pv, mv};
       const Ten<T>* ops[2][3] = {{&w.Xp, &I.vvp, &w.Sp}, {&w.Xm, &I.vvm, &w.Sm}};
-      for (int h = 0; h < 2; ++h) {
+      bool paired = false;
+      if constexpr (sizeof(T) == 4) {
+        // split-BF16: both GEMMs in one launch when both qualify for the split kernel and the tuning
+        // table holds no choice of its own for either
+        bool ok = split16 && cur->pair_splits >= 0 && rows_[1] > 0 && kn[1] > 0;
+        for (int h = 0; h < 2 && ok; ++h)
+          ok = 2.0 * (double)rows_[h] * (double)kn[h] * (double)kn[h] >= cur->bf16_min_flops &&
+               (!cur->use_tuning || tuned_choice(2, rows_[h], kn[h], kn[h], true, false, 0, 1).kind == 0);
+        if (ok) {
+          Bf16Job jobs[2];
+          for (int h = 0; h < 2; ++h)
+            jobs[h] = Bf16Job{rows_[h], kn[h], kn[h], 1.0, GemmOp<float>{ops[h][0]->re, ops[h][0]->im, kn[h], 0},
+                              GemmOp<float>{ops[h][1]->re, nullptr, kn[h], 1, true}, ops[h][2]->re, ops[h][2]->im,
+                              kn[h], 0.0};
+          E.ladder_flops = 4.0 * (double)(rows_[0] * kn[0] * kn[0] + rows_[1] * kn[1] * kn[1]);
+          cur->ladder_flops = E.ladder_flops;
+          cur->ladder = 1;
+          if (E.trace) fprintf(stderr, "[rtcc] ladder X+V+ and X-V- paired\n");
+          paired = gemm_bf16x3_pair(*cur, jobs);
+          cur->ladder = 0;
+        }
+      }
+      for (int h = 0; h < 2 && !paired; ++h) {
         if (rows_[h] == 0 || kn[h] == 0) continue;
         GemmOp<T> a{ops[h][0]->re, ops[h][0]->im, kn[h], 0};
         GemmOp<T> b{ops[h][1]->re, nullptr, kn[h], 1, true};  // V+- are symmetric matrices
