@@ -46,12 +46,12 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6}
 # full ladder product (RTCC_LADDER=full); the default symmetric / antisymmetric form has no figure.
 LADDER_TRAFFIC_BF16X3 = {"fetch_bytes": 246305.8 * 1024 * 2.0, "write_bytes": 38464.0 * 1024 * 1.0,
                          "kernel": "gemm_bf16x3_nt<1, 0, 1, 4>"}
-# The same for the symmetric / antisymmetric ladder (the default): the mean over the launches of its two
-# GEMMs (X+V+: 420 x 2926 x 2926, 3 K splits; X-V-: 380 x 2850 x 2850, 4 K splits) in the RK4 step of
-# bench.py --workload profile (FETCH_SIZE 32,743.6 KiB, WRITE_SIZE 37,161.6 KiB per dispatch; the same
+# The same for the symmetric / antisymmetric ladder (the default): its two GEMMs (X+V+: 420 x 2926 x 2926,
+# X-V-: 380 x 2850 x 2850, 3 K splits each) in one launch of gemm_bf16x3_nt2<1, 0, 1, 4>, in the RK4 step of
+# bench.py --workload profile (FETCH_SIZE 73,660.2 KiB, WRITE_SIZE 69,636.2 KiB per dispatch; the same
 # run's state clone: FETCH_SIZE x2.0, WRITE_SIZE x1.0). Commands: profiles/ladder_traffic_o20v76.md.
-LADDER_TRAFFIC_BF16X3_SYM = {"fetch_bytes": 32743.6 * 1024 * 2.0, "write_bytes": 37161.6 * 1024 * 1.0,
-                             "kernel": "gemm_bf16x3_nt<1, 0, 1, 4>"}
+LADDER_TRAFFIC_BF16X3_SYM = {"fetch_bytes": 73660.2 * 1024 * 2.0, "write_bytes": 69636.2 * 1024 * 1.0,
+                             "kernel": "gemm_bf16x3_nt2<1, 0, 1, 4>"}
 
 
 def log(*a):
@@ -757,8 +757,8 @@ def main():
         return (2 * pad(rows, 128) * pad(k, 32) * 2 * planes_a + 2 * pad(cols, 256) * pad(k, 32) * 2
                 + rows * cols * 8)
     alg_min = (packed(2 * o * o, v * v, v * v, 2) if full_ladder else
-               0.5 * (packed(o * (o + 1), v * (v + 1) // 2, v * (v + 1) // 2, 2)
-                      + packed(o * (o - 1), v * (v - 1) // 2, v * (v - 1) // 2, 2)))
+               packed(o * (o + 1), v * (v + 1) // 2, v * (v + 1) // 2, 2)
+               + packed(o * (o - 1), v * (v - 1) // 2, v * (v - 1) // 2, 2))
     peak = PEAK_TFLOPS["fp32"] if head == "fp32" else PEAK_TFLOPS["bf16"] / 3
     line = {
         "metric": "RK4 steps/s (T+Λ RHS) o=20,v=76: FP32-MFMA vs FP64, dipole err vs oracle",
@@ -789,7 +789,7 @@ def main():
                                    "real multiply (algorithmic fp32-equivalent flops)"),
                      "traffic": (lt["fetch_bytes"] + lt["write_bytes"] if measured_traffic else None),
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
-                                     "symmetric form: mean of its two GEMMs)",
+                                     "symmetric form: its two GEMMs in one launch)",
                      "traffic_algorithmic_min": alg_min if measured_traffic else None,
                      "avg_ms": rh["ladder_ms"], "flops_per_launch": rh["ladder_flops"],
                      "fp32": {"achieved": r32["ladder_tflops"], "peak": PEAK_TFLOPS["fp32"],
