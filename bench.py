@@ -11,9 +11,12 @@ the same starting state. The headline ``value`` is the split-BF16 path when its 
 within 1e-6 au of the FP64 path over the whole gate trajectory (``--gate-steps`` RK4 steps from
 the kick, 500 by default), else the complex-FP32 path.
 
-The ladder GEMM (the dominant kernel) is timed live with HIP events recorded on the stream it
-runs on, around every launch of a second, eagerly issued pass of the timed steps. The CPU oracle
-is timed on a bounded sample on the host (see ``cpu_baseline.sample``).
+The dominant kernel -- the large complex x complex products of the ring and Lambda terms, in the
+split-BF16 path the register-staged kernel gemm_bf16x3_nt<1, 1, 0, 4> -- is timed live with HIP
+events recorded on the stream each launch runs on, around every launch of a second, eagerly issued
+pass of the timed steps (``roofline``); the ladder GEMMs likewise in a third pass
+(``ladder_roofline``). The CPU oracle is timed on a bounded sample on the host (see
+``cpu_baseline.sample``).
 
 Other workloads: ``--workload spectrum`` (RK4 and adaptive Cash-Karp to t = 100 au in every
 precision, absorption-peak shifts against FP64), ``sp-spectra`` (the paper's narrow-pulse double- vs
@@ -43,7 +46,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6}
 # same counter on a plain device copy of the same run (the 72,247.5 KiB state clone: FETCH_SIZE
 # 36,139.2 KiB, x2.0; WRITE_SIZE 72,247.5 KiB, x1.0). Commands and raw figures:
 # profiles/ladder_traffic_o20v76.md. To be re-measured whenever that kernel changes. It applies to the
-# full ladder product (RTCC_LADDER=full); the default symmetric / antisymmetric form has no figure.
+# full ladder product (RTCC_LADDER=full).
 LADDER_TRAFFIC_BF16X3 = {"fetch_bytes": 246305.8 * 1024 * 2.0, "write_bytes": 38464.0 * 1024 * 1.0,
                          "kernel": "gemm_bf16x3_nt<1, 0, 1, 4>"}
 # The same for the symmetric / antisymmetric ladder (the default): its two GEMMs (X+V+: 420 x 2926 x 2926,
@@ -52,6 +55,13 @@ LADDER_TRAFFIC_BF16X3 = {"fetch_bytes": 246305.8 * 1024 * 2.0, "write_bytes": 38
 # run's state clone: FETCH_SIZE x2.0, WRITE_SIZE x1.0). Commands: profiles/ladder_traffic_o20v76.md.
 LADDER_TRAFFIC_BF16X3_SYM = {"fetch_bytes": 73660.2 * 1024 * 2.0, "write_bytes": 69636.2 * 1024 * 1.0,
                              "kernel": "gemm_bf16x3_nt2<1, 0, 1, 4>"}
+# The dominant kernel of the split-BF16 step, the register-staged complex x complex kernel
+# gemm_bf16x3_nt<1, 1, 0, 4> (the ring and Lambda products, 18 launches per right-hand side at o=20
+# v=76): mean HBM bytes per dispatch over its launches in the RK4 step of bench.py --workload profile,
+# calibrated on the same run's state clone like the ladder's (FETCH_SIZE 39,446.6 KiB x2.0, WRITE_SIZE
+# 32,779.1 KiB x1.0 per dispatch, 216 dispatches). Commands: profiles/cc_gemm_o20v76.md.
+CC_TRAFFIC_BF16X3 = {"fetch_bytes": 39446.6 * 1024 * 2.0, "write_bytes": 32779.1 * 1024 * 1.0,
+                     "kernel": "gemm_bf16x3_nt<1, 1, 0, 4>"}
 
 
 def log(*a):
@@ -154,7 +164,7 @@ def bench_batch(args):
     pst = min(steps, 5)
     R.profile(True)
     propagate_batch(systems, yp, fields, (warm + steps) * dt, dt, pst, None)
-    nl, ms, fl = R.profile_read()
+    nl, ms, fl, _ = R.profile_read()
     R.profile(False)
     del yp
 
@@ -704,28 +714,36 @@ def main():
         R.propagate_rk4(y, W * args.dt, args.dt, K, None, m[W:W + K + 1])
         torch.cuda.synchronize()
         te = time.perf_counter()
-        # ladder-GEMM timing: the same steps again with HIP events around every ladder launch
-        # (events cannot be timed inside a captured graph, so this pass issues plain launches)
-        yp = y.clone()
-        mu_p = torch.zeros((K + 1, 6), dtype=torch.float64, device="cuda")
-        R.profile(True)
-        tp0 = time.perf_counter()
-        R.propagate_rk4(yp, (W + K) * args.dt, args.dt, K, None, mu_p)
-        n, ms, fl = R.profile_read()
-        tp1 = time.perf_counter()
-        R.profile(False)
-        del yp, mu_p
+        # kernel timing: the same steps again with HIP events around every launch of the timed class
+        # (events cannot be timed inside a captured graph, so these passes issue plain launches): the
+        # large complex x complex products (the dominant kernel), then the ladder GEMMs
+        prof = {}
+        for target in ("complex", "ladder"):
+            yp = y.clone()
+            mu_p = torch.zeros((K + 1, 6), dtype=torch.float64, device="cuda")
+            R.profile(True, target)
+            tp0 = time.perf_counter()
+            R.propagate_rk4(yp, (W + K) * args.dt, args.dt, K, None, mu_p)
+            prof[target] = R.profile_read()
+            tp1 = time.perf_counter()
+            R.profile(False)
+            del yp, mu_p
         # the rest of the gate trajectory (untimed)
         if G > W + K:
             _propagate_chunked(R, y, (W + K) * args.dt, args.dt, G - W - K, m, W + K, 250, f"gate {prec}")
         bad = R.check_state(y)
         if bad:
             raise SystemExit(f"non-finite state after {prec} propagation ({bad} entries)")
+        n, ms, fl, _ = prof["ladder"]
         avg = ms / max(n, 1)
+        nc, msc, flc, byc = prof["complex"]
+        avgc = msc / max(nc, 1)
         results[prec] = {"ms_per_step": 1e3 * (te - ts) / K, "steps_per_s": K / (te - ts),
                          "eager_ms_per_step": 1e3 * (tp1 - tp0) / K,
                          "ladder_launches": n, "ladder_ms": avg, "ladder_flops": fl,
-                         "ladder_tflops": fl / (avg * 1e-3) / 1e12 if n else 0.0}
+                         "ladder_tflops": fl / (avg * 1e-3) / 1e12 if n else 0.0,
+                         "cc_launches": nc, "cc_ms": avgc, "cc_flops": flc, "cc_bytes": byc,
+                         "cc_tflops": flc / (avgc * 1e-3) / 1e12 if nc else 0.0}
         mm = m.cpu().numpy()
         traj[prec] = mm[:, 0::2] + 1j * mm[:, 1::2]
         finals[prec] = y
@@ -760,6 +778,11 @@ def main():
                packed(o * (o + 1), v * (v + 1) // 2, v * (v + 1) // 2, 2)
                + packed(o * (o - 1), v * (v - 1) // 2, v * (v - 1) // 2, 2))
     peak = PEAK_TFLOPS["fp32"] if head == "fp32" else PEAK_TFLOPS["bf16"] / 3
+    peak_note = ("fp32 MFMA peak" if head == "fp32" else "bf16 dense MFMA peak / 3 products per real multiply "
+                 "(algorithmic fp32-equivalent flops)")
+    cc_traffic = CC_TRAFFIC_BF16X3 if (measured_traffic and CC_TRAFFIC_BF16X3 and not full_ladder) else None
+    sub = lambda p, key: {"achieved": results[p][key + "_tflops"], "peak": PEAK_TFLOPS[p],
+                          "frac": results[p][key + "_tflops"] / PEAK_TFLOPS[p], "avg_ms": results[p][key + "_ms"]}
     line = {
         "metric": "RK4 steps/s (T+Λ RHS) o=20,v=76: FP32-MFMA vs FP64, dipole err vs oracle",
         "value": rh["steps_per_s"], "unit": "RK4 steps/s", "n_gpus": 1, "steps": K,
@@ -781,22 +804,32 @@ def main():
         "fp32_over_fp64": r32["steps_per_s"] / results["fp64"]["steps_per_s"],
         "bf16x3_over_fp64": rbf["steps_per_s"] / results["fp64"]["steps_per_s"],
         "dipole_fp64_gpu_vs_oracle_max_abs": oracle_err,
-        "roofline": {"bound": "mfma", "kernel": (f"ladder GEMM ({head})" if full_ladder else
-                                                 f"ladder GEMMs X+V+ and X-V- ({head})"),
-                     "achieved": rh["ladder_tflops"],
-                     "peak": peak, "unit": "TFLOP/s", "frac": rh["ladder_tflops"] / peak,
-                     "peak_note": ("fp32 MFMA peak" if head == "fp32" else "bf16 dense MFMA peak / 3 products per "
-                                   "real multiply (algorithmic fp32-equivalent flops)"),
-                     "traffic": (lt["fetch_bytes"] + lt["write_bytes"] if measured_traffic else None),
-                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
-                                     "symmetric form: its two GEMMs in one launch)",
-                     "traffic_algorithmic_min": alg_min if measured_traffic else None,
-                     "avg_ms": rh["ladder_ms"], "flops_per_launch": rh["ladder_flops"],
-                     "fp32": {"achieved": r32["ladder_tflops"], "peak": PEAK_TFLOPS["fp32"],
-                              "frac": r32["ladder_tflops"] / PEAK_TFLOPS["fp32"], "avg_ms": r32["ladder_ms"]},
-                     "fp64": {"achieved": results["fp64"]["ladder_tflops"], "peak": PEAK_TFLOPS["fp64"],
-                              "frac": results["fp64"]["ladder_tflops"] / PEAK_TFLOPS["fp64"],
-                              "avg_ms": results["fp64"]["ladder_ms"]}},
+        # the dominant kernel: the large complex x complex products (ring and Lambda terms), 28% of the
+        # split-BF16 step's kernel time at (20,76); the ladder, dominant before its symmetric form, follows
+        "roofline": {"bound": "mfma",
+                     "kernel": ("complex x complex split-BF16 GEMM gemm_bf16x3_nt<1, 1, 0, 4> (ring and Lambda "
+                                "products; all its launches in a step)" if head == "bf16x3" else
+                                "complex x complex FP32 tile GEMMs of at least 5e8 flop (ring and Lambda products)"),
+                     "achieved": rh["cc_tflops"], "peak": peak, "unit": "TFLOP/s", "frac": rh["cc_tflops"] / peak,
+                     "peak_note": peak_note,
+                     "traffic": (cc_traffic["fetch_bytes"] + cc_traffic["write_bytes"]) if cc_traffic else None,
+                     "traffic_unit": "bytes per launch, mean over the step's launches (HBM, rocprofv3 FETCH_SIZE + "
+                                     "WRITE_SIZE, copy-calibrated)",
+                     "traffic_algorithmic_min": rh["cc_bytes"],
+                     "avg_ms": rh["cc_ms"], "flops_per_launch": rh["cc_flops"],
+                     "launches_per_step": rh["cc_launches"] / K,
+                     "fp32": sub("fp32", "cc"), "fp64": sub("fp64", "cc")},
+        "ladder_roofline": {"bound": "mfma", "kernel": (f"ladder GEMM ({head})" if full_ladder else
+                                                        f"ladder GEMMs X+V+ and X-V- ({head})"),
+                            "achieved": rh["ladder_tflops"],
+                            "peak": peak, "unit": "TFLOP/s", "frac": rh["ladder_tflops"] / peak,
+                            "peak_note": peak_note,
+                            "traffic": (lt["fetch_bytes"] + lt["write_bytes"] if measured_traffic else None),
+                            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                            "copy-calibrated; symmetric form: its two GEMMs in one launch)",
+                            "traffic_algorithmic_min": alg_min if measured_traffic else None,
+                            "avg_ms": rh["ladder_ms"], "flops_per_launch": rh["ladder_flops"],
+                            "fp32": sub("fp32", "ladder"), "fp64": sub("fp64", "ladder")},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

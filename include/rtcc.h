@@ -274,15 +274,23 @@ int rtcc_kick(rtcc_ctx* ctx, void* y, double kappa, const double n[3]);
 /* *nonfinite (HOST) = number of non-finite complex entries of y. Synchronises. */
 int rtcc_check_state(rtcc_ctx* ctx, const void* y, int64_t* nonfinite);
 
-/* Live timing of the dominant kernel, the particle-particle ladder GEMM. rtcc_profile(ctx, 1)
- * resets the statistics and brackets every subsequent ladder launch with HIP events recorded on
- * the stream it is issued on (with RTCC_BF16X3 the split-BF16 GEMM kernel alone, which runs under
- * a name of its own; otherwise the whole GEMM call); rtcc_profile(ctx, 0) stops. While profiling is on, rtcc_propagate_rk4 issues
+/* Live timing of one class of GEMM launches with HIP events recorded on the stream each launch is
+ * issued on. rtcc_profile(ctx, 1) resets the statistics and times every subsequent launch of the
+ * particle-particle ladder, the GEMM kernel alone without packing or split-K reduction (in the
+ * split-BF16 path a kernel under a name of its own); rtcc_profile(ctx, 2) resets them and times every
+ * complex x complex product of at least 5e8 algorithmic flops (the ring and Lambda products of the
+ * right-hand side, Eq. simtranH), the GEMM kernel alone without packing or split-K reduction -- with
+ * RTCC_BF16X3 only the launches of the register-staged 128 x 256 split-BF16 kernel
+ * (gemm_bf16x3_nt<1, 1, 0, 4>), which has the largest share of the split-BF16 step at o = 20, v = 76;
+ * rtcc_profile(ctx, 0) stops; other values: RTCC_EINVAL. While profiling is on, rtcc_propagate_rk4 issues
  * its kernels one by one instead of replaying the captured step graph (events recorded inside a
  * captured graph cannot be timed); rtcc_propagate_batch does the same when any of its contexts
- * is profiling, and times that context's batched ladder. rtcc_profile_read synchronises and returns
- * the number of timed launches, their summed duration in ms and the algorithmic real flops per
- * launch, averaged over the timed launches (real x complex products: 4 flops per row, column and k).
+ * is profiling, and times that context's batched launches. rtcc_profile_read synchronises and returns
+ * (HOST) the number of timed launches, their summed duration in ms, and per launch, averaged over the
+ * timed launches, the algorithmic real flops (real x complex products: 4 flops per row, column and k;
+ * complex x complex: 8) and -- bytes_per_launch may be NULL; 0 for the ladder -- the algorithmic HBM
+ * bytes of the complex products: each operand read once and the output written once (read once more
+ * when accumulated into), 8 bytes per complex FP32 (or packed hi / lo BF16) element, 16 per FP64.
  * The ladder is by default the two GEMMs of its symmetric / antisymmetric form, X+ V+ over the
  * (i <= j) x (e <= f) and X- V- over the (i < j) x (e < f) pair triangles (rows o(o+1) and o(o-1) per
  * member for tau and lambda2, K = N = v(v+1)/2 and v(v-1)/2), a quarter of the flops of the full
@@ -291,7 +299,8 @@ int rtcc_check_state(rtcc_ctx* ctx, const void* y, int64_t* nonfinite);
  * RTCC_LADDER=symmetric-nolds the symmetric form with its element fold / unfold kernels (the LDS-staged
  * ones serve v <= 96). */
 int rtcc_profile(rtcc_ctx* ctx, int enable);
-int rtcc_profile_read(rtcc_ctx* ctx, int64_t* launches, double* total_ms, double* flops_per_launch);
+int rtcc_profile_read(rtcc_ctx* ctx, int64_t* launches, double* total_ms, double* flops_per_launch,
+                      double* bytes_per_launch);
 
 /* Diagnostics: out[0] = o, out[1] = v, out[2] = state length (complex entries),
  * out[3] = real flops issued to the MFMA GEMMs by the last rtcc_rhs call,

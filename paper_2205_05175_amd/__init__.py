@@ -122,7 +122,7 @@ def load_library(path: str = LIB_PATH):
     L.rtcc_check_state.argtypes = [vp, vp, ctypes.POINTER(i64)]
     L.rtcc_info.argtypes = [vp, ctypes.POINTER(i64)]
     L.rtcc_profile.argtypes = [vp, i]
-    L.rtcc_profile_read.argtypes = [vp, ctypes.POINTER(i64), dp, dp]
+    L.rtcc_profile_read.argtypes = [vp, ctypes.POINTER(i64), dp, dp, dp]
     L.rtcc_destroy.argtypes = [vp]
     L.rtcc_destroy.restype = None
     L.rtcc_last_error.argtypes = [vp]
@@ -354,13 +354,17 @@ class RTCC:
         self._check(self.L.rtcc_check_state(self.ctx, self._state(y), ctypes.byref(k)))
         return k.value
 
-    def profile(self, enable=True):
-        self._check(self.L.rtcc_profile(self.ctx, 1 if enable else 0))
+    def profile(self, enable=True, target="ladder"):
+        """Time the ladder GEMMs (target "ladder") or the large complex x complex products ("complex")."""
+        mode = {"ladder": 1, "complex": 2}[target] if enable else 0
+        self._check(self.L.rtcc_profile(self.ctx, mode))
 
     def profile_read(self):
-        n, ms, fl = ctypes.c_int64(0), ctypes.c_double(0.0), ctypes.c_double(0.0)
-        self._check(self.L.rtcc_profile_read(self.ctx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)))
-        return n.value, ms.value, fl.value
+        """(timed launches, summed ms, algorithmic flops per launch, algorithmic bytes per launch)."""
+        n, ms, fl, by = ctypes.c_int64(0), ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+        self._check(self.L.rtcc_profile_read(self.ctx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl),
+                                             ctypes.byref(by)))
+        return n.value, ms.value, fl.value, by.value
 
     def info(self):
         out = (ctypes.c_int64 * 6)()

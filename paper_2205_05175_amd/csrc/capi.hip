@@ -123,7 +123,7 @@ struct rtcc_ctx {
   std::vector<hipEvent_t> ev;
   int ev_used = 0;
   int64_t prof_launches = 0;
-  double prof_ms = 0.0, prof_flops = 0.0;
+  double prof_ms = 0.0, prof_flops = 0.0, prof_bytes = 0.0;
   // streams: all work runs on `stream` (owned), ordered with the caller's `ustream` by events
   hipStream_t ustream = nullptr;
   hipEvent_t e_in = nullptr, e_out = nullptr;
@@ -229,25 +229,28 @@ void eval_rhs(rtcc_ctx* c, Ints<T>& I, Work<T>& w, const void* y, const double E
   pack_rhs<T>(c->stream, c->o, c->v, planes(w, false), out, scale);
 }
 
+// Add the durations of the recorded event pairs (each pair on one stream: the main stream or a branch
+// engine's, which need not have been joined yet when the buffer fills mid-step) and free the buffer.
 void prof_flush(rtcc_ctx* c) {
   if (c->ev_used == 0) return;
-  RTCC_HIP(hipStreamSynchronize(c->stream));
   for (int i = 0; i < c->ev_used; i += 2) {
     float ms = 0.f;
+    RTCC_HIP(hipEventSynchronize(c->ev[i + 1]));
     RTCC_HIP(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
     c->prof_ms += ms;
   }
   c->ev_used = 0;
 }
 
-void prof_mark(void* user, int phase, double flops, hipStream_t st) {
+void prof_mark(void* user, int phase, double flops, double bytes, hipStream_t st) {
   rtcc_ctx* c = (rtcc_ctx*)user;
   if (!c->prof) return;
   if (phase == 0 && c->ev_used + 2 > (int)c->ev.size()) prof_flush(c);
   RTCC_HIP(hipEventRecord(c->ev[c->ev_used++], st));
   if (phase == 1) {
     c->prof_launches++;
-    c->prof_flops += flops;  // the ladder may be one GEMM or two of different sizes
+    c->prof_flops += flops;  // timed launches may differ in size
+    c->prof_bytes += bytes;
   }
 }
 
@@ -306,10 +309,21 @@ void rhs_any(rtcc_ctx* c, const void* y, const double E[3], void* out, double sc
   }
 }
 
+// The FP64 density is not one of the launches kernel timing brackets: marks are off while it is issued.
+struct NoMark {
+  Engine& E;
+  void (*m)(void*, int, double, double, hipStream_t);
+  explicit NoMark(Engine& e) : E(e), m(e.mark) { e.mark = nullptr; }
+  ~NoMark() { E.mark = m; }
+};
+
 void dipole_dev(rtcc_ctx* c, const void* y, double* out6) {
   Work<double>& w = c->W64;
   unpack_state<double>(c->stream, y, c->o, c->v, planes(w, true));
-  density<double>(c->E, w);
+  {
+    NoMark nm(c->E);
+    density<double>(c->E, w);
+  }
   int64_t nn = (int64_t)c->n * c->n;
   for (int a = 0; a < 3; ++a)
     dot_planar_real<double>(c->stream, nn, w.rho.re, w.rho.im, c->mu + a * nn, c->red, out6 + 2 * a);
@@ -480,7 +494,10 @@ void dipole_batch_dev(rtcc_ctx* c, const void* y, double* out) {
   BatchWS& B = *c->batch;
   Work<double>& w = B.W64;
   unpack_state<double>(B.E.stream, y, c->o, c->v, planes(w, true), B.nb);
-  density<double>(B.E, w);
+  {
+    NoMark nm(B.E);
+    density<double>(B.E, w);
+  }
   dipole_batch(B.E.stream, B.nb, (int64_t)c->n * c->n, w.rho.re, w.rho.im, w.rho.bs, c->mu, c->mu_ref_dev, out);
 }
 
@@ -1283,8 +1300,9 @@ int rtcc_propagate_batch(rtcc_ctx* const* ctxs, int nsys, const int* nprop, void
       off += nprop[s];
       upload_fields(c0->stream, B.fhost.data(), nprop[s], B.fdev);
       dip[s] = mu_dev && mu_dev[s];
-      B.E.mark = c->E.mark;  // ladder timing of a profiling context
+      B.E.mark = c->E.mark;  // kernel timing of a profiling context
       B.E.mark_user = c;
+      B.E.mark_mode = c->E.mark_mode;
       if (c->prof) profiling = true;
     }
     // initial time and dipoles on every system's stream
@@ -1597,7 +1615,7 @@ int rtcc_ground_state(rtcc_ctx* c, void* y, double tol, int maxiter, double* e_c
 }
 
 int rtcc_profile(rtcc_ctx* c, int enable) {
-  if (!c) return RTCC_EINVAL;
+  if (!c || enable < 0 || enable > 2) return RTCC_EINVAL;
   return guarded(c, [&] {
     if (c->ev.empty()) {
       c->ev.resize(1024);
@@ -1608,20 +1626,24 @@ int rtcc_profile(rtcc_ctx* c, int enable) {
       c->prof_launches = 0;
       c->prof_ms = 0.0;
       c->prof_flops = 0.0;
+      c->prof_bytes = 0.0;
     }
     c->prof = enable != 0;
     c->E.mark = enable ? prof_mark : nullptr;
     c->E.mark_user = c;
+    if (enable) c->E.mark_mode = enable;
   });
 }
 
-int rtcc_profile_read(rtcc_ctx* c, int64_t* launches, double* total_ms, double* flops_per_launch) {
+int rtcc_profile_read(rtcc_ctx* c, int64_t* launches, double* total_ms, double* flops_per_launch,
+                      double* bytes_per_launch) {
   if (!c || !launches || !total_ms || !flops_per_launch) return RTCC_EINVAL;
   return guarded(c, [&] {
     prof_flush(c);
     *launches = c->prof_launches;
     *total_ms = c->prof_ms;
     *flops_per_launch = c->prof_launches ? c->prof_flops / (double)c->prof_launches : 0.0;
+    if (bytes_per_launch) *bytes_per_launch = c->prof_launches ? c->prof_bytes / (double)c->prof_launches : 0.0;
   });
 }
 

@@ -113,12 +113,16 @@ struct Engine {
   Memo* memo = nullptr;  // nullptr: no memo (batched and adjoint workspaces)
   Scratch scratch;
   int64_t gemm_flops = 0;  // algorithmic real flops issued (accounting)
-  // optional hook called before (phase 0) and after (phase 1) the ladder GEMM launch with the
-  // launch's algorithmic real flops and the stream it is issued on
-  void (*mark)(void*, int, double, hipStream_t) = nullptr;
+  // optional hook called before (phase 0) and after (phase 1) a timed launch with the launch's
+  // algorithmic real flops and bytes and the stream it is issued on; mark_mode selects the launches:
+  // 1 the ladder GEMM(s); 2 every complex x complex product of at least bf16_min_flops (the ring and
+  // Lambda products), the GEMM kernel alone -- in the split-BF16 context only its register-staged
+  // 128 x 256 kernel (gemm_bf16x3_nt<1, 1, 0, 4>), the kernel with the largest share of the step
+  void (*mark)(void*, int, double, double, hipStream_t) = nullptr;
   void* mark_user = nullptr;
+  int mark_mode = 1;
   // 1 while the ladder GEMM is issued: the split-BF16 path then launches its kernel under a name of
-  // its own and calls `mark` around that kernel alone (other paths: around the whole GEMM call)
+  // its own; with mark_mode 1 every path calls `mark` around the GEMM kernel alone
   int ladder = 0;
   double ladder_flops = 0.0;  // algorithmic real flops of the last ladder GEMM
   bool trace = false;         // print every contraction's layout decisions to stderr

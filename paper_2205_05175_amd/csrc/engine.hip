@@ -407,6 +407,7 @@ void fork_branches(Engine& E) {
     b->cache = E.cache;
     b->mark = E.mark;
     b->mark_user = E.mark_user;
+    b->mark_mode = E.mark_mode;
     b->trace = E.trace;
     b->bf16x3 = E.bf16x3;
     b->bf16_min_flops = E.bf16_min_flops;

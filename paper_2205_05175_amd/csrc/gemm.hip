@@ -968,6 +968,14 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
   }
   const int z = nbt * splits;
   const int cfg = BM * 1000 + BN;
+  // timing of the large complex x complex products (the tile kernel alone; see Engine::mark_mode)
+  const double cc_flops = 8.0 * M * N * K * nbt;
+  const bool ccm = E.mark && E.mark_mode == 2 && AC && BC && cc_flops >= E.bf16_min_flops && !(sizeof(T) == 4 && E.bf16x3);
+  const double cc_bytes =
+      2.0 * sizeof(T) * nbt * (M * K + K * N + M * N * (beta != 0.0 ? 2 : 1));
+  if (ccm) E.mark(E.mark_user, 0, cc_flops, cc_bytes, E.stream);
+  const bool lm = E.ladder && E.mark && E.mark_mode == 1;  // a ladder GEMM (its kernel alone)
+  if (lm) E.mark(E.mark_user, 0, E.ladder_flops, 0.0, E.stream);
   if (BK == kBK && BM == 64 && BN == 64) launch_typed<T, 64, 64>(E.stream, p, z, vec);
   else if (cfg == 128128) {
     if constexpr (sizeof(T) == 4) launch_typed<T, 128, 128>(E.stream, p, z, vec);
@@ -982,6 +990,8 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
   else if (cfg == 32096 && BK == 64) launch_typed<T, 32, 96, 64, true>(E.stream, p, z, vec);
   else if (cfg == 96032) launch_typed<T, 96, 32, 32, true>(E.stream, p, z, vec);
   else RTCC_CHECK(false, kEInval, "gemm: no kernel for the chosen tile");
+  if (ccm) E.mark(E.mark_user, 1, cc_flops, cc_bytes, E.stream);
+  if (lm) E.mark(E.mark_user, 1, E.ladder_flops, 0.0, E.stream);
   if (splits > 1) splitk_reduce_launch<T>(E.stream, Pre, Pim, splits, M, N, Cre, Cim, ldc, bt.c, nbt, alpha, beta);
   E.scratch.reset(mark);
   E.gemm_flops += 2 * M * N * K * nbt * ((AC && BC) ? 4 : (AC || BC) ? 2 : 1);

@@ -720,7 +720,12 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   }
   const dim3 grid((unsigned)(p.ntiles * splits));
   const bool lad = E.ladder != 0;
-  if (lad && E.mark) E.mark(E.mark_user, 0, E.ladder_flops, E.stream);
+  if (lad && E.mark && E.mark_mode == 1) E.mark(E.mark_user, 0, E.ladder_flops, 0.0, E.stream);
+  // timing of the complex x complex register-staged 128 x 256 kernel: algorithmic flops and bytes
+  // (operands read once, the output written once and read once when accumulated into)
+  const bool ccm = E.mark && E.mark_mode == 2 && AC && BC && !lad && kern == 1 && WN == 4;
+  const double cc_flops = 8.0 * M * N * K, cc_bytes = 8.0 * (M * K + N * K + M * N * (beta != 0.0 ? 2 : 1));
+  if (ccm) E.mark(E.mark_user, 0, cc_flops, cc_bytes, E.stream);
   const dim3 block(kern == 4 ? 256 : 128 * WN);
   RTCC_CHECK(kern != 3 || WN == 2, kEInval, "gemm_bf16x3: the two-per-CU kernel takes 128 x 128 tiles");
   RTCC_CHECK(kern != 4 || WN == 4, kEInval, "gemm_bf16x3: the wide-wave kernel takes 128 x 256 tiles");
@@ -758,7 +763,8 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
     else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1, 0, 2>), grid, block, 0, E.stream, p);
   }
   RTCC_HIP(hipGetLastError());
-  if (lad && E.mark) E.mark(E.mark_user, 1, E.ladder_flops, E.stream);
+  if (lad && E.mark && E.mark_mode == 1) E.mark(E.mark_user, 1, E.ladder_flops, 0.0, E.stream);
+  if (ccm) E.mark(E.mark_user, 1, cc_flops, cc_bytes, E.stream);
   if (splits > 1) splitk_reduce_launch<float>(E.stream, Pre, Pim, splits, M, N, Cre, Cim, ldc, 0, 1, alpha, beta);
   E.scratch.reset(mark);
   E.gemm_flops += 2 * M * N * K * ((AC && BC) ? 4 : 2);
@@ -847,11 +853,11 @@ bool gemm_bf16x3_pair(Engine& E, const Bf16Job (&jobs)[2]) {
   }
   const int wg0 = p[0].ntiles * p[0].splits, wg = wg0 + p[1].ntiles * p[1].splits;
   const bool lad = E.ladder != 0;
-  if (lad && E.mark) E.mark(E.mark_user, 0, E.ladder_flops, E.stream);
+  if (lad && E.mark && E.mark_mode == 1) E.mark(E.mark_user, 0, E.ladder_flops, 0.0, E.stream);
   if (lad) hipLaunchKernelGGL((gemm_bf16x3_nt2<1, 0, 1, WN>), dim3((unsigned)wg), dim3(128 * WN), 0, E.stream, p[0], p[1], wg0);
   else hipLaunchKernelGGL((gemm_bf16x3_nt2<1, 0, 0, WN>), dim3((unsigned)wg), dim3(128 * WN), 0, E.stream, p[0], p[1], wg0);
   RTCC_HIP(hipGetLastError());
-  if (lad && E.mark) E.mark(E.mark_user, 1, E.ladder_flops, E.stream);
+  if (lad && E.mark && E.mark_mode == 1) E.mark(E.mark_user, 1, E.ladder_flops, 0.0, E.stream);
   for (int h = 0; h < 2; ++h) {
     const Bf16Job& j = jobs[h];
     if (p[h].splits > 1)

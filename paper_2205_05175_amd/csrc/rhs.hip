@@ -358,7 +358,7 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
       const int64_t po = (int64_t)o * (o + 1) / 2, pm = (int64_t)o * (o - 1) / 2;
       const int64_t pv = (int64_t)v * (v + 1) / 2, mv = (int64_t)v * (v - 1) / 2;
       ladder_fold<T>(cur->stream, nblk, o, v, w.X.re, w.X.im, w.Xp.re, w.Xp.im, w.Xm.re, w.Xm.im, E.ladder_lds);
-      const bool split16 = sizeof(T) == 4 && cur->bf16x3;  // the split-BF16 path marks its kernel itself
+      const bool split16 = sizeof(T) == 4 && cur->bf16x3;
       const int64_t rows_[2] = {nblk * po, nblk * pm}, kn[2] = {pv, mv};
       const Ten<T>* ops[2][3] = {{&w.Xp, &I.vvp, &w.Sp}, {&w.Xm, &I.vvm, &w.Sm}};
       bool paired = false;
@@ -392,9 +392,7 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
         if (E.trace) fprintf(stderr, "[rtcc] ladder %s M=%lld N=K=%lld\n", h ? "X-V-" : "X+V+", (long long)rows_[h],
                              (long long)kn[h]);
         cur->ladder = 1;
-        if (E.mark && !split16) E.mark(E.mark_user, 0, E.ladder_flops, cur->stream);
         gemm<T>(*cur, rows_[h], kn[h], kn[h], 1.0, a, b, ops[h][2]->re, ops[h][2]->im, kn[h], 0.0);
-        if (E.mark && !split16) E.mark(E.mark_user, 1, E.ladder_flops, cur->stream);
         cur->ladder = 0;
       }
       ladder_unfold<T>(cur->stream, nblk, o, v, w.Sp.re, w.Sp.im, w.Sm.re, w.Sm.im, w.Lad.re, w.Lad.im,
@@ -409,10 +407,7 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
       cur->ladder_flops = E.ladder_flops;
       if (E.trace) fprintf(stderr, "[rtcc] ladder full M=%lld N=K=%lld\n", (long long)rows, (long long)vv);
       cur->ladder = 1;
-      const bool split16 = sizeof(T) == 4 && cur->bf16x3;  // the split-BF16 path marks its kernel itself
-      if (E.mark && !split16) E.mark(E.mark_user, 0, E.ladder_flops, cur->stream);
       gemm<T>(*cur, rows, vv, vv, 1.0, a, b, w.Lad.re, w.Lad.im, vv, 0.0);
-      if (E.mark && !split16) E.mark(E.mark_user, 1, E.ladder_flops, cur->stream);
       cur->ladder = 0;
     }
     C(1, "ijef,mafe->ijam", tau, I.ovvv, w.Z1, 0);
