@@ -262,14 +262,18 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmParams<T> p) {
   }
 }
 
-// Sum the split-K partial planes and apply alpha/beta. A block handles 16 outputs with 16
-// lanes each; lane l sums the splits l, l+16, ... and the 16 lane sums are added in lane order,
-// so the result does not depend on scheduling.
+// Sum the split-K partial planes and apply alpha/beta. A block of 1024 threads handles 16 outputs
+// with 64 lanes each (a wave reads four partial planes, 64 contiguous bytes from each): lane l sums
+// the splits l, l + 64, ... in order with eight loads in flight, and the 64 lane sums of an output
+// are added by a fixed pairwise tree, so the result does not depend on scheduling. The many-split
+// products (a small output with K split hundreds of ways) have few outputs: the wide blocks keep
+// every partial load of a block in flight at once.
 template <typename T>
-__global__ __launch_bounds__(256) void splitk_reduce(const T* Pre, const T* Pim, int splits, int64_t stride, int M,
-                                                     int N, T* Cre, T* Cim, int64_t ldc, int64_t sc, T alpha,
-                                                     T beta) {
-  __shared__ T shr[16][17], shi[16][17];
+__global__ __launch_bounds__(1024) void splitk_reduce(const T* Pre, const T* Pim, int splits, int64_t stride, int M,
+                                                      int N, T* Cre, T* Cim, int64_t ldc, int64_t sc, T alpha,
+                                                      T beta) {
+  constexpr int kLanes = 64;
+  __shared__ T shr[kLanes][17], shi[kLanes][17];
   const int ol = threadIdx.x & 15, sl = threadIdx.x >> 4;
   // member blockIdx.y: partial planes y * splits ... y * splits + splits - 1
   Pre += (int64_t)blockIdx.y * splits * stride;
@@ -280,14 +284,13 @@ __global__ __launch_bounds__(256) void splitk_reduce(const T* Pre, const T* Pim,
   const bool ok = idx < (int64_t)M * N;
   T sr = 0, si = 0;
   if (ok) {
-    // eight partial loads in flight per step, added in split order
     int s = sl;
-    for (; s + 7 * 16 < splits; s += 8 * 16) {
+    for (; s + 7 * kLanes < splits; s += 8 * kLanes) {
       T vr[8], vi[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        vr[u] = Pre[(int64_t)(s + 16 * u) * stride + idx];
-        vi[u] = Pim ? Pim[(int64_t)(s + 16 * u) * stride + idx] : T(0);
+        vr[u] = Pre[(int64_t)(s + kLanes * u) * stride + idx];
+        vi[u] = Pim ? Pim[(int64_t)(s + kLanes * u) * stride + idx] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -295,7 +298,7 @@ __global__ __launch_bounds__(256) void splitk_reduce(const T* Pre, const T* Pim,
         si += vi[u];
       }
     }
-    for (; s < splits; s += 16) {
+    for (; s < splits; s += kLanes) {
       sr += Pre[(int64_t)s * stride + idx];
       if (Pim) si += Pim[(int64_t)s * stride + idx];
     }
@@ -303,12 +306,17 @@ __global__ __launch_bounds__(256) void splitk_reduce(const T* Pre, const T* Pim,
   shr[sl][ol] = sr;
   shi[sl][ol] = si;
   __syncthreads();
-  if (sl == 0 && ok) {
-    T ar = 0, ai = 0;
-    for (int k = 0; k < 16; ++k) {
-      ar += shr[k][ol];
-      ai += shi[k][ol];
+  // lane sums: (0 + 32), (1 + 33), ... then (0 + 16), ... down to lane 0
+#pragma unroll
+  for (int h = kLanes / 2; h >= 1; h >>= 1) {
+    if (sl < h) {
+      shr[sl][ol] += shr[sl + h][ol];
+      shi[sl][ol] += shi[sl + h][ol];
     }
+    __syncthreads();
+  }
+  if (sl == 0 && ok) {
+    const T ar = shr[0][ol], ai = shi[0][ol];
     int row = (int)(idx / N), col = (int)(idx % N);
     int64_t off = (int64_t)row * ldc + col;
     T outr = alpha * ar, outi = alpha * ai;
@@ -363,15 +371,79 @@ __global__ __launch_bounds__(256) void splitk_reduce_few(const T* Pre, const T* 
   }
 }
 
+// Few splits, FP32 rows of a multiple of 4 with 16-byte aligned planes: the same sums (split order, then
+// alpha and beta) for four consecutive outputs per thread with 16-byte loads and stores.
+__global__ __launch_bounds__(256) void splitk_reduce_few4(const float* Pre, const float* Pim, int splits,
+                                                          int64_t stride, int M, int N, float* Cre, float* Cim,
+                                                          int64_t ldc, int64_t sc, float alpha, float beta) {
+  Pre += (int64_t)blockIdx.y * splits * stride;
+  if (Pim) Pim += (int64_t)blockIdx.y * splits * stride;
+  Cre += (int64_t)blockIdx.y * sc;
+  if (Cim) Cim += (int64_t)blockIdx.y * sc;
+  const int64_t n4 = (int64_t)M * N / 4;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n4; q += (int64_t)gridDim.x * 256) {
+    const int64_t idx = 4 * q;
+    float4 ar = make_float4(0.f, 0.f, 0.f, 0.f), ai = ar;
+    int s = 0;
+    for (; s + 4 <= splits; s += 4) {
+      float4 vr[4], vi[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        vr[u] = *reinterpret_cast<const float4*>(Pre + (int64_t)(s + u) * stride + idx);
+        vi[u] = Pim ? *reinterpret_cast<const float4*>(Pim + (int64_t)(s + u) * stride + idx)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ar.x += vr[u].x; ar.y += vr[u].y; ar.z += vr[u].z; ar.w += vr[u].w;
+        ai.x += vi[u].x; ai.y += vi[u].y; ai.z += vi[u].z; ai.w += vi[u].w;
+      }
+    }
+    for (; s < splits; ++s) {
+      const float4 v = *reinterpret_cast<const float4*>(Pre + (int64_t)s * stride + idx);
+      ar.x += v.x; ar.y += v.y; ar.z += v.z; ar.w += v.w;
+      if (Pim) {
+        const float4 w = *reinterpret_cast<const float4*>(Pim + (int64_t)s * stride + idx);
+        ai.x += w.x; ai.y += w.y; ai.z += w.z; ai.w += w.w;
+      }
+    }
+    const int row = (int)(idx / N), col = (int)(idx - (int64_t)row * N);
+    const int64_t off = (int64_t)row * ldc + col;
+    float4 outr = make_float4(alpha * ar.x, alpha * ar.y, alpha * ar.z, alpha * ar.w);
+    float4 outi = make_float4(alpha * ai.x, alpha * ai.y, alpha * ai.z, alpha * ai.w);
+    if (beta != 0.f) {
+      const float4 cr = *reinterpret_cast<const float4*>(Cre + off);
+      outr.x += beta * cr.x; outr.y += beta * cr.y; outr.z += beta * cr.z; outr.w += beta * cr.w;
+      if (Cim) {
+        const float4 ci = *reinterpret_cast<const float4*>(Cim + off);
+        outi.x += beta * ci.x; outi.y += beta * ci.y; outi.z += beta * ci.z; outi.w += beta * ci.w;
+      }
+    }
+    *reinterpret_cast<float4*>(Cre + off) = outr;
+    if (Cim && Pim) *reinterpret_cast<float4*>(Cim + off) = outi;
+  }
+}
+
 template <typename T>
 void splitk_reduce_launch(hipStream_t st, const T* Pre, const T* Pim, int splits, int64_t M, int64_t N, T* Cre,
                           T* Cim, int64_t ldc, int64_t sc, int nbatch, double alpha, double beta) {
   const int64_t n = M * N;
+  if constexpr (sizeof(T) == 4) {
+    const auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    if (splits <= 24 && N % 4 == 0 && ldc % 4 == 0 && sc % 4 == 0 && al16(Pre) && (!Pim || al16(Pim)) && al16(Cre) &&
+        (!Cim || al16(Cim))) {
+      hipLaunchKernelGGL(splitk_reduce_few4, dim3((unsigned)std::min<int64_t>(cdiv(n / 4, 256), 8192), (unsigned)nbatch),
+                         dim3(256), 0, st, Pre, Pim, splits, n, (int)M, (int)N, Cre, Cim, ldc, sc, (float)alpha,
+                         (float)beta);
+      RTCC_HIP(hipGetLastError());
+      return;
+    }
+  }
   if (splits <= 24) {
     hipLaunchKernelGGL(splitk_reduce_few<T>, dim3((unsigned)std::min<int64_t>(cdiv(n, 256), 8192), (unsigned)nbatch),
                        dim3(256), 0, st, Pre, Pim, splits, n, (int)M, (int)N, Cre, Cim, ldc, sc, (T)alpha, (T)beta);
   } else {
-    hipLaunchKernelGGL(splitk_reduce<T>, dim3((unsigned)cdiv(n, 16), (unsigned)nbatch), dim3(256), 0, st, Pre, Pim,
+    hipLaunchKernelGGL(splitk_reduce<T>, dim3((unsigned)cdiv(n, 16), (unsigned)nbatch), dim3(1024), 0, st, Pre, Pim,
                        splits, n, (int)M, (int)N, Cre, Cim, ldc, sc, (T)alpha, (T)beta);
   }
   RTCC_HIP(hipGetLastError());
