@@ -809,7 +809,7 @@ def main():
         "roofline": {"bound": "mfma",
                      "kernel": ("complex x complex split-BF16 GEMM gemm_bf16x3_nt<1, 1, 0, 4> (ring and Lambda "
                                 "products; all its launches in a step)" if head == "bf16x3" else
-                                "complex x complex FP32 tile GEMMs of at least 5e8 flop (ring and Lambda products)"),
+                                "complex x complex FP32 tile GEMMs with 2 M N K >= 5e8 (ring and Lambda products)"),
                      "achieved": rh["cc_tflops"], "peak": peak, "unit": "TFLOP/s", "frac": rh["cc_tflops"] / peak,
                      "peak_note": peak_note,
                      "traffic": (cc_traffic["fetch_bytes"] + cc_traffic["write_bytes"]) if cc_traffic else None,

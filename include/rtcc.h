@@ -54,7 +54,10 @@ typedef struct rtcc_ctx rtcc_ctx;
  *                 element into two BF16 halves (hi = bf16(x), lo = bf16(x - hi)) and forms
  *                 hi*hi + hi*lo + lo*hi with v_mfma_f32_32x32x16_bf16, FP32 accumulation;
  *                 smaller products as RTCC_FP32 (the threshold can be overridden by the
- *                 environment variable RTCC_BF16_MIN_FLOPS, read by rtcc_init). */
+ *                 environment variable RTCC_BF16_MIN_FLOPS, read by rtcc_init). Independent
+ *                 products of one part of the Lambda1 residual (the three l2s x t2
+ *                 intermediates of each of its two groups) go out as one launch with one K
+ *                 split for all; RTCC_NO_GROUP=1, read by rtcc_init, issues them one by one. */
 enum { RTCC_FP64 = 0, RTCC_FP32 = 1, RTCC_BF16X3 = 2 };
 
 enum {
@@ -278,10 +281,11 @@ int rtcc_check_state(rtcc_ctx* ctx, const void* y, int64_t* nonfinite);
  * issued on. rtcc_profile(ctx, 1) resets the statistics and times every subsequent launch of the
  * particle-particle ladder, the GEMM kernel alone without packing or split-K reduction (in the
  * split-BF16 path a kernel under a name of its own); rtcc_profile(ctx, 2) resets them and times every
- * complex x complex product of at least 5e8 algorithmic flops (the ring and Lambda products of the
- * right-hand side, Eq. simtranH), the GEMM kernel alone without packing or split-K reduction -- with
- * RTCC_BF16X3 only the launches of the register-staged 128 x 256 split-BF16 kernel
- * (gemm_bf16x3_nt<1, 1, 0, 4>), which has the largest share of the split-BF16 step at o = 20, v = 76;
+ * complex x complex product with 2 M N K >= 5e8 (those RTCC_BF16X3 gives the split kernel: the ring and
+ * Lambda products of the right-hand side, Eq. simtranH), the GEMM kernel alone without packing or split-K
+ * reduction -- with RTCC_BF16X3 only the launches of the register-staged 128 x 256 split-BF16 kernel
+ * (gemm_bf16x3_nt<1, 1, 0, 4>, one launch also where it carries several independent products), which
+ * has the largest share of the split-BF16 step at o = 20, v = 76;
  * rtcc_profile(ctx, 0) stops; other values: RTCC_EINVAL. While profiling is on, rtcc_propagate_rk4 issues
  * its kernels one by one instead of replaying the captured step graph (events recorded inside a
  * captured graph cannot be timed); rtcc_propagate_batch does the same when any of its contexts

@@ -446,6 +446,7 @@ void ensure_batch(rtcc_ctx* c, std::unique_ptr<BatchWS>& slot, int nb) {
   B->E.trace = c->E.trace;
   B->E.bf16_min_flops = c->E.bf16_min_flops;
   B->E.bf16_kernel = c->E.bf16_kernel;
+  B->E.group_products = c->E.group_products;
   B->E.sym_ladder = c->E.sym_ladder;
   B->E.ladder_lds = c->E.ladder_lds;
   B->E.pair_splits = c->E.pair_splits;
@@ -943,6 +944,8 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
                "RTCC_LADDER_PAIR_SPLITS must be -1 (no pairing) to 16");
     const char* ng = std::getenv("RTCC_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');
+    const char* ngr = std::getenv("RTCC_NO_GROUP");
+    c->E.group_products = !(ngr && ngr[0] == '1');
     const char* tr = std::getenv("RTCC_TRACE");
     c->E.trace = tr && tr[0] == '1';
     const char* nbr = std::getenv("RTCC_NO_BRANCH");

@@ -115,7 +115,7 @@ struct Engine {
   int64_t gemm_flops = 0;  // algorithmic real flops issued (accounting)
   // optional hook called before (phase 0) and after (phase 1) a timed launch with the launch's
   // algorithmic real flops and bytes and the stream it is issued on; mark_mode selects the launches:
-  // 1 the ladder GEMM(s); 2 every complex x complex product of at least bf16_min_flops (the ring and
+  // 1 the ladder GEMM(s); 2 every complex x complex product with 2 M N K >= bf16_min_flops (the ring and
   // Lambda products), the GEMM kernel alone -- in the split-BF16 context only its register-staged
   // 128 x 256 kernel (gemm_bf16x3_nt<1, 1, 0, 4>), the kernel with the largest share of the step
   void (*mark)(void*, int, double, double, hipStream_t) = nullptr;
@@ -136,6 +136,7 @@ struct Engine {
   int bf16_kernel = 1;  // split-BF16 kernel: 1 register-staged, 2 direct-to-LDS ring, 3 the ring at 2 per CU,
                         // 4 wide waves (64 x 128 per wave)
   bool use_tuning = true;               // consult the tuning table (single, non-batched products)
+  bool group_products = true;           // ein_multi may issue independent products as one launch
   const GemmChoice* force = nullptr;    // this choice for every product (kernel tests, the autotuner)
   // Batch size of the tensors with bs != 0. Every contraction then runs for all members: a
   // member index carried by one operand only becomes part of the GEMM's M or N (one fat GEMM
@@ -164,6 +165,24 @@ void join_branches(Engine& E);
 template <typename T>
 void ein(Engine& E, double alpha, const char* spec, const Ten<T>& A, const Ten<T>& B, const Ten<T>& C,
          double beta);
+
+// One contraction of a group issued together (ein_multi).
+template <typename T>
+struct EinTerm {
+  double alpha;
+  const char* spec;
+  const Ten<T>* A;
+  const Ten<T>* B;
+  const Ten<T>* C;
+  double beta;
+};
+// Two or three independent contractions into distinct outputs, each a single GEMM for the split-BF16
+// kernel (FP32 context with the split enabled, no member batch, 2 M N K >= bf16_min_flops, an output the
+// GEMM writes in place, no tuning-table entry of its own, operands of one kind): operands permuted as ein
+// would, then one launch (gemm_bf16x3_multi). Returns false, with nothing issued, when any term does not
+// qualify; the caller then issues them one by one.
+template <typename T>
+bool ein_multi(Engine& E, const EinTerm<T>* terms, int n);
 
 // C = alpha * permute(A) + beta * C   ("ijab->jiba"; the identity spec is an axpby)
 template <typename T>
@@ -212,6 +231,11 @@ struct Bf16Job {
 // marked as one ladder launch); returns false (nothing launched) for other operand kinds or when the
 // context selects another split-BF16 kernel.
 bool gemm_bf16x3_pair(Engine& E, const Bf16Job (&jobs)[2]);
+// Two or three independent products of the same operand kinds (complex output) in one launch of the
+// register-staged 128 x 256 kernel, with one K split for all from the cost model over their summed tiles
+// (within one workgroup per CU), each then reduced on its own; returns false (nothing launched) for other
+// operand kinds or when the context selects another split-BF16 kernel.
+bool gemm_bf16x3_multi(Engine& E, const Bf16Job* jobs, int n);
 
 // y(n) = alpha * sum_k x(k) W(k, n) + beta * y(n) for n < N, k < K, with x(k) at k * incx, y(n) at n * incy
 // and W(k, n) at (k / K2) sk1 + (k % K2) sk2 + (n / N2) sn1 + (n % N2) sn2 (two-level indices: a

@@ -413,6 +413,7 @@ void fork_branches(Engine& E) {
     b->bf16_min_flops = E.bf16_min_flops;
     b->bf16_kernel = E.bf16_kernel;
     b->pair_splits = E.pair_splits;
+    b->group_products = E.group_products;
     b->use_tuning = E.use_tuning;
     b->nb = E.nb;
     b->gemm_flops = 0;
@@ -429,10 +430,11 @@ void join_branches(Engine& E) {
   }
 }
 
+// The index classes of a contraction: every output letter in exactly one input with the output's
+// extent, every input letter in the output or in the other input with matching extents; a complex
+// output unless both inputs are real. Throws kEInval otherwise.
 template <typename T>
-void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const Ten<T>& B0, const Ten<T>& C0,
-         double beta) {
-  Spec sp = parse3(specstr);
+void check_spec(const Spec& sp, const char* specstr, const Ten<T>& A0, const Ten<T>& B0, const Ten<T>& C0) {
   RTCC_CHECK((int)sp.a.size() == A0.nd && (int)sp.b.size() == B0.nd && (int)sp.c.size() == C0.nd, kEInval,
              std::string("rank mismatch in ") + specstr);
   for (const std::string* x : {&sp.a, &sp.b, &sp.c})
@@ -456,6 +458,13 @@ void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const T
     RTCC_CHECK(ina || inc, kEInval, std::string("summed-only index in ") + specstr);
   }
   RTCC_CHECK(C0.cplx() || (!A0.cplx() && !B0.cplx()), kEInval, std::string("complex into real in ") + specstr);
+}
+
+template <typename T>
+void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const Ten<T>& B0, const Ten<T>& C0,
+         double beta) {
+  Spec sp = parse3(specstr);
+  check_spec(sp, specstr, A0, B0, C0);
 
   // batch axis: prepended as letter Z to every batched operand
   const bool bA = E.nb > 1 && A0.bs != 0, bB = E.nb > 1 && B0.bs != 0, bC = E.nb > 1 && C0.bs != 0;
@@ -590,6 +599,87 @@ void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const T
 }
 
 template <typename T>
+bool ein_multi(Engine& E, const EinTerm<T>* terms, int n) {
+  if constexpr (sizeof(T) != 4) {
+    return false;
+  } else {
+    if (!E.group_products || !E.bf16x3 || E.nb != 1 || E.force || E.bf16_kernel != 1 || n < 2 || n > 3) return false;
+    // every term first checked without issuing anything
+    Spec sp[3];
+    Plan pl[3];
+    int64_t M[3], N[3], K[3];
+    for (int h = 0; h < n; ++h) {
+      const EinTerm<T>& t = terms[h];
+      sp[h] = parse3(t.spec);
+      check_spec(sp[h], t.spec, *t.A, *t.B, *t.C);
+      if (t.C->re == nullptr || !t.C->cplx()) return false;
+      for (int g = 0; g < h; ++g)
+        if (terms[g].C->re == t.C->re) return false;  // distinct outputs
+      pl[h] = plan_for(*t.A, sp[h].a, *t.B, sp[h].b, *t.C, sp[h].c, "");
+      M[h] = N[h] = K[h] = 1;
+      for (char c : pl[h].m) M[h] *= dim_of(*t.C, sp[h].c, c);
+      for (char c : pl[h].n) N[h] *= dim_of(*t.C, sp[h].c, c);
+      for (char c : pl[h].k) K[h] *= dim_of(*t.A, sp[h].a, c);
+      GemmOp<T> oc;
+      if (M[h] < 2 || N[h] < 2 || 2.0 * M[h] * N[h] * K[h] < E.bf16_min_flops) return false;
+      if (!view2d(*t.C, sp[h].c, pl[h].m, pl[h].n, &oc)) return false;
+      if ((t.A->im != nullptr) != (terms[0].A->im != nullptr) || (t.B->im != nullptr) != (terms[0].B->im != nullptr))
+        return false;
+    }
+    size_t mark = E.scratch.used;
+    Bf16Job jobs[3];
+    for (int h = 0; h < n; ++h) {
+      const EinTerm<T>& t = terms[h];
+      const Ten<T>&A = *t.A, &B = *t.B, &C = *t.C;
+      const std::string &bm = pl[h].m, &bn = pl[h].n, &bk = pl[h].k;
+      std::string sa = sp[h].a, sb = sp[h].b;
+      GemmOp<T> oa, ob, oc;
+      Ten<T> Ap = A, Bp = B;
+      if (!view2d(A, sa, bm, bk, &oa)) {
+        Ap = (A.konst && E.cache) ? cached_permute(E, A, sa, bm + bk)
+             : memo_fixed(E, A.re) ? memo_permute(E, A, sa, bm + bk)
+                                   : permuted_copy(E, A, sa, bm + bk);
+        sa = bm + bk;
+        view2d(Ap, sa, bm, bk, &oa);
+      }
+      if (!view2d(B, sb, bk, bn, &ob)) {
+        Bp = (B.konst && E.cache) ? cached_permute(E, B, sb, bk + bn)
+             : memo_fixed(E, B.re) ? memo_permute(E, B, sb, bk + bn)
+                                   : permuted_copy(E, B, sb, bk + bn);
+        sb = bk + bn;
+        view2d(Bp, sb, bk, bn, &ob);
+      }
+      view2d(C, sp[h].c, bm, bn, &oc);
+      if (E.trace)
+        fprintf(stderr, "[rtcc] ein-multi %d/%d %-22s M=%lld N=%lld K=%lld\n", h + 1, n, t.spec, (long long)M[h],
+                (long long)N[h], (long long)K[h]);
+      if (oc.trans == 0) {
+        jobs[h] = Bf16Job{M[h], N[h], K[h], t.alpha, oa, ob, C.re, C.im, oc.ld, t.beta};
+      } else {
+        // C^T(n, m) = B^T(n, k) A^T(k, m)
+        GemmOp<T> at = oa, bt = ob;
+        at.trans ^= 1;
+        bt.trans ^= 1;
+        jobs[h] = Bf16Job{N[h], M[h], K[h], t.alpha, bt, at, C.re, C.im, oc.ld, t.beta};
+      }
+    }
+    bool tuned = false;
+    for (int h = 0; h < n && E.use_tuning; ++h)
+      tuned |= tuned_choice(2, jobs[h].M, jobs[h].N, jobs[h].K, jobs[h].A.im != nullptr, jobs[h].B.im != nullptr,
+                            jobs[h].A.trans, jobs[h].B.trans).kind != 0;
+    const bool done = !tuned && gemm_bf16x3_multi(E, jobs, n);
+    if (!done) {
+      // a product with a table entry of its own (or a kernel choice the launch cannot take): one by one
+      for (int h = 0; h < n; ++h)
+        gemm<T>(E, jobs[h].M, jobs[h].N, jobs[h].K, jobs[h].alpha, jobs[h].A, jobs[h].B, jobs[h].Cre, jobs[h].Cim,
+                jobs[h].ldc, jobs[h].beta);
+    }
+    E.scratch.reset(mark);
+    return true;
+  }
+}
+
+template <typename T>
 void padd(Engine& E, double alpha, const char* specstr, const Ten<T>& A, const Ten<T>& C, double beta) {
   std::string s(specstr);
   size_t arrow = s.find("->");
@@ -631,6 +721,8 @@ template void ein<double>(Engine&, double, const char*, const Ten<double>&, cons
 template void ein<float>(Engine&, double, const char*, const Ten<float>&, const Ten<float>&, const Ten<float>&,
                          double);
 template void padd<double>(Engine&, double, const char*, const Ten<double>&, const Ten<double>&, double);
+template bool ein_multi<double>(Engine&, const EinTerm<double>*, int);
+template bool ein_multi<float>(Engine&, const EinTerm<float>*, int);
 template void padd<float>(Engine&, double, const char*, const Ten<float>&, const Ten<float>&, double);
 
 }  // namespace rtcc

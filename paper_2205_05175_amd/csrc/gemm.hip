@@ -1040,9 +1040,11 @@ void gemm(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmOp<T> A,
   }
   const int z = nbt * splits;
   const int cfg = BM * 1000 + BN;
-  // timing of the large complex x complex products (the tile kernel alone; see Engine::mark_mode)
+  // timing of the large complex x complex products, those the split-BF16 context gives the split kernel
+  // (2 M N K >= bf16_min_flops): the tile kernel alone (see Engine::mark_mode)
   const double cc_flops = 8.0 * M * N * K * nbt;
-  const bool ccm = E.mark && E.mark_mode == 2 && AC && BC && cc_flops >= E.bf16_min_flops && !(sizeof(T) == 4 && E.bf16x3);
+  const bool ccm = E.mark && E.mark_mode == 2 && AC && BC && 2.0 * M * N * K * nbt >= E.bf16_min_flops &&
+                   !(sizeof(T) == 4 && E.bf16x3);
   const double cc_bytes =
       2.0 * sizeof(T) * nbt * (M * K + K * N + M * N * (beta != 0.0 ? 2 : 1));
   if (ccm) E.mark(E.mark_user, 0, cc_flops, cc_bytes, E.stream);

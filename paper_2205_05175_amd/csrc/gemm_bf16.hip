@@ -514,10 +514,15 @@ __device__ __forceinline__ void nt_body(const Params& p, int bid) {
   store_tile<AC, BC, 2>(p, accr, acci, split, m0 + wm * 64, n0 + wn * 64, lane);
 }
 
-// LADDER = 1: the same kernel under a name of its own for the particle-particle ladder.
+// Up to three independent products of the same kind in one launch: workgroups [0, wg1) take p0,
+// [wg1, wg2) p1, the rest p2 (a single product passes wg1 = wg2 = its grid). LADDER = 1: the same
+// kernel under a name of its own for the particle-particle ladder.
 template <int AC, int BC, int LADDER, int WN>
-__global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p) {
-  nt_body<AC, BC, WN>(p, blockIdx.x);
+__global__ __launch_bounds__(128 * WN) void gemm_bf16x3_nt(Params p0, Params p1, Params p2, int wg1, int wg2) {
+  const int b = blockIdx.x;
+  if (b < wg1) nt_body<AC, BC, WN>(p0, b);
+  else if (b < wg2) nt_body<AC, BC, WN>(p1, b - wg1);
+  else nt_body<AC, BC, WN>(p2, b - wg2);
 }
 
 // Two products of the same kind in one launch: workgroups [0, wg0) take p0, the rest p1 (the two GEMMs
@@ -718,7 +723,8 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
     p.Cim = Cim;
     p.ldc = ldc;
   }
-  const dim3 grid((unsigned)(p.ntiles * splits));
+  const int nwg = p.ntiles * splits;
+  const dim3 grid((unsigned)nwg);
   const bool lad = E.ladder != 0;
   if (lad && E.mark && E.mark_mode == 1) E.mark(E.mark_user, 0, E.ladder_flops, 0.0, E.stream);
   // timing of the complex x complex register-staged 128 x 256 kernel: algorithmic flops and bytes
@@ -752,15 +758,15 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
       else hipLaunchKernelGGL((gemm_bf16x3_dma<0, 1, 0, 2, 0>), grid, block, 0, E.stream, p);
     }
   } else if (WN == 4) {
-    if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 1, 4>), grid, block, 0, E.stream, p);
-    else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1, 0, 4>), grid, block, 0, E.stream, p);
-    else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 0, 4>), grid, block, 0, E.stream, p);
-    else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1, 0, 4>), grid, block, 0, E.stream, p);
+    if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 1, 4>), grid, block, 0, E.stream, p, p, p, nwg, nwg);
+    else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1, 0, 4>), grid, block, 0, E.stream, p, p, p, nwg, nwg);
+    else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 0, 4>), grid, block, 0, E.stream, p, p, p, nwg, nwg);
+    else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1, 0, 4>), grid, block, 0, E.stream, p, p, p, nwg, nwg);
   } else {
-    if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 1, 2>), grid, block, 0, E.stream, p);
-    else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1, 0, 2>), grid, block, 0, E.stream, p);
-    else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 0, 2>), grid, block, 0, E.stream, p);
-    else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1, 0, 2>), grid, block, 0, E.stream, p);
+    if (lad && AC && !BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 1, 2>), grid, block, 0, E.stream, p, p, p, nwg, nwg);
+    else if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1, 0, 2>), grid, block, 0, E.stream, p, p, p, nwg, nwg);
+    else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 0, 2>), grid, block, 0, E.stream, p, p, p, nwg, nwg);
+    else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1, 0, 2>), grid, block, 0, E.stream, p, p, p, nwg, nwg);
   }
   RTCC_HIP(hipGetLastError());
   if (lad && E.mark && E.mark_mode == 1) E.mark(E.mark_user, 1, E.ladder_flops, 0.0, E.stream);
@@ -867,6 +873,112 @@ bool gemm_bf16x3_pair(Engine& E, const Bf16Job (&jobs)[2]) {
     if (E.trace)
       fprintf(stderr, "[rtcc] gemm-bf16x3 pair %d/2 M=%lld N=%lld K=%lld cr ta=%d tb=%d wn=%d splits=%d\n", h + 1,
               (long long)j.M, (long long)j.N, (long long)j.K, j.A.trans, j.B.trans, WN, p[h].splits);
+  }
+  E.scratch.reset(mark);
+  return true;
+}
+
+bool gemm_bf16x3_multi(Engine& E, const Bf16Job* jobs, int n) {
+  if (n < 2 || n > 3 || E.bf16_kernel != 1) return false;
+  const bool AC = jobs[0].A.im != nullptr, BC = jobs[0].B.im != nullptr;
+  if (!AC && !BC) return false;
+  for (int h = 0; h < n; ++h) {
+    const Bf16Job& j = jobs[h];
+    if (j.M <= 0 || j.N <= 0 || j.K <= 0 || (j.A.im != nullptr) != AC || (j.B.im != nullptr) != BC || !j.Cim)
+      return false;
+    RTCC_CHECK(j.M < (1LL << 30) && j.N < (1LL << 30) && j.K < (1LL << 30), kEInval,
+               "gemm_bf16x3_multi: dimension too large");
+  }
+  constexpr int WN = 4, kBN = 64 * WN;
+  size_t mark = E.scratch.used;
+  Params p[3];
+  int64_t tiles = 0;
+  int stages = 0;
+  double flops = 0.0, bytes = 0.0, plane_bytes = 0.0;
+  for (int h = 0; h < n; ++h) {
+    const Bf16Job& j = jobs[h];
+    const Packed pa = pack_operand(E, j.A.re, j.A.im, j.A.ld, j.A.trans, j.M, j.K, j.A.konst, kRowPad);
+    const Packed pb = pack_operand(E, j.B.re, j.B.im, j.B.ld, j.B.trans ? 0 : 1, j.N, j.K, j.B.konst, kBN);
+    Params& q = p[h];
+    q.A = pa.p;
+    q.B = pb.p;
+    q.pa = pa.plane;
+    q.pb = pb.plane;
+    q.Kp = pa.Kp;
+    q.Mp = pa.Rp;
+    q.Np = pb.Rp;
+    q.M = (int)j.M;
+    q.N = (int)j.N;
+    q.tiles_m = (int)cdiv(j.M, kBM);
+    q.tiles_n = (int)cdiv(j.N, kBN);
+    q.ntiles = q.tiles_m * q.tiles_n;
+    q.alpha = (float)j.alpha;
+    q.beta = (float)j.beta;
+    tiles += q.ntiles;
+    stages = std::max(stages, q.Kp / kBK);
+    flops += 2.0 * j.M * j.N * j.K * ((AC && BC) ? 4 : 2);
+    bytes += 8.0 * (j.M * j.K + j.N * j.K + j.M * j.N * (j.beta != 0.0 ? 2 : 1));
+    plane_bytes += (double)j.M * j.N * 8.0;
+  }
+  // one K split for all, from the single-product cost model over the summed tiles (the longest K sets the
+  // per-tile time), within one workgroup per CU: the launch replaces products that ran one after another
+  const double tile_time = 2.0 * kBM * kBN * (double)stages * kBK * ((AC && BC) ? 4 : 2) / (0.35 * 2516.6e12 / 3 / 256);
+  int splits = 1;
+  double best = 1e300;
+  constexpr int kSplitWG = 256;
+  for (int sp = 1; sp <= 16 && (sp == 1 || stages / sp >= 4); ++sp) {
+    if (sp > 1 && tiles * sp > kSplitWG) break;
+    const double rounds = (double)cdiv(tiles * sp, 256);
+    const double t = rounds * tile_time / sp + (sp > 1 ? (2.0 * sp + 2.0) * plane_bytes / 12e12 : 0.0);
+    if (t < best * 0.97) {
+      best = t;
+      splits = sp;
+    }
+  }
+  float* P[3][2] = {};
+  int wg[3] = {0, 0, 0};
+  for (int h = 0; h < n; ++h) {
+    const Bf16Job& j = jobs[h];
+    Params& q = p[h];
+    const int st = q.Kp / kBK, per = (int)cdiv(st, splits);
+    q.kchunk = per * kBK;
+    q.splits = (int)cdiv(st, per);
+    if (q.splits > 1) {
+      q.split_stride = j.M * j.N;
+      P[h][0] = E.scratch.get<float>(q.splits * j.M * j.N);
+      P[h][1] = E.scratch.get<float>(q.splits * j.M * j.N);
+      q.Cre = P[h][0];
+      q.Cim = P[h][1];
+      q.ldc = j.N;
+    } else {
+      q.split_stride = 0;
+      q.Cre = j.Cre;
+      q.Cim = j.Cim;
+      q.ldc = j.ldc;
+    }
+    wg[h] = q.ntiles * q.splits;
+  }
+  if (n == 2) p[2] = p[1];
+  const int wg1 = wg[0], wg2 = wg[0] + wg[1], total = wg2 + (n == 3 ? wg[2] : 0);
+  // timed as one launch of the complex x complex kernel (see Engine::mark_mode)
+  const bool ccm = E.mark && E.mark_mode == 2 && AC && BC;
+  if (ccm) E.mark(E.mark_user, 0, flops, bytes, E.stream);
+  const dim3 grid((unsigned)total), block(128 * WN);
+  if (AC && BC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 1, 0, 4>), grid, block, 0, E.stream, p[0], p[1], p[2], wg1, wg2);
+  else if (AC) hipLaunchKernelGGL((gemm_bf16x3_nt<1, 0, 0, 4>), grid, block, 0, E.stream, p[0], p[1], p[2], wg1, wg2);
+  else hipLaunchKernelGGL((gemm_bf16x3_nt<0, 1, 0, 4>), grid, block, 0, E.stream, p[0], p[1], p[2], wg1, wg2);
+  RTCC_HIP(hipGetLastError());
+  if (ccm) E.mark(E.mark_user, 1, flops, bytes, E.stream);
+  for (int h = 0; h < n; ++h) {
+    const Bf16Job& j = jobs[h];
+    if (p[h].splits > 1)
+      splitk_reduce_launch<float>(E.stream, P[h][0], P[h][1], p[h].splits, j.M, j.N, j.Cre, j.Cim, j.ldc, 0, 1,
+                                  j.alpha, j.beta);
+    E.gemm_flops += 2 * j.M * j.N * j.K * ((AC && BC) ? 4 : 2);
+    if (E.trace)
+      fprintf(stderr, "[rtcc] gemm-bf16x3 multi %d/%d M=%lld N=%lld K=%lld %s%s ta=%d tb=%d wn=%d splits=%d\n", h + 1,
+              n, (long long)j.M, (long long)j.N, (long long)j.K, AC ? "c" : "r", BC ? "c" : "r", j.A.trans,
+              j.B.trans, WN, p[h].splits);
   }
   E.scratch.reset(mark);
   return true;

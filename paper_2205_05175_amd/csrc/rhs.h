@@ -57,13 +57,13 @@ struct Work {
   Ten<T> f, fov, foo, fvv;                         // field-dressed Fock matrix (real) and blocks
   Ten<T> t1, l1, t2, X, tau, l2, taut, t2s, l2s;    // amplitudes; X = [tau; l2] (ladder operand)
   Ten<T> Fae, Fmi, Fme, Hvv, Hoo, Gvv, Goo, Q, Gx;  // one-body
-  Ten<T> W, M, Mp, Hooov, Z1, Y, U, U2, Y3, Y6, B4, B5, B7, D, Nn, Xin, Qnf;
+  Ten<T> W, M, Mp, Hooov, Z1, Y, U, U2, Y3, Y3B, Y3C, Y6, B4, B5, B7, D, Nn, Xin, Qnf;
   Ten<T> Lad, LadT, LadL;
   Ten<T> Xp, Xm, Sp, Sm;                           // symmetric / antisymmetric ladder operands and products
-  Ten<T> Pd, Px, Bd, Bx, WW, Wd, Wx, HH, HHd, HHx, HH5, T2R, L2R, Zt, ZLt, B2, B3, Wr;
+  Ten<T> Pd, Px, Bd, Bx, WW, Wd, Wx, HH, HHd, HHx, HH5, T2R, L2R, Zt, ZLt, B2, B3, Wr, WrB, WrC;
   Ten<T> Z, ZL, S1t;                               // (1+P) brackets; t1-t1 ring piece
   Ten<T> R1, R2, S1, S2;                           // residuals: R_T (T1,T2), R_L (L1,L2)
-  Ten<T> S1b, S1c, Wr2;                            // partial Lambda1 sums of the concurrent groups
+  Ten<T> S1b, S1c, Wr2, Wr2B, Wr2C;                // partial Lambda1 sums of the concurrent groups
   Ten<T> rho, Dvv, Doo, P1;                        // one-particle density
 };
 

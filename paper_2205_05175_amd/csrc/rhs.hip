@@ -170,6 +170,8 @@ void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
   w.U = A.cplx<T>({o, o, v, o});
   w.U2 = A.cplx<T>({o, o, o, v});
   w.Y3 = A.cplx<T>({o, o, o, v});
+  w.Y3B = A.cplx<T>({o, o, o, v});
+  w.Y3C = A.cplx<T>({o, o, o, v});
   w.Y6 = A.cplx<T>({o, o, v, o});
   w.B4 = A.cplx<T>({o, o, v, o});
   w.B5 = A.cplx<T>({o, o, o, v});
@@ -208,7 +210,10 @@ void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
   w.ZLt = A.cplx<T>({o, v, o, v});
   w.B2 = A.cplx<T>({o, v, o, v});
   w.B3 = A.cplx<T>({o, v, o, v});
+  // the three l2s x t2 intermediates of each of the two Lambda1 groups, formed together
   w.Wr = A.cplx<T>({o, v, o, v});
+  w.WrB = A.cplx<T>({o, v, o, v});
+  w.WrC = A.cplx<T>({o, v, o, v});
   w.Z = A.cplx<T>({o, o, v, v});
   w.S1t = A.cplx<T>({o, v, o, o});
   w.ZL = A.cplx<T>({o, o, v, v});
@@ -218,6 +223,8 @@ void build_work(Arena& A, int o, int v, Work<T>& w, int nb) {
   w.S1b = A.cplx<T>({o, v});
   w.S1c = A.cplx<T>({o, v});
   w.Wr2 = A.cplx<T>({v, o, o, v});
+  w.Wr2B = A.cplx<T>({v, o, o, v});
+  w.Wr2C = A.cplx<T>({v, o, o, v});
   w.S2 = A.cplx<T>({o, o, v, v});
   w.rho = A.cplx<T>({n, n});
   w.Dvv = A.cplx<T>({v, v});
@@ -414,9 +421,13 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
 
     // ring intermediates (element X_mbej at (m,e,j,b))
     if (par) cur = E.br[1];
-    C(1, "njfb,mnef->mejb", t2, I.Loovv, w.Pd, 0);
+    {
+      const EinTerm<T> ring[2] = {{1, "njfb,mnef->mejb", &t2, &I.Loovv, &w.Pd, 0},
+                                  {1, "jnfb,mnfe->mejb", &t2, &I.oovv, &w.Px, 0}};
+      if (!ein_multi<T>(*cur, ring, 2))
+        for (const EinTerm<T>& x : ring) C(x.alpha, x.spec, *x.A, *x.B, *x.C, x.beta);
+    }
     C(-1, "jnfb,mnef->mejb", t2, I.oovv, w.Pd, 1);
-    C(1, "jnfb,mnfe->mejb", t2, I.oovv, w.Px, 0);
   }
   // Lambda intermediates used by more than one of the concurrent parts
   if (lambda && tb) {
@@ -498,13 +509,16 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   if (tb) {
     // group B (the Wr part of A1)
     // Wr in the product's own row-major layout (i f | n g), which the next contraction reads as
-    // rows i over one contiguous run of its summed letters
-    C(1, "imef,nmeg->ifng", w.l2s, t2, w.Wr, 0);
+    // rows i over one contiguous run of its summed letters; the three l2s x t2 products are independent
+    // and go out as one launch where the split-BF16 kernel takes them
+    const EinTerm<T> wr[3] = {{1, "imef,nmeg->ifng", &w.l2s, &t2, &w.Wr, 0},
+                              {1, "imef,nmgf->ieng", &w.l2s, &t2, &w.WrB, 0},
+                              {1, "imef,nmfg->ieng", &w.l2s, &t2, &w.WrC, 0}};
+    if (!ein_multi<T>(*cur, wr, 3))
+      for (const EinTerm<T>& x : wr) C(x.alpha, x.spec, *x.A, *x.B, *x.C, x.beta);
     C(-1, "ifng,nfag->ia", w.Wr, I.ovvv, w.S1b, 0);
-    C(1, "imef,nmgf->ieng", w.l2s, t2, w.Wr, 0);
-    C(1, "ieng,nega->ia", w.Wr, I.Lovvv, w.S1b, 1);
-    C(1, "imef,nmfg->ieng", w.l2s, t2, w.Wr, 0);
-    C(-1, "ieng,nega->ia", w.Wr, I.ovvv, w.S1b, 1);
+    C(1, "ieng,nega->ia", w.WrB, I.Lovvv, w.S1b, 1);
+    C(-1, "ieng,nega->ia", w.WrC, I.ovvv, w.S1b, 1);
   }
   if (par) cur = &E;
   P(1, "ia->ia", w.Fme, w.S1, 0);
@@ -541,24 +555,32 @@ void residuals(Engine& E, const Ints<T>& I, Work<T>& w, bool tb, bool lambda) {
   C(-1, "imen,nema->ia", w.U, I.ovov, w.S1, 1);
   // group C: the Y3 part of A1, then -A2 = -sum_mne l2s_mn^ae Hbar_iemn
   if (par) cur = E.br[1];
-  C(1, "imnf,kmfg->inkg", w.U2, t2, w.Y3, 0);
+  {
+    const EinTerm<T> y3[3] = {{1, "imnf,kmfg->inkg", &w.U2, &t2, &w.Y3, 0},
+                              {1, "imnf,kmgf->inkg", &w.U2, &t2, &w.Y3B, 0},
+                              {1, "imen,kmeg->inkg", &w.U, &t2, &w.Y3C, 0}};
+    if (!ein_multi<T>(*cur, y3, 3))
+      for (const EinTerm<T>& x : y3) C(x.alpha, x.spec, *x.A, *x.B, *x.C, x.beta);
+  }
   C(1, "inkg,nkag->ia", w.Y3, I.oovv, w.S1c, 0);
-  C(1, "imnf,kmgf->inkg", w.U2, t2, w.Y3, 0);
-  C(-1, "inkg,nkag->ia", w.Y3, I.Loovv, w.S1c, 1);
-  C(1, "imen,kmeg->inkg", w.U, t2, w.Y3, 0);
-  C(1, "inkg,nkga->ia", w.Y3, I.oovv, w.S1c, 1);
+  C(-1, "inkg,nkag->ia", w.Y3B, I.Loovv, w.S1c, 1);
+  C(1, "inkg,nkga->ia", w.Y3C, I.oovv, w.S1c, 1);
   C(-1, "mnae,mnie->ia", w.l2s, I.ooov, w.S1c, 1);
   C(1, "mnae,ke->mnak", w.l2s, t1, w.Y6, 0);
   C(1, "mnak,ikmn->ia", w.Y6, w.W, w.S1c, 1);
   C(-1, "mnae,nmei->ia", w.l2s, w.Z1, w.S1c, 1);
   // Wr2 as (a m | k f): the product's output rows (a m) and columns (k f), and for the next
   // contraction rows a over the contiguous run of its summed letters
-  C(1, "mnae,nkef->amkf", w.l2s, t2, w.Wr2, 0);
+  {
+    const EinTerm<T> wr2[3] = {{1, "mnae,nkef->amkf", &w.l2s, &t2, &w.Wr2, 0},
+                               {1, "mnae,nkfe->amkf", &w.l2s, &t2, &w.Wr2B, 0},
+                               {1, "mnae,mkfe->ankf", &w.l2s, &t2, &w.Wr2C, 0}};
+    if (!ein_multi<T>(*cur, wr2, 3))
+      for (const EinTerm<T>& x : wr2) C(x.alpha, x.spec, *x.A, *x.B, *x.C, x.beta);
+  }
   C(-1, "amkf,ikmf->ia", w.Wr2, I.Looov, w.S1c, 1);
-  C(1, "mnae,nkfe->amkf", w.l2s, t2, w.Wr2, 0);
-  C(1, "amkf,ikmf->ia", w.Wr2, I.ooov, w.S1c, 1);
-  C(1, "mnae,mkfe->ankf", w.l2s, t2, w.Wr2, 0);
-  C(1, "ankf,kinf->ia", w.Wr2, I.ooov, w.S1c, 1);
+  C(1, "amkf,ikmf->ia", w.Wr2B, I.ooov, w.S1c, 1);
+  C(1, "ankf,kinf->ia", w.Wr2C, I.ooov, w.S1c, 1);
   C(1, "mf,iefn->mien", t1, I.ovvo, w.B4, 0);
   C(-1, "mnae,mien->ia", w.l2s, w.B4, w.S1c, 1);
   C(1, "mf,ikfg->mikg", t1, I.oovv, w.B5, 0);

@@ -1,7 +1,8 @@
 """Live kernel timing (rtcc_profile / rtcc_profile_read) times exactly the launches it is meant to time.
 
-Mode 2 ("complex") brackets every complex x complex product of at least 5e8 algorithmic flops -- in the
-split-BF16 context only launches of the register-staged 128 x 256 kernel -- and mode 1 ("ladder") the
+Mode 2 ("complex") brackets every complex x complex product with 2 M N K >= 5e8 -- in the
+split-BF16 context only launches of the register-staged 128 x 256 kernel, where a launch may carry the
+two or three independent products of a Lambda1 group -- and mode 1 ("ladder") the
 ladder GEMMs. One right-hand side at (16,42) (complex products of 672 x 672 and 256 x 672 outputs, the
 split-BF16 ones on 18-tile grids, so the 128 x 256 kernel runs) is evaluated with the engine trace on;
 the trace's GEMM lines give the expected launch count and flop sum (8 M N K per complex product), which
@@ -27,11 +28,21 @@ def _need_gpu(require_gpu):
 
 
 def _expected(trace, prec):
-    """(launches, summed flops, summed minimum bytes) of the complex products the trace shows."""
-    n, fl, by = 0, 0.0, 0.0
+    """(launches, summed flops, summed minimum bytes, grouped launches) of the complex products the trace
+    shows."""
+    n, fl, by, ng = 0, 0.0, 0.0, 0
     esz = 16 if prec == "fp64" else 8
     for line in trace.splitlines():
         if prec == "bf16x3":
+            # single products, and the products issued together as one launch ("multi h/n")
+            g = re.search(r"\[rtcc\] gemm-bf16x3 multi (\d)/\d M=(\d+) N=(\d+) K=(\d+) cc ", line)
+            if g:
+                M, N, K = int(g[2]), int(g[3]), int(g[4])
+                n += g[1] == "1"
+                ng += g[1] == "1"
+                fl += 8.0 * M * N * K
+                by += esz * (M * K + K * N + M * N)
+                continue
             m = re.search(r"\[rtcc\] gemm-bf16x3 M=(\d+) N=(\d+) K=(\d+) cc .* wn=(\d) splits=\d+ kernel=(\d)", line)
             if not m or m[4] != "4" or m[5] != "1":
                 continue
@@ -41,12 +52,12 @@ def _expected(trace, prec):
             if not m:
                 continue
             M, N, K, nb = (int(x) for x in m.groups())
-            if 8.0 * M * N * K * nb < 5e8:
+            if 2.0 * M * N * K * nb < 5e8:
                 continue
         n += 1
         fl += 8.0 * M * N * K * nb
         by += esz * nb * (M * K + K * N + M * N)
-    return n, fl, by
+    return n, fl, by, ng
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
@@ -65,9 +76,12 @@ def test_complex_product_timing_counts_the_traced_products(monkeypatch, capfd, p
     n, ms, fl, by = R.profile_read()
     R.profile(False)
     trace = capfd.readouterr().err
-    en, efl, eby = _expected(trace, prec)
-    print(f"  timed {n} launches, {ms:.3f} ms, {fl:.4g} flop and {by:.4g} B per launch; trace {en}", flush=True)
-    assert en >= 10 and n == en
+    en, efl, eby, eng = _expected(trace, prec)
+    print(f"  timed {n} launches, {ms:.3f} ms, {fl:.4g} flop and {by:.4g} B per launch; trace {en} "
+          f"({eng} grouped)", flush=True)
+    # ten complex products with 2 M N K >= 5e8; in the split-BF16 context the two Lambda1 groups of three
+    # independent products go out as one launch each
+    assert n == en and en == (6 if prec == "bf16x3" else 10) and eng == (2 if prec == "bf16x3" else 0)
     assert fl * n == pytest.approx(efl, rel=1e-12)
     assert ms > 0.0
     # the bytes count the output once more where a product accumulates into it
