@@ -56,11 +56,12 @@ LADDER_TRAFFIC_BF16X3 = {"fetch_bytes": 246305.8 * 1024 * 2.0, "write_bytes": 38
 LADDER_TRAFFIC_BF16X3_SYM = {"fetch_bytes": 73660.2 * 1024 * 2.0, "write_bytes": 69636.2 * 1024 * 1.0,
                              "kernel": "gemm_bf16x3_nt2<1, 0, 1, 4>"}
 # The dominant kernel of the split-BF16 step, the register-staged complex x complex kernel
-# gemm_bf16x3_nt<1, 1, 0, 4> (the ring and Lambda products, 18 launches per right-hand side at o=20
-# v=76): mean HBM bytes per dispatch over its launches in the RK4 step of bench.py --workload profile,
-# calibrated on the same run's state clone like the ladder's (FETCH_SIZE 39,446.6 KiB x2.0, WRITE_SIZE
-# 32,779.1 KiB x1.0 per dispatch, 216 dispatches). Commands: profiles/cc_gemm_o20v76.md.
-CC_TRAFFIC_BF16X3 = {"fetch_bytes": 39446.6 * 1024 * 2.0, "write_bytes": 32779.1 * 1024 * 1.0,
+# gemm_bf16x3_nt<1, 1, 0, 4> (the ring and Lambda products, 12 launches per right-hand side at o=20
+# v=76, three of them carrying three independent products each): mean HBM bytes per dispatch over its
+# launches in the RK4 step of bench.py --workload profile, calibrated on the same run's state clone like
+# the ladder's (FETCH_SIZE 59,570.3 KiB x2.0, WRITE_SIZE 37,153.6 KiB x1.0 per dispatch, 144 dispatches).
+# Commands: profiles/cc_gemm_o20v76.md.
+CC_TRAFFIC_BF16X3 = {"fetch_bytes": 59570.3 * 1024 * 2.0, "write_bytes": 37153.6 * 1024 * 1.0,
                      "kernel": "gemm_bf16x3_nt<1, 1, 0, 4>"}
 
 
