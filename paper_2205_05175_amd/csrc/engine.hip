@@ -598,6 +598,21 @@ void ein(Engine& E, double alpha, const char* specstr, const Ten<T>& A0, const T
   E.scratch.reset(mark);
 }
 
+// Whether the memory of two tensors (either plane) intersects.
+template <typename T>
+bool overlaps(const Ten<T>& x, const Ten<T>& y) {
+  auto span = [](const Ten<T>& t) {
+    int64_t e = 1;
+    for (int i = 0; i < t.nd; ++i) e += (t.d[i] - 1) * t.s[i];
+    return e;
+  };
+  const int64_t ex = span(x), ey = span(y);
+  for (const T* a : {x.re, x.im})
+    for (const T* b : {y.re, y.im})
+      if (a && b && a < b + ey && b < a + ex) return true;
+  return false;
+}
+
 template <typename T>
 bool ein_multi(Engine& E, const EinTerm<T>* terms, int n) {
   if constexpr (sizeof(T) != 4) {
@@ -613,8 +628,10 @@ bool ein_multi(Engine& E, const EinTerm<T>* terms, int n) {
       sp[h] = parse3(t.spec);
       check_spec(sp[h], t.spec, *t.A, *t.B, *t.C);
       if (t.C->re == nullptr || !t.C->cplx()) return false;
-      for (int g = 0; g < h; ++g)
-        if (terms[g].C->re == t.C->re) return false;  // distinct outputs
+      // independent: no output shares memory with another term's output or inputs
+      for (int g = 0; g < n; ++g)
+        if (g != h && (overlaps(*terms[g].C, *t.C) || overlaps(*terms[g].C, *t.A) || overlaps(*terms[g].C, *t.B)))
+          return false;
       pl[h] = plan_for(*t.A, sp[h].a, *t.B, sp[h].b, *t.C, sp[h].c, "");
       M[h] = N[h] = K[h] = 1;
       for (char c : pl[h].m) M[h] *= dim_of(*t.C, sp[h].c, c);
