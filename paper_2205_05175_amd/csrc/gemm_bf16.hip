@@ -49,14 +49,17 @@ constexpr int kKPad = 32;            // packed K is a multiple of this
 // dst plane (2 c + h) = h ? lo : hi of plane c of the source, k-blocked as [Kp / 16][2][Rp][8]: one
 // 16-wide k stage of 128 rows is two contiguous 2 KB runs. Element (r, k) of the source is
 // src[r * ld + k] (trans = 0) or src[k * ld + r] (trans = 1). A thread makes one row's 16-wide k
-// block: consecutive threads take consecutive rows, so the 16-byte chunks they store are contiguous;
-// the loads are four 16-byte vectors (trans = 0, aligned) or 16 loads coalesced across rows (trans = 1).
+// block: consecutive lanes take consecutive rows, so the 16-byte chunks they store are contiguous;
+// the loads are four 16-byte vectors (trans = 0, aligned; the two halves of a wave read the two
+// halves of each row's 128-byte run) or 16 loads coalesced across rows (trans = 1).
 __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ sre, const float* __restrict__ sim,
                                                    int64_t ld, int trans, int R, int K, int Rp, int Kp, int vec,
                                                    __bf16* __restrict__ dst) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= Rp) return;
-  const int kb = blockIdx.y, k0 = kb * 16;
+  // a wave takes 32 rows and two neighbouring k blocks: lanes 0-31 block 2 y, lanes 32-63 block 2 y + 1,
+  // so with trans = 0 each row's 128-byte run is read by one load instruction
+  const int t = threadIdx.x, r = blockIdx.x * 128 + (t >> 6) * 32 + (t & 31);
+  const int kb = 2 * blockIdx.y + ((t >> 5) & 1), k0 = kb * 16;
+  if (r >= Rp || kb * 16 >= Kp) return;
   const int64_t plane = (int64_t)Rp * Kp;
   const int64_t o0 = ((int64_t)(2 * kb) * Rp + r) * 8, o1 = o0 + (int64_t)Rp * 8;  // halves k0..7, k8..15
   const int np = sim ? 2 : 1;
@@ -110,9 +113,9 @@ Packed pack_operand(Engine& E, const float* re, const float* im, int64_t ld, int
   P.np = im ? 2 : 1;
   P.plane = (int64_t)P.Rp * P.Kp;
   const size_t bytes = (size_t)P.plane * 2 * P.np * sizeof(__bf16);
-  RTCC_CHECK(P.Kp / 16 <= 65535, kEInval, "gemm_bf16x3: K too large");
+  RTCC_CHECK(P.Kp / 32 <= 65535, kEInval, "gemm_bf16x3: K too large");
   const bool vec = !trans && ld % 4 == 0 && ((uintptr_t)re % 16) == 0 && (!im || ((uintptr_t)im % 16) == 0);
-  const dim3 grid((unsigned)cdiv(P.Rp, 256), (unsigned)(P.Kp / 16));
+  const dim3 grid((unsigned)cdiv(P.Rp, 128), (unsigned)(P.Kp / 32));
   auto fill = [&](void* dst, hipStream_t st) {
     hipLaunchKernelGGL(pack_kernel, grid, dim3(256), 0, st, re, im, ld, trans, (int)R, (int)K, P.Rp, P.Kp, (int)vec,
                        (__bf16*)dst);
