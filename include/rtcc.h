@@ -57,7 +57,9 @@ typedef struct rtcc_ctx rtcc_ctx;
  *                 environment variable RTCC_BF16_MIN_FLOPS, read by rtcc_init). Independent
  *                 products of one part of the Lambda1 residual (the three l2s x t2
  *                 intermediates of each of its two groups) go out as one launch with one K
- *                 split for all; RTCC_NO_GROUP=1, read by rtcc_init, issues them one by one. */
+ *                 split for all; RTCC_NO_GROUP=1, read by rtcc_init, issues them one by one.
+ *                 K splits are chosen within a workgroup cap, 160 for a single product and 256
+ *                 for a grouped launch (RTCC_SPLIT_WG, RTCC_GROUP_WG). */
 enum { RTCC_FP64 = 0, RTCC_FP32 = 1, RTCC_BF16X3 = 2 };
 
 enum {

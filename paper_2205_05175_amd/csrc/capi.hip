@@ -447,6 +447,8 @@ void ensure_batch(rtcc_ctx* c, std::unique_ptr<BatchWS>& slot, int nb) {
   B->E.bf16_min_flops = c->E.bf16_min_flops;
   B->E.bf16_kernel = c->E.bf16_kernel;
   B->E.group_products = c->E.group_products;
+  B->E.split_wg = c->E.split_wg;
+  B->E.group_wg = c->E.group_wg;
   B->E.sym_ladder = c->E.sym_ladder;
   B->E.ladder_lds = c->E.ladder_lds;
   B->E.pair_splits = c->E.pair_splits;
@@ -946,6 +948,11 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     c->use_graph = !(ng && ng[0] == '1');
     const char* ngr = std::getenv("RTCC_NO_GROUP");
     c->E.group_products = !(ngr && ngr[0] == '1');
+    const char* swg = std::getenv("RTCC_SPLIT_WG");
+    if (swg && swg[0]) c->E.split_wg = std::atoi(swg);
+    const char* gwg = std::getenv("RTCC_GROUP_WG");
+    if (gwg && gwg[0]) c->E.group_wg = std::atoi(gwg);
+    RTCC_CHECK(c->E.split_wg >= 1 && c->E.group_wg >= 1, kEInval, "RTCC_SPLIT_WG and RTCC_GROUP_WG must be positive");
     const char* tr = std::getenv("RTCC_TRACE");
     c->E.trace = tr && tr[0] == '1';
     const char* nbr = std::getenv("RTCC_NO_BRANCH");

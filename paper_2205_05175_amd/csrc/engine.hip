@@ -414,6 +414,8 @@ void fork_branches(Engine& E) {
     b->bf16_kernel = E.bf16_kernel;
     b->pair_splits = E.pair_splits;
     b->group_products = E.group_products;
+    b->split_wg = E.split_wg;
+    b->group_wg = E.group_wg;
     b->use_tuning = E.use_tuning;
     b->nb = E.nb;
     b->gemm_flops = 0;

@@ -697,7 +697,7 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   const double plane_bytes = (double)M * N * 4.0 * 2.0;
   int splits = 1;
   double best = 1e300;
-  constexpr int kSplitWG = 160;
+  const int kSplitWG = E.split_wg;
   for (int sp = 1; sp <= 16 && (sp == 1 || stages / sp >= 4); ++sp) {
     if (sp > 1 && p.ntiles * sp > kSplitWG) break;
     const double rounds = (double)cdiv((int64_t)p.ntiles * sp, 256);
@@ -928,7 +928,7 @@ bool gemm_bf16x3_multi(Engine& E, const Bf16Job* jobs, int n) {
   const double tile_time = 2.0 * kBM * kBN * (double)stages * kBK * ((AC && BC) ? 4 : 2) / (0.35 * 2516.6e12 / 3 / 256);
   int splits = 1;
   double best = 1e300;
-  constexpr int kSplitWG = 256;
+  const int kSplitWG = E.group_wg;
   for (int sp = 1; sp <= 16 && (sp == 1 || stages / sp >= 4); ++sp) {
     if (sp > 1 && tiles * sp > kSplitWG) break;
     const double rounds = (double)cdiv(tiles * sp, 256);
