@@ -759,6 +759,11 @@ def main():
     gpu_dip = R.dipole(y64)
     cpu, oracle_err = (None, None) if args.no_cpu else cpu_baseline_leg(fock, mu, o, v, y64.cpu().numpy(), gpu_dip)
 
+    # measured ceilings of this device, reported beside the published ones (the roofline `peak`)
+    from paper_2205_05175_amd import peak_probe
+    measured = {"bf16_tflops": peak_probe("bf16", 12000), "fp32_tflops": peak_probe("fp32", 6000),
+                "fp64_tflops": peak_probe("fp64", 3000), "hbm_copy_gbs": peak_probe("copy", 1 << 32)}
+    log(f"[bench] measured peaks {measured}")
     r32 = results["fp32"]
     rbf = results["bf16x3"]
     # the headline path is split-BF16 when its dipole stays within 1e-6 au of FP64 over the gate trajectory,
@@ -779,11 +784,13 @@ def main():
                packed(o * (o + 1), v * (v + 1) // 2, v * (v + 1) // 2, 2)
                + packed(o * (o - 1), v * (v - 1) // 2, v * (v - 1) // 2, 2))
     peak = PEAK_TFLOPS["fp32"] if head == "fp32" else PEAK_TFLOPS["bf16"] / 3
+    peak_meas = measured["fp32_tflops"] if head == "fp32" else measured["bf16_tflops"] / 3
     peak_note = ("fp32 MFMA peak" if head == "fp32" else "bf16 dense MFMA peak / 3 products per real multiply "
                  "(algorithmic fp32-equivalent flops)")
     cc_traffic = CC_TRAFFIC_BF16X3 if (measured_traffic and CC_TRAFFIC_BF16X3 and not full_ladder) else None
     sub = lambda p, key: {"achieved": results[p][key + "_tflops"], "peak": PEAK_TFLOPS[p],
-                          "frac": results[p][key + "_tflops"] / PEAK_TFLOPS[p], "avg_ms": results[p][key + "_ms"]}
+                          "frac": results[p][key + "_tflops"] / PEAK_TFLOPS[p], "avg_ms": results[p][key + "_ms"],
+                          "frac_of_measured": results[p][key + "_tflops"] / measured[p + "_tflops"]}
     line = {
         "metric": "RK4 steps/s (T+Λ RHS) o=20,v=76: FP32-MFMA vs FP64, dipole err vs oracle",
         "value": rh["steps_per_s"], "unit": "RK4 steps/s", "n_gpus": 1, "steps": K,
@@ -812,7 +819,8 @@ def main():
                                 "products; all its launches in a step)" if head == "bf16x3" else
                                 "complex x complex FP32 tile GEMMs with 2 M N K >= 5e8 (ring and Lambda products)"),
                      "achieved": rh["cc_tflops"], "peak": peak, "unit": "TFLOP/s", "frac": rh["cc_tflops"] / peak,
-                     "peak_note": peak_note,
+                     "peak_note": peak_note, "peak_measured": peak_meas,
+                     "frac_of_measured": rh["cc_tflops"] / peak_meas,
                      "traffic": (cc_traffic["fetch_bytes"] + cc_traffic["write_bytes"]) if cc_traffic else None,
                      "traffic_unit": "bytes per launch, mean over the step's launches (HBM, rocprofv3 FETCH_SIZE + "
                                      "WRITE_SIZE, copy-calibrated)",
@@ -824,13 +832,16 @@ def main():
                                                         f"ladder GEMMs X+V+ and X-V- ({head})"),
                             "achieved": rh["ladder_tflops"],
                             "peak": peak, "unit": "TFLOP/s", "frac": rh["ladder_tflops"] / peak,
-                            "peak_note": peak_note,
+                            "peak_note": peak_note, "peak_measured": peak_meas,
+                            "frac_of_measured": rh["ladder_tflops"] / peak_meas,
                             "traffic": (lt["fetch_bytes"] + lt["write_bytes"] if measured_traffic else None),
                             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                             "copy-calibrated; symmetric form: its two GEMMs in one launch)",
                             "traffic_algorithmic_min": alg_min if measured_traffic else None,
                             "avg_ms": rh["ladder_ms"], "flops_per_launch": rh["ladder_flops"],
                             "fp32": sub("fp32", "ladder"), "fp64": sub("fp64", "ladder")},
+        "peak_measured": dict(measured, note="rtcc_peak_probe on this device: sustained MFMA loops (no memory "
+                              "traffic) and a 4 GiB device copy (bytes read + written)"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -351,6 +351,17 @@ int rtcc_load_tuning(const char* path, int* nentries);
  * v < 1, null pointers or o v > 2^20 (the message is rtcc_last_error(NULL)). */
 int rtcc_check_state_noalloc(int o, int v, const void* y, double* out_dev, void* hip_stream);
 
+/* Measured machine ceilings of the device the caller has current, for reading the kernels' roofline
+ * fractions beside the datasheet figures. kind 0, 1, 2: the sustained rate of v_mfma_f64_16x16x4f64,
+ * v_mfma_f32_16x16x4f32 and v_mfma_f32_32x32x16_bf16 (every wave of a 4096 x 256-thread grid runs
+ * `size` rounds of independent accumulator chains, no memory traffic; 1 <= size <= 2^24), *value (HOST)
+ * in TFLOP/s (2 M N K flops per instruction); kind 3: a plain device copy of `size` bytes (a multiple of
+ * 16 KiB, at most 64 GiB) with 16-byte loads and stores, *value in GB/s counting bytes read plus bytes
+ * written. Each measurement is the mean of several timed launches after an untimed one on a stream of its
+ * own; the probe allocates and frees its buffers and synchronises. Returns RTCC_EINVAL for other
+ * arguments (the message is rtcc_last_error(NULL)), RTCC_EHIP on a HIP error. */
+int rtcc_peak_probe(int kind, int64_t size, double* value);
+
 void rtcc_destroy(rtcc_ctx* ctx);
 const char* rtcc_last_error(const rtcc_ctx* ctx);
 

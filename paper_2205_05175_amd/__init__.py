@@ -106,6 +106,7 @@ def load_library(path: str = LIB_PATH):
                             ctypes.POINTER(i), i, ctypes.POINTER(ctypes.c_float), vp]
     L.rtcc_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(i)]
     L.rtcc_check_state_noalloc.argtypes = [i, i, vp, vp, vp]
+    L.rtcc_peak_probe.argtypes = [i, i64, dp]
     L.rtcc_mixed_schedule.argtypes = [d, d, d, d, ctypes.POINTER(Field), i, dp, ctypes.POINTER(i)]
     L.rtcc_propagate_rk4_mixed.argtypes = [vp, vp, d, d, d, d, ctypes.POINTER(Field), vp, vp]
     L.rtcc_propagate_cashkarp.argtypes = [vp, vp, d, d, d, d, ctypes.POINTER(Field), i, i, dp, dp,
@@ -142,7 +143,7 @@ def load_library(path: str = LIB_PATH):
 EXPORTED = ("rtcc_init", "rtcc_set_precision", "rtcc_rhs", "rtcc_step_rk4", "rtcc_propagate_rk4",
             "rtcc_propagate_batch", "rtcc_rhs_vjp", "rtcc_dipole_vjp", "rtcc_step_rk4_vjp", "rtcc_step_cashkarp",
             "rtcc_set_guard", "rtcc_mixed_schedule", "rtcc_propagate_rk4_mixed", "rtcc_propagate_cashkarp",
-            "rtcc_gemm", "rtcc_load_tuning", "rtcc_check_state_noalloc", "rtcc_tableau_builtin",
+            "rtcc_gemm", "rtcc_load_tuning", "rtcc_check_state_noalloc", "rtcc_peak_probe", "rtcc_tableau_builtin",
             "rtcc_step_tableau", "rtcc_propagate_embedded",
             "rtcc_dipole", "rtcc_dipole_dev", "rtcc_ground_state", "rtcc_kick", "rtcc_check_state", "rtcc_info",
             "rtcc_profile", "rtcc_profile_read", "rtcc_destroy", "rtcc_last_error")
@@ -454,6 +455,18 @@ def check_state_noalloc(o, v, y, out, stream=None):
                                     ctypes.c_void_p(st.cuda_stream))
     if rc != 0:
         raise RTCCError(rc, L.rtcc_last_error(None).decode())
+
+
+def peak_probe(kind, size):
+    """rtcc_peak_probe: "fp64" / "fp32" / "bf16" MFMA rate in TFLOP/s (size = rounds per wave) or "copy"
+    HBM copy bandwidth in GB/s (size = bytes per buffer), measured on the current device."""
+    L = load_library()
+    k = {"fp64": 0, "fp32": 1, "bf16": 2, "copy": 3}[kind]
+    v = ctypes.c_double(0.0)
+    rc = L.rtcc_peak_probe(k, int(size), ctypes.byref(v))
+    if rc != 0:
+        raise RTCCError(rc, L.rtcc_last_error(None).decode())
+    return v.value
 
 
 def state_size(o, v):

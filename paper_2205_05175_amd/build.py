@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "librtcc.so")
-SOURCES = ["gemm.hip", "gemm_bf16.hip", "elementwise.hip", "ladder.hip", "engine.hip", "rhs.hip", "capi.hip",
+SOURCES = ["gemm.hip", "gemm_bf16.hip", "elementwise.hip", "ladder.hip", "engine.hip", "rhs.hip", "capi.hip", "probe.hip",
            "noalloc.hip"]
 ARCH = os.environ.get("RTCC_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

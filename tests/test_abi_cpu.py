@@ -98,3 +98,18 @@ def test_builtin_tableaux_match_oracle():
     with pytest.raises(P.RTCCError):
         P.Tableau.builtin(99)
     assert L.rtcc_tableau_builtin(1, None) == -1
+
+
+def test_peak_probe_rejects_bad_arguments():
+    """rtcc_peak_probe validates its arguments before touching a device: an unknown kind, an empty size and a
+    null output return RTCC_EINVAL."""
+    import ctypes
+    P, L = _lib()
+    v = ctypes.c_double(0.0)
+    assert L.rtcc_peak_probe(4, 100, ctypes.byref(v)) == -1
+    assert L.rtcc_peak_probe(-1, 100, ctypes.byref(v)) == -1
+    assert L.rtcc_peak_probe(2, 0, ctypes.byref(v)) == -1
+    assert L.rtcc_peak_probe(2, 100, None) == -1
+    assert b"invalid" in L.rtcc_last_error(None)
+    with pytest.raises(KeyError):
+        P.peak_probe("fp16", 10)
