@@ -761,7 +761,7 @@ def main():
 
     # measured ceilings of this device, reported beside the published ones (the roofline `peak`)
     from paper_2205_05175_amd import peak_probe
-    measured = {"bf16_tflops": peak_probe("bf16", 12000), "fp32_tflops": peak_probe("fp32", 6000),
+    measured = {"bf16_tflops": peak_probe("bf16", 6000), "fp32_tflops": peak_probe("fp32", 3000),
                 "fp64_tflops": peak_probe("fp64", 3000), "hbm_copy_gbs": peak_probe("copy", 1 << 32)}
     log(f"[bench] measured peaks {measured}")
     r32 = results["fp32"]

@@ -3,7 +3,8 @@
 // give the measured ceilings the kernels' roofline fractions can be read against, beside the datasheet
 // figures.
 //
-// MFMA: every wave keeps four (BF16) or eight independent accumulator chains busy for `size` rounds (no memory traffic
+// MFMA: every wave keeps eight (BF16, FP64) or sixteen (FP32) independent accumulator chains busy for `size`
+// rounds, enough to cover each instruction's latency (measured: fewer chains give less; no memory traffic
 // inside the loop; operands are lane-dependent values the compiler cannot fold) over a grid of 4096
 // workgroups of 256 threads (64 waves per CU); flops = 2 M N K per instruction. Copy: 16-byte loads and
 // stores (four loads in flight per thread) over two buffers of `size` bytes each; GB/s counts the bytes
@@ -25,7 +26,7 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int kBlocks = 4096, kThreads = 256;
 
-// v_mfma_f32_32x32x16_bf16: 32 x 32 x 16, four chains
+// v_mfma_f32_32x32x16_bf16: 32 x 32 x 16, eight chains
 __global__ __launch_bounds__(kThreads) void mfma_bf16_loop(int iters, float* out) {
   const int l = threadIdx.x;
   bf8 a, b;
@@ -33,32 +34,32 @@ __global__ __launch_bounds__(kThreads) void mfma_bf16_loop(int iters, float* out
     a[j] = (__bf16)(1e-3f * (float)((l + j) & 7));
     b[j] = (__bf16)(1e-3f * (float)((l * 3 + j) & 7));
   }
-  f16v c[4];
-  for (int q = 0; q < 4; ++q)
+  f16v c[8];
+  for (int q = 0; q < 8; ++q)
     for (int e = 0; e < 16; ++e) c[q][e] = 0.f;
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) c[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c[q], 0, 0, 0);
+    for (int q = 0; q < 8; ++q) c[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c[q], 0, 0, 0);
   }
   float s = 0.f;
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < 8; ++q)
     for (int e = 0; e < 16; ++e) s += c[q][e];
   out[blockIdx.x * kThreads + l] = s;
 }
 
-// v_mfma_f32_16x16x4f32: 16 x 16 x 4, eight chains
+// v_mfma_f32_16x16x4f32: 16 x 16 x 4, sixteen chains
 __global__ __launch_bounds__(kThreads) void mfma_f32_loop(int iters, float* out) {
   const int l = threadIdx.x;
   const float a = 1e-3f * (float)(l & 7), b = 1e-3f * (float)((l * 3) & 7);
-  f4v c[8];
-  for (int q = 0; q < 8; ++q)
+  f4v c[16];
+  for (int q = 0; q < 16; ++q)
     for (int e = 0; e < 4; ++e) c[q][e] = 0.f;
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) c[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c[q], 0, 0, 0);
+    for (int q = 0; q < 16; ++q) c[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c[q], 0, 0, 0);
   }
   float s = 0.f;
-  for (int q = 0; q < 8; ++q)
+  for (int q = 0; q < 16; ++q)
     for (int e = 0; e < 4; ++e) s += c[q][e];
   out[blockIdx.x * kThreads + l] = s;
 }
@@ -131,10 +132,10 @@ extern "C" int rtcc_peak_probe(int kind, int64_t size, double* value) {
       double ms = 0.0, flops = 0.0;
       if (kind == 2) {
         ms = time_ms(st, 3, [&] { hipLaunchKernelGGL(mfma_bf16_loop, dim3(kBlocks), dim3(kThreads), 0, st, iters, out); });
-        flops = waves * iters * 4 * (2.0 * 32 * 32 * 16);
+        flops = waves * iters * 8 * (2.0 * 32 * 32 * 16);
       } else if (kind == 1) {
         ms = time_ms(st, 3, [&] { hipLaunchKernelGGL(mfma_f32_loop, dim3(kBlocks), dim3(kThreads), 0, st, iters, out); });
-        flops = waves * iters * 8 * (2.0 * 16 * 16 * 4);
+        flops = waves * iters * 16 * (2.0 * 16 * 16 * 4);
       } else {
         ms = time_ms(st, 3, [&] { hipLaunchKernelGGL(mfma_f64_loop, dim3(kBlocks), dim3(kThreads), 0, st, iters, out); });
         flops = waves * iters * 8 * (2.0 * 16 * 16 * 4);

@@ -9,7 +9,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 PUBLISHED = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6, "copy": 8000.0}
-ROUNDS = {"fp64": 1500, "fp32": 3000, "bf16": 6000}
+ROUNDS = {"fp64": 1500, "fp32": 1500, "bf16": 3000}
 
 
 @pytest.fixture(autouse=True)
