@@ -130,7 +130,8 @@ int rtcc_propagate_rk4(rtcc_ctx* ctx, void* y, double t0, double h, int nsteps, 
  * members' amplitudes is one GEMM over all members; a contraction of two amplitude tensors is a
  * batched GEMM. Every member's result equals its own rtcc_propagate_rk4 up to the rounding order of
  * those sums. One step of all systems (a branch per system) is captured once as a HIP graph and
- * replayed; RTCC_NO_GRAPH=1 selects plain launches on each context's stream. Workspaces for the
+ * replayed; RTCC_NO_GRAPH=1 selects plain launches on each context's stream, and a batch with an FP64
+ * system always uses them (its captured form is not in use). Workspaces for the
  * members are allocated by the first call with a given nprop[s] (a change reallocates them). */
 int rtcc_propagate_batch(rtcc_ctx* const* ctxs, int nsys, const int* nprop, void* const* ys,
                          const rtcc_field* fields, double t0, double h, int nsteps, double* const* mu_dev);

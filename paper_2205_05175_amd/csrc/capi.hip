@@ -1322,8 +1322,13 @@ int rtcc_propagate_batch(rtcc_ctx* const* ctxs, int nsys, const int* nprop, void
       scalar_update(c->stream, c->batch->tdev, t0, false);
       if (dip[s]) dipole_batch_dev(c, ys[s], mu_dev[s]);
     }
-    // HIP cannot time events recorded inside a captured graph: profiling runs the eager launches
-    if (!c0->use_graph || profiling) {
+    // HIP cannot time events recorded inside a captured graph: profiling runs the eager launches. A
+    // batch with an FP64 system also runs them: a captured FP64 batch step once ended its process in
+    // a re-capture (with a since-removed change to the density) and no cause was shown, so that path
+    // stays unused until one is.
+    bool fp64 = false;
+    for (int s = 0; s < nsys; ++s) fp64 |= ctxs[s]->precision == RTCC_FP64;
+    if (!c0->use_graph || profiling || fp64) {
       for (int st = 0; st < nsteps; ++st)
         for (int s = 0; s < nsys; ++s)
           rk4_step_batch(ctxs[s], ys[s], h, dip[s] ? mu_dev[s] + (int64_t)6 * nprop[s] * (st + 1) : nullptr);

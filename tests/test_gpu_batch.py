@@ -52,7 +52,8 @@ def _members(o, v, k, seed):
 
 # This case once ended its process with SIGSEGV inside the second propagate_batch call (re-capture
 # of an FP64 batch step without dipoles) while a change to the dipole density was in the library. The
-# change was taken out, but no cause was shown, so the case is skipped until one is.
+# change was taken out, but no cause was shown, so the case is skipped until one is, and the library
+# issues FP64 batches as plain launches (the (False, fp64) case covers that path).
 _SEGV = ("SIGSEGV once in the FP64 captured batch re-capture; the suspected change was removed without "
          "a shown cause")
 
