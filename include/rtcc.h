@@ -59,7 +59,8 @@ typedef struct rtcc_ctx rtcc_ctx;
  *                 intermediates of each of its two groups) go out as one launch with one K
  *                 split for all; RTCC_NO_GROUP=1, read by rtcc_init, issues them one by one.
  *                 K splits are chosen within a workgroup cap, 160 for a single product and 256
- *                 for a grouped launch (RTCC_SPLIT_WG, RTCC_GROUP_WG). */
+ *                 for a grouped launch (RTCC_SPLIT_WG, RTCC_GROUP_WG); workgroups walk the
+ *                 output tiles in bands of 8 tile rows (RTCC_TILE_BAND, 1 to 64). */
 enum { RTCC_FP64 = 0, RTCC_FP32 = 1, RTCC_BF16X3 = 2 };
 
 enum {

@@ -449,6 +449,7 @@ void ensure_batch(rtcc_ctx* c, std::unique_ptr<BatchWS>& slot, int nb) {
   B->E.group_products = c->E.group_products;
   B->E.split_wg = c->E.split_wg;
   B->E.group_wg = c->E.group_wg;
+  B->E.tile_band = c->E.tile_band;
   B->E.sym_ladder = c->E.sym_ladder;
   B->E.ladder_lds = c->E.ladder_lds;
   B->E.pair_splits = c->E.pair_splits;
@@ -953,6 +954,9 @@ int rtcc_init(rtcc_ctx** out, int o, int v, const double* eri, const double* foc
     const char* gwg = std::getenv("RTCC_GROUP_WG");
     if (gwg && gwg[0]) c->E.group_wg = std::atoi(gwg);
     RTCC_CHECK(c->E.split_wg >= 1 && c->E.group_wg >= 1, kEInval, "RTCC_SPLIT_WG and RTCC_GROUP_WG must be positive");
+    const char* tb = std::getenv("RTCC_TILE_BAND");
+    if (tb && tb[0]) c->E.tile_band = std::atoi(tb);
+    RTCC_CHECK(c->E.tile_band >= 1 && c->E.tile_band <= 64, kEInval, "RTCC_TILE_BAND must be 1 to 64");
     const char* tr = std::getenv("RTCC_TRACE");
     c->E.trace = tr && tr[0] == '1';
     const char* nbr = std::getenv("RTCC_NO_BRANCH");

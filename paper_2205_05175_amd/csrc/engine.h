@@ -139,6 +139,7 @@ struct Engine {
   bool group_products = true;           // ein_multi may issue independent products as one launch
   int split_wg = 160;                   // split-BF16 K splits: workgroup cap of a single product
   int group_wg = 256;                   // ... of a grouped launch
+  int tile_band = 8;                    // split-BF16 tile map: output-tile rows per band
   const GemmChoice* force = nullptr;    // this choice for every product (kernel tests, the autotuner)
   // Batch size of the tensors with bs != 0. Every contraction then runs for all members: a
   // member index carried by one operand only becomes part of the GEMM's M or N (one fat GEMM

@@ -416,6 +416,7 @@ void fork_branches(Engine& E) {
     b->group_products = E.group_products;
     b->split_wg = E.split_wg;
     b->group_wg = E.group_wg;
+    b->tile_band = E.tile_band;
     b->use_tuning = E.use_tuning;
     b->nb = E.nb;
     b->gemm_flops = 0;

@@ -158,6 +158,7 @@ struct Params {
   int Kp, Mp, Np;   // padded K and rows
   int M, N;
   int tiles_m, tiles_n, ntiles;
+  int band;  // output-tile rows per band of the workgroup -> tile map
   int kchunk, splits;
   float* Cre;
   float* Cim;
@@ -176,13 +177,13 @@ __device__ inline f16 mma(bf8 a, bf8 b, f16 c) { return __builtin_amdgcn_mfma_f3
 
 // Split and tile (tm, tn) of workgroup b: the eight XCDs take workgroups round-robin; renumber so
 // XCD x owns a contiguous range of (split, tile) pairs, split slowest, and walk the tiles of one
-// split in bands of 8 tile rows (tiles of a band share B columns, all share the split's k range).
+// split in bands of p.band tile rows (tiles of a band share B columns, all share the split's k range).
 __device__ inline void tile_of(int b, const Params& p, int* split, int* tm, int* tn) {
   const int n = p.ntiles * p.splits, q = n / 8, r = n % 8, x = b % 8, j = b / 8;
   const int lin = x * q + min(x, r) + j;
   *split = lin / p.ntiles;
   const int id = lin - *split * p.ntiles;
-  constexpr int G = 8;
+  const int G = p.band;
   const int band = id / (G * p.tiles_n);
   const int first = band * G;
   const int rows = min(G, p.tiles_m - first);
@@ -683,6 +684,7 @@ bool gemm_bf16x3(Engine& E, int64_t M, int64_t N, int64_t K, double alpha, GemmO
   p.tiles_m = (int)cdiv(M, kBM);
   p.tiles_n = (int)cdiv(N, kBN);
   p.ntiles = p.tiles_m * p.tiles_n;
+  p.band = E.tile_band;
   p.alpha = (float)alpha;
   p.beta = (float)beta;
   // Split K when it shortens the estimated time: workgroups run in rounds of one per CU (256), a
@@ -813,6 +815,7 @@ bool gemm_bf16x3_pair(Engine& E, const Bf16Job (&jobs)[2]) {
     q.tiles_m = (int)cdiv(j.M, kBM);
     q.tiles_n = (int)cdiv(j.N, kBN);
     q.ntiles = q.tiles_m * q.tiles_n;
+    q.band = E.tile_band;
     q.alpha = (float)j.alpha;
     q.beta = (float)j.beta;
     tiles += q.ntiles;
@@ -915,6 +918,7 @@ bool gemm_bf16x3_multi(Engine& E, const Bf16Job* jobs, int n) {
     q.tiles_m = (int)cdiv(j.M, kBM);
     q.tiles_n = (int)cdiv(j.N, kBN);
     q.ntiles = q.tiles_m * q.tiles_n;
+    q.band = E.tile_band;
     q.alpha = (float)j.alpha;
     q.beta = (float)j.beta;
     tiles += q.ntiles;

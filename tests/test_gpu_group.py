@@ -5,7 +5,9 @@ complex x complex) and the two ring-formation products (real x complex) go out g
 * grouped = one launch per product (RTCC_NO_GROUP=1) up to the rounding of their different K splits;
 * with tuning-table entries for the grouped shapes every group falls back to one launch per product, each
   through the table: bitwise the right-hand side of RTCC_NO_GROUP=1 under the same table;
-* the group is really formed (trace lines), and the fallback really happens (no "multi" lines).
+* the group is really formed (trace lines), and the fallback really happens (no "multi" lines);
+* the band height of the workgroup -> output-tile map (RTCC_TILE_BAND) only moves tiles between
+  workgroups: any band gives the bitwise right-hand side of the default one.
 """
 import ctypes
 import os
@@ -27,10 +29,11 @@ def _need_gpu(require_gpu):
     yield
 
 
-def _rhs(monkeypatch, capfd, group):
+def _rhs(monkeypatch, capfd, group, band="8"):
     import torch
     from paper_2205_05175_amd import RTCC
     monkeypatch.setenv("RTCC_NO_GROUP", "0" if group else "1")
+    monkeypatch.setenv("RTCC_TILE_BAND", band)
     monkeypatch.setenv("RTCC_TRACE", "1")
     R = RTCC(*make_system(O, V, 0), O, V, "bf16x3")
     y = torch.tensor(pack_state(*random_state(O, V, 5, 0.02, 0.01)), device="cuda")
@@ -75,3 +78,11 @@ def test_grouped_products_match_single_launches(monkeypatch, capfd):
     finally:
         os.unlink(path)
         L.rtcc_load_tuning(TUNING_PATH.encode() if os.path.exists(TUNING_PATH) else None, None)
+
+
+@pytest.mark.parametrize("band", ["1", "3", "64"])
+def test_tile_band_moves_tiles_only(monkeypatch, capfd, band):
+    print(f"tile band {band} at ({O},{V}) bf16x3", flush=True)
+    ref, _ = _rhs(monkeypatch, capfd, True)
+    out, _ = _rhs(monkeypatch, capfd, True, band)
+    assert np.array_equal(out, ref)
