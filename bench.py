@@ -44,24 +44,24 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6}
 # HBM bytes per launch of the split-BF16 ladder kernel (gemm_bf16x3_nt<1, 0, 1, 4>, o=20 v=76),
 # from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by the
 # same counter on a plain device copy of the same run (the 72,247.5 KiB state clone: FETCH_SIZE
-# 36,139.2 KiB, x2.0; WRITE_SIZE 72,247.5 KiB, x1.0). Commands and raw figures:
+# 36,150.1 KiB, x2.0; WRITE_SIZE 72,248.4 KiB, x1.0). Commands and raw figures:
 # profiles/ladder_traffic_o20v76.md. To be re-measured whenever that kernel changes. It applies to the
 # full ladder product (RTCC_LADDER=full).
-LADDER_TRAFFIC_BF16X3 = {"fetch_bytes": 246305.8 * 1024 * 2.0, "write_bytes": 38464.0 * 1024 * 1.0,
+LADDER_TRAFFIC_BF16X3 = {"fetch_bytes": 246317.7 * 1024 * 2.0, "write_bytes": 38517.8 * 1024 * 1.0,
                          "kernel": "gemm_bf16x3_nt<1, 0, 1, 4>"}
 # The same for the symmetric / antisymmetric ladder (the default): its two GEMMs (X+V+: 420 x 2926 x 2926,
 # X-V-: 380 x 2850 x 2850, 3 K splits each) in one launch of gemm_bf16x3_nt2<1, 0, 1, 4>, in the RK4 step of
-# bench.py --workload profile (FETCH_SIZE 73,660.2 KiB, WRITE_SIZE 69,636.2 KiB per dispatch; the same
+# bench.py --workload profile (FETCH_SIZE 73,664.2 KiB, WRITE_SIZE 69,977.8 KiB per dispatch; the same
 # run's state clone: FETCH_SIZE x2.0, WRITE_SIZE x1.0). Commands: profiles/ladder_traffic_o20v76.md.
-LADDER_TRAFFIC_BF16X3_SYM = {"fetch_bytes": 73660.2 * 1024 * 2.0, "write_bytes": 69636.2 * 1024 * 1.0,
+LADDER_TRAFFIC_BF16X3_SYM = {"fetch_bytes": 73664.2 * 1024 * 2.0, "write_bytes": 69977.8 * 1024 * 1.0,
                              "kernel": "gemm_bf16x3_nt2<1, 0, 1, 4>"}
 # The dominant kernel of the split-BF16 step, the register-staged complex x complex kernel
 # gemm_bf16x3_nt<1, 1, 0, 4> (the ring and Lambda products, 12 launches per right-hand side at o=20
 # v=76, three of them carrying three independent products each): mean HBM bytes per dispatch over its
 # launches in the RK4 step of bench.py --workload profile, calibrated on the same run's state clone like
-# the ladder's (FETCH_SIZE 59,570.3 KiB x2.0, WRITE_SIZE 37,153.6 KiB x1.0 per dispatch, 144 dispatches).
+# the ladder's (FETCH_SIZE 59,570.3 KiB x2.0, WRITE_SIZE 37,188.1 KiB x1.0 per dispatch, 144 dispatches).
 # Commands: profiles/cc_gemm_o20v76.md.
-CC_TRAFFIC_BF16X3 = {"fetch_bytes": 59570.3 * 1024 * 2.0, "write_bytes": 37153.6 * 1024 * 1.0,
+CC_TRAFFIC_BF16X3 = {"fetch_bytes": 59570.3 * 1024 * 2.0, "write_bytes": 37188.1 * 1024 * 1.0,
                      "kernel": "gemm_bf16x3_nt<1, 1, 0, 4>"}
 
 
