@@ -14,7 +14,10 @@ tests check what holds at any size:
 * linearity in the field: the Hamiltonian is linear in E, so F(y, E) - F(y, 0) is linear in E;
 * the dipole of the propagated FP64 state against the oracle's dipole, which needs no two-electron
   integrals and so is evaluated by the oracle at full size;
-* the benchmark's acceptance bound: split-BF16 and FP32 trajectories within 1e-6 au of FP64.
+* the benchmark's acceptance bound: split-BF16 and FP32 trajectories within 1e-6 au of FP64;
+* the band height of the split-BF16 workgroup -> output-tile map only moves tiles between workgroups
+  (K-split products, grouped launches and the paired ladder launch included): bitwise the same
+  right-hand side.
 """
 import numpy as np
 import pytest
@@ -98,6 +101,22 @@ def test_fullsize_rhs_precisions_and_pair_symmetry(system):
         print(f"  {prec}: pair asymmetry {asym:.3e}")
         assert asym < 10 * tol
     R.close()
+
+
+def test_fullsize_tile_band_moves_tiles_only(system, monkeypatch):
+    import torch
+    from paper_2205_05175_amd import RTCC
+    eri, fock, mu = system
+    y = torch.tensor(pack_state(*random_state(O, V, 3, 0.05, 0.02)), device="cuda")
+    E = [0.003, -0.002, 0.01]
+    out = {}
+    for band in ("8", "5"):
+        print(f"full-size rhs bf16x3, tile band {band}", flush=True)
+        monkeypatch.setenv("RTCC_TILE_BAND", band)
+        R = RTCC(eri, fock, mu, O, V, "bf16x3")
+        out[band] = R.rhs(y, E).cpu().numpy()
+        R.close()
+    assert np.array_equal(out["8"], out["5"])
 
 
 def test_fullsize_rhs_linear_in_field(system):
