@@ -14,6 +14,7 @@ workgroups per CU) with 128 x 128 or 128 x 256 tiles and 1 to 16 splits, within 
 library applies to split grids.
 
 Usage: python -m paper_2205_05175_amd.autotune --o 20 --v 76 [--out FILE] [--precisions fp64,fp32,bf16x3]
+       [--max-flops F]   (only products with 2 M N K < F; the others keep their table entries)
 """
 from __future__ import annotations
 
@@ -161,6 +162,9 @@ def main():
     ap.add_argument("--out", default=DEFAULT_TABLE)
     ap.add_argument("--min-gain", type=float, default=0.03)
     ap.add_argument("--batch", type=int, default=0, help="tune the products of a batched step of this many members")
+    ap.add_argument("--max-flops", type=float, default=0.0,
+                    help="tune only the products with 2 M N K below this (0: all); in the split-BF16 context 5e8 "
+                         "selects the products that stay on the FP32 tile kernel")
     args = ap.parse_args()
     import torch
     from paper_2205_05175_amd import load_library
@@ -177,6 +181,8 @@ def main():
         shapes = collect_shapes(args.o, args.v, prec, args.batch)
         print(f"[autotune] ({args.o},{args.v}) x{max(args.batch, 1)} {prec}: {len(shapes)} GEMM shapes", flush=True)
         for shape, count in sorted(shapes.items()):
+            if args.max_flops > 0 and 2.0 * shape[0] * shape[1] * shape[2] >= args.max_flops:
+                continue
             t1 = time.time()
             base, (best_t, c) = tune_shape(L, prec, shape)
             M, N, K, ac, bc, ta, tb = shape
