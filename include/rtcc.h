@@ -55,9 +55,11 @@ typedef struct rtcc_ctx rtcc_ctx;
  *                 hi*hi + hi*lo + lo*hi with v_mfma_f32_32x32x16_bf16, FP32 accumulation;
  *                 smaller products as RTCC_FP32 (the threshold can be overridden by the
  *                 environment variable RTCC_BF16_MIN_FLOPS, read by rtcc_init). Independent
- *                 products of one part of the Lambda1 residual (the three l2s x t2
- *                 intermediates of each of its two groups) go out as one launch with one K
- *                 split for all; RTCC_NO_GROUP=1, read by rtcc_init, issues them one by one.
+ *                 products of one part of the right-hand side (the three l2s x t2
+ *                 intermediates of each of the two Lambda1 groups, the three Y3
+ *                 intermediates, the two ring-formation products) go out as one launch with
+ *                 one K split for all; RTCC_NO_GROUP=1, read by rtcc_init, issues them one
+ *                 by one.
  *                 K splits are chosen within a workgroup cap, 160 for a single product and 256
  *                 for a grouped launch (RTCC_SPLIT_WG, RTCC_GROUP_WG); workgroups walk the
  *                 output tiles in bands of 8 tile rows (RTCC_TILE_BAND, 1 to 64). */
