@@ -141,6 +141,24 @@ def candidates(prec, shape):
     return out
 
 
+def shapes_to_tune(shapes, max_flops=0.0):
+    """The (shape, call count) pairs to time, in a fixed order: all of them, or with max_flops > 0 only
+    those with 2 M N K below max_flops (the table entries of the others stay as they are)."""
+    return [(s, c) for s, c in sorted(shapes.items()) if max_flops <= 0 or 2.0 * s[0] * s[1] * s[2] < max_flops]
+
+
+def load_entries(path):
+    """The entries of an existing table by key (prec, M, N, K, ac, bc, ta, tb), each line kept verbatim
+    (comment and malformed lines are dropped)."""
+    keep = {}
+    if os.path.exists(path):
+        for line in open(path):
+            body = line.split("#")[0].split()
+            if len(body) == 12:
+                keep[tuple(int(x) for x in body[:8])] = line.rstrip("\n")
+    return keep
+
+
 def tune_shape(L, prec, shape, target_ms=3.0):
     ops = Operands(*shape, prec)
     t0 = run_gemm(L, prec, ops, None, reps=3)
@@ -170,19 +188,12 @@ def main():
     from paper_2205_05175_amd import load_library
     L = load_library()
     L.rtcc_load_tuning(None, None)  # time the library's own rules, not an older table
-    keep = {}
-    if os.path.exists(args.out):  # entries of other sizes stay
-        for line in open(args.out):
-            body = line.split("#")[0].split()
-            if len(body) == 12:
-                keep[tuple(int(x) for x in body[:8])] = line.rstrip("\n")
+    keep = load_entries(args.out)  # entries of other sizes stay
     total_gain = 0.0
     for prec in args.precisions.split(","):
         shapes = collect_shapes(args.o, args.v, prec, args.batch)
         print(f"[autotune] ({args.o},{args.v}) x{max(args.batch, 1)} {prec}: {len(shapes)} GEMM shapes", flush=True)
-        for shape, count in sorted(shapes.items()):
-            if args.max_flops > 0 and 2.0 * shape[0] * shape[1] * shape[2] >= args.max_flops:
-                continue
+        for shape, count in shapes_to_tune(shapes, args.max_flops):
             t1 = time.time()
             base, (best_t, c) = tune_shape(L, prec, shape)
             M, N, K, ac, bc, ta, tb = shape
